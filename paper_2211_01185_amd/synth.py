@@ -1,0 +1,285 @@
+"""Seeded synthetic workloads (particle beds and given fluid fields).
+
+This module only draws inputs: it holds none of the method's arithmetic and
+imports nothing from the rest of the package, so the HIP path and the CPU
+oracle can both be fed from it.  Every generator takes its seed from
+``seed_for(config, index)`` and uses numpy's PCG64.
+
+Workloads (stand-ins for the paper's beds, whose meshes and packings are not
+available):
+  * ``plain``     2,000 spheres, d = 3 mm, random sequential addition in a
+                  0.05 x 0.05 x 0.2 m box; Q2 4x4x16 mesh; uniform (0,0,0.5) m/s.
+  * ``fluidized`` 100,000 spheres, d = 1 mm, jittered simple-cubic lattice at
+                  solid fraction 0.4 in 0.1 x 0.1 x 0.4 m; Q2 20x20x80 mesh;
+                  (0,0,1.2) m/s + N(0, 0.05) per velocity node; linear pressure
+                  carrying the bed's buoyant weight (Eq. "dpf").
+  * ``spouted``   500,000 spheres, lognormal d (median 2 mm, sigma 0.2, clipped
+                  to 1-4 mm), random sequential addition in z < 0.45 m of a
+                  0.15 x 0.15 x 0.6 m box; Q2 30x30x120 mesh; Gaussian jet of
+                  peak 20 m/s and width 0.01 m decaying as exp(-z/0.2).
+  * ``lattice``   the plain geometry on a simple-cubic lattice of spacing
+                  0.98 d: every neighbour overlaps (contact-heavy parity case).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BASE_SEED = 2211011850
+G = 9.81
+
+
+def seed_for(config: int, index: int = 0) -> int:
+    return BASE_SEED + 1000 * config + index
+
+
+def rng_for(config: int, index: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_for(config, index)))
+
+
+@dataclass
+class Workload:
+    name: str
+    x: np.ndarray        # (3, N) positions
+    v: np.ndarray        # (3, N) velocities
+    w: np.ndarray        # (3, N) angular velocities
+    radius: np.ndarray   # (N,)
+    density: np.ndarray  # (N,)
+    dem: dict            # box_lo, box_hi, gravity, dt, E, nu, e, mu, E_w, nu_w, e_w, mu_w
+    fluid: dict          # order, n_el, rho_f, mu_f, model, eps_min
+    run: dict            # steps, coupling_every, precision ("fp64" | "fp32")
+    U: np.ndarray = field(default=None)  # (3, n_v) nodal velocity
+    P: np.ndarray = field(default=None)  # (n_p,) nodal Q1 pressure
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+
+def _material(**over) -> dict:
+    base = dict(E=1e6, nu=0.3, e=0.9, mu=0.3)
+    base.update(over)
+    out = dict(base)
+    for k in ("E", "nu", "e", "mu"):
+        out[k + "_w"] = over.get(k + "_w", base[k])
+    return out
+
+
+def node_grid(lo, hi, n_el, order):
+    """Coordinates (3, n_nodes) of the structured Q_order node lattice, x fastest."""
+    axes = [np.linspace(lo[a], hi[a], order * n_el[a] + 1) for a in range(3)]
+    zz, yy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel(), zz.ravel()])
+
+
+def rsa_monodisperse(rng, n, d, lo, hi, max_tries=2000000):
+    """Random sequential addition: centres at least d/2 from every wall and
+    strictly more than d apart."""
+    r = 0.5 * d
+    lo_c = np.asarray(lo, float) + r
+    hi_c = np.asarray(hi, float) - r
+    pts = np.zeros((0, 3))
+    tries = 0
+    while pts.shape[0] < n and tries < max_tries:
+        cand = lo_c + (hi_c - lo_c) * rng.random((min(4 * (n - pts.shape[0]), 4096), 3))
+        tries += cand.shape[0]
+        for c in cand:
+            if pts.shape[0] and np.min(np.sum((pts - c) ** 2, axis=1)) <= d * d:
+                continue
+            pts = np.vstack([pts, c])
+            if pts.shape[0] == n:
+                break
+    if pts.shape[0] < n:
+        raise RuntimeError("random sequential addition did not reach the requested count")
+    return pts.T.copy()
+
+
+def rsa_polydisperse(rng, radius, lo, hi):
+    """Random sequential addition of spheres with the given radii (placed in the
+    given order) inside [lo, hi], wall distance >= r, centre distance > r_i + r_j.
+    Batched with a k-d tree over the accepted spheres."""
+    from scipy.spatial import cKDTree
+
+    n = radius.shape[0]
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    rmax = float(radius.max())
+    pts = np.zeros((n, 3))
+    placed = 0
+    tree = None
+    tree_pts = np.zeros((0, 3))
+    tree_r = np.zeros(0)
+    pending = np.zeros((0, 3))
+    pending_r = np.zeros(0)
+    while placed < n:
+        batch = min(n - placed, 20000)
+        rb = radius[placed:placed + batch]
+        cand = lo + rb[:, None] + (hi - lo - 2 * rb[:, None]) * rng.random((batch, 3))
+        ok = np.ones(batch, dtype=bool)
+        # against accepted spheres in the tree and in the not-yet-indexed list
+        if tree is not None:
+            nb = tree.query_ball_point(cand, rb + rmax)
+            for k in range(batch):
+                idx = nb[k]
+                if idx:
+                    dd = np.sum((tree_pts[idx] - cand[k]) ** 2, axis=1)
+                    if np.any(dd <= (tree_r[idx] + rb[k]) ** 2):
+                        ok[k] = False
+        if pending.shape[0]:
+            ptree = cKDTree(pending)
+            nb = ptree.query_ball_point(cand, rb + rmax)
+            for k in range(batch):
+                if not ok[k] or not nb[k]:
+                    continue
+                idx = nb[k]
+                dd = np.sum((pending[idx] - cand[k]) ** 2, axis=1)
+                if np.any(dd <= (pending_r[idx] + rb[k]) ** 2):
+                    ok[k] = False
+        # within the batch, in order: a candidate is dropped if it overlaps an
+        # earlier accepted candidate of the same batch
+        btree = cKDTree(cand)
+        pairs = btree.query_pairs(2 * rmax, output_type="ndarray")
+        if pairs.shape[0]:
+            a, b = pairs[:, 0], pairs[:, 1]
+            lo_i = np.minimum(a, b)
+            hi_i = np.maximum(a, b)
+            dd = np.sum((cand[lo_i] - cand[hi_i]) ** 2, axis=1)
+            clash = dd <= (rb[lo_i] + rb[hi_i]) ** 2
+            lo_i, hi_i = lo_i[clash], hi_i[clash]
+            order = np.argsort(hi_i, kind="stable")
+            for p in order:
+                if ok[lo_i[p]]:
+                    ok[hi_i[p]] = False
+        # accepted candidates keep their radii order; rejected radii retry
+        acc = np.nonzero(ok)[0]
+        rej = np.nonzero(~ok)[0]
+        new_r = np.concatenate([rb[acc], rb[rej]])
+        radius[placed:placed + batch] = new_r
+        pts[placed:placed + acc.shape[0]] = cand[acc]
+        pending = np.vstack([pending, cand[acc]])
+        pending_r = np.concatenate([pending_r, rb[acc]])
+        placed += acc.shape[0]
+        if pending.shape[0] > 50000 or placed == n:
+            tree_pts = np.vstack([tree_pts, pending])
+            tree_r = np.concatenate([tree_r, pending_r])
+            tree = cKDTree(tree_pts)
+            pending = np.zeros((0, 3))
+            pending_r = np.zeros(0)
+    return pts.T.copy()
+
+
+def jittered_lattice(rng, n, d, lo, hi, solid_fraction):
+    """Simple-cubic lattice of spacing s = d (pi/(6 phi))^(1/3) filled layer by
+    layer from the floor, each centre jittered uniformly by +-0.4999 (s - d) per
+    axis (no initial overlap)."""
+    s = d * (math.pi / (6.0 * solid_fraction)) ** (1.0 / 3.0)
+    nx = int((hi[0] - lo[0]) // s)
+    ny = int((hi[1] - lo[1]) // s)
+    per_layer = nx * ny
+    layers = -(-n // per_layer)
+    if lo[2] + layers * s > hi[2]:
+        raise ValueError("lattice does not fit the box")
+    k = np.arange(n)
+    ix = k % nx
+    iy = (k // nx) % ny
+    iz = k // per_layer
+    off_x = lo[0] + 0.5 * ((hi[0] - lo[0]) - nx * s)
+    off_y = lo[1] + 0.5 * ((hi[1] - lo[1]) - ny * s)
+    x = np.stack([off_x + (ix + 0.5) * s, off_y + (iy + 0.5) * s, lo[2] + (iz + 0.5) * s])
+    jit = 0.4999 * (s - d)
+    x += rng.uniform(-jit, jit, size=x.shape)
+    return x
+
+
+def plain(n=2000, seed_index=0) -> Workload:
+    """2,000 monodisperse spheres, d = 3 mm, rho = 2500 (FP64 correctness config)."""
+    rng = rng_for(1, seed_index)
+    d = 3e-3
+    lo, hi = [0.0, 0.0, 0.0], [0.05, 0.05, 0.2]
+    x = rsa_monodisperse(rng, n, d, lo, hi)
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    fluid = dict(order=2, n_el=[4, 4, 16], rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, fluid["n_el"], 2)
+    U = np.zeros((3, nodes.shape[1]))
+    U[2] = 0.5
+    P = np.zeros(node_grid(lo, hi, fluid["n_el"], 1).shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
+    return Workload("plain", x, v, np.zeros((3, n)), np.full(n, 0.5 * d), np.full(n, 2500.0), dem,
+                    fluid, dict(steps=100, coupling_every=10, precision="fp64"), U, P)
+
+
+def lattice(n_side=(12, 12, 14), spacing_factor=0.98, seed_index=0, d=3e-3) -> Workload:
+    """Plain-config spheres on a simple-cubic lattice of spacing 0.98 d, small
+    random velocities and spins; every lattice neighbour overlaps by 2 %."""
+    rng = rng_for(1, 100 + seed_index)
+    s = spacing_factor * d
+    nx, ny, nz = n_side
+    lo = [0.0, 0.0, 0.0]
+    hi = [nx * s + 0.01, ny * s + 0.01, nz * s + 0.02]
+    k = np.arange(nx * ny * nz)
+    x = np.stack([0.005 + (k % nx + 0.5) * s, 0.005 + ((k // nx) % ny + 0.5) * s,
+                  0.5 * d + (k // (nx * ny)) * s])
+    x += rng.uniform(-0.002 * d, 0.002 * d, size=x.shape)
+    n = x.shape[1]
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    w = rng.normal(0.0, 5.0, size=(3, n))
+    # mesh: elements of ~4 d
+    n_el = [max(1, int((hi[a] - lo[a]) // (4 * d))) for a in range(3)]
+    fluid = dict(order=2, n_el=n_el, rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, n_el, 2)
+    U = np.zeros((3, nodes.shape[1]))
+    U[2] = 0.5 + 0.05 * rng.standard_normal(nodes.shape[1])
+    P = 100.0 * (1.0 - node_grid(lo, hi, n_el, 1)[2] / hi[2])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
+    return Workload("lattice", x, v, w, np.full(n, 0.5 * d), np.full(n, 2500.0), dem, fluid,
+                    dict(steps=20, coupling_every=10, precision="fp64"), U, P)
+
+
+def fluidized(n=100_000, seed_index=0, height=0.4) -> Workload:
+    """100,000 spheres, d = 1 mm, rho = 2500, jittered lattice at solid fraction
+    0.4; Q2 20x20x80; U = (0,0,1.2) + N(0,0.05) per node; linear pressure."""
+    rng = rng_for(2, seed_index)
+    d = 1e-3
+    lo, hi = [0.0, 0.0, 0.0], [0.1, 0.1, height]
+    x = jittered_lattice(rng, n, d, lo, hi, 0.4)
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    n_el = [20, 20, int(round(80 * height / 0.4))]
+    fluid = dict(order=2, n_el=n_el, rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, n_el, 2)
+    U = rng.normal(0.0, 0.05, size=(3, nodes.shape[1]))
+    U[2] += 1.2
+    # pressure drop equal to the buoyant weight of the bed over the cross-section
+    vp = math.pi / 6.0 * d ** 3
+    area = (hi[0] - lo[0]) * (hi[1] - lo[1])
+    dp = n * vp * (2500.0 - fluid["rho_f"]) * G / area
+    P = dp * (1.0 - node_grid(lo, hi, n_el, 1)[2] / hi[2])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
+    return Workload("fluidized", x, v, np.zeros((3, n)), np.full(n, 0.5 * d), np.full(n, 2500.0), dem,
+                    fluid, dict(steps=1000, coupling_every=10, precision="fp32"), U, P)
+
+
+def spouted(n=500_000, seed_index=0, box=(0.15, 0.15, 0.6), fill_height=0.45, n_el=(30, 30, 120)) -> Workload:
+    """500,000 polydisperse spheres (lognormal d, median 2 mm, sigma 0.2,
+    clipped to [1, 4] mm), rho = 2500; Q2 mesh; Gaussian jet."""
+    rng = rng_for(3, seed_index)
+    d = np.exp(rng.normal(math.log(2e-3), 0.2, size=n))
+    d = np.clip(d, 1e-3, 4e-3)
+    radius = 0.5 * d
+    lo, hi = [0.0, 0.0, 0.0], list(box)
+    x = rsa_polydisperse(rng, radius, lo, [hi[0], hi[1], fill_height])
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    fluid = dict(order=2, n_el=list(n_el), rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, fluid["n_el"], 2)
+    cx, cy = 0.5 * hi[0], 0.5 * hi[1]
+    rr = (nodes[0] - cx) ** 2 + (nodes[1] - cy) ** 2
+    U = np.zeros((3, nodes.shape[1]))
+    U[2] = 20.0 * np.exp(-rr / (2 * 0.01 ** 2)) * np.exp(-nodes[2] / 0.2)
+    P = np.zeros(node_grid(lo, hi, fluid["n_el"], 1).shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
+    return Workload("spouted", x, v, np.zeros((3, n)), radius, np.full(n, 2500.0), dem, fluid,
+                    dict(steps=500, coupling_every=10, precision="fp32"), U, P)
+
+
+WORKLOADS = {"plain": plain, "lattice": lattice, "fluidized": fluidized, "spouted": spouted}

@@ -1,0 +1,279 @@
+"""Pins of the oracle's DEM step against facts that do not come from its code:
+brute-force contact search, Hertz contact theory, rigid-body kinematics,
+Newton's third law and exact free fall."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import beta as beta_fn
+
+from paper_2211_01185_amd import synth
+
+G = 9.81
+
+
+def brute_force_pairs(x, r):
+    """All i<j with (R_i+R_j)^2 - (dx^2+dy^2+dz^2) > 0, evaluated left to right."""
+    n = x.shape[1]
+    out = []
+    for i in range(n - 1):
+        dx = x[0, i + 1:] - x[0, i]
+        dy = x[1, i + 1:] - x[1, i]
+        dz = x[2, i + 1:] - x[2, i]
+        rs = r[i] + r[i + 1:]
+        d2 = dx * dx + dy * dy + dz * dz
+        js = np.nonzero(rs * rs - d2 > 0.0)[0] + i + 1
+        out.extend((i, int(j)) for j in js)
+    return out
+
+
+def params_for(O, wl, **over):
+    d = dict(wl.dem)
+    d.update(over)
+    return O.make_params(d["box_lo"], d["box_hi"], d["gravity"], d["dt"], d["E"], d["nu"], d["e"],
+                         d["mu"], d["E_w"], d["nu_w"], d["e_w"], d["mu_w"])
+
+
+def two_spheres(O, d=3e-3, rho=2500.0, v0=0.01, gap=1e-7, e=1.0, mu=0.3, dt=1e-6, E=1e6, nu=0.3):
+    lo, hi = [0.0, 0.0, 0.0], [0.05, 0.05, 0.05]
+    c = 0.025
+    x = np.array([[c - 0.5 * d - 0.5 * gap, c + 0.5 * d + 0.5 * gap], [c, c], [c, c]])
+    v = np.array([[0.5 * v0, -0.5 * v0], [0.0, 0.0], [0.0, 0.0]])
+    p = O.make_params(lo, hi, [0, 0, 0], dt, E, nu, e, mu)
+    return O.OracleBed(p, x, v, np.zeros((3, 2)), np.full(2, 0.5 * d), np.full(2, rho))
+
+
+# ---------------------------------------------------------------- contacts
+@pytest.mark.parametrize("factory", ["lattice", "plain", "poly"])
+def test_contact_search_matches_brute_force(oracle_mod, factory):
+    O = oracle_mod
+    if factory == "lattice":
+        wl = synth.lattice(n_side=(8, 8, 9))
+        x, r = wl.x, wl.radius
+    elif factory == "plain":
+        wl = synth.plain(n=600)
+        # squeeze the bed so that many pairs touch
+        x = wl.x.copy()
+        x[2] *= 0.15
+        r = wl.radius * 1.6
+    else:
+        rng = np.random.default_rng(7)
+        n = 700
+        r = rng.uniform(0.5e-3, 2e-3, n)
+        x = rng.uniform(0.0, 0.03, (3, n))
+        wl = None
+    lo, hi = [0.0, 0.0, 0.0], list(np.max(x, axis=1) + 0.01)
+    pi, pj = O.find_pairs(x, r, lo, hi)
+    got = list(zip(pi.tolist(), pj.tolist()))
+    want = brute_force_pairs(x, r)
+    assert len(want) > 50
+    assert got == sorted(want)
+
+
+def test_contact_predicate_is_strict(oracle_mod):
+    O = oracle_mod
+    # exactly touching (distance == R_i + R_j in binary) is not a contact
+    x = np.array([[0.25, 0.75], [0.5, 0.5], [0.5, 0.5]])
+    r = np.array([0.25, 0.25])
+    pi, _ = O.find_pairs(x, r, [0, 0, 0], [1, 1, 1])
+    assert pi.size == 0
+    x[0, 1] = np.nextafter(0.75, 0.0)
+    pi, _ = O.find_pairs(x, r, [0, 0, 0], [1, 1, 1])
+    assert pi.size == 1
+
+
+def test_binning_properties(oracle_mod):
+    """Every centre lies inside its element and its cell, and touching pairs
+    sit in the same or adjacent cells (the broad-search stencil property)."""
+    O = oracle_mod
+    wl = synth.lattice(n_side=(10, 10, 10))
+    lo, hi = np.array(wl.dem["box_lo"]), np.array(wl.dem["box_hi"])
+    n_el = wl.fluid["n_el"]
+    k = [max(1, int(((hi[a] - lo[a]) / n_el[a]) // (2 * wl.radius.max() * (1 + 1e-9)))) for a in range(3)]
+    elem, cell, outside = O.bin_particles(wl.x, lo, hi, n_el, k)
+    assert outside == 0
+    he = (hi - lo) / np.array(n_el)
+    e3 = np.stack([elem % n_el[0], (elem // n_el[0]) % n_el[1], elem // (n_el[0] * n_el[1])])
+    kk = k[0] * k[1] * k[2]
+    sub = cell % kk
+    s3 = np.stack([sub % k[0], (sub // k[0]) % k[1], sub // (k[0] * k[1])])
+    assert np.all(cell // kk == elem)
+    hc = he / np.array(k)
+    for a in range(3):
+        lo_e = lo[a] + e3[a] * he[a]
+        assert np.all(wl.x[a] >= lo_e - 1e-15) and np.all(wl.x[a] <= lo_e + he[a] + 1e-15)
+        lo_c = lo_e + s3[a] * hc[a]
+        assert np.all(wl.x[a] >= lo_c - 1e-15) and np.all(wl.x[a] <= lo_c + hc[a] + 1e-15)
+    g = np.stack([e3[a] * k[a] + s3[a] for a in range(3)])
+    pi, pj = O.find_pairs(wl.x, wl.radius, lo, hi)
+    assert pi.size > 100
+    assert np.max(np.abs(g[:, pi] - g[:, pj])) <= 1
+
+
+def test_binning_boundary_and_outside(oracle_mod):
+    O = oracle_mod
+    x = np.array([[0.0, 1.0, 0.5, -1e-9, 0.999999999], [0.0, 1.0, 0.5, 0.5, 0.5], [0.0, 1.0, 0.5, 0.5, 0.5]])
+    elem, cell, outside = O.bin_particles(x, [0, 0, 0], [1, 1, 1], [4, 4, 4], [2, 2, 2])
+    assert outside == 1
+    assert elem[0] == 0 and elem[1] == 63  # hi face goes to the last element
+    assert elem[2] == (2 * 4 + 2) * 4 + 2   # interior face goes to the upper element
+    assert cell[2] == elem[2] * 8 + 0
+
+
+# ---------------------------------------------------------------- normal law
+def contact_history(bed, nsteps):
+    """Count of contacting steps and the final velocities."""
+    touching = 0
+    first = last = None
+    for k in range(nsteps):
+        bed.step(1)
+        i, j, _ = bed.contacts()
+        if i.size:
+            touching += 1
+            if first is None:
+                first = k
+            last = k
+    return first, last, bed.state()
+
+
+def hertz_contact_time(me, Re, Ye, v0):
+    """Hertz impact duration: t_c = 2 (2/5) B(2/5, 1/2) (15/16)^(2/5) (m_e^2/(R_e Y_e^2 v0))^(1/5)."""
+    coef = 2.0 * 0.4 * beta_fn(0.4, 0.5) * (15.0 / 16.0) ** 0.4
+    return coef * (me * me / (Re * Ye * Ye * v0)) ** 0.2
+
+
+def test_hertz_impact_contact_time_and_elastic_rebound(oracle_mod):
+    O = oracle_mod
+    d, rho, v0, dt, E, nu = 3e-3, 2500.0, 0.01, 1e-6, 1e6, 0.3
+    bed = two_spheres(O, d=d, rho=rho, v0=v0, e=1.0, dt=dt, E=E, nu=nu)
+    first, last, st = contact_history(bed, 4000)
+    m = rho * math.pi / 6 * d ** 3
+    me, Re = m / 2, d / 4
+    Ye = 1.0 / (2 * (1 - nu * nu) / E)
+    tc = hertz_contact_time(me, Re, Ye, v0)
+    assert abs(tc - 1.9299e-3) < 1e-6
+    measured = (last - first + 1) * dt
+    assert abs(measured - tc) <= 2 * dt
+    vrel = st["v"][0, 1] - st["v"][0, 0]
+    assert abs(vrel / v0 - 1.0) < 1e-6
+    # momentum is conserved exactly by the pair force
+    assert abs(st["v"][0, 0] + st["v"][0, 1]) < 1e-15
+
+
+@pytest.mark.parametrize("e", [0.7, 0.9])
+def test_restitution_is_reproduced(oracle_mod, e):
+    """With the unclamped damped normal law the rebound ratio equals e,
+    independently of the impact speed."""
+    O = oracle_mod
+    for v0 in (0.01, 0.1):
+        bed = two_spheres(O, v0=v0, e=e, dt=1e-5)
+        contact_history(bed, 800 if v0 == 0.01 else 300)
+        st = bed.state()
+        vrel = st["v"][0, 1] - st["v"][0, 0]
+        assert abs(vrel / v0 - e) < 1e-3
+
+
+def test_priming_force_is_hertz(oracle_mod):
+    """At creation the stored force of a static overlap is (4/3) Y_e sqrt(R_e) dn^(3/2)."""
+    O = oracle_mod
+    d, E, nu = 3e-3, 1e6, 0.3
+    dn = 0.02 * d
+    x = np.array([[0.02, 0.02 + d - dn], [0.02, 0.02], [0.02, 0.02]])
+    p = O.make_params([0, 0, 0], [0.05, 0.05, 0.05], [0, 0, 0], 1e-5, E, nu, 0.5, 0.3)
+    bed = O.OracleBed(p, x, np.zeros((3, 2)), np.zeros((3, 2)), np.full(2, d / 2), np.full(2, 2500.0))
+    Ye = E / (2 * (1 - nu * nu))
+    dn_actual = d - (x[0, 1] - x[0, 0])
+    F = 4.0 / 3.0 * Ye * math.sqrt(d / 4) * dn_actual ** 1.5
+    st = bed.state()
+    assert abs(-st["Fc"][0, 0] / F - 1) < 1e-12 and abs(st["Fc"][0, 1] / F - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- walls, friction
+def test_static_overlap_on_wall(oracle_mod):
+    """A sphere settled on the floor carries its weight: mg = (4/3) Y_e sqrt(R) dn^(3/2),
+    with Y_e combining particle and wall moduli (Hertz sphere-on-flat)."""
+    O = oracle_mod
+    d, rho, E, nu, E_w, nu_w = 3e-3, 2500.0, 1e6, 0.3, 4e6, 0.25
+    R = d / 2
+    m = rho * math.pi / 6 * d ** 3
+    Ye = 1.0 / ((1 - nu * nu) / E + (1 - nu_w * nu_w) / E_w)
+    dn = (3 * m * G / (4 * Ye * math.sqrt(R))) ** (2.0 / 3.0)
+    x = np.array([[0.02], [0.02], [R - 0.5 * dn]])
+    p = O.make_params([0, 0, 0], [0.04, 0.04, 0.04], [0, 0, -G], 1e-5, E, nu, 0.3, 0.3, E_w, nu_w, 0.3, 0.3)
+    bed = O.OracleBed(p, x, np.zeros((3, 1)), np.zeros((3, 1)), np.full(1, R), np.full(1, rho))
+    bed.step(20000)
+    st = bed.state()
+    measured = R - st["x"][2, 0]
+    assert abs(measured / dn - 1) < 1e-3
+    assert abs(st["v"][2, 0]) < 1e-6
+
+
+def test_sliding_sphere_starts_rolling_at_five_sevenths(oracle_mod):
+    """Sliding phase v(t) = v0 - mu g t, then rolling without slip at 5/7 v0,
+    reached at t = 2 v0 / (7 mu g) (uniform solid sphere)."""
+    O = oracle_mod
+    d, rho, E, nu, mu, v0, dt = 3e-3, 2500.0, 1e6, 0.3, 0.3, 0.1, 1e-5
+    R = d / 2
+    m = rho * math.pi / 6 * d ** 3
+    Ye = 1.0 / (2 * (1 - nu * nu) / E)
+    dn = (3 * m * G / (4 * Ye * math.sqrt(R))) ** (2.0 / 3.0)
+    x = np.array([[0.005], [0.02], [R - dn]])
+    v = np.array([[v0], [0.0], [0.0]])
+    p = O.make_params([0, 0, 0], [0.1, 0.04, 0.04], [0, 0, -G], dt, E, nu, 0.3, mu)
+    bed = O.OracleBed(p, x, v, np.zeros((3, 1)), np.full(1, R), np.full(1, rho))
+    t_roll = 2 * v0 / (7 * mu * G)
+    half = int(0.5 * t_roll / dt)
+    bed.step(half)
+    st = bed.state()
+    assert abs(st["v"][0, 0] - (v0 - mu * G * half * dt)) / v0 < 5e-3
+    bed.step(int(2.0 * t_roll / dt))
+    st = bed.state()
+    assert abs(st["v"][0, 0] / (5.0 / 7.0 * v0) - 1) < 2e-3
+    # rolling without slip: contact-point velocity v_x - R w_y vanishes
+    assert abs(st["v"][0, 0] - R * st["w"][1, 0]) / v0 < 2e-3
+
+
+# ---------------------------------------------------------------- balance laws
+def test_newton_third_law(oracle_mod):
+    O = oracle_mod
+    wl = synth.lattice(n_side=(7, 7, 7))
+    x = wl.x.copy()
+    x[2] += 0.005  # lift off the floor: no wall contacts
+    p = params_for(O, wl, gravity=[0.0, 0.0, 0.0])
+    bed = O.OracleBed(p, x, wl.v, wl.w, wl.radius, wl.density)
+    for _ in range(3):
+        bed.step(1)
+        st = bed.state()
+        i, j, _ = bed.contacts()
+        assert np.all(j >= 0) and i.size > 500
+        tot = np.abs(st["Fc"]).sum()
+        assert np.all(np.abs(st["Fc"].sum(axis=1)) <= 1e-13 * tot)
+
+
+def test_free_fall_is_exact(oracle_mod):
+    O = oracle_mod
+    x0 = np.array([[0.5], [0.5], [0.9]])
+    v0 = np.array([[0.1], [-0.2], [0.3]])
+    p = O.make_params([0, 0, 0], [1, 1, 1], [0.0, 0.0, -G], 1e-4, 1e6, 0.3, 0.9, 0.3)
+    bed = O.OracleBed(p, x0, v0, np.zeros((3, 1)), np.full(1, 1e-3), np.full(1, 2500.0))
+    n = 1000
+    bed.step(n)
+    t = n * 1e-4
+    st = bed.state()
+    g = np.array([0.0, 0.0, -G])
+    assert np.allclose(st["x"][:, 0], x0[:, 0] + v0[:, 0] * t + 0.5 * g * t * t, rtol=1e-12, atol=1e-14)
+    assert np.allclose(st["v"][:, 0], v0[:, 0] + g * t, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- errors
+def test_domain_and_nan_errors(oracle_mod):
+    O = oracle_mod
+    p = O.make_params([0, 0, 0], [1, 1, 1], [0.0, 0.0, -G], 1e-4, 1e6, 0.3, 0.9, 0.3)
+    bed = O.OracleBed(p, np.array([[0.5], [0.5], [1.5]]), np.zeros((3, 1)), np.zeros((3, 1)),
+                      np.full(1, 1e-3), np.full(1, 2500.0))
+    assert bed.error & O.ERR_DOMAIN
+    v = np.zeros((3, 1))
+    v[0, 0] = np.nan
+    bed = O.OracleBed(p, np.array([[0.5], [0.5], [0.5]]), v, np.zeros((3, 1)), np.full(1, 1e-3),
+                      np.full(1, 2500.0))
+    assert bed.error & O.ERR_NAN
