@@ -1,0 +1,203 @@
+/*
+ * cfddem.h -- C ABI of the MI355X (gfx950) particle-side hot path of
+ * unresolved CFD-DEM (El Geitani, Golshan & Blais, "Towards High-Order
+ * CFD-DEM: Development and Validation", arXiv 2211.01185).
+ *
+ * One DEM step (Section 2.2): cell-list broad search, fine contact search,
+ * Hertz-Mindlin nonlinear spring-dashpot normal and tangential forces
+ * (Table "tab:viscoelastic" and the contact-force equation) with a Coulomb
+ * limit, velocity-Verlet integration of Eqs. "newton_law" and
+ * "angular_momentum".  One coupling step (Section 2.3): particle-centroid
+ * void fraction (Eq. "void_fraction") at the quadrature points of a given
+ * Q1/Q2 hex mesh, Di Felice drag (Eq. "drag" and the per-particle drag
+ * expression), buoyancy and pressure-gradient forces on the particles, and the
+ * drag (plus, for model B, the pressure-gradient force) reduced back to the
+ * quadrature points (Eqs. "fa" / "fb").
+ *
+ * Conventions for every entry point
+ *  - SI units; FP64 in and out.
+ *  - Per-particle vectors are component-major: x[c*n + i], c = 0,1,2.
+ *  - Particle i is the i-th particle given to dem_create ("original ID").
+ *    Every output is in original-ID order; the library's internal order
+ *    (re-sorted by cell) is never exposed.
+ *  - Pointers are DEVICE pointers unless the comment says "host".
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *    on it and return without waiting, except where "synchronizes" is stated.
+ *  - The caller owns every buffer, including the workspace; the library never
+ *    allocates device memory and never frees caller memory.  A context must
+ *    be used from one host thread at a time.
+ *  - Errors: argument errors return at once without enqueuing work.  Errors
+ *    found on the device (a particle outside the box, a capacity overflow, a
+ *    NaN) set a sticky device flag; dem_poll reports it, and from then on
+ *    every call on the context returns that error (the context is poisoned)
+ *    until dem_destroy.
+ */
+#ifndef CFDDEM_H
+#define CFDDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFDDEM_ABI_VERSION 1
+
+typedef struct dem_ctx dem_ctx;
+typedef int32_t dem_status;
+
+enum {
+  DEM_OK = 0,
+  DEM_E_ARG = -1,         /* invalid argument or parameter */
+  DEM_E_WORKSPACE = -2,   /* workspace NULL, misaligned (256 B) or too small */
+  DEM_E_HIP = -3,         /* a HIP runtime call failed */
+  DEM_E_DOMAIN = -4,      /* a particle centre left the box */
+  DEM_E_CAPACITY = -5,    /* per-cell or per-particle contact capacity exceeded */
+  DEM_E_NAN = -6,         /* NaN in the particle state */
+  DEM_E_UNSUPPORTED = -7, /* valid but not implemented (e.g. another drag law) */
+  DEM_E_ABI = -8          /* abi_version mismatch */
+};
+
+enum { DEM_FP64 = 0, DEM_FP32_FORCES = 1 };
+enum { DEM_DRAG_DIFELICE = 0 };
+enum { DEM_MODEL_A = 0, DEM_MODEL_B = 1 };
+
+/* DEM parameters (host struct).  Material constants follow Table
+ * "tab:viscoelastic": the particle-particle contact uses (E, nu) for both
+ * bodies, the particle-wall contact combines the particle's (E, nu) with the
+ * wall's (E_w, nu_w).  e must be in (0, 1]; mu >= 0. */
+typedef struct {
+  int32_t abi_version;   /* must be CFDDEM_ABI_VERSION */
+  int32_t precision;     /* DEM_FP64, or DEM_FP32_FORCES: pair-force and drag
+                            arithmetic in FP32; positions, velocities,
+                            tangential history, overlaps/normals and every
+                            accumulation stay FP64 */
+  int64_t n;             /* particle count, >= 1 */
+  double box_lo[3];      /* the six box faces are the walls */
+  double box_hi[3];
+  double gravity[3];
+  double dt;             /* DEM time step, > 0 */
+  double E, nu, e, mu;   /* particle: Young, Poisson; pair restitution, Coulomb friction */
+  double E_w, nu_w, e_w, mu_w; /* wall: Young, Poisson; particle-wall restitution, friction */
+  int32_t max_contacts;  /* contacts per particle including walls, 1..32; 0 = 16 */
+  int32_t cell_capacity; /* particles per DEM cell, 1..1024; 0 = derived from sizes */
+  int32_t resort_every;  /* DEM steps between re-sorts of the particle arrays by
+                            cell; 0 = never (order of creation) */
+  int32_t reserved;      /* must be 0 */
+  double d_max;          /* largest particle diameter (sizes the DEM cells:
+                            cells are at least this wide) */
+  double d_min;          /* smallest particle diameter (sizes cell_capacity);
+                            dem_create rejects radii outside [d_min, d_max]/2 */
+} dem_params;
+
+/* Coupling parameters (host struct).  The structured hex mesh spans the DEM
+ * box: n_el[a] equal elements along axis a.  Velocity nodes form the
+ * (order*n_el[a]+1)-per-axis lattice, pressure nodes the Q1 lattice
+ * (n_el[a]+1 per axis); both are numbered x fastest, then y, then z.
+ * Quadrature: Gauss-Legendre, (order+1) points per axis, numbered x fastest
+ * within an element; element index (ez*n_el[1]+ey)*n_el[0]+ex; quadrature
+ * arrays are element-major: q_global = element*(order+1)^3 + q_local. */
+typedef struct {
+  int32_t order;   /* 1 = Q1-Q1, 2 = Q2-Q1 */
+  int32_t n_el[3]; /* >= 1 each */
+  double rho_f;    /* fluid density, > 0 */
+  double mu_f;     /* fluid DYNAMIC viscosity (Pa s), > 0 */
+  int32_t drag;    /* DEM_DRAG_DIFELICE */
+  int32_t model;   /* DEM_MODEL_A or DEM_MODEL_B (decides what is handed to
+                      the fluid, Eqs. "fa" / "fb") */
+  double eps_min;  /* the drag closure sees clamp(eps, eps_min, 1); (0, 1] */
+} cfd_params;
+
+/* Bytes of device workspace dem_create needs for these parameters.  Pure host
+ * function: no HIP call.  Returns 0 when the parameters are invalid. */
+size_t dem_workspace_bytes(const dem_params *dp, const cfd_params *cp);
+
+/* Create a bed.  x, v, omega: 3 x n (component-major); radius, density: n.
+ * All five are device arrays, read during the call's stream work and copied
+ * into the workspace (the caller may reuse them once the stream reaches this
+ * point).  workspace: device memory of ws_bytes >= dem_workspace_bytes(),
+ * 256-byte aligned, owned by the caller and kept alive until dem_destroy.
+ * The DEM cell grid is nested in the mesh elements (each element is split
+ * into k_a >= 1 cells per axis, cells at least one maximum diameter wide), so
+ * the mesh is fixed at creation.
+ * Creation "primes" the stored contact force and torque with one contact
+ * evaluation at the initial state with zero tangential overlap; the held
+ * fluid force starts at zero.  *out receives the context (host pointer). */
+dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *x,
+                      const double *v, const double *omega, const double *radius,
+                      const double *density, void *workspace, size_t ws_bytes,
+                      void *stream, dem_ctx **out);
+
+/* Advance n_steps >= 0 DEM steps with the held fluid force (Section 2.3.1:
+ * the coupling force is computed once per CFD step and held during the
+ * f_coupling DEM sub-steps).  Per step: half kick and drift, binning of the
+ * new positions, contact search and forces at the half-step velocities,
+ * second half kick. */
+dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream);
+
+/* One coupling step at the current particle state with the given fluid field.
+ *   u_nodes: 3 x n_v nodal velocity (component-major over velocity nodes)
+ *   p_nodes: n_p nodal pressure (Q1); must not contain the hydrostatic part
+ *            rho_f g.x, since buoyancy is applied to the particles explicitly
+ *   eps_q, beta_q: n_el*n_q outputs (void fraction, beta_q = sum beta_p / V_e)
+ *   fpf_q: 3 x (n_el*n_q) force density on the fluid (component-major)
+ *   elem_sums: NULL, or 12 x n_el (component-major over elements):
+ *     0 particle count, 1 sum V_p, 2 sum beta_p, 3-5 sum beta_p u_p,
+ *     6-8 sum f_D, 9-11 sum f_gradp
+ * Also stores f_fp = f_D + f_B + f_gradp per particle, held by the following
+ * dem_step calls. */
+dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_nodes,
+                          double *eps_q, double *beta_q, double *fpf_q, double *elem_sums,
+                          void *stream);
+
+/* Copy the state out in original-ID order (each argument may be NULL):
+ * positions, velocities, angular velocities, held fluid force, all 3 x n. */
+dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, double *f_fp,
+                          void *stream);
+
+/* Stored contact force and torque (sums over the contacts of the last
+ * evaluation), 3 x n, original-ID order.  Either may be NULL. */
+dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream);
+
+/* Element and DEM-cell index of every particle at its last binning, original-ID
+ * order.  Element index as in cfd_params; cell index
+ * element*(kx*ky*kz) + (sz*ky+sy)*kx + sx with sub-cell s_a in [0, k_a).
+ * k (host, 3 ints, may be NULL) receives the cells per element per axis. */
+dem_status dem_read_cells(dem_ctx *ctx, int32_t *elem, int32_t *cell, int32_t *k, void *stream);
+
+/* Contacts of the last evaluation as pairs (i, j): particle pairs with i < j
+ * (original IDs) and wall contacts (i, -1-w), w = 0..5 for the x-lo, x-hi,
+ * y-lo, y-hi, z-lo, z-hi faces; sorted by (i, j).  pairs: 2 x cap int64
+ * (row 0 = i, row 1 = j), delta_t: 3 x cap (component-major) tangential
+ * overlap of each contact.  Synchronizes the stream; *n_out (host) receives
+ * the total count, which may exceed cap (then only cap are written). */
+dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int64_t cap,
+                             int64_t *n_out, void *stream);
+
+/* Synchronizes the stream; reports the sticky device error (0 or a negative
+ * DEM_E_* code, host out) and the number of contacts of the last evaluation
+ * (host out).  Either pointer may be NULL. */
+dem_status dem_poll(dem_ctx *ctx, int32_t *sticky_error, int64_t *n_contacts, void *stream);
+
+/* Per-kernel timing of the dominant DEM kernel: when enabled, every launch of
+ * the contact-force kernel is bracketed by HIP events on its stream.
+ * dem_kernel_timing_read synchronizes the stream and returns (host outs) the
+ * number of timed launches and their summed duration in milliseconds, and
+ * restarts the count. */
+dem_status dem_kernel_timing(dem_ctx *ctx, int32_t enable);
+dem_status dem_kernel_timing_read(dem_ctx *ctx, int64_t *launches, double *total_ms,
+                                  void *stream);
+
+/* Release the context (host memory and HIP events).  The workspace stays the
+ * caller's.  Work already enqueued must have completed or be on the stream
+ * that the caller synchronizes before freeing the workspace. */
+dem_status dem_destroy(dem_ctx *ctx);
+
+/* Static description of a status code. */
+const char *dem_status_string(dem_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

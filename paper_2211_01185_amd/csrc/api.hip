@@ -1,0 +1,800 @@
+// api.hip -- host side of the libcfddem C ABI (include/cfddem.h): parameter
+// validation, workspace layout, the step / couple sequencing on the caller's
+// stream, accessors in original-ID order, and the periodic re-sort of the
+// particle arrays by cell.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "cfddem.h"
+#include "device.h"
+
+namespace cfddem {
+hipError_t launch_drift_bin(const Dev &D, int par, bool drift, hipStream_t st);
+hipError_t launch_force_kick(const Dev &D, int par, int hold, int hnew, bool advance, bool fp32,
+                             hipStream_t st);
+hipError_t launch_couple(const Dev &D, const Cpl &C, int par, const double *U, const double *P,
+                         double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
+                         hipStream_t st);
+}  // namespace cfddem
+
+using namespace cfddem;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kAlign = 256;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// ---------------------------------------------------------------------------
+// derived sizes
+// ---------------------------------------------------------------------------
+struct Sizes {
+  int n, maxc, cap;
+  Grid grid;
+  int scan_blocks;  // blocks of the device scan over max(ncells, n) items
+};
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// DEM_OK when the parameters are valid; fills the derived grid / capacity.
+dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
+  if (!dp || !cp) return DEM_E_ARG;
+  if (dp->abi_version != CFDDEM_ABI_VERSION) return DEM_E_ABI;
+  if (dp->n < 1 || dp->n > (int64_t)0x7ffffff0) return DEM_E_ARG;
+  if (dp->precision != DEM_FP64 && dp->precision != DEM_FP32_FORCES) return DEM_E_ARG;
+  if (!finite_pos(dp->dt) || !finite_pos(dp->E) || !finite_pos(dp->E_w)) return DEM_E_ARG;
+  if (!(dp->nu > -1.0 && dp->nu < 0.5) || !(dp->nu_w > -1.0 && dp->nu_w < 0.5)) return DEM_E_ARG;
+  if (!(dp->e > 0.0 && dp->e <= 1.0) || !(dp->e_w > 0.0 && dp->e_w <= 1.0)) return DEM_E_ARG;
+  if (!(dp->mu >= 0.0) || !(dp->mu_w >= 0.0)) return DEM_E_ARG;
+  if (!finite_pos(dp->d_max) || !finite_pos(dp->d_min) || dp->d_min > dp->d_max) return DEM_E_ARG;
+  if (dp->max_contacts < 0 || dp->max_contacts > kMaxContacts) return DEM_E_ARG;
+  if (dp->cell_capacity < 0 || dp->cell_capacity > 1024) return DEM_E_ARG;
+  if (dp->resort_every < 0 || dp->reserved != 0) return DEM_E_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (!isfinite(dp->box_lo[a]) || !isfinite(dp->box_hi[a]) || !(dp->box_hi[a] > dp->box_lo[a]))
+      return DEM_E_ARG;
+    if (!isfinite(dp->gravity[a])) return DEM_E_ARG;
+    if (cp->n_el[a] < 1) return DEM_E_ARG;
+  }
+  if (cp->order != 1 && cp->order != 2) return DEM_E_ARG;
+  if (!finite_pos(cp->rho_f) || !finite_pos(cp->mu_f)) return DEM_E_ARG;
+  if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
+  if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
+  if (cp->drag != DEM_DRAG_DIFELICE) return DEM_E_UNSUPPORTED;
+
+  S.n = (int)dp->n;
+  S.maxc = dp->max_contacts ? dp->max_contacts : 16;
+  Grid &G = S.grid;
+  double hc_max = 0.0;
+  long long n_elem = 1, ncells = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double len = dp->box_hi[a] - dp->box_lo[a];
+    G.lo[a] = dp->box_lo[a];
+    G.hi[a] = dp->box_hi[a];
+    G.n_el[a] = cp->n_el[a];
+    G.he[a] = len / (double)cp->n_el[a];
+    G.inv_he[a] = (double)cp->n_el[a] / len;
+    // cells strictly wider than the largest diameter, nested in the element
+    double kd = floor(G.he[a] / (dp->d_max * (1.0 + 1e-9)));
+    if (kd < 1.0) kd = 1.0;
+    if (kd > 64.0) kd = 64.0;
+    G.k[a] = (int)kd;
+    G.inv_hc[a] = (double)(G.k[a] * cp->n_el[a]) / len;
+    G.gc[a] = G.k[a] * cp->n_el[a];
+    if (G.he[a] / G.k[a] > hc_max) hc_max = G.he[a] / G.k[a];
+    n_elem *= cp->n_el[a];
+    ncells *= (long long)G.gc[a];
+  }
+  // every element must hold at least one maximum diameter per axis
+  for (int a = 0; a < 3; ++a)
+    if (G.he[a] < dp->d_max) return DEM_E_UNSUPPORTED;
+  if (ncells > 0x7fffffffLL || n_elem > 0x7fffffffLL) return DEM_E_ARG;
+  G.kk = G.k[0] * G.k[1] * G.k[2];
+  G.n_elem = (int)n_elem;
+  G.ncells = (int)ncells;
+  if (dp->cell_capacity) {
+    S.cap = dp->cell_capacity;
+  } else {
+    // centres at mutual distance >= 0.9 d_min: the balls of that diameter are
+    // disjoint and lie in the cell grown by half of it; bound by the densest
+    // sphere packing fraction.
+    const double del = 0.9 * dp->d_min;
+    const double grown = hc_max + del;
+    double c = 0.7405 * grown * grown * grown / (kPi / 6.0 * del * del * del);
+    c = ceil(c);
+    if (c < 8.0) c = 8.0;
+    if (c > 1024.0) c = 1024.0;
+    S.cap = (int)c;
+  }
+  const long long items = G.ncells > S.n ? G.ncells : S.n;
+  S.scan_blocks = (int)((items + kScanTile - 1) / kScanTile);
+  return DEM_OK;
+}
+
+// Workspace carving: every array 256-byte aligned.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Buffers {
+  Dev D;
+  // alternates for the re-sort (swapped with D's arrays)
+  double *x2, *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2;
+  int *oid2, *cell2, *cellp2;
+  int *perm;                    // new index -> old index of the last re-sort
+  int *start;                   // first sorted index of each cell (re-sort)
+  long long *cnt64, *off64;     // per-particle contact counts / offsets
+  long long *bsum;              // per-block partial sums of the device scan
+  unsigned long long *scalars;  // [0] contact count, [1] radius max bits, [2] radius min bits
+};
+
+size_t carve(const Sizes &S, char *base, Buffers &B) {
+  Carver c{base};
+  const size_t n = (size_t)S.n, mc = (size_t)S.maxc;
+  Dev &D = B.D;
+  D.err = c.take<int>(64);
+  B.scalars = c.take<unsigned long long>(8);
+  D.x = c.take<double>(3 * n);
+  D.v = c.take<double>(3 * n);
+  D.w = c.take<double>(3 * n);
+  D.vh = c.take<double>(3 * n);
+  D.wh = c.take<double>(3 * n);
+  D.Fc = c.take<double>(3 * n);
+  D.Tc = c.take<double>(3 * n);
+  D.ffp = c.take<double>(3 * n);
+  D.rad = c.take<double>(n);
+  D.mass = c.take<double>(n);
+  D.oid = c.take<int>(n);
+  D.cell = c.take<int>(n);
+  D.cell_prev = c.take<int>(n);
+  for (int b = 0; b < 2; ++b) {
+    D.hn[b] = c.take<int>(n);
+    D.hid[b] = c.take<int>(mc * n);
+    D.hdt[b] = c.take<double>(3 * mc * n);
+    D.cnt[b] = c.take<int>((size_t)S.grid.ncells);
+  }
+  D.slot = c.take<int>((size_t)S.grid.ncells * S.cap);
+  B.x2 = c.take<double>(3 * n);
+  B.v2 = c.take<double>(3 * n);
+  B.w2 = c.take<double>(3 * n);
+  B.Fc2 = c.take<double>(3 * n);
+  B.Tc2 = c.take<double>(3 * n);
+  B.ffp2 = c.take<double>(3 * n);
+  B.rad2 = c.take<double>(n);
+  B.mass2 = c.take<double>(n);
+  B.oid2 = c.take<int>(n);
+  B.cell2 = c.take<int>(n);
+  B.cellp2 = c.take<int>(n);
+  B.perm = c.take<int>(n);
+  B.start = c.take<int>((size_t)S.grid.ncells);
+  B.cnt64 = c.take<long long>(n + 1);
+  B.off64 = c.take<long long>(n + 1);
+  B.bsum = c.take<long long>((size_t)S.scan_blocks + 1);
+  return c.off + kAlign;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels: state copy-in, scatter to original order, re-sort gathers
+// ---------------------------------------------------------------------------
+__global__ void k_init(Dev D, const double *x, const double *v, const double *w, const double *r,
+                       const double *rho, unsigned long long *rbits) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.n) return;
+  const int n = D.n;
+  for (int c = 0; c < 3; ++c) {
+    D.x[c * n + k] = x[c * n + k];
+    D.v[c * n + k] = v[c * n + k];
+    D.w[c * n + k] = w[c * n + k];
+    D.Fc[c * n + k] = 0.0;
+    D.Tc[c * n + k] = 0.0;
+    D.ffp[c * n + k] = 0.0;
+  }
+  const double rk = r[k];
+  D.rad[k] = rk;
+  D.mass[k] = rho[k] * (4.0 / 3.0 * kPi * rk * rk * rk);
+  D.oid[k] = k;
+  D.cell[k] = 0;
+  D.cell_prev[k] = 0;
+  D.hn[0][k] = 0;
+  D.hn[1][k] = 0;
+  // radius and density checks: NaN or non-positive values poison the max
+  unsigned long long bits = (rk > 0.0 && rho[k] > 0.0 && isfinite(rk) && isfinite(rho[k]))
+                                ? (unsigned long long)__double_as_longlong(rk)
+                                : 0x7ff8000000000000ULL;
+  atomicMax(&rbits[0], bits);
+  atomicMin(&rbits[1], bits);
+}
+
+__global__ void k_scatter3(int n, const int *oid, const double *src, double *dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = oid[k];
+  for (int c = 0; c < 3; ++c) dst[c * n + o] = src[c * n + k];
+}
+
+__global__ void k_scatter_cells(int n, int kk, const int *oid, const int *cell, int *elem_out,
+                                int *cell_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = oid[k];
+  if (elem_out) elem_out[o] = cell[k] / kk;
+  if (cell_out) cell_out[o] = cell[k];
+}
+
+__global__ void k_iota(int n, int *vals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  vals[k] = k;
+}
+
+// Device exclusive scan in three passes: tile-local scan + tile totals, scan
+// of the tile totals in one block, add the tile offsets.  `clamp` > 0 caps
+// every input at that value (cell counts are capped at the slot capacity).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(long long n, const TI *in, int clamp,
+                                                             TO *out, long long *bsum) {
+  __shared__ long long part[kScanThreads];
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  long long v[kScanItems];
+  long long s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    long long t = (base + i < n) ? (long long)in[base + i] : 0;
+    if (clamp > 0 && t > clamp) t = clamp;
+    v[i] = s;
+    s += t;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const long long add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const long long excl = part[threadIdx.x] - s;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) out[base + i] = (TO)(v[i] + excl);
+  if (threadIdx.x == kScanThreads - 1) bsum[blockIdx.x] = part[threadIdx.x];
+}
+
+// exclusive scan of the tile totals; bsum[nb] receives the grand total
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int nb, long long *bsum) {
+  __shared__ long long part[kScanThreads];
+  long long carry = 0;
+  for (int base = 0; base < nb; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    const long long s = i < nb ? bsum[i] : 0;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const long long add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + part[threadIdx.x] - s;
+    const long long tile_total = part[kScanThreads - 1];
+    __syncthreads();
+    carry += tile_total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(long long n, TO *out, const long long *bsum) {
+  const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
+  const long long add = bsum[blockIdx.x];
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) out[base + i] = (TO)((long long)out[base + i] + add);
+}
+
+template <typename TI, typename TO>
+hipError_t device_exclusive_scan(long long n, const TI *in, int clamp, TO *out, long long *bsum,
+                                 hipStream_t st) {
+  const int nb = (int)((n + kScanTile - 1) / kScanTile);
+  if (nb == 0) return hipSuccess;
+  k_scan_tiles<TI, TO><<<nb, kScanThreads, 0, st>>>(n, in, clamp, out, bsum);
+  k_scan_totals<<<1, kScanThreads, 0, st>>>(nb, bsum);
+  k_scan_add<TO><<<nb, kScanThreads, 0, st>>>(n, out, bsum);
+  return hipGetLastError();
+}
+
+// New position of every particle when the arrays are ordered by cell: the
+// cell's first index plus the particle's rank among the cell's particles by
+// original ID (independent of the atomic insertion order).
+__global__ void k_rank(Dev D, int par, const int *start, int *perm) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.n) return;
+  const int c = D.cell[k];
+  int m = D.cnt[par][c];
+  if (m > D.cap) m = D.cap;
+  const int o = D.oid[k];
+  int rank = 0;
+  const int *sl = D.slot + (size_t)c * D.cap;
+  for (int s = 0; s < m; ++s) rank += D.oid[sl[s]] < o;
+  const int dst = start[c] + rank;
+  if (dst >= 0 && dst < D.n) perm[dst] = k;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long a, unsigned long long b) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    p[0] = a;
+    p[1] = b;
+  }
+}
+
+struct PermSrc {
+  const double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass;
+  const int *oid, *cell, *cellp;
+  const int *hn, *hid;
+  const double *hdt;
+};
+struct PermDst {
+  double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass;
+  int *oid, *cell, *cellp;
+  int *hn, *hid;
+  double *hdt;
+};
+
+__global__ void k_permute(int n, int maxc, const int *perm, PermSrc s, PermDst d) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int o = perm[k];
+  if (o < 0 || o >= n) o = k;  // only after a capacity error (already flagged)
+  for (int c = 0; c < 3; ++c) {
+    d.x[c * n + k] = s.x[c * n + o];
+    d.v[c * n + k] = s.v[c * n + o];
+    d.w[c * n + k] = s.w[c * n + o];
+    d.Fc[c * n + k] = s.Fc[c * n + o];
+    d.Tc[c * n + k] = s.Tc[c * n + o];
+    d.ffp[c * n + k] = s.ffp[c * n + o];
+  }
+  d.rad[k] = s.rad[o];
+  d.mass[k] = s.mass[o];
+  d.oid[k] = s.oid[o];
+  d.cell[k] = s.cell[o];
+  d.cellp[k] = s.cellp[o];
+  const int h = s.hn[o];
+  d.hn[k] = h;
+  const size_t mn = (size_t)maxc * n;
+  for (int t = 0; t < h; ++t) {
+    d.hid[(size_t)t * n + k] = s.hid[(size_t)t * n + o];
+    for (int c = 0; c < 3; ++c)
+      d.hdt[(size_t)c * mn + (size_t)t * n + k] = s.hdt[(size_t)c * mn + (size_t)t * n + o];
+  }
+}
+
+// contacts that particle k reports: walls, and partners with a larger original ID
+__global__ void k_contact_count(int n, const int *oid, const int *hn, const int *hid,
+                                long long *cnt, unsigned long long *total) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = oid[k];
+  int m = 0;
+  for (int t = 0; t < hn[k]; ++t) {
+    const int code = hid[(size_t)t * n + k];
+    if (code < kWalls || code - kWalls > o) ++m;
+  }
+  cnt[o] = m;
+  if (total) atomicAdd(total, (unsigned long long)hn[k]);
+}
+
+__global__ void k_contact_write(int n, int maxc, const int *oid, const int *hn, const int *hid,
+                                const double *hdt, const long long *off, long long cap,
+                                long long *pairs, double *dt_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = oid[k];
+  long long w = off[o];
+  const size_t mn = (size_t)maxc * n;
+  const int h = hn[k];
+  // walls first in descending face index (ascending -1-w), then partners
+  for (int t = h - 1; t >= 0; --t) {
+    const int code = hid[(size_t)t * n + k];
+    if (code >= kWalls) continue;
+    if (w < cap) {
+      pairs[w] = o;
+      pairs[cap + w] = -1 - code;
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = hdt[(size_t)c * mn + (size_t)t * n + k];
+    }
+    ++w;
+  }
+  for (int t = 0; t < h; ++t) {
+    const int code = hid[(size_t)t * n + k];
+    if (code < kWalls || code - kWalls <= o) continue;
+    if (w < cap) {
+      pairs[w] = o;
+      pairs[cap + w] = code - kWalls;
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = hdt[(size_t)c * mn + (size_t)t * n + k];
+    }
+    ++w;
+  }
+}
+
+inline int blocks(int n, int b) { return (n + b - 1) / b; }
+
+dem_status err_to_status(int bits) {
+  if (bits & kErrNan) return DEM_E_NAN;
+  if (bits & kErrDomain) return DEM_E_DOMAIN;
+  if (bits & kErrCapacity) return DEM_E_CAPACITY;
+  return DEM_OK;
+}
+
+}  // namespace
+
+struct dem_ctx {
+  dem_params dp;
+  cfd_params cp;
+  Sizes S;
+  Buffers B;
+  Cpl C;
+  bool fp32;
+  int par = 0;   // count buffer of the current grid
+  int hcur = 0;  // history buffer of the current contact list
+  long long steps_done = 0;
+  int since_sort = 0;
+  dem_status poisoned = DEM_OK;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
+  size_t ev_used = 0;
+};
+
+#define HIP_TRY(...)                        \
+  do {                                      \
+    if ((__VA_ARGS__) != hipSuccess) return DEM_E_HIP; \
+  } while (0)
+
+static dem_status resort(dem_ctx *ctx, hipStream_t st) {
+  Buffers &B = ctx->B;
+  Dev &D = B.D;
+  const int n = D.n;
+  // the current grid holds every particle at its current cell
+  HIP_TRY(device_exclusive_scan<int, int>(D.grid.ncells, D.cnt[ctx->par], D.cap, B.start, B.bsum, st));
+  k_rank<<<blocks(n, 256), 256, 0, st>>>(D, ctx->par, B.start, B.perm);
+  HIP_TRY(hipGetLastError());
+  const int ho = ctx->hcur, hn = ctx->hcur ^ 1;
+  PermSrc s{D.x, D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.oid, D.cell, D.cell_prev,
+            D.hn[ho], D.hid[ho], D.hdt[ho]};
+  PermDst d{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.oid2, B.cell2, B.cellp2,
+            D.hn[hn], D.hid[hn], D.hdt[hn]};
+  k_permute<<<blocks(n, 256), 256, 0, st>>>(n, D.maxc, B.perm, s, d);
+  HIP_TRY(hipGetLastError());
+  std::swap(D.x, B.x2);
+  std::swap(D.v, B.v2);
+  std::swap(D.w, B.w2);
+  std::swap(D.Fc, B.Fc2);
+  std::swap(D.Tc, B.Tc2);
+  std::swap(D.ffp, B.ffp2);
+  std::swap(D.rad, B.rad2);
+  std::swap(D.mass, B.mass2);
+  std::swap(D.oid, B.oid2);
+  std::swap(D.cell, B.cell2);
+  std::swap(D.cell_prev, B.cellp2);
+  ctx->hcur = hn;
+  ctx->since_sort = 0;
+  return DEM_OK;
+}
+
+static dem_status force_launch(dem_ctx *ctx, int par, bool advance, hipStream_t st) {
+  const int hold = ctx->hcur, hnew = ctx->hcur ^ 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev.push_back(e);
+      }
+    }
+    e0 = ctx->ev[ctx->ev_used];
+    e1 = ctx->ev[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  HIP_TRY(launch_force_kick(ctx->B.D, par, hold, hnew, advance, ctx->fp32, st));
+  if (ctx->timing) HIP_TRY(hipEventRecord(e1, st));
+  ctx->hcur = hnew;
+  return DEM_OK;
+}
+
+extern "C" {
+
+size_t dem_workspace_bytes(const dem_params *dp, const cfd_params *cp) {
+  Sizes S;
+  if (derive(dp, cp, S) != DEM_OK) return 0;
+  Buffers B;
+  return carve(S, nullptr, B);
+}
+
+dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *x,
+                      const double *v, const double *omega, const double *radius,
+                      const double *density, void *workspace, size_t ws_bytes, void *stream,
+                      dem_ctx **out) {
+  if (!out) return DEM_E_ARG;
+  *out = nullptr;
+  Sizes S;
+  dem_status s = derive(dp, cp, S);
+  if (s != DEM_OK) return s;
+  if (!x || !v || !omega || !radius || !density) return DEM_E_ARG;
+  Buffers B;
+  const size_t need = carve(S, nullptr, B);
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need) return DEM_E_WORKSPACE;
+  dem_ctx *ctx = new (std::nothrow) dem_ctx();
+  if (!ctx) return DEM_E_ARG;
+  ctx->dp = *dp;
+  ctx->cp = *cp;
+  ctx->S = S;
+  ctx->fp32 = dp->precision == DEM_FP32_FORCES;
+  carve(S, (char *)workspace, ctx->B);
+  Dev &D = ctx->B.D;
+  D.n = S.n;
+  D.cap = S.cap;
+  D.maxc = S.maxc;
+  D.dt = dp->dt;
+  for (int a = 0; a < 3; ++a) D.g[a] = dp->gravity[a];
+  D.grid = S.grid;
+  auto material = [](double Y1, double nu1, double Y2, double nu2, double e, double mu) {
+    Material m;
+    m.Ye = 1.0 / ((1.0 - nu1 * nu1) / Y1 + (1.0 - nu2 * nu2) / Y2);
+    m.Ge = 1.0 / (2.0 * (2.0 - nu1) * (1.0 + nu1) / Y1 + 2.0 * (2.0 - nu2) * (1.0 + nu2) / Y2);
+    const double l = log(e);
+    const double beta = l / sqrt(l * l + kPi * kPi);
+    m.eta_coef = -2.0 * sqrt(5.0 / 6.0) * beta;
+    m.mu = mu;
+    return m;
+  };
+  D.pp = material(dp->E, dp->nu, dp->E, dp->nu, dp->e, dp->mu);
+  D.pw = material(dp->E, dp->nu, dp->E_w, dp->nu_w, dp->e_w, dp->mu_w);
+  // coupling constants
+  Cpl &C = ctx->C;
+  C.order = cp->order;
+  C.nq1 = cp->order + 1;
+  C.nq = C.nq1 * C.nq1 * C.nq1;
+  C.nvx = cp->order * cp->n_el[0] + 1;
+  C.nvy = cp->order * cp->n_el[1] + 1;
+  C.npx = cp->n_el[0] + 1;
+  C.npy = cp->n_el[1] + 1;
+  C.rho_f = cp->rho_f;
+  C.mu_f = cp->mu_f;
+  C.eps_min = cp->eps_min;
+  C.model = cp->model;
+  C.Ve = S.grid.he[0] * S.grid.he[1] * S.grid.he[2];
+  {
+    double gp[3];
+    if (C.nq1 == 2) {
+      gp[0] = 0.5 - 0.5 / sqrt(3.0);
+      gp[1] = 0.5 + 0.5 / sqrt(3.0);
+      gp[2] = 0.0;
+    } else {
+      gp[0] = 0.5 - 0.5 * sqrt(0.6);
+      gp[1] = 0.5;
+      gp[2] = 0.5 + 0.5 * sqrt(0.6);
+    }
+    for (int i = 0; i < 3; ++i) {
+      const double t = gp[i];
+      if (cp->order == 2) {
+        C.Lq[0][i] = 2.0 * (t - 0.5) * (t - 1.0);
+        C.Lq[1][i] = -4.0 * t * (t - 1.0);
+        C.Lq[2][i] = 2.0 * t * (t - 0.5);
+      } else {
+        C.Lq[0][i] = 1.0 - t;
+        C.Lq[1][i] = t;
+        C.Lq[2][i] = 0.0;
+      }
+      C.Lq1[0][i] = 1.0 - t;
+      C.Lq1[1][i] = t;
+    }
+  }
+
+  hipStream_t st = (hipStream_t)stream;
+  const int n = S.n;
+  auto fail = [&](dem_status code) {
+    delete ctx;
+    return code;
+  };
+  if (hipMemsetAsync(D.err, 0, sizeof(int) * 64, st) != hipSuccess) return fail(DEM_E_HIP);
+  k_fill_u64<<<1, 64, 0, st>>>(ctx->B.scalars, 0ULL, ~0ULL);
+  if (hipGetLastError() != hipSuccess) return fail(DEM_E_HIP);
+  for (int b = 0; b < 2; ++b)
+    if (hipMemsetAsync(D.cnt[b], 0, sizeof(int) * (size_t)S.grid.ncells, st) != hipSuccess)
+      return fail(DEM_E_HIP);
+  k_init<<<blocks(n, 256), 256, 0, st>>>(D, x, v, omega, radius, density, ctx->B.scalars);
+  k_iota<<<blocks(n, 256), 256, 0, st>>>(n, ctx->B.perm);
+  if (hipGetLastError() != hipSuccess) return fail(DEM_E_HIP);
+  unsigned long long rb[2];
+  if (hipMemcpyAsync(rb, ctx->B.scalars, sizeof(rb), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(DEM_E_HIP);
+  double rmax, rmin;
+  memcpy(&rmax, &rb[0], sizeof(double));
+  memcpy(&rmin, &rb[1], sizeof(double));
+  if (!(rmax > 0.0) || isnan(rmax) || isnan(rmin) || 2.0 * rmax > dp->d_max * (1.0 + 1e-12) ||
+      2.0 * rmin < dp->d_min * (1.0 - 1e-12))
+    return fail(DEM_E_ARG);
+
+  // priming: bin the initial positions, optionally sort by cell, evaluate
+  ctx->par = 0;
+  ctx->hcur = 0;
+  if (launch_drift_bin(D, 0, false, st) != hipSuccess) return fail(DEM_E_HIP);
+  if (dp->resort_every > 0) {
+    if (resort(ctx, st) != DEM_OK) return fail(DEM_E_HIP);
+    if (launch_drift_bin(ctx->B.D, 1, false, st) != hipSuccess) return fail(DEM_E_HIP);
+    ctx->par = 1;
+  }
+  if (force_launch(ctx, ctx->par, false, st) != DEM_OK) return fail(DEM_E_HIP);
+  *out = ctx;
+  return DEM_OK;
+}
+
+dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
+  if (!ctx || n_steps < 0) return DEM_E_ARG;
+  if (ctx->poisoned) return ctx->poisoned;
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < n_steps; ++s) {
+    if (ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
+      dem_status r = resort(ctx, st);
+      if (r != DEM_OK) return r;
+    }
+    const int par = ctx->par ^ 1;
+    HIP_TRY(launch_drift_bin(ctx->B.D, par, true, st));
+    dem_status r = force_launch(ctx, par, true, st);
+    if (r != DEM_OK) return r;
+    ctx->par = par;
+    ctx->steps_done++;
+    ctx->since_sort++;
+  }
+  return DEM_OK;
+}
+
+dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_nodes,
+                          double *eps_q, double *beta_q, double *fpf_q, double *elem_sums,
+                          void *stream) {
+  if (!ctx || !u_nodes || !p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
+  if (ctx->poisoned) return ctx->poisoned;
+  HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->par, u_nodes, p_nodes, eps_q, beta_q, fpf_q,
+                        elem_sums, ctx->fp32, (hipStream_t)stream));
+  return DEM_OK;
+}
+
+dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, double *f_fp,
+                          void *stream) {
+  if (!ctx) return DEM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev &D = ctx->B.D;
+  const double *src[4] = {D.x, D.v, D.w, D.ffp};
+  double *dst[4] = {x, v, omega, f_fp};
+  for (int i = 0; i < 4; ++i) {
+    if (!dst[i]) continue;
+    k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, src[i], dst[i]);
+    HIP_TRY(hipGetLastError());
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream) {
+  if (!ctx) return DEM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev &D = ctx->B.D;
+  if (F_c) k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.Fc, F_c);
+  if (T_c) k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.Tc, T_c);
+  HIP_TRY(hipGetLastError());
+  return DEM_OK;
+}
+
+dem_status dem_read_cells(dem_ctx *ctx, int32_t *elem, int32_t *cell, int32_t *k, void *stream) {
+  if (!ctx) return DEM_E_ARG;
+  const Dev &D = ctx->B.D;
+  if (k)
+    for (int a = 0; a < 3; ++a) k[a] = D.grid.k[a];
+  if (elem || cell) {
+    k_scatter_cells<<<blocks(D.n, 256), 256, 0, (hipStream_t)stream>>>(D.n, D.grid.kk, D.oid,
+                                                                        D.cell, elem, cell);
+    HIP_TRY(hipGetLastError());
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int64_t cap,
+                             int64_t *n_out, void *stream) {
+  if (!ctx || !n_out || cap < 0 || (cap > 0 && (!pairs || !delta_t))) return DEM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Buffers &B = ctx->B;
+  const Dev &D = B.D;
+  const int n = D.n, h = ctx->hcur;
+  k_contact_count<<<blocks(n, 256), 256, 0, st>>>(n, D.oid, D.hn[h], D.hid[h], B.cnt64, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(device_exclusive_scan<long long, long long>(n, B.cnt64, 0, B.off64, B.bsum, st));
+  long long total = 0;
+  const int nb = (n + kScanTile - 1) / kScanTile;
+  HIP_TRY(hipMemcpyAsync(&total, B.bsum + nb, sizeof(long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n_out = total;
+  if (cap > 0) {
+    k_contact_write<<<blocks(n, 256), 256, 0, st>>>(n, D.maxc, D.oid, D.hn[h], D.hid[h], D.hdt[h],
+                                                   B.off64, cap, (long long *)pairs, delta_t);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return DEM_OK;
+}
+
+dem_status dem_poll(dem_ctx *ctx, int32_t *sticky_error, int64_t *n_contacts, void *stream) {
+  if (!ctx) return DEM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Buffers &B = ctx->B;
+  const Dev &D = B.D;
+  HIP_TRY(hipMemsetAsync(B.scalars, 0, sizeof(unsigned long long), st));
+  const int h = ctx->hcur;
+  k_contact_count<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.hn[h], D.hid[h], B.cnt64,
+                                                   B.scalars);
+  HIP_TRY(hipGetLastError());
+  int bits = 0;
+  unsigned long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&total, B.scalars, sizeof(total), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const dem_status e = err_to_status(bits);
+  if (e != DEM_OK && ctx->poisoned == DEM_OK) ctx->poisoned = e;
+  if (sticky_error) *sticky_error = ctx->poisoned;
+  if (n_contacts) *n_contacts = (int64_t)total;
+  return ctx->poisoned;
+}
+
+dem_status dem_kernel_timing(dem_ctx *ctx, int32_t enable) {
+  if (!ctx) return DEM_E_ARG;
+  ctx->timing = enable != 0;
+  return DEM_OK;
+}
+
+dem_status dem_kernel_timing_read(dem_ctx *ctx, int64_t *launches, double *total_ms, void *stream) {
+  if (!ctx) return DEM_E_ARG;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  double sum = 0.0;
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+    sum += ms;
+  }
+  if (launches) *launches = (int64_t)(ctx->ev_used / 2);
+  if (total_ms) *total_ms = sum;
+  ctx->ev_used = 0;
+  return DEM_OK;
+}
+
+dem_status dem_destroy(dem_ctx *ctx) {
+  if (!ctx) return DEM_E_ARG;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  delete ctx;
+  return DEM_OK;
+}
+
+const char *dem_status_string(dem_status s) {
+  switch (s) {
+    case DEM_OK: return "ok";
+    case DEM_E_ARG: return "invalid argument";
+    case DEM_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case DEM_E_HIP: return "HIP runtime error";
+    case DEM_E_DOMAIN: return "particle outside the box";
+    case DEM_E_CAPACITY: return "cell or contact capacity exceeded";
+    case DEM_E_NAN: return "NaN in the particle state";
+    case DEM_E_UNSUPPORTED: return "unsupported option";
+    case DEM_E_ABI: return "ABI version mismatch";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

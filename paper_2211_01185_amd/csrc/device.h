@@ -1,0 +1,113 @@
+// device.h -- device-side data layout and small helpers shared by the HIP
+// kernels of libcfddem (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cfddem {
+
+constexpr int kMaxContacts = 32;   // compile-time bound of dem_params.max_contacts
+constexpr int kForceBlock = 128;   // threads per block of the contact-force kernel
+constexpr int kElemMaxParticles = 1024;  // particles one coupling wave can hold
+constexpr int kWalls = 6;          // partner codes 0..5 are the box faces
+
+// sticky device error bits
+enum : int { kErrDomain = 1, kErrCapacity = 2, kErrNan = 4 };
+
+struct Material {
+  double Ye;        // effective Young's modulus
+  double Ge;        // effective shear modulus
+  double eta_coef;  // -2 sqrt(5/6) beta(e)  (>= 0)
+  double mu;        // Coulomb coefficient
+};
+
+// Structured grid: mesh elements split into k[a] DEM cells per axis.
+struct Grid {
+  double lo[3], hi[3];
+  double he[3];      // element size
+  double inv_he[3];  // n_el / (hi - lo)
+  double inv_hc[3];  // (k n_el) / (hi - lo)
+  int n_el[3];
+  int k[3];
+  int kk;            // k0 k1 k2: cells per element
+  int gc[3];         // cells per axis, k n_el
+  int n_elem;        // n_el0 n_el1 n_el2
+  int ncells;        // n_elem kk
+};
+
+// Everything a DEM kernel needs, passed by value.  Arrays are indexed by the
+// internal (sorted) particle index; vectors are component-major (c*n + k).
+struct Dev {
+  int n;
+  int cap;    // slots per cell
+  int maxc;   // contacts per particle
+  double dt;
+  double g[3];
+  Material pp, pw;
+  Grid grid;
+  double *x, *v, *w;     // boundary state
+  double *vh, *wh;       // half-step velocities
+  double *Fc, *Tc;       // stored contact force / torque
+  double *ffp;           // held fluid force
+  double *rad, *mass;
+  int *oid;              // original ID of each internal index
+  int *cell, *cell_prev; // cell at the last and the previous binning
+  int *cnt[2];           // particles per cell, double-buffered
+  int *slot;             // ncells x cap particle indices
+  int *hn[2];            // contact count per particle (history buffers)
+  int *hid[2];           // maxc x n partner codes (0..5 wall, 6+oid particle)
+  double *hdt[2];        // 3 x maxc x n tangential overlap
+  int *err;              // sticky error bits
+};
+
+// Coupling constants.
+struct Cpl {
+  int order;        // 1 or 2
+  int nq1;          // quadrature points per axis (order + 1)
+  int nq;           // per element
+  int nvx, nvy;     // velocity node lattice (x, y extents)
+  int npx, npy;     // pressure node lattice
+  double rho_f, mu_f, eps_min;
+  int model;
+  double Ve;        // element volume
+  double Lq[3][3];  // Lq[a][i]: 1D velocity basis a at Gauss point i
+  double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)
+};
+
+__device__ inline int floor_clamp(double t, int n) {
+  double f = floor(t);
+  if (!(f >= 0.0)) return 0;
+  if (f > (double)(n - 1)) return n - 1;
+  return (int)f;
+}
+
+// Hierarchical binning, evaluated without FMA contraction so that the indices
+// are a pure function of the IEEE operations written here.
+__device__ inline void bin_point(const Grid &G, const double xp[3], int &elem, int &cell,
+                                 bool &inside) {
+#pragma clang fp contract(off)
+  int e[3], s[3];
+  inside = true;
+  for (int a = 0; a < 3; ++a) {
+    const double xa = xp[a];
+    if (!(xa >= G.lo[a] && xa <= G.hi[a])) inside = false;
+    e[a] = floor_clamp((xa - G.lo[a]) * G.inv_he[a], G.n_el[a]);
+    const double origin = G.lo[a] + (double)e[a] * G.he[a];
+    s[a] = floor_clamp((xa - origin) * G.inv_hc[a], G.k[a]);
+  }
+  elem = (e[2] * G.n_el[1] + e[1]) * G.n_el[0] + e[0];
+  cell = elem * G.kk + (s[2] * G.k[1] + s[1]) * G.k[0] + s[0];
+}
+
+// Fine-search predicate (R_i+R_j)^2 - (dx^2+dy^2+dz^2) > 0, no contraction.
+__device__ inline bool touching(double xi0, double xi1, double xi2, double xj0, double xj1,
+                                double xj2, double ri, double rj) {
+#pragma clang fp contract(off)
+  const double dx = xj0 - xi0, dy = xj1 - xi1, dz = xj2 - xi2;
+  const double rs = ri + rj;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  return rs * rs - d2 > 0.0;
+}
+
+}  // namespace cfddem

@@ -1,0 +1,174 @@
+"""GPU (HIP, through the C ABI) versus the FP64 CPU oracle on identical seeded
+inputs.  Integer work (cell indices, contact sets) must match bit for bit;
+floating-point arrays within max|gpu - oracle| / max|oracle| <= 1e-10 (FP64
+path) or 1e-5 (FP32 force path) on single steps and short sequences."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_01185_amd import synth
+from tests.parity_util import (TOL, assert_close, compare_contacts, compare_states, gpu_bed, gpu_state,
+                               oracle_bed)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fields(wl):
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device="cuda").contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device="cuda").contiguous()
+    return U, P
+
+
+def _workload(name):
+    if name == "lattice":
+        return synth.lattice()
+    if name == "plain":
+        return synth.plain()
+    if name == "lattice_ragged":
+        # 7*9*11 = 693 particles: a ragged tail in every launch
+        return synth.lattice(n_side=(7, 9, 11), seed_index=3)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["lattice", "plain", "lattice_ragged"])
+def test_binning_is_bit_exact(name):
+    wl = _workload(name)
+    gb = gpu_bed(wl)
+    elem, cell, k = gb.read_cells()
+    oe, oc, outside = O.bin_particles(wl.x, wl.dem["box_lo"], wl.dem["box_hi"], wl.fluid["n_el"], k)
+    assert outside == 0
+    assert np.array_equal(elem.cpu().numpy(), oe)
+    assert np.array_equal(cell.cpu().numpy().astype(np.int64), oc)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["lattice", "lattice_ragged"])
+def test_priming_forces(name, precision):
+    wl = _workload(name)
+    gb = gpu_bed(wl, precision)
+    ob, _ = oracle_bed(wl)
+    ncont = compare_contacts(gb, ob, TOL[precision])
+    assert ncont > wl.n  # dense lattice: several contacts per particle
+    compare_states(gb, ob, TOL[precision], keys=("Fc", "Tc"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["lattice", "plain", "lattice_ragged"])
+def test_single_step(name, precision):
+    wl = _workload(name)
+    gb = gpu_bed(wl, precision)
+    ob, _ = oracle_bed(wl)
+    gb.step(1)
+    ob.step(1)
+    compare_contacts(gb, ob, TOL[precision])
+    compare_states(gb, ob, TOL[precision])
+    err, _ = gb.poll()
+    assert err == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_coupling_step(precision, model):
+    wl = _workload("lattice")
+    wl.fluid["model"] = model
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    out = gb.couple(U, P, elem_sums=True)
+    ref = ob.couple(fl, wl.U, wl.P)
+    tol = TOL[precision]
+    assert np.array_equal(out["elem_sums"][0].cpu().numpy(), ref["elem_sums"][0])  # counts
+    assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-12)  # FP64 in both modes
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+    g = gpu_state(gb)
+    assert_close("f_fp", g["ffp"], ob.state()["ffp"], tol)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coupled_sequence(precision):
+    """couple, 10 DEM steps with the held force, couple, 10 steps."""
+    wl = _workload("lattice")
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    tol = TOL[precision]
+    for _ in range(2):
+        out = gb.couple(U, P)
+        ref = ob.couple(fl, wl.U, wl.P)
+        assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+        gb.step(10)
+        ob.step(10)
+    compare_contacts(gb, ob, 10 * tol)
+    compare_states(gb, ob, 10 * tol)
+
+
+def test_resort_does_not_change_results():
+    """Re-sorting the arrays by cell every step changes only summation order."""
+    wl = _workload("lattice")
+    a = gpu_bed(wl, "fp64")
+    b = gpu_bed(wl, "fp64", resort_every=1)
+    ob, _ = oracle_bed(wl)
+    for bed in (a, b):
+        bed.step(5)
+    ob.step(5)
+    for bed in (a, b):
+        compare_contacts(bed, ob, 1e-10)
+        compare_states(bed, ob, 1e-10)
+
+
+def test_run_to_run_determinism():
+    wl = _workload("lattice")
+    runs = []
+    for _ in range(2):
+        gb = gpu_bed(wl, "fp64", resort_every=3)
+        U, P = _fields(wl)
+        gb.couple(U, P)
+        gb.step(7)
+        runs.append(gpu_state(gb))
+    for k in runs[0]:
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
+def test_single_particle_and_wall_contact():
+    wl = synth.plain(n=1)
+    wl.x[:, 0] = [0.01, 0.02, 0.0014]  # 0.1 mm into the floor
+    gb = gpu_bed(wl)
+    ob, fl = oracle_bed(wl)
+    compare_contacts(gb, ob, 1e-10)
+    gb.step(3)
+    ob.step(3)
+    compare_contacts(gb, ob, 1e-10)
+    compare_states(gb, ob, 1e-10)
+
+
+def test_domain_error_is_sticky():
+    from paper_2211_01185_amd import cfddem
+    wl = synth.plain(n=50)
+    wl.x[2, 7] = 0.25  # above the lid
+    gb = gpu_bed(wl)
+    err, _ = gb.poll()
+    assert err == cfddem.DEM_E_DOMAIN
+    with pytest.raises(cfddem.CfddemError):
+        gb.step(1)
+
+
+def test_contact_capacity_error():
+    from paper_2211_01185_amd import cfddem
+    wl = synth.lattice(n_side=(6, 6, 6))
+    gb = gpu_bed(wl, max_contacts=2)
+    err, _ = gb.poll()
+    assert err == cfddem.DEM_E_CAPACITY
+
+
+def test_nan_error():
+    from paper_2211_01185_amd import cfddem
+    wl = synth.plain(n=50)
+    wl.v[0, 3] = np.nan
+    gb = gpu_bed(wl)
+    gb.step(1)
+    err, _ = gb.poll()
+    assert err == cfddem.DEM_E_NAN
