@@ -53,7 +53,7 @@ enum {
   DEM_E_WORKSPACE = -2,   /* workspace NULL, misaligned (256 B) or too small */
   DEM_E_HIP = -3,         /* a HIP runtime call failed */
   DEM_E_DOMAIN = -4,      /* a particle centre left the box */
-  DEM_E_CAPACITY = -5,    /* per-cell or per-particle contact capacity exceeded */
+  DEM_E_CAPACITY = -5,    /* cell, neighbour-list or element capacity exceeded */
   DEM_E_NAN = -6,         /* NaN in the particle state */
   DEM_E_UNSUPPORTED = -7, /* valid but not implemented (e.g. another drag law) */
   DEM_E_ABI = -8          /* abi_version mismatch */
@@ -80,7 +80,8 @@ typedef struct {
   double dt;             /* DEM time step, > 0 */
   double E, nu, e, mu;   /* particle: Young, Poisson; pair restitution, Coulomb friction */
   double E_w, nu_w, e_w, mu_w; /* wall: Young, Poisson; particle-wall restitution, friction */
-  int32_t max_contacts;  /* contacts per particle including walls, 1..32; 0 = 16 */
+  int32_t max_neighbors; /* neighbour-list capacity per particle: partners closer
+                            than R_i + R_j + skin, 1..64; 0 = 32 */
   int32_t cell_capacity; /* particles per DEM cell, 1..1024; 0 = derived from sizes */
   int32_t resort_every;  /* DEM steps between re-sorts of the particle arrays by
                             cell; 0 = never (order of creation) */
@@ -89,6 +90,10 @@ typedef struct {
                             cells are at least this wide) */
   double d_min;          /* smallest particle diameter (sizes cell_capacity);
                             dem_create rejects radii outside [d_min, d_max]/2 */
+  double skin;           /* neighbour-list skin (m), >= 0; 0 = 0.1 d_min.  The
+                            broad search lists partners within R_i + R_j + skin
+                            and is redone on the device as soon as a particle
+                            has moved more than skin/2 since the last one */
 } dem_params;
 
 /* Coupling parameters (host struct).  The structured hex mesh spans the DEM
@@ -132,8 +137,10 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
 /* Advance n_steps >= 0 DEM steps with the held fluid force (Section 2.3.1:
  * the coupling force is computed once per CFD step and held during the
  * f_coupling DEM sub-steps).  Per step: half kick and drift, binning of the
- * new positions, contact search and forces at the half-step velocities,
- * second half kick. */
+ * new positions into the cell grid, broad search (cell-list neighbour lists,
+ * only when some particle moved more than skin/2 since the last one), fine
+ * search (exact overlap test over the lists and the six walls), contact
+ * forces at the half-step velocities, second half kick. */
 dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream);
 
 /* One coupling step at the current particle state with the given fluid field.

@@ -41,8 +41,8 @@ class DemParams(C.Structure):
         ("dt", C.c_double),
         ("E", C.c_double), ("nu", C.c_double), ("e", C.c_double), ("mu", C.c_double),
         ("E_w", C.c_double), ("nu_w", C.c_double), ("e_w", C.c_double), ("mu_w", C.c_double),
-        ("max_contacts", C.c_int32), ("cell_capacity", C.c_int32), ("resort_every", C.c_int32),
-        ("reserved", C.c_int32), ("d_max", C.c_double), ("d_min", C.c_double),
+        ("max_neighbors", C.c_int32), ("cell_capacity", C.c_int32), ("resort_every", C.c_int32),
+        ("reserved", C.c_int32), ("d_max", C.c_double), ("d_min", C.c_double), ("skin", C.c_double),
     ]
 
 
@@ -113,7 +113,7 @@ def _check(status: int, where: str):
 
 
 def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, precision="fp64",
-                max_contacts=0, cell_capacity=0, resort_every=0):
+                max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0):
     """Fill the two C parameter structs from plain dicts (see synth.Workload)."""
     dp = DemParams()
     dp.abi_version = ABI_VERSION
@@ -126,12 +126,13 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     for k in ("E", "nu", "e", "mu"):
         setattr(dp, k, float(dem[k]))
         setattr(dp, k + "_w", float(dem.get(k + "_w", dem[k])))
-    dp.max_contacts = int(max_contacts)
+    dp.max_neighbors = int(max_neighbors)
     dp.cell_capacity = int(cell_capacity)
     dp.resort_every = int(resort_every)
     dp.reserved = 0
     dp.d_max = float(d_max)
     dp.d_min = float(d_min)
+    dp.skin = float(skin)
     cp = CfdParams()
     cp.order = int(fluid["order"])
     cp.n_el[:] = [int(v) for v in fluid["n_el"]]
@@ -155,7 +156,7 @@ class Bed:
     """One bed on the GPU: a dem_ctx plus the torch-owned workspace."""
 
     def __init__(self, dem: dict, fluid: dict, x, v, w, radius, density, precision="fp64",
-                 max_contacts=0, cell_capacity=0, resort_every=0, device="cuda", stream=None):
+                 max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, device="cuda", stream=None):
         import torch
 
         self._torch = torch
@@ -175,7 +176,7 @@ class Bed:
             raise ValueError("radius and density must be (n,)")
         rr = r.detach().cpu().numpy()
         self.dp, self.cp = make_params(dem, fluid, self.n, 2.0 * float(rr.max()), 2.0 * float(rr.min()),
-                                       precision, max_contacts, cell_capacity, resort_every)
+                                       precision, max_neighbors, cell_capacity, resort_every, skin)
         nbytes = workspace_bytes(self.dp, self.cp)
         if nbytes == 0:
             raise CfddemError(DEM_E_ARG, "dem_workspace_bytes")

@@ -13,8 +13,8 @@
 #include "device.h"
 
 namespace cfddem {
-hipError_t launch_drift_bin(const Dev &D, int par, bool drift, hipStream_t st);
-hipError_t launch_force_kick(const Dev &D, int par, int hold, int hnew, bool advance, bool fp32,
+hipError_t launch_drift_bin(const Dev &D, int par, bool drift, bool force_flag, hipStream_t st);
+hipError_t launch_force_kick(const Dev &D, int par, const int *src, bool advance, bool fp32,
                              hipStream_t st);
 hipError_t launch_couple(const Dev &D, const Cpl &C, int par, const double *U, const double *P,
                          double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
@@ -35,7 +35,8 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 // derived sizes
 // ---------------------------------------------------------------------------
 struct Sizes {
-  int n, maxc, cap;
+  int n, maxn, cap;
+  double skin;
   Grid grid;
   int scan_blocks;  // blocks of the device scan over max(ncells, n) items
 };
@@ -53,7 +54,8 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!(dp->e > 0.0 && dp->e <= 1.0) || !(dp->e_w > 0.0 && dp->e_w <= 1.0)) return DEM_E_ARG;
   if (!(dp->mu >= 0.0) || !(dp->mu_w >= 0.0)) return DEM_E_ARG;
   if (!finite_pos(dp->d_max) || !finite_pos(dp->d_min) || dp->d_min > dp->d_max) return DEM_E_ARG;
-  if (dp->max_contacts < 0 || dp->max_contacts > kMaxContacts) return DEM_E_ARG;
+  if (dp->max_neighbors < 0 || dp->max_neighbors > kMaxNeighbors) return DEM_E_ARG;
+  if (!(dp->skin >= 0.0) || !isfinite(dp->skin)) return DEM_E_ARG;
   if (dp->cell_capacity < 0 || dp->cell_capacity > 1024) return DEM_E_ARG;
   if (dp->resort_every < 0 || dp->reserved != 0) return DEM_E_ARG;
   for (int a = 0; a < 3; ++a) {
@@ -69,7 +71,15 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (cp->drag != DEM_DRAG_DIFELICE) return DEM_E_UNSUPPORTED;
 
   S.n = (int)dp->n;
-  S.maxc = dp->max_contacts ? dp->max_contacts : 16;
+  S.maxn = dp->max_neighbors ? dp->max_neighbors : 32;
+  S.skin = dp->skin > 0.0 ? dp->skin : 0.1 * dp->d_min;
+  // the broad search needs cells at least d_max + skin wide; an element
+  // narrower than that caps the skin
+  for (int a = 0; a < 3; ++a) {
+    const double he = (dp->box_hi[a] - dp->box_lo[a]) / (double)cp->n_el[a];
+    const double room = he / (1.0 + 1e-9) - dp->d_max;
+    if (room < S.skin) S.skin = room > 0.0 ? room : 0.0;
+  }
   Grid &G = S.grid;
   double hc_max = 0.0;
   long long n_elem = 1, ncells = 1;
@@ -81,7 +91,7 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
     G.he[a] = len / (double)cp->n_el[a];
     G.inv_he[a] = (double)cp->n_el[a] / len;
     // cells strictly wider than the largest diameter, nested in the element
-    double kd = floor(G.he[a] / (dp->d_max * (1.0 + 1e-9)));
+    double kd = floor(G.he[a] / ((dp->d_max + S.skin) * (1.0 + 1e-9)));
     if (kd < 1.0) kd = 1.0;
     if (kd > 64.0) kd = 64.0;
     G.k[a] = (int)kd;
@@ -133,8 +143,9 @@ struct Carver {
 struct Buffers {
   Dev D;
   // alternates for the re-sort (swapped with D's arrays)
-  double *x2, *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2;
+  double *x2, *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2, *whdt2;
   int *oid2, *cell2, *cellp2;
+  unsigned char *wmask2;
   int *perm;                    // new index -> old index of the last re-sort
   int *start;                   // first sorted index of each cell (re-sort)
   long long *cnt64, *off64;     // per-particle contact counts / offsets
@@ -144,9 +155,13 @@ struct Buffers {
 
 size_t carve(const Sizes &S, char *base, Buffers &B) {
   Carver c{base};
-  const size_t n = (size_t)S.n, mc = (size_t)S.maxc;
+  const size_t n = (size_t)S.n, mn = (size_t)S.maxn;
   Dev &D = B.D;
-  D.err = c.take<int>(64);
+  D.err = c.take<int>(64);  // [0] error bits, [16..17] flags, [32..33] list buffer
+  if (base) {
+    D.flag = D.err + 16;
+    D.lbuf = D.err + 32;
+  }
   B.scalars = c.take<unsigned long long>(8);
   D.x = c.take<double>(3 * n);
   D.v = c.take<double>(3 * n);
@@ -158,15 +173,19 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   D.ffp = c.take<double>(3 * n);
   D.rad = c.take<double>(n);
   D.mass = c.take<double>(n);
+  D.xb = c.take<double>(3 * n);
   D.oid = c.take<int>(n);
   D.cell = c.take<int>(n);
   D.cell_prev = c.take<int>(n);
   for (int b = 0; b < 2; ++b) {
-    D.hn[b] = c.take<int>(n);
-    D.hid[b] = c.take<int>(mc * n);
-    D.hdt[b] = c.take<double>(3 * mc * n);
+    D.ln[b] = c.take<int>(n);
+    D.nbr[b] = c.take<unsigned long long>(mn * n);
+    D.hmask[b] = c.take<unsigned long long>(n);
+    D.hdt[b] = c.take<double>(3 * mn * n);
     D.cnt[b] = c.take<int>((size_t)S.grid.ncells);
   }
+  D.wmask = c.take<unsigned char>(n);
+  D.whdt = c.take<double>(3 * kWalls * n);
   D.slot = c.take<int>((size_t)S.grid.ncells * S.cap);
   B.x2 = c.take<double>(3 * n);
   B.v2 = c.take<double>(3 * n);
@@ -179,6 +198,8 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   B.oid2 = c.take<int>(n);
   B.cell2 = c.take<int>(n);
   B.cellp2 = c.take<int>(n);
+  B.wmask2 = c.take<unsigned char>(n);
+  B.whdt2 = c.take<double>(3 * kWalls * n);
   B.perm = c.take<int>(n);
   B.start = c.take<int>((size_t)S.grid.ncells);
   B.cnt64 = c.take<long long>(n + 1);
@@ -209,8 +230,12 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   D.oid[k] = k;
   D.cell[k] = 0;
   D.cell_prev[k] = 0;
-  D.hn[0][k] = 0;
-  D.hn[1][k] = 0;
+  for (int c = 0; c < 3; ++c) D.xb[c * n + k] = x[c * n + k];
+  D.ln[0][k] = 0;
+  D.ln[1][k] = 0;
+  D.hmask[0][k] = 0;
+  D.hmask[1][k] = 0;
+  D.wmask[k] = 0;
   // radius and density checks: NaN or non-positive values poison the max
   unsigned long long bits = (rk > 0.0 && rho[k] > 0.0 && isfinite(rk) && isfinite(rho[k]))
                                 ? (unsigned long long)__double_as_longlong(rk)
@@ -338,19 +363,19 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long a, unsigned
 }
 
 struct PermSrc {
-  const double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass;
+  const double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   const int *oid, *cell, *cellp;
-  const int *hn, *hid;
-  const double *hdt;
+  const unsigned char *wmask;
 };
 struct PermDst {
-  double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass;
+  double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   int *oid, *cell, *cellp;
-  int *hn, *hid;
-  double *hdt;
+  unsigned char *wmask;
 };
 
-__global__ void k_permute(int n, int maxc, const int *perm, PermSrc s, PermDst d) {
+// Gather every per-particle array into cell order.  Neighbour lists are not
+// moved: the broad search that follows a re-sort reads them through perm.
+__global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int o = perm[k];
@@ -368,58 +393,52 @@ __global__ void k_permute(int n, int maxc, const int *perm, PermSrc s, PermDst d
   d.oid[k] = s.oid[o];
   d.cell[k] = s.cell[o];
   d.cellp[k] = s.cellp[o];
-  const int h = s.hn[o];
-  d.hn[k] = h;
-  const size_t mn = (size_t)maxc * n;
-  for (int t = 0; t < h; ++t) {
-    d.hid[(size_t)t * n + k] = s.hid[(size_t)t * n + o];
-    for (int c = 0; c < 3; ++c)
-      d.hdt[(size_t)c * mn + (size_t)t * n + k] = s.hdt[(size_t)c * mn + (size_t)t * n + o];
-  }
+  d.wmask[k] = s.wmask[o];
+  for (int j = 0; j < 3 * kWalls; ++j) d.whdt[(size_t)j * n + k] = s.whdt[(size_t)j * n + o];
 }
 
-// contacts that particle k reports: walls, and partners with a larger original ID
-__global__ void k_contact_count(int n, const int *oid, const int *hn, const int *hid,
-                                long long *cnt, unsigned long long *total) {
+// Contacts of the last evaluation that particle k reports: its walls, and the
+// touching list entries whose partner has a larger original ID.
+__global__ void k_contact_count(Dev D, int lb, long long *cnt, unsigned long long *total) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int o = oid[k];
-  int m = 0;
-  for (int t = 0; t < hn[k]; ++t) {
-    const int code = hid[(size_t)t * n + k];
-    if (code < kWalls || code - kWalls > o) ++m;
-  }
+  if (k >= D.n) return;
+  const int n = D.n;
+  const int o = D.oid[k];
+  int m = __popc((unsigned)D.wmask[k]);
+  const unsigned long long mask = D.hmask[lb][k];
+  for (int t = 0; t < D.ln[lb][k]; ++t)
+    if (((mask >> t) & 1ull) && (int)(D.nbr[lb][(size_t)t * n + k] >> 32) > o) ++m;
   cnt[o] = m;
-  if (total) atomicAdd(total, (unsigned long long)hn[k]);
+  if (total) atomicAdd(total, (unsigned long long)m);
 }
 
-__global__ void k_contact_write(int n, int maxc, const int *oid, const int *hn, const int *hid,
-                                const double *hdt, const long long *off, long long cap,
-                                long long *pairs, double *dt_out) {
+__global__ void k_contact_write(Dev D, int lb, const long long *off, long long cap, long long *pairs,
+                                double *dt_out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int o = oid[k];
+  if (k >= D.n) return;
+  const int n = D.n;
+  const int o = D.oid[k];
   long long w = off[o];
-  const size_t mn = (size_t)maxc * n;
-  const int h = hn[k];
-  // walls first in descending face index (ascending -1-w), then partners
-  for (int t = h - 1; t >= 0; --t) {
-    const int code = hid[(size_t)t * n + k];
-    if (code >= kWalls) continue;
+  const size_t mn = (size_t)D.maxn * n;
+  // walls in descending face index (ascending -1-w), then partners by oid
+  const unsigned wm = D.wmask[k];
+  for (int wall = kWalls - 1; wall >= 0; --wall) {
+    if (!((wm >> wall) & 1u)) continue;
     if (w < cap) {
       pairs[w] = o;
-      pairs[cap + w] = -1 - code;
-      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = hdt[(size_t)c * mn + (size_t)t * n + k];
+      pairs[cap + w] = -1 - wall;
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.whdt[(size_t)(c * kWalls + wall) * n + k];
     }
     ++w;
   }
-  for (int t = 0; t < h; ++t) {
-    const int code = hid[(size_t)t * n + k];
-    if (code < kWalls || code - kWalls <= o) continue;
+  const unsigned long long mask = D.hmask[lb][k];
+  for (int t = 0; t < D.ln[lb][k]; ++t) {
+    const int ob = (int)(D.nbr[lb][(size_t)t * n + k] >> 32);
+    if (!((mask >> t) & 1ull) || ob <= o) continue;
     if (w < cap) {
       pairs[w] = o;
-      pairs[cap + w] = code - kWalls;
-      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = hdt[(size_t)c * mn + (size_t)t * n + k];
+      pairs[cap + w] = ob;
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.hdt[lb][(size_t)c * mn + (size_t)t * n + k];
     }
     ++w;
   }
@@ -443,8 +462,8 @@ struct dem_ctx {
   Buffers B;
   Cpl C;
   bool fp32;
-  int par = 0;   // count buffer of the current grid
-  int hcur = 0;  // history buffer of the current contact list
+  int par = 0;   // parity of the last step: grid buffer, flags
+  const int *pending_src = nullptr;  // permutation to apply at the next broad search
   long long steps_done = 0;
   int since_sort = 0;
   dem_status poisoned = DEM_OK;
@@ -466,12 +485,11 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   HIP_TRY(device_exclusive_scan<int, int>(D.grid.ncells, D.cnt[ctx->par], D.cap, B.start, B.bsum, st));
   k_rank<<<blocks(n, 256), 256, 0, st>>>(D, ctx->par, B.start, B.perm);
   HIP_TRY(hipGetLastError());
-  const int ho = ctx->hcur, hn = ctx->hcur ^ 1;
-  PermSrc s{D.x, D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.oid, D.cell, D.cell_prev,
-            D.hn[ho], D.hid[ho], D.hdt[ho]};
-  PermDst d{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.oid2, B.cell2, B.cellp2,
-            D.hn[hn], D.hid[hn], D.hdt[hn]};
-  k_permute<<<blocks(n, 256), 256, 0, st>>>(n, D.maxc, B.perm, s, d);
+  PermSrc s{D.x, D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell, D.cell_prev,
+            D.wmask};
+  PermDst d{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.whdt2, B.oid2, B.cell2,
+            B.cellp2, B.wmask2};
+  k_permute<<<blocks(n, 256), 256, 0, st>>>(n, B.perm, s, d);
   HIP_TRY(hipGetLastError());
   std::swap(D.x, B.x2);
   std::swap(D.v, B.v2);
@@ -484,13 +502,16 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   std::swap(D.oid, B.oid2);
   std::swap(D.cell, B.cell2);
   std::swap(D.cell_prev, B.cellp2);
-  ctx->hcur = hn;
+  std::swap(D.whdt, B.whdt2);
+  std::swap(D.wmask, B.wmask2);
+  ctx->pending_src = B.perm;
   ctx->since_sort = 0;
   return DEM_OK;
 }
 
 static dem_status force_launch(dem_ctx *ctx, int par, bool advance, hipStream_t st) {
-  const int hold = ctx->hcur, hnew = ctx->hcur ^ 1;
+  const int *src = advance ? ctx->pending_src : nullptr;
+  ctx->pending_src = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     if (ctx->ev_used + 2 > ctx->ev.size()) {
@@ -505,9 +526,8 @@ static dem_status force_launch(dem_ctx *ctx, int par, bool advance, hipStream_t 
     ctx->ev_used += 2;
     HIP_TRY(hipEventRecord(e0, st));
   }
-  HIP_TRY(launch_force_kick(ctx->B.D, par, hold, hnew, advance, ctx->fp32, st));
+  HIP_TRY(launch_force_kick(ctx->B.D, par, src, advance, ctx->fp32, st));
   if (ctx->timing) HIP_TRY(hipEventRecord(e1, st));
-  ctx->hcur = hnew;
   return DEM_OK;
 }
 
@@ -543,7 +563,9 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   Dev &D = ctx->B.D;
   D.n = S.n;
   D.cap = S.cap;
-  D.maxc = S.maxc;
+  D.maxn = S.maxn;
+  D.skin = S.skin;
+  D.trig2 = (0.499 * S.skin) * (0.499 * S.skin);
   D.dt = dp->dt;
   for (int a = 0; a < 3; ++a) D.g[a] = dp->gravity[a];
   D.grid = S.grid;
@@ -628,11 +650,11 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
 
   // priming: bin the initial positions, optionally sort by cell, evaluate
   ctx->par = 0;
-  ctx->hcur = 0;
-  if (launch_drift_bin(D, 0, false, st) != hipSuccess) return fail(DEM_E_HIP);
+  if (launch_drift_bin(D, 0, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
   if (dp->resort_every > 0) {
     if (resort(ctx, st) != DEM_OK) return fail(DEM_E_HIP);
-    if (launch_drift_bin(ctx->B.D, 1, false, st) != hipSuccess) return fail(DEM_E_HIP);
+    ctx->pending_src = nullptr;  // nothing to carry at creation
+    if (launch_drift_bin(ctx->B.D, 1, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
     ctx->par = 1;
   }
   if (force_launch(ctx, ctx->par, false, st) != DEM_OK) return fail(DEM_E_HIP);
@@ -650,7 +672,7 @@ dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
       if (r != DEM_OK) return r;
     }
     const int par = ctx->par ^ 1;
-    HIP_TRY(launch_drift_bin(ctx->B.D, par, true, st));
+    HIP_TRY(launch_drift_bin(ctx->B.D, par, true, ctx->pending_src != nullptr, st));
     dem_status r = force_launch(ctx, par, true, st);
     if (r != DEM_OK) return r;
     ctx->par = par;
@@ -714,8 +736,11 @@ dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int6
   hipStream_t st = (hipStream_t)stream;
   Buffers &B = ctx->B;
   const Dev &D = B.D;
-  const int n = D.n, h = ctx->hcur;
-  k_contact_count<<<blocks(n, 256), 256, 0, st>>>(n, D.oid, D.hn[h], D.hid[h], B.cnt64, nullptr);
+  const int n = D.n;
+  int lb = 0;
+  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->par ^ 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  k_contact_count<<<blocks(n, 256), 256, 0, st>>>(D, lb, B.cnt64, nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(device_exclusive_scan<long long, long long>(n, B.cnt64, 0, B.off64, B.bsum, st));
   long long total = 0;
@@ -724,8 +749,7 @@ dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int6
   HIP_TRY(hipStreamSynchronize(st));
   *n_out = total;
   if (cap > 0) {
-    k_contact_write<<<blocks(n, 256), 256, 0, st>>>(n, D.maxc, D.oid, D.hn[h], D.hid[h], D.hdt[h],
-                                                   B.off64, cap, (long long *)pairs, delta_t);
+    k_contact_write<<<blocks(n, 256), 256, 0, st>>>(D, lb, B.off64, cap, (long long *)pairs, delta_t);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
   }
@@ -738,9 +762,10 @@ dem_status dem_poll(dem_ctx *ctx, int32_t *sticky_error, int64_t *n_contacts, vo
   Buffers &B = ctx->B;
   const Dev &D = B.D;
   HIP_TRY(hipMemsetAsync(B.scalars, 0, sizeof(unsigned long long), st));
-  const int h = ctx->hcur;
-  k_contact_count<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.hn[h], D.hid[h], B.cnt64,
-                                                   B.scalars);
+  int lb = 0;
+  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->par ^ 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  k_contact_count<<<blocks(D.n, 256), 256, 0, st>>>(D, lb, B.cnt64, B.scalars);
   HIP_TRY(hipGetLastError());
   int bits = 0;
   unsigned long long total = 0;

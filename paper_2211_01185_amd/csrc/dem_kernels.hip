@@ -1,15 +1,20 @@
 // dem_kernels.hip -- one DEM step on gfx950 (Section 2.2 of El Geitani,
 // Golshan & Blais, arXiv 2211.01185):
 //   drift_bin   : half kick + drift with the stored forces, binning of the new
-//                 centre into the nested cell grid (atomic slot insertion)
-//   force_kick  : 27-cell broad search + fine search, Hertz-Mindlin contact
-//                 law (Table "tab:viscoelastic", contact-force equation) with
-//                 tangential history and Coulomb limit, per-particle gather of
-//                 force and torque (no float atomics), second half kick
-// Both kernels are one thread per particle over SoA FP64 arrays.  A pair is
-// evaluated by both of its particles in the canonical orientation (lower
-// original ID first), so both sides compute bit-identical forces and
-// tangential overlaps and each stores its own copy of the history.
+//                 centre into the nested cell grid (atomic slot insertion),
+//                 and the displacement test that requests a new broad search
+//   force_kick  : broad search (only when requested: cell-list neighbour list
+//                 within R_i + R_j + skin over the 27-cell stencil, sorted by
+//                 partner original ID, history carried by a merge), fine
+//                 search (exact overlap test over the list and the walls),
+//                 Hertz-Mindlin contact law (Table "tab:viscoelastic",
+//                 contact-force equation) with tangential history and Coulomb
+//                 limit, per-particle gather of force and torque (no float
+//                 atomics), second half kick
+// One thread per particle over SoA FP64 arrays.  A pair is evaluated by both
+// of its particles in the canonical orientation (lower original ID first), so
+// both sides compute bit-identical forces and tangential overlaps and each
+// keeps its own copy of the history in its own list slot.
 #include "device.h"
 
 namespace cfddem {
@@ -17,8 +22,10 @@ namespace cfddem {
 // ---------------------------------------------------------------------------
 // drift + binning
 // ---------------------------------------------------------------------------
+// par: count buffer to fill (cleared by the previous force_kick).
+// force_flag: request a broad search regardless of displacements.
 template <bool DRIFT>
-__global__ __launch_bounds__(256) void drift_bin(Dev D, int par) {
+__global__ __launch_bounds__(256) void drift_bin(Dev D, int par, int force_flag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
   const int n = D.n;
@@ -60,6 +67,9 @@ __global__ __launch_bounds__(256) void drift_bin(Dev D, int par) {
   else
     bits |= kErrCapacity;
   if (bits) atomicOr(D.err, bits);
+  // a list built at xb stays complete while every particle is within skin/2
+  const double d0 = xp[0] - D.xb[k], d1 = xp[1] - D.xb[n + k], d2 = xp[2] - D.xb[2 * n + k];
+  if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) atomicOr(&D.flag[par], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -115,178 +125,198 @@ __device__ inline void contact_law(const Material &M, const double n[3], double 
   nxft[2] = (double)(R(n[0]) * ft[1] - R(n[1]) * ft[0]);
 }
 
+// Broad-search predicate: (R_i + R_j + skin)^2 - |x_j - x_i|^2 > 0.  Every
+// pair that satisfies the fine-search predicate satisfies this one.
+__device__ inline bool within_cutoff(double xi0, double xi1, double xi2, double xj0, double xj1,
+                                     double xj2, double cut) {
+  const double dx = xj0 - xi0, dy = xj1 - xi1, dz = xj2 - xi2;
+  return cut * cut - (dx * dx + dy * dy + dz * dz) > 0.0;
+}
+
 // ---------------------------------------------------------------------------
-// contact search + forces + second half kick
+// broad search + fine search + forces + second half kick
 // ---------------------------------------------------------------------------
-// par: grid buffer built by the preceding drift_bin; the other count buffer is
-// cleared at the cells of the previous binning (it is the next step's buffer).
-// hold: history buffer to read; hnew: buffer to write.
+// par: grid / flag parity of this step (the drift_bin just before filled
+//      cnt[par] and may have raised flag[par]); the other count buffer and
+//      flag are cleared here for the next step.
+// prime: creation-time evaluation (no history advance, no kick).
+// src: after a re-sort, the index each particle had when its list was built
+//      (NULL otherwise).
 template <typename R, bool ADVANCE>
-__global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, int hold, int hnew) {
-  __shared__ unsigned long long lst[kMaxContacts][kForceBlock];
-  const int tx = threadIdx.x;
-  const int a = blockIdx.x * kForceBlock + tx;
+__global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const int *src) {
+  const int a = blockIdx.x * kForceBlock + threadIdx.x;
   if (a >= D.n) return;
   const int n = D.n;
   const Grid &G = D.grid;
+  const int lold = D.lbuf[par];
+  const bool rebuild = !ADVANCE || src != nullptr || D.flag[par] != 0;
+  const int cur = rebuild ? (lold ^ 1) : lold;
 
   const double xa0 = D.x[a], xa1 = D.x[n + a], xa2 = D.x[2 * n + a];
   const double ra = D.rad[a];
   const int oa = D.oid[a];
-  const int ca = D.cell[a];
-  int g3[3];
-  {
-    const int el = ca / G.kk, sub = ca - el * G.kk;
-    const int e0 = el % G.n_el[0], e1 = (el / G.n_el[0]) % G.n_el[1], e2 = el / (G.n_el[0] * G.n_el[1]);
-    const int s0 = sub % G.k[0], s1 = (sub / G.k[0]) % G.k[1], s2 = sub / (G.k[0] * G.k[1]);
-    g3[0] = e0 * G.k[0] + s0;
-    g3[1] = e1 * G.k[1] + s1;
-    g3[2] = e2 * G.k[2] + s2;
-  }
-
-  // ---- broad search over the 27-cell stencil, fine search, sorted insert
-  int nc = 0;
+  const size_t mn = (size_t)D.maxn * n;
   int bits = 0;
-  const int *cnt = D.cnt[par];
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int gz = g3[2] + dz;
-    if (gz < 0 || gz >= G.gc[2]) continue;
-    const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int gy = g3[1] + dy;
-      if (gy < 0 || gy >= G.gc[1]) continue;
-      const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int gx = g3[0] + dx;
-        if (gx < 0 || gx >= G.gc[0]) continue;
-        const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
-        const int c2 = ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk + (sz * G.k[1] + sy) * G.k[0] + sx;
-        int m = cnt[c2];
-        if (m > D.cap) m = D.cap;
-        const int *sl = D.slot + (size_t)c2 * D.cap;
-        for (int s = 0; s < m; ++s) {
-          const int b = sl[s];
-          if (b == a) continue;
-          if (!touching(xa0, xa1, xa2, D.x[b], D.x[n + b], D.x[2 * n + b], ra, D.rad[b])) continue;
-          const unsigned long long key =
-              ((unsigned long long)(unsigned)(D.oid[b] + kWalls) << 32) | (unsigned)b;
-          if (nc < D.maxc) {
-            int p = nc;
-            while (p > 0 && lst[p - 1][tx] > key) {
-              lst[p][tx] = lst[p - 1][tx];
-              --p;
+  unsigned long long mask_prev;
+
+  if (rebuild) {
+    // ---- broad search over the 27-cell stencil, insertion-sorted by oid
+    const int ca = D.cell[a];
+    const int el = ca / G.kk, sub = ca - el * G.kk;
+    const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
+    const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
+    const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
+    unsigned long long *lst = D.nbr[cur];
+    const int *cnt = D.cnt[par];
+    int m = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int gz = g2 + dz;
+      if (gz < 0 || gz >= G.gc[2]) continue;
+      const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int gy = g1 + dy;
+        if (gy < 0 || gy >= G.gc[1]) continue;
+        const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int gx = g0 + dx;
+          if (gx < 0 || gx >= G.gc[0]) continue;
+          const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
+          const int c2 =
+              ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk + (sz * G.k[1] + sy) * G.k[0] + sx;
+          int cm = cnt[c2];
+          if (cm > D.cap) cm = D.cap;
+          const int *sl = D.slot + (size_t)c2 * D.cap;
+          for (int s = 0; s < cm; ++s) {
+            const int b = sl[s];
+            if (b == a) continue;
+            if (!within_cutoff(xa0, xa1, xa2, D.x[b], D.x[n + b], D.x[2 * n + b],
+                               ra + D.rad[b] + D.skin))
+              continue;
+            const unsigned long long key =
+                ((unsigned long long)(unsigned)D.oid[b] << 32) | (unsigned)b;
+            if (m < D.maxn) {
+              int p = m;
+              while (p > 0 && lst[(size_t)(p - 1) * n + a] > key) {
+                lst[(size_t)p * n + a] = lst[(size_t)(p - 1) * n + a];
+                --p;
+              }
+              lst[(size_t)p * n + a] = key;
+              ++m;
+            } else {
+              bits |= kErrCapacity;
             }
-            lst[p][tx] = key;
-            ++nc;
-          } else {
-            bits |= kErrCapacity;
           }
         }
       }
     }
-  }
-  // walls: codes 0..5 sort before every particle code
-  {
-    int nw = 0;
-    unsigned long long wk[kWalls];
-    const double xa[3] = {xa0, xa1, xa2};
-    for (int wall = 0; wall < kWalls; ++wall) {
-      const int ax = wall >> 1;
-      const double dist = (wall & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
-      if (ra - dist > 0.0) wk[nw++] = (unsigned long long)wall << 32;
-    }
-    if (nw) {
-      if (nc + nw > D.maxc) {
-        bits |= kErrCapacity;
-        nc = D.maxc - nw > 0 ? D.maxc - nw : 0;
+    // ---- carry the tangential history of entries that were touching
+    const int s = src ? src[a] : a;
+    const int mo = D.ln[lold][s];
+    const unsigned long long mask_old = D.hmask[lold][s];
+    const unsigned long long *olst = D.nbr[lold];
+    unsigned long long carried = 0;
+    int q = 0;
+    for (int t = 0; t < m; ++t) {
+      const unsigned ot = (unsigned)(lst[(size_t)t * n + a] >> 32);
+      while (q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) < ot) ++q;
+      if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot && ((mask_old >> q) & 1ull)) {
+        for (int c = 0; c < 3; ++c)
+          D.hdt[cur][(size_t)c * mn + (size_t)t * n + a] = D.hdt[lold][(size_t)c * mn + (size_t)q * n + s];
+        carried |= 1ull << t;
       }
-      for (int p = nc - 1; p >= 0; --p) lst[p + nw][tx] = lst[p][tx];
-      for (int p = 0; p < nw && p < D.maxc; ++p) lst[p][tx] = wk[p];
-      nc = nc + nw > D.maxc ? D.maxc : nc + nw;
     }
+    D.ln[cur][a] = m;
+    D.xb[a] = xa0;
+    D.xb[n + a] = xa1;
+    D.xb[2 * n + a] = xa2;
+    mask_prev = carried;
+  } else {
+    mask_prev = D.hmask[cur][a];
   }
 
-  // ---- forces, history carried by merging the sorted old and new lists
+  // ---- fine search and forces: walls first, then list entries by oid
   const double va0 = D.vh[a], va1 = D.vh[n + a], va2 = D.vh[2 * n + a];
   const double wa0 = D.wh[a], wa1 = D.wh[n + a], wa2 = D.wh[2 * n + a];
   const double ma = D.mass[a];
-  const int hn_old = ADVANCE ? D.hn[hold][a] : 0;
-  const int *hid_old = D.hid[hold];
-  const double *hdt_old = D.hdt[hold];
-  int *hid_new = D.hid[hnew];
-  double *hdt_new = D.hdt[hnew];
-  const size_t mn = (size_t)D.maxc * n;
-  int p = 0;
-  int old_code = (p < hn_old) ? hid_old[(size_t)p * n + a] : 0x7fffffff;
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-
-  for (int t = 0; t < nc; ++t) {
-    const unsigned long long key = lst[t][tx];
-    const int code = (int)(key >> 32);
-    const int b = (int)(unsigned)(key & 0xffffffffu);
-    while (old_code < code) {
-      ++p;
-      old_code = (p < hn_old) ? hid_old[(size_t)p * n + a] : 0x7fffffff;
-    }
-    double dto[3] = {0.0, 0.0, 0.0};
-    if (ADVANCE && old_code == code) {
-      for (int c = 0; c < 3; ++c) dto[c] = hdt_old[(size_t)c * mn + (size_t)p * n + a];
-    }
-    double f[3], nxft[3], dtn[3], nrm[3], vij[3];
-    if (code < kWalls) {
-      const int ax = code >> 1;
-      const double xa[3] = {xa0, xa1, xa2};
-      const double dist = (code & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
-      nrm[0] = nrm[1] = nrm[2] = 0.0;
-      nrm[ax] = (code & 1) ? 1.0 : -1.0;
+  {
+    const double xa[3] = {xa0, xa1, xa2};
+    const unsigned wold = ADVANCE ? D.wmask[a] : 0u;
+    unsigned wnew = 0;
+    for (int wall = 0; wall < kWalls; ++wall) {
+      const int ax = wall >> 1;
+      const double dist = (wall & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
+      if (!(ra - dist > 0.0)) continue;
+      double nrm[3] = {0.0, 0.0, 0.0}, vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
+      nrm[ax] = (wall & 1) ? 1.0 : -1.0;
       const double dn = ra - dist;
       const double rw0 = ra * wa0, rw1 = ra * wa1, rw2 = ra * wa2;
       vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
       vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
       vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
+      if ((wold >> wall) & 1u)
+        for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
       contact_law<R, ADVANCE>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, f, nxft, dtn);
       for (int c = 0; c < 3; ++c) {
         F[c] += f[c];
         T[c] += ra * nxft[c];
+        D.whdt[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
       }
-    } else {
-      const double xb0 = D.x[b], xb1 = D.x[n + b], xb2 = D.x[2 * n + b];
-      const double vb0 = D.vh[b], vb1 = D.vh[n + b], vb2 = D.vh[2 * n + b];
-      const double wb0 = D.wh[b], wb1 = D.wh[n + b], wb2 = D.wh[2 * n + b];
-      const double rb = D.rad[b], mb = D.mass[b];
-      const bool first = oa < D.oid[b];  // canonical: lower original ID is "i"
-      const double xi0 = first ? xa0 : xb0, xi1 = first ? xa1 : xb1, xi2 = first ? xa2 : xb2;
-      const double xj0 = first ? xb0 : xa0, xj1 = first ? xb1 : xa1, xj2 = first ? xb2 : xa2;
-      const double vi0 = first ? va0 : vb0, vi1 = first ? va1 : vb1, vi2 = first ? va2 : vb2;
-      const double vj0 = first ? vb0 : va0, vj1 = first ? vb1 : va1, vj2 = first ? vb2 : va2;
-      const double wi0 = first ? wa0 : wb0, wi1 = first ? wa1 : wb1, wi2 = first ? wa2 : wb2;
-      const double wj0 = first ? wb0 : wa0, wj1 = first ? wb1 : wa1, wj2 = first ? wb2 : wa2;
-      const double ri = first ? ra : rb, rj = first ? rb : ra;
-      const double mi = first ? ma : mb, mj = first ? mb : ma;
-      const double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
-      const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      nrm[0] = d0 / dist;
-      nrm[1] = d1 / dist;
-      nrm[2] = d2 / dist;
-      const double dn = (ri + rj) - dist;
-      const double rw0 = ri * wi0 + rj * wj0, rw1 = ri * wi1 + rj * wj1, rw2 = ri * wi2 + rj * wj2;
-      vij[0] = vi0 - vj0 + (rw1 * nrm[2] - rw2 * nrm[1]);
-      vij[1] = vi1 - vj1 + (rw2 * nrm[0] - rw0 * nrm[2]);
-      vij[2] = vi2 - vj2 + (rw0 * nrm[1] - rw1 * nrm[0]);
-      const double Re = 1.0 / (1.0 / ri + 1.0 / rj);
-      const double me = 1.0 / (1.0 / mi + 1.0 / mj);
-      contact_law<R, ADVANCE>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, f, nxft, dtn);
-      const double lever = first ? ri : rj;  // torque on i: R_i n x f_t, on j: R_j n x f_t
-      const double sgn = first ? 1.0 : -1.0;
-      for (int c = 0; c < 3; ++c) {
-        F[c] += sgn * f[c];
-        T[c] += lever * nxft[c];
-      }
+      wnew |= 1u << wall;
     }
-    hid_new[(size_t)t * n + a] = code;
-    for (int c = 0; c < 3; ++c) hdt_new[(size_t)c * mn + (size_t)t * n + a] = dtn[c];
+    D.wmask[a] = (unsigned char)wnew;
   }
-  D.hn[hnew][a] = nc;
+
+  const int m = D.ln[cur][a];
+  const unsigned long long *lst = D.nbr[cur];
+  double *hdt = D.hdt[cur];
+  unsigned long long mask_new = 0;
+  for (int t = 0; t < m; ++t) {
+    const unsigned long long key = lst[(size_t)t * n + a];
+    const int b = (int)(unsigned)(key & 0xffffffffu);
+    const int ob = (int)(unsigned)(key >> 32);
+    const double xb0 = D.x[b], xb1 = D.x[n + b], xb2 = D.x[2 * n + b];
+    const double rb = D.rad[b];
+    if (!touching(xa0, xa1, xa2, xb0, xb1, xb2, ra, rb)) continue;
+    double dto[3] = {0.0, 0.0, 0.0};
+    if (ADVANCE && ((mask_prev >> t) & 1ull))
+      for (int c = 0; c < 3; ++c) dto[c] = hdt[(size_t)c * mn + (size_t)t * n + a];
+    const double vb0 = D.vh[b], vb1 = D.vh[n + b], vb2 = D.vh[2 * n + b];
+    const double wb0 = D.wh[b], wb1 = D.wh[n + b], wb2 = D.wh[2 * n + b];
+    const double mb = D.mass[b];
+    const bool first = oa < ob;  // canonical: lower original ID is "i"
+    const double xi0 = first ? xa0 : xb0, xi1 = first ? xa1 : xb1, xi2 = first ? xa2 : xb2;
+    const double xj0 = first ? xb0 : xa0, xj1 = first ? xb1 : xa1, xj2 = first ? xb2 : xa2;
+    const double vi0 = first ? va0 : vb0, vi1 = first ? va1 : vb1, vi2 = first ? va2 : vb2;
+    const double vj0 = first ? vb0 : va0, vj1 = first ? vb1 : va1, vj2 = first ? vb2 : va2;
+    const double wi0 = first ? wa0 : wb0, wi1 = first ? wa1 : wb1, wi2 = first ? wa2 : wb2;
+    const double wj0 = first ? wb0 : wa0, wj1 = first ? wb1 : wa1, wj2 = first ? wb2 : wa2;
+    const double ri = first ? ra : rb, rj = first ? rb : ra;
+    const double mi = first ? ma : mb, mj = first ? mb : ma;
+    const double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
+    const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    double nrm[3], vij[3], f[3], nxft[3], dtn[3];
+    nrm[0] = d0 / dist;
+    nrm[1] = d1 / dist;
+    nrm[2] = d2 / dist;
+    const double dn = (ri + rj) - dist;
+    const double rw0 = ri * wi0 + rj * wj0, rw1 = ri * wi1 + rj * wj1, rw2 = ri * wi2 + rj * wj2;
+    vij[0] = vi0 - vj0 + (rw1 * nrm[2] - rw2 * nrm[1]);
+    vij[1] = vi1 - vj1 + (rw2 * nrm[0] - rw0 * nrm[2]);
+    vij[2] = vi2 - vj2 + (rw0 * nrm[1] - rw1 * nrm[0]);
+    const double Re = 1.0 / (1.0 / ri + 1.0 / rj);
+    const double me = 1.0 / (1.0 / mi + 1.0 / mj);
+    contact_law<R, ADVANCE>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, f, nxft, dtn);
+    const double lever = first ? ri : rj;  // torque on i: R_i n x f_t, on j: R_j n x f_t
+    const double sgn = first ? 1.0 : -1.0;
+    for (int c = 0; c < 3; ++c) {
+      F[c] += sgn * f[c];
+      T[c] += lever * nxft[c];
+      hdt[(size_t)c * mn + (size_t)t * n + a] = dtn[c];
+    }
+    mask_new |= 1ull << t;
+  }
+  D.hmask[cur][a] = mask_new;
 
   for (int c = 0; c < 3; ++c) {
     D.Fc[c * n + a] = F[c];
@@ -306,36 +336,40 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, int ho
     if (vnew[0] != vnew[0] || vnew[1] != vnew[1] || vnew[2] != vnew[2]) bits |= kErrNan;
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
-  // the other count buffer becomes the next binning's: clear what it holds
+  // the other count buffer and flag belong to the next step: clear them
   D.cnt[par ^ 1][D.cell_prev[a]] = 0;
+  if (a == 0) {
+    D.flag[par ^ 1] = 0;
+    D.lbuf[par ^ 1] = cur;
+  }
   if (bits) atomicOr(D.err, bits);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_drift_bin(const Dev &D, int par, bool drift, hipStream_t st) {
+hipError_t launch_drift_bin(const Dev &D, int par, bool drift, bool force_flag, hipStream_t st) {
   const int grid = (D.n + 255) / 256;
   if (drift)
-    drift_bin<true><<<grid, 256, 0, st>>>(D, par);
+    drift_bin<true><<<grid, 256, 0, st>>>(D, par, force_flag ? 1 : 0);
   else
-    drift_bin<false><<<grid, 256, 0, st>>>(D, par);
+    drift_bin<false><<<grid, 256, 0, st>>>(D, par, force_flag ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_force_kick(const Dev &D, int par, int hold, int hnew, bool advance, bool fp32,
+hipError_t launch_force_kick(const Dev &D, int par, const int *src, bool advance, bool fp32,
                              hipStream_t st) {
   const int grid = (D.n + kForceBlock - 1) / kForceBlock;
   if (fp32) {
     if (advance)
-      force_kick<float, true><<<grid, kForceBlock, 0, st>>>(D, par, hold, hnew);
+      force_kick<float, true><<<grid, kForceBlock, 0, st>>>(D, par, src);
     else
-      force_kick<float, false><<<grid, kForceBlock, 0, st>>>(D, par, hold, hnew);
+      force_kick<float, false><<<grid, kForceBlock, 0, st>>>(D, par, src);
   } else {
     if (advance)
-      force_kick<double, true><<<grid, kForceBlock, 0, st>>>(D, par, hold, hnew);
+      force_kick<double, true><<<grid, kForceBlock, 0, st>>>(D, par, src);
     else
-      force_kick<double, false><<<grid, kForceBlock, 0, st>>>(D, par, hold, hnew);
+      force_kick<double, false><<<grid, kForceBlock, 0, st>>>(D, par, src);
   }
   return hipGetLastError();
 }

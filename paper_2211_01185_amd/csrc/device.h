@@ -7,7 +7,7 @@
 
 namespace cfddem {
 
-constexpr int kMaxContacts = 32;   // compile-time bound of dem_params.max_contacts
+constexpr int kMaxNeighbors = 64;  // bound of dem_params.max_neighbors (one 64-bit mask)
 constexpr int kForceBlock = 128;   // threads per block of the contact-force kernel
 constexpr int kElemMaxParticles = 1024;  // particles one coupling wave can hold
 constexpr int kWalls = 6;          // partner codes 0..5 are the box faces
@@ -41,9 +41,11 @@ struct Grid {
 struct Dev {
   int n;
   int cap;    // slots per cell
-  int maxc;   // contacts per particle
+  int maxn;   // neighbour-list entries per particle
   double dt;
   double g[3];
+  double skin;        // neighbour-list skin
+  double trig2;       // squared displacement that triggers a new broad search
   Material pp, pw;
   Grid grid;
   double *x, *v, *w;     // boundary state
@@ -51,13 +53,20 @@ struct Dev {
   double *Fc, *Tc;       // stored contact force / torque
   double *ffp;           // held fluid force
   double *rad, *mass;
+  double *xb;            // positions at the last broad search
   int *oid;              // original ID of each internal index
   int *cell, *cell_prev; // cell at the last and the previous binning
   int *cnt[2];           // particles per cell, double-buffered
   int *slot;             // ncells x cap particle indices
-  int *hn[2];            // contact count per particle (history buffers)
-  int *hid[2];           // maxc x n partner codes (0..5 wall, 6+oid particle)
-  double *hdt[2];        // 3 x maxc x n tangential overlap
+  int *flag;             // [2] broad search requested, by step parity
+  int *lbuf;             // [2] neighbour-list buffer in use, by step parity
+  // neighbour lists (buffer lbuf): entries sorted by partner original ID
+  int *ln[2];                    // entries per particle
+  unsigned long long *nbr[2];    // maxn x n: (partner oid << 32) | partner index
+  unsigned long long *hmask[2];  // bit t: entry t touched at the last evaluation
+  double *hdt[2];                // 3 x maxn x n tangential overlap of each entry
+  unsigned char *wmask;          // bit w: wall w touched at the last evaluation
+  double *whdt;                  // 3 x 6 x n tangential overlap against each wall
   int *err;              // sticky error bits
 };
 

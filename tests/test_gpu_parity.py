@@ -159,7 +159,7 @@ def test_domain_error_is_sticky():
 def test_contact_capacity_error():
     from paper_2211_01185_amd import cfddem
     wl = synth.lattice(n_side=(6, 6, 6))
-    gb = gpu_bed(wl, max_contacts=2)
+    gb = gpu_bed(wl, max_neighbors=2)
     err, _ = gb.poll()
     assert err == cfddem.DEM_E_CAPACITY
 
@@ -172,3 +172,31 @@ def test_nan_error():
     gb.step(1)
     err, _ = gb.poll()
     assert err == cfddem.DEM_E_NAN
+
+
+@pytest.mark.parametrize("skin", [0.0, 1e-6, 3e-4])
+def test_contact_set_matches_positions_across_rebuilds(skin):
+    """After many steps and device-triggered broad searches, the contact set is
+    exactly the set the definition gives at the GPU's own positions (a check
+    that holds whatever the trajectory divergence)."""
+    wl = synth.lattice(n_side=(9, 9, 10), seed_index=5)
+    wl.v *= 20.0  # 0.2 m/s: several skin lengths over the run
+    gb = gpu_bed(wl, "fp64", skin=skin, resort_every=17)
+    lo, hi = wl.dem["box_lo"], wl.dem["box_hi"]
+    for _ in range(6):
+        gb.step(25)
+        x = gb.read_state()["x"].cpu().numpy()
+        gi, gj, _ = gb.read_contacts()
+        pi, pj = O.find_pairs(x, wl.radius, lo, hi)
+        want = set(zip(pi.tolist(), pj.tolist()))
+        for i in range(wl.n):
+            for wall in range(6):
+                ax = wall // 2
+                dist = x[ax, i] - lo[ax] if wall % 2 == 0 else hi[ax] - x[ax, i]
+                if wl.radius[i] - dist > 0.0:
+                    want.add((i, -1 - wall))
+        got = set(zip(gi.tolist(), gj.tolist()))
+        assert got == want
+        assert len(got) > wl.n
+    err, _ = gb.poll()
+    assert err == 0
