@@ -13,10 +13,11 @@
 #include "device.h"
 
 namespace cfddem {
-hipError_t launch_drift_bin(const Dev &D, int par, bool drift, bool force_flag, hipStream_t st);
-hipError_t launch_force_kick(const Dev &D, int par, const int *src, bool advance, bool fp32,
-                             hipStream_t st);
-hipError_t launch_couple(const Dev &D, const Cpl &C, int par, const double *U, const double *P,
+hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st);
+hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st);
+hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
+                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, const double *U, const double *P,
                          double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
                          hipStream_t st);
 }  // namespace cfddem
@@ -144,7 +145,7 @@ struct Buffers {
   Dev D;
   // alternates for the re-sort (swapped with D's arrays)
   double *x2, *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2, *whdt2;
-  int *oid2, *cell2, *cellp2;
+  int *oid2, *cell2;
   unsigned char *wmask2;
   int *perm;                    // new index -> old index of the last re-sort
   int *start;                   // first sorted index of each cell (re-sort)
@@ -157,17 +158,24 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   Carver c{base};
   const size_t n = (size_t)S.n, mn = (size_t)S.maxn;
   Dev &D = B.D;
-  D.err = c.take<int>(64);  // [0] error bits, [16..17] flags, [32..33] list buffer
+  D.err = c.take<int>(64);  // [0] error bits, [16..18] flags, [32..34] list buffer
   if (base) {
     D.flag = D.err + 16;
     D.lbuf = D.err + 32;
   }
   B.scalars = c.take<unsigned long long>(8);
-  D.x = c.take<double>(3 * n);
+  for (int b = 0; b < 2; ++b) {
+    D.xs[b] = c.take<double>(3 * n);
+    D.vhs[b] = c.take<double>(3 * n);
+    D.whs[b] = c.take<double>(3 * n);
+    D.slot[b] = c.take<int>((size_t)S.grid.ncells * S.cap);
+  }
+  for (int b = 0; b < 3; ++b) {
+    D.cell[b] = c.take<int>(n);
+    D.cnt[b] = c.take<int>((size_t)S.grid.ncells);
+  }
   D.v = c.take<double>(3 * n);
   D.w = c.take<double>(3 * n);
-  D.vh = c.take<double>(3 * n);
-  D.wh = c.take<double>(3 * n);
   D.Fc = c.take<double>(3 * n);
   D.Tc = c.take<double>(3 * n);
   D.ffp = c.take<double>(3 * n);
@@ -175,18 +183,14 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   D.mass = c.take<double>(n);
   D.xb = c.take<double>(3 * n);
   D.oid = c.take<int>(n);
-  D.cell = c.take<int>(n);
-  D.cell_prev = c.take<int>(n);
   for (int b = 0; b < 2; ++b) {
     D.ln[b] = c.take<int>(n);
     D.nbr[b] = c.take<unsigned long long>(mn * n);
     D.hmask[b] = c.take<unsigned long long>(n);
     D.hdt[b] = c.take<double>(3 * mn * n);
-    D.cnt[b] = c.take<int>((size_t)S.grid.ncells);
   }
   D.wmask = c.take<unsigned char>(n);
   D.whdt = c.take<double>(3 * kWalls * n);
-  D.slot = c.take<int>((size_t)S.grid.ncells * S.cap);
   B.x2 = c.take<double>(3 * n);
   B.v2 = c.take<double>(3 * n);
   B.w2 = c.take<double>(3 * n);
@@ -197,7 +201,6 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   B.mass2 = c.take<double>(n);
   B.oid2 = c.take<int>(n);
   B.cell2 = c.take<int>(n);
-  B.cellp2 = c.take<int>(n);
   B.wmask2 = c.take<unsigned char>(n);
   B.whdt2 = c.take<double>(3 * kWalls * n);
   B.perm = c.take<int>(n);
@@ -217,7 +220,7 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   if (k >= D.n) return;
   const int n = D.n;
   for (int c = 0; c < 3; ++c) {
-    D.x[c * n + k] = x[c * n + k];
+    D.xs[0][c * n + k] = x[c * n + k];
     D.v[c * n + k] = v[c * n + k];
     D.w[c * n + k] = w[c * n + k];
     D.Fc[c * n + k] = 0.0;
@@ -228,8 +231,7 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   D.rad[k] = rk;
   D.mass[k] = rho[k] * (4.0 / 3.0 * kPi * rk * rk * rk);
   D.oid[k] = k;
-  D.cell[k] = 0;
-  D.cell_prev[k] = 0;
+  for (int b = 0; b < 3; ++b) D.cell[b][k] = 0;
   for (int c = 0; c < 3; ++c) D.xb[c * n + k] = x[c * n + k];
   D.ln[0][k] = 0;
   D.ln[1][k] = 0;
@@ -341,15 +343,15 @@ hipError_t device_exclusive_scan(long long n, const TI *in, int clamp, TO *out, 
 // New position of every particle when the arrays are ordered by cell: the
 // cell's first index plus the particle's rank among the cell's particles by
 // original ID (independent of the atomic insertion order).
-__global__ void k_rank(Dev D, int par, const int *start, int *perm) {
+__global__ void k_rank(Dev D, int p2, int p3, const int *start, int *perm) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
-  const int c = D.cell[k];
-  int m = D.cnt[par][c];
+  const int c = D.cell[p3][k];
+  int m = D.cnt[p3][c];
   if (m > D.cap) m = D.cap;
   const int o = D.oid[k];
   int rank = 0;
-  const int *sl = D.slot + (size_t)c * D.cap;
+  const int *sl = D.slot[p2] + (size_t)c * D.cap;
   for (int s = 0; s < m; ++s) rank += D.oid[sl[s]] < o;
   const int dst = start[c] + rank;
   if (dst >= 0 && dst < D.n) perm[dst] = k;
@@ -364,12 +366,12 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long a, unsigned
 
 struct PermSrc {
   const double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
-  const int *oid, *cell, *cellp;
+  const int *oid, *cell;
   const unsigned char *wmask;
 };
 struct PermDst {
   double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
-  int *oid, *cell, *cellp;
+  int *oid, *cell;
   unsigned char *wmask;
 };
 
@@ -392,7 +394,6 @@ __global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   d.mass[k] = s.mass[o];
   d.oid[k] = s.oid[o];
   d.cell[k] = s.cell[o];
-  d.cellp[k] = s.cellp[o];
   d.wmask[k] = s.wmask[o];
   for (int j = 0; j < 3 * kWalls; ++j) d.whdt[(size_t)j * n + k] = s.whdt[(size_t)j * n + o];
 }
@@ -462,9 +463,8 @@ struct dem_ctx {
   Buffers B;
   Cpl C;
   bool fp32;
-  int par = 0;   // parity of the last step: grid buffer, flags
+  long long s = 0;  // index of the last completed step (0 = creation)
   const int *pending_src = nullptr;  // permutation to apply at the next broad search
-  long long steps_done = 0;
   int since_sort = 0;
   dem_status poisoned = DEM_OK;
   bool timing = false;
@@ -481,17 +481,18 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   Buffers &B = ctx->B;
   Dev &D = B.D;
   const int n = D.n;
-  // the current grid holds every particle at its current cell
-  HIP_TRY(device_exclusive_scan<int, int>(D.grid.ncells, D.cnt[ctx->par], D.cap, B.start, B.bsum, st));
-  k_rank<<<blocks(n, 256), 256, 0, st>>>(D, ctx->par, B.start, B.perm);
+  const int p2 = (int)(ctx->s & 1), p3 = (int)(ctx->s % 3);
+  // the grid of the last step holds every particle at its current cell
+  HIP_TRY(device_exclusive_scan<int, int>(D.grid.ncells, D.cnt[p3], D.cap, B.start, B.bsum, st));
+  k_rank<<<blocks(n, 256), 256, 0, st>>>(D, p2, p3, B.start, B.perm);
   HIP_TRY(hipGetLastError());
-  PermSrc s{D.x, D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell, D.cell_prev,
-            D.wmask};
-  PermDst d{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.whdt2, B.oid2, B.cell2,
-            B.cellp2, B.wmask2};
-  k_permute<<<blocks(n, 256), 256, 0, st>>>(n, B.perm, s, d);
+  PermSrc src{D.xs[p2], D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell[p3],
+              D.wmask};
+  PermDst dst{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.whdt2, B.oid2, B.cell2,
+              B.wmask2};
+  k_permute<<<blocks(n, 256), 256, 0, st>>>(n, B.perm, src, dst);
   HIP_TRY(hipGetLastError());
-  std::swap(D.x, B.x2);
+  std::swap(D.xs[p2], B.x2);
   std::swap(D.v, B.v2);
   std::swap(D.w, B.w2);
   std::swap(D.Fc, B.Fc2);
@@ -500,8 +501,7 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   std::swap(D.rad, B.rad2);
   std::swap(D.mass, B.mass2);
   std::swap(D.oid, B.oid2);
-  std::swap(D.cell, B.cell2);
-  std::swap(D.cell_prev, B.cellp2);
+  std::swap(D.cell[p3], B.cell2);
   std::swap(D.whdt, B.whdt2);
   std::swap(D.wmask, B.wmask2);
   ctx->pending_src = B.perm;
@@ -509,7 +509,8 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   return DEM_OK;
 }
 
-static dem_status force_launch(dem_ctx *ctx, int par, bool advance, hipStream_t st) {
+// Launch step s (or the creation-time evaluation when !advance).
+static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool cont, hipStream_t st) {
   const int *src = advance ? ctx->pending_src : nullptr;
   ctx->pending_src = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -524,10 +525,8 @@ static dem_status force_launch(dem_ctx *ctx, int par, bool advance, hipStream_t 
     e0 = ctx->ev[ctx->ev_used];
     e1 = ctx->ev[ctx->ev_used + 1];
     ctx->ev_used += 2;
-    HIP_TRY(hipEventRecord(e0, st));
   }
-  HIP_TRY(launch_force_kick(ctx->B.D, par, src, advance, ctx->fp32, st));
-  if (ctx->timing) HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(launch_force_kick(ctx->B.D, s, src, advance, cont, ctx->fp32, st, e0, e1));
   return DEM_OK;
 }
 
@@ -631,7 +630,7 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   if (hipMemsetAsync(D.err, 0, sizeof(int) * 64, st) != hipSuccess) return fail(DEM_E_HIP);
   k_fill_u64<<<1, 64, 0, st>>>(ctx->B.scalars, 0ULL, ~0ULL);
   if (hipGetLastError() != hipSuccess) return fail(DEM_E_HIP);
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < 3; ++b)
     if (hipMemsetAsync(D.cnt[b], 0, sizeof(int) * (size_t)S.grid.ncells, st) != hipSuccess)
       return fail(DEM_E_HIP);
   k_init<<<blocks(n, 256), 256, 0, st>>>(D, x, v, omega, radius, density, ctx->B.scalars);
@@ -649,15 +648,15 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
     return fail(DEM_E_ARG);
 
   // priming: bin the initial positions, optionally sort by cell, evaluate
-  ctx->par = 0;
+  ctx->s = 0;
   if (launch_drift_bin(D, 0, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
   if (dp->resort_every > 0) {
     if (resort(ctx, st) != DEM_OK) return fail(DEM_E_HIP);
     ctx->pending_src = nullptr;  // nothing to carry at creation
-    if (launch_drift_bin(ctx->B.D, 1, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
-    ctx->par = 1;
+    if (launch_clear_grid(ctx->B.D, 0, st) != hipSuccess) return fail(DEM_E_HIP);
+    if (launch_drift_bin(ctx->B.D, 0, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
   }
-  if (force_launch(ctx, ctx->par, false, st) != DEM_OK) return fail(DEM_E_HIP);
+  if (force_launch(ctx, 0, false, false, st) != DEM_OK) return fail(DEM_E_HIP);
   *out = ctx;
   return DEM_OK;
 }
@@ -665,20 +664,22 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
 dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
   if (!ctx || n_steps < 0) return DEM_E_ARG;
   if (ctx->poisoned) return ctx->poisoned;
+  if (n_steps == 0) return DEM_OK;
   hipStream_t st = (hipStream_t)stream;
-  for (int s = 0; s < n_steps; ++s) {
-    if (ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
-      dem_status r = resort(ctx, st);
-      if (r != DEM_OK) return r;
-    }
-    const int par = ctx->par ^ 1;
-    HIP_TRY(launch_drift_bin(ctx->B.D, par, true, ctx->pending_src != nullptr, st));
-    dem_status r = force_launch(ctx, par, true, st);
+  if (ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
+    dem_status r = resort(ctx, st);
     if (r != DEM_OK) return r;
-    ctx->par = par;
-    ctx->steps_done++;
-    ctx->since_sort++;
   }
+  // the held fluid force may have changed since the last step: open the run
+  // with a separate half kick + drift, then one kernel per step
+  const long long s0 = ctx->s + 1;
+  HIP_TRY(launch_drift_bin(ctx->B.D, s0, true, ctx->pending_src != nullptr, st));
+  for (int i = 0; i < n_steps; ++i) {
+    dem_status r = force_launch(ctx, s0 + i, true, i + 1 < n_steps, st);
+    if (r != DEM_OK) return r;
+  }
+  ctx->s += n_steps;
+  ctx->since_sort += n_steps;
   return DEM_OK;
 }
 
@@ -687,7 +688,7 @@ dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_n
                           void *stream) {
   if (!ctx || !u_nodes || !p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
   if (ctx->poisoned) return ctx->poisoned;
-  HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->par, u_nodes, p_nodes, eps_q, beta_q, fpf_q,
+  HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->s, u_nodes, p_nodes, eps_q, beta_q, fpf_q,
                         elem_sums, ctx->fp32, (hipStream_t)stream));
   return DEM_OK;
 }
@@ -697,7 +698,7 @@ dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, dou
   if (!ctx) return DEM_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   const Dev &D = ctx->B.D;
-  const double *src[4] = {D.x, D.v, D.w, D.ffp};
+  const double *src[4] = {D.xs[ctx->s & 1], D.v, D.w, D.ffp};
   double *dst[4] = {x, v, omega, f_fp};
   for (int i = 0; i < 4; ++i) {
     if (!dst[i]) continue;
@@ -723,8 +724,8 @@ dem_status dem_read_cells(dem_ctx *ctx, int32_t *elem, int32_t *cell, int32_t *k
   if (k)
     for (int a = 0; a < 3; ++a) k[a] = D.grid.k[a];
   if (elem || cell) {
-    k_scatter_cells<<<blocks(D.n, 256), 256, 0, (hipStream_t)stream>>>(D.n, D.grid.kk, D.oid,
-                                                                        D.cell, elem, cell);
+    k_scatter_cells<<<blocks(D.n, 256), 256, 0, (hipStream_t)stream>>>(
+        D.n, D.grid.kk, D.oid, D.cell[ctx->s % 3], elem, cell);
     HIP_TRY(hipGetLastError());
   }
   return DEM_OK;
@@ -738,7 +739,7 @@ dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int6
   const Dev &D = B.D;
   const int n = D.n;
   int lb = 0;
-  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->par ^ 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->s + 1) % 3, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   k_contact_count<<<blocks(n, 256), 256, 0, st>>>(D, lb, B.cnt64, nullptr);
   HIP_TRY(hipGetLastError());
@@ -763,7 +764,7 @@ dem_status dem_poll(dem_ctx *ctx, int32_t *sticky_error, int64_t *n_contacts, vo
   const Dev &D = B.D;
   HIP_TRY(hipMemsetAsync(B.scalars, 0, sizeof(unsigned long long), st));
   int lb = 0;
-  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->par ^ 1), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&lb, D.lbuf + (ctx->s + 1) % 3, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   k_contact_count<<<blocks(D.n, 256), 256, 0, st>>>(D, lb, B.cnt64, B.scalars);
   HIP_TRY(hipGetLastError());

@@ -68,7 +68,7 @@ __device__ inline void basis1d(int order, double t, double L[3]) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int par,
+__global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, int p3,
                                                          const double *__restrict__ U,
                                                          const double *__restrict__ P,
                                                          double *__restrict__ eps_q,
@@ -86,7 +86,9 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int par,
   const int nqtot = G.n_elem * C.nq;
 
   // ---- 1. particles of this element: counts of its cells, scan, gather
-  const int *cnt = D.cnt[par];
+  const int *cnt = D.cnt[p3];
+  const int *slot = D.slot[p2];
+  const double *X = D.xs[p2];
   const int base = e * G.kk;
   int mine = 0;
   for (int c = lane; c < G.kk; c += kWave) {
@@ -99,12 +101,23 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int par,
     if (lane == 0) atomicOr(D.err, kErrCapacity);
     total = 0;
   }
-  if (total > 0) {
+  if (total == 0) {
+    // empty element: eps = 1, no drag, nothing handed to the fluid
+    for (int q = lane; q < C.nq; q += kWave) {
+      const long qg = (long)e * C.nq + q;
+      eps_q[qg] = 1.0;
+      beta_q[qg] = 0.0;
+      for (int c = 0; c < 3; ++c) fpf_q[(long)c * nqtot + qg] = 0.0;
+    }
+    if (esums && lane < 12) esums[lane * G.n_elem + e] = 0.0;
+    return;
+  }
+  {
     int w = off;
     for (int c = lane; c < G.kk; c += kWave) {
       int m = cnt[base + c];
       if (m > D.cap) m = D.cap;
-      const int *sl = D.slot + (size_t)(base + c) * D.cap;
+      const int *sl = slot + (size_t)(base + c) * D.cap;
       for (int s = 0; s < m; ++s) ids[w++] = sl[s];
     }
   }
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int par,
       const int k = ids[t];
       double xp[3], up[3], xi[3];
       for (int c = 0; c < 3; ++c) {
-        xp[c] = D.x[c * n + k];
+        xp[c] = X[c * n + k];
         up[c] = D.v[c * n + k];
       }
       const int ee[3] = {ex, ey, ez};
@@ -264,14 +277,15 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int par,
   }
 }
 
-hipError_t launch_couple(const Dev &D, const Cpl &C, int par, const double *U, const double *P,
+hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, const double *U, const double *P,
                          double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
                          hipStream_t st) {
   const int grid = D.grid.n_elem;
+  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   if (fp32)
-    couple_elements<float><<<grid, kWave, 0, st>>>(D, C, par, U, P, eps_q, beta_q, fpf_q, esums);
+    couple_elements<float><<<grid, kWave, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q, fpf_q, esums);
   else
-    couple_elements<double><<<grid, kWave, 0, st>>>(D, C, par, U, P, eps_q, beta_q, fpf_q, esums);
+    couple_elements<double><<<grid, kWave, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q, fpf_q, esums);
   return hipGetLastError();
 }
 

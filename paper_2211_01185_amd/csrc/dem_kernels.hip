@@ -1,35 +1,62 @@
-// dem_kernels.hip -- one DEM step on gfx950 (Section 2.2 of El Geitani,
-// Golshan & Blais, arXiv 2211.01185):
-//   drift_bin   : half kick + drift with the stored forces, binning of the new
-//                 centre into the nested cell grid (atomic slot insertion),
-//                 and the displacement test that requests a new broad search
-//   force_kick  : broad search (only when requested: cell-list neighbour list
-//                 within R_i + R_j + skin over the 27-cell stencil, sorted by
-//                 partner original ID, history carried by a merge), fine
-//                 search (exact overlap test over the list and the walls),
-//                 Hertz-Mindlin contact law (Table "tab:viscoelastic",
+// dem_kernels.hip -- DEM steps on gfx950 (Section 2.2 of El Geitani, Golshan
+// & Blais, arXiv 2211.01185), one kernel launch per step:
+//   drift_bin   : opens a run of steps: half kick + drift from the boundary
+//                 state, binning of the new centres into the nested cell grid
+//                 (atomic slot insertion), displacement test that requests a
+//                 new broad search
+//   force_kick  : step s: broad search when requested (cell-list neighbour
+//                 list within R_i + R_j + skin over the 27-cell stencil,
+//                 sorted by partner original ID, history carried by a merge),
+//                 fine search (exact overlap test over the list and the six
+//                 walls), Hertz-Mindlin contact law (Table "tab:viscoelastic",
 //                 contact-force equation) with tangential history and Coulomb
 //                 limit, per-particle gather of force and torque (no float
-//                 atomics), second half kick
+//                 atomics), second half kick; when another step follows, also
+//                 its half kick, drift, binning and displacement test
 // One thread per particle over SoA FP64 arrays.  A pair is evaluated by both
 // of its particles in the canonical orientation (lower original ID first), so
 // both sides compute bit-identical forces and tangential overlaps and each
 // keeps its own copy of the history in its own list slot.
+#include <hip/hip_ext.h>
+
 #include "device.h"
 
 namespace cfddem {
 
+// Binning of x into the grid of a step (counts cnt, slots sl, cells cl) and
+// the displacement test against the last broad-search positions.
+__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], int *cnt, int *sl,
+                                    int *cl, int *flag, bool force_flag, int &bits) {
+  int elem, cell;
+  bool inside;
+  bin_point(D.grid, xp, elem, cell, inside);
+  if (!inside) bits |= kErrDomain;
+  if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
+  cl[k] = cell;
+  const int s = atomicAdd(&cnt[cell], 1);
+  if (s >= 0 && s < D.cap)
+    sl[(size_t)cell * D.cap + s] = k;
+  else
+    bits |= kErrCapacity;
+  // a list built at xb stays complete while every particle is within skin/2
+  const int n = D.n;
+  const double d0 = xp[0] - D.xb[k], d1 = xp[1] - D.xb[n + k], d2 = xp[2] - D.xb[2 * n + k];
+  if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------------------
-// drift + binning
+// drift + binning (first step of a run; also the creation-time binning)
 // ---------------------------------------------------------------------------
-// par: count buffer to fill (cleared by the previous force_kick).
-// force_flag: request a broad search regardless of displacements.
+// p2 = s & 1, p3 = s % 3 of the step being opened.  DRIFT = false bins the
+// positions already in xs[p2] (creation).
 template <bool DRIFT>
-__global__ __launch_bounds__(256) void drift_bin(Dev D, int par, int force_flag) {
+__global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int force_flag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
+  const double *x0 = D.xs[p2 ^ 1];
+  double *x1 = D.xs[p2], *vh = D.vhs[p2], *wh = D.whs[p2];
   if (DRIFT) {
     const double m = D.mass[k];
     const double r = D.rad[k];
@@ -38,38 +65,32 @@ __global__ __launch_bounds__(256) void drift_bin(Dev D, int par, int force_flag)
       const int i = c * n + k;
       const double acc = (D.Fc[i] + D.ffp[i]) / m + D.g[c];
       const double alpha = D.Tc[i] / inertia;
-      const double vh = D.v[i] + 0.5 * D.dt * acc;
-      const double wh = D.w[i] + 0.5 * D.dt * alpha;
-      xp[c] = D.x[i] + D.dt * vh;
-      D.vh[i] = vh;
-      D.wh[i] = wh;
-      D.x[i] = xp[c];
+      const double vhc = D.v[i] + 0.5 * D.dt * acc;
+      const double whc = D.w[i] + 0.5 * D.dt * alpha;
+      xp[c] = x0[i] + D.dt * vhc;
+      vh[i] = vhc;
+      wh[i] = whc;
+      x1[i] = xp[c];
     }
   } else {
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + k;
-      xp[c] = D.x[i];
-      D.vh[i] = D.v[i];
-      D.wh[i] = D.w[i];
+      xp[c] = x1[i];
+      vh[i] = D.v[i];
+      wh[i] = D.w[i];
     }
   }
-  int elem, cell;
-  bool inside;
-  bin_point(D.grid, xp, elem, cell, inside);
   int bits = 0;
-  if (!inside) bits |= kErrDomain;
-  if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
-  D.cell_prev[k] = D.cell[k];
-  D.cell[k] = cell;
-  const int s = atomicAdd(&D.cnt[par][cell], 1);
-  if (s < D.cap)
-    D.slot[(size_t)cell * D.cap + s] = k;
-  else
-    bits |= kErrCapacity;
+  bin_and_test(D, k, xp, D.cnt[p3], D.slot[p2], D.cell[p3], D.flag + p3, force_flag != 0, bits);
   if (bits) atomicOr(D.err, bits);
-  // a list built at xb stays complete while every particle is within skin/2
-  const double d0 = xp[0] - D.xb[k], d1 = xp[1] - D.xb[n + k], d2 = xp[2] - D.xb[2 * n + k];
-  if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) atomicOr(&D.flag[par], 1);
+}
+
+// Clear the counts of grid p3 at the cells its particles were binned into.
+__global__ void clear_grid(Dev D, int p3) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.n) return;
+  D.cnt[p3][D.cell[p3][k]] = 0;
+  if (k == 0) D.flag[p3] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -134,25 +155,28 @@ __device__ inline bool within_cutoff(double xi0, double xi1, double xi2, double 
 }
 
 // ---------------------------------------------------------------------------
-// broad search + fine search + forces + second half kick
+// one DEM step (plus the opening of the next one when CONT)
 // ---------------------------------------------------------------------------
-// par: grid / flag parity of this step (the drift_bin just before filled
-//      cnt[par] and may have raised flag[par]); the other count buffer and
-//      flag are cleared here for the next step.
-// prime: creation-time evaluation (no history advance, no kick).
+// p2 = s & 1, p3 = s % 3.  The grid p3 / slot buffer p2 hold x_s.
+// ADVANCE = false: creation-time evaluation (no history advance, no kick).
 // src: after a re-sort, the index each particle had when its list was built
 //      (NULL otherwise).
-template <typename R, bool ADVANCE>
-__global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const int *src) {
+template <typename R, bool ADVANCE, bool CONT>
+__global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3, const int *src) {
   const int a = blockIdx.x * kForceBlock + threadIdx.x;
   if (a >= D.n) return;
   const int n = D.n;
   const Grid &G = D.grid;
-  const int lold = D.lbuf[par];
-  const bool rebuild = !ADVANCE || src != nullptr || D.flag[par] != 0;
+  const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
+  const int r3 = p3 == 0 ? 2 : p3 - 1;  // (s - 1) % 3
+  const double *xs = D.xs[p2];
+  const double *vhs = D.vhs[p2];
+  const double *whs = D.whs[p2];
+  const int lold = D.lbuf[p3];
+  const bool rebuild = !ADVANCE || src != nullptr || D.flag[p3] != 0;
   const int cur = rebuild ? (lold ^ 1) : lold;
 
-  const double xa0 = D.x[a], xa1 = D.x[n + a], xa2 = D.x[2 * n + a];
+  const double xa0 = xs[a], xa1 = xs[n + a], xa2 = xs[2 * n + a];
   const double ra = D.rad[a];
   const int oa = D.oid[a];
   const size_t mn = (size_t)D.maxn * n;
@@ -161,13 +185,14 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
 
   if (rebuild) {
     // ---- broad search over the 27-cell stencil, insertion-sorted by oid
-    const int ca = D.cell[a];
+    const int ca = D.cell[p3][a];
     const int el = ca / G.kk, sub = ca - el * G.kk;
     const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
     const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
     const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
     unsigned long long *lst = D.nbr[cur];
-    const int *cnt = D.cnt[par];
+    const int *cnt = D.cnt[p3];
+    const int *slot = D.slot[p2];
     int m = 0;
     for (int dz = -1; dz <= 1; ++dz) {
       const int gz = g2 + dz;
@@ -185,11 +210,11 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
               ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk + (sz * G.k[1] + sy) * G.k[0] + sx;
           int cm = cnt[c2];
           if (cm > D.cap) cm = D.cap;
-          const int *sl = D.slot + (size_t)c2 * D.cap;
+          const int *sl = slot + (size_t)c2 * D.cap;
           for (int s = 0; s < cm; ++s) {
             const int b = sl[s];
             if (b == a) continue;
-            if (!within_cutoff(xa0, xa1, xa2, D.x[b], D.x[n + b], D.x[2 * n + b],
+            if (!within_cutoff(xa0, xa1, xa2, xs[b], xs[n + b], xs[2 * n + b],
                                ra + D.rad[b] + D.skin))
               continue;
             const unsigned long long key =
@@ -219,9 +244,11 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
     for (int t = 0; t < m; ++t) {
       const unsigned ot = (unsigned)(lst[(size_t)t * n + a] >> 32);
       while (q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) < ot) ++q;
-      if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot && ((mask_old >> q) & 1ull)) {
+      if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot &&
+          ((mask_old >> q) & 1ull)) {
         for (int c = 0; c < 3; ++c)
-          D.hdt[cur][(size_t)c * mn + (size_t)t * n + a] = D.hdt[lold][(size_t)c * mn + (size_t)q * n + s];
+          D.hdt[cur][(size_t)c * mn + (size_t)t * n + a] =
+              D.hdt[lold][(size_t)c * mn + (size_t)q * n + s];
         carried |= 1ull << t;
       }
     }
@@ -235,8 +262,8 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
   }
 
   // ---- fine search and forces: walls first, then list entries by oid
-  const double va0 = D.vh[a], va1 = D.vh[n + a], va2 = D.vh[2 * n + a];
-  const double wa0 = D.wh[a], wa1 = D.wh[n + a], wa2 = D.wh[2 * n + a];
+  const double va0 = vhs[a], va1 = vhs[n + a], va2 = vhs[2 * n + a];
+  const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
   const double ma = D.mass[a];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   {
@@ -275,14 +302,14 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
     const unsigned long long key = lst[(size_t)t * n + a];
     const int b = (int)(unsigned)(key & 0xffffffffu);
     const int ob = (int)(unsigned)(key >> 32);
-    const double xb0 = D.x[b], xb1 = D.x[n + b], xb2 = D.x[2 * n + b];
+    const double xb0 = xs[b], xb1 = xs[n + b], xb2 = xs[2 * n + b];
     const double rb = D.rad[b];
     if (!touching(xa0, xa1, xa2, xb0, xb1, xb2, ra, rb)) continue;
     double dto[3] = {0.0, 0.0, 0.0};
     if (ADVANCE && ((mask_prev >> t) & 1ull))
       for (int c = 0; c < 3; ++c) dto[c] = hdt[(size_t)c * mn + (size_t)t * n + a];
-    const double vb0 = D.vh[b], vb1 = D.vh[n + b], vb2 = D.vh[2 * n + b];
-    const double wb0 = D.wh[b], wb1 = D.wh[n + b], wb2 = D.wh[2 * n + b];
+    const double vb0 = vhs[b], vb1 = vhs[n + b], vb2 = vhs[2 * n + b];
+    const double wb0 = whs[b], wb1 = whs[n + b], wb2 = whs[2 * n + b];
     const double mb = D.mass[b];
     const bool first = oa < ob;  // canonical: lower original ID is "i"
     const double xi0 = first ? xa0 : xb0, xi1 = first ? xa1 : xb1, xi2 = first ? xa2 : xb2;
@@ -322,25 +349,44 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
     D.Fc[c * n + a] = F[c];
     D.Tc[c * n + a] = T[c];
   }
+  if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
+  // the grid of step s-1 is free: clear it for step s+2
+  D.cnt[r3][D.cell[r3][a]] = 0;
+
   if (ADVANCE) {
     const double inertia = 0.4 * ma * ra * ra;
-    double vnew[3];
+    double vb[3], wb[3], acc[3], alpha[3];
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + a;
-      const double acc = (F[c] + D.ffp[i]) / ma + D.g[c];
-      const double alpha = T[c] / inertia;
-      vnew[c] = D.vh[i] + 0.5 * D.dt * acc;
-      D.v[i] = vnew[c];
-      D.w[i] = D.wh[i] + 0.5 * D.dt * alpha;
+      acc[c] = (F[c] + D.ffp[i]) / ma + D.g[c];
+      alpha[c] = T[c] / inertia;
+      vb[c] = vhs[i] + 0.5 * D.dt * acc[c];
+      wb[c] = whs[i] + 0.5 * D.dt * alpha[c];
+      D.v[i] = vb[c];
+      D.w[i] = wb[c];
     }
-    if (vnew[0] != vnew[0] || vnew[1] != vnew[1] || vnew[2] != vnew[2]) bits |= kErrNan;
+    if (vb[0] != vb[0] || vb[1] != vb[1] || vb[2] != vb[2]) bits |= kErrNan;
+    if (CONT) {
+      // open step s+1 with the same held fluid force
+      double xp[3];
+      double *x1 = D.xs[p2 ^ 1], *vh1 = D.vhs[p2 ^ 1], *wh1 = D.whs[p2 ^ 1];
+      const double xa[3] = {xa0, xa1, xa2};
+      for (int c = 0; c < 3; ++c) {
+        const int i = c * n + a;
+        const double vhc = vb[c] + 0.5 * D.dt * acc[c];
+        const double whc = wb[c] + 0.5 * D.dt * alpha[c];
+        xp[c] = xa[c] + D.dt * vhc;
+        vh1[i] = vhc;
+        wh1[i] = whc;
+        x1[i] = xp[c];
+      }
+      bin_and_test(D, a, xp, D.cnt[q3], D.slot[p2 ^ 1], D.cell[q3], D.flag + q3, false, bits);
+    }
   }
-  if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
-  // the other count buffer and flag belong to the next step: clear them
-  D.cnt[par ^ 1][D.cell_prev[a]] = 0;
   if (a == 0) {
-    D.flag[par ^ 1] = 0;
-    D.lbuf[par ^ 1] = cur;
+    D.flag[r3] = 0;
+    if (!CONT) D.flag[q3] = 0;
+    D.lbuf[q3] = cur;
   }
   if (bits) atomicOr(D.err, bits);
 }
@@ -348,28 +394,51 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int par, const 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_drift_bin(const Dev &D, int par, bool drift, bool force_flag, hipStream_t st) {
+hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st) {
   const int grid = (D.n + 255) / 256;
+  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   if (drift)
-    drift_bin<true><<<grid, 256, 0, st>>>(D, par, force_flag ? 1 : 0);
+    drift_bin<true><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0);
   else
-    drift_bin<false><<<grid, 256, 0, st>>>(D, par, force_flag ? 1 : 0);
+    drift_bin<false><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_force_kick(const Dev &D, int par, const int *src, bool advance, bool fp32,
-                             hipStream_t st) {
+hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st) {
+  clear_grid<<<(D.n + 255) / 256, 256, 0, st>>>(D, (int)(s % 3));
+  return hipGetLastError();
+}
+
+template <typename R, bool ADVANCE, bool CONT>
+static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
+                      hipEvent_t e1) {
   const int grid = (D.n + kForceBlock - 1) / kForceBlock;
-  if (fp32) {
-    if (advance)
-      force_kick<float, true><<<grid, kForceBlock, 0, st>>>(D, par, src);
+  if (e0)
+    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT>, dim3(grid), dim3(kForceBlock), 0, st, e0,
+                          e1, 0, D, p2, p3, src);
+  else
+    force_kick<R, ADVANCE, CONT><<<grid, kForceBlock, 0, st>>>(D, p2, p3, src);
+}
+
+// e0/e1: when non-NULL, events recorded at the kernel's own start and end.
+hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
+                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
+  if (!advance) {
+    if (fp32)
+      launch_fk<float, false, false>(D, p2, p3, src, st, e0, e1);
     else
-      force_kick<float, false><<<grid, kForceBlock, 0, st>>>(D, par, src);
+      launch_fk<double, false, false>(D, p2, p3, src, st, e0, e1);
+  } else if (fp32) {
+    if (cont)
+      launch_fk<float, true, true>(D, p2, p3, src, st, e0, e1);
+    else
+      launch_fk<float, true, false>(D, p2, p3, src, st, e0, e1);
   } else {
-    if (advance)
-      force_kick<double, true><<<grid, kForceBlock, 0, st>>>(D, par, src);
+    if (cont)
+      launch_fk<double, true, true>(D, p2, p3, src, st, e0, e1);
     else
-      force_kick<double, false><<<grid, kForceBlock, 0, st>>>(D, par, src);
+      launch_fk<double, true, false>(D, p2, p3, src, st, e0, e1);
   }
   return hipGetLastError();
 }

@@ -38,6 +38,9 @@ struct Grid {
 
 // Everything a DEM kernel needs, passed by value.  Arrays are indexed by the
 // internal (sorted) particle index; vectors are component-major (c*n + k).
+// Step s keeps its positions and half-step velocities in buffer s&1 and its
+// cell grid counts in buffer s%3, so that one kernel can read step s while it
+// prepares step s+1 and clears what step s-1 left behind.
 struct Dev {
   int n;
   int cap;    // slots per cell
@@ -48,18 +51,19 @@ struct Dev {
   double trig2;       // squared displacement that triggers a new broad search
   Material pp, pw;
   Grid grid;
-  double *x, *v, *w;     // boundary state
-  double *vh, *wh;       // half-step velocities
+  double *xs[2];         // positions x_s, by step parity
+  double *vhs[2], *whs[2];  // half-step velocities of step s, by parity
+  double *v, *w;         // boundary velocities (end of the last step)
   double *Fc, *Tc;       // stored contact force / torque
   double *ffp;           // held fluid force
   double *rad, *mass;
   double *xb;            // positions at the last broad search
   int *oid;              // original ID of each internal index
-  int *cell, *cell_prev; // cell at the last and the previous binning
-  int *cnt[2];           // particles per cell, double-buffered
-  int *slot;             // ncells x cap particle indices
-  int *flag;             // [2] broad search requested, by step parity
-  int *lbuf;             // [2] neighbour-list buffer in use, by step parity
+  int *cell[3];          // cell of x_s, by step mod 3
+  int *cnt[3];           // particles per cell, by step mod 3
+  int *slot[2];          // ncells x cap particle indices, by step parity
+  int *flag;             // [3] broad search requested, by step mod 3
+  int *lbuf;             // [3] neighbour-list buffer in use, by step mod 3
   // neighbour lists (buffer lbuf): entries sorted by partner original ID
   int *ln[2];                    // entries per particle
   unsigned long long *nbr[2];    // maxn x n: (partner oid << 32) | partner index

@@ -200,3 +200,24 @@ def test_contact_set_matches_positions_across_rebuilds(skin):
         assert len(got) > wl.n
     err, _ = gb.poll()
     assert err == 0
+
+
+def test_garbage_workspace_is_harmless():
+    """Creation must initialise every buffer it later reads: run on a workspace
+    recycled from a block the caching allocator held full of 0xAB bytes."""
+    wl = synth.lattice(n_side=(9, 9, 10), seed_index=6)
+    wl.v *= 20.0
+    junk = torch.full((64 << 20,), 0xAB, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    gb = gpu_bed(wl, "fp64", resort_every=7)
+    lo, hi = wl.dem["box_lo"], wl.dem["box_hi"]
+    for _ in range(3):
+        gb.step(11)
+        x = gb.read_state()["x"].cpu().numpy()
+        gi, gj, _ = gb.read_contacts()
+        pi, pj = O.find_pairs(x, wl.radius, lo, hi)
+        got = set((i, j) for i, j in zip(gi.tolist(), gj.tolist()) if j >= 0)
+        assert got == set(zip(pi.tolist(), pj.tolist()))
+    err, _ = gb.poll()
+    assert err == 0
