@@ -157,14 +157,36 @@ __device__ inline bool within_cutoff(double xi0, double xi1, double xi2, double 
 // ---------------------------------------------------------------------------
 // one DEM step (plus the opening of the next one when CONT)
 // ---------------------------------------------------------------------------
+// L consecutive lanes of a wavefront share one particle: lane l walks the list
+// entries t = l, l + L, ..., lane L-1 also the walls, and the partial force
+// and torque are summed over the L lanes in a fixed butterfly order.  A broad
+// search is done by every lane of the group (identical work, identical
+// writes), so no lane waits for another.  Lane 0 finishes the step.
 // p2 = s & 1, p3 = s % 3.  The grid p3 / slot buffer p2 hold x_s.
 // ADVANCE = false: creation-time evaluation (no history advance, no kick).
 // src: after a re-sort, the index each particle had when its list was built
 //      (NULL otherwise).
-template <typename R, bool ADVANCE, bool CONT>
+template <int L>
+__device__ inline double group_sum(double v) {
+  for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+template <int L>
+__device__ inline unsigned long long group_or(unsigned long long v) {
+  for (int off = 1; off < L; off <<= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffu), off, 64);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), off, 64);
+    v |= ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+template <typename R, bool ADVANCE, bool CONT, int L>
 __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3, const int *src) {
-  const int a = blockIdx.x * kForceBlock + threadIdx.x;
-  if (a >= D.n) return;
+  const int gid = blockIdx.x * kForceBlock + threadIdx.x;
+  const int a = gid / L;
+  const int lane = gid % L;
+  if (a >= D.n) return;  // whole groups leave together
   const int n = D.n;
   const Grid &G = D.grid;
   const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
@@ -182,6 +204,7 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
   const size_t mn = (size_t)D.maxn * n;
   int bits = 0;
   unsigned long long mask_prev;
+  int m;  // list length (kept in registers: only lane 0 stores it)
 
   if (rebuild) {
     // ---- broad search over the 27-cell stencil, insertion-sorted by oid
@@ -193,7 +216,7 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
     unsigned long long *lst = D.nbr[cur];
     const int *cnt = D.cnt[p3];
     const int *slot = D.slot[p2];
-    int m = 0;
+    m = 0;
     for (int dz = -1; dz <= 1; ++dz) {
       const int gz = g2 + dz;
       if (gz < 0 || gz >= G.gc[2]) continue;
@@ -252,53 +275,27 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
         carried |= 1ull << t;
       }
     }
-    D.ln[cur][a] = m;
-    D.xb[a] = xa0;
-    D.xb[n + a] = xa1;
-    D.xb[2 * n + a] = xa2;
+    if (lane == 0) {
+      D.ln[cur][a] = m;
+      D.xb[a] = xa0;
+      D.xb[n + a] = xa1;
+      D.xb[2 * n + a] = xa2;
+    }
     mask_prev = carried;
   } else {
     mask_prev = D.hmask[cur][a];
+    m = D.ln[cur][a];
   }
 
-  // ---- fine search and forces: walls first, then list entries by oid
+  // ---- fine search and forces over this lane's list entries
   const double va0 = vhs[a], va1 = vhs[n + a], va2 = vhs[2 * n + a];
   const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
   const double ma = D.mass[a];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-  {
-    const double xa[3] = {xa0, xa1, xa2};
-    const unsigned wold = ADVANCE ? D.wmask[a] : 0u;
-    unsigned wnew = 0;
-    for (int wall = 0; wall < kWalls; ++wall) {
-      const int ax = wall >> 1;
-      const double dist = (wall & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
-      if (!(ra - dist > 0.0)) continue;
-      double nrm[3] = {0.0, 0.0, 0.0}, vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
-      nrm[ax] = (wall & 1) ? 1.0 : -1.0;
-      const double dn = ra - dist;
-      const double rw0 = ra * wa0, rw1 = ra * wa1, rw2 = ra * wa2;
-      vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
-      vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
-      vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
-      if ((wold >> wall) & 1u)
-        for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
-      contact_law<R, ADVANCE>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, f, nxft, dtn);
-      for (int c = 0; c < 3; ++c) {
-        F[c] += f[c];
-        T[c] += ra * nxft[c];
-        D.whdt[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
-      }
-      wnew |= 1u << wall;
-    }
-    D.wmask[a] = (unsigned char)wnew;
-  }
-
-  const int m = D.ln[cur][a];
   const unsigned long long *lst = D.nbr[cur];
   double *hdt = D.hdt[cur];
   unsigned long long mask_new = 0;
-  for (int t = 0; t < m; ++t) {
+  for (int t = lane; t < m; t += L) {
     const unsigned long long key = lst[(size_t)t * n + a];
     const int b = (int)(unsigned)(key & 0xffffffffu);
     const int ob = (int)(unsigned)(key >> 32);
@@ -343,8 +340,46 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
     }
     mask_new |= 1ull << t;
   }
-  D.hmask[cur][a] = mask_new;
+  // ---- walls (last lane of the group)
+  if (lane == L - 1) {
+    const double xa[3] = {xa0, xa1, xa2};
+    const unsigned wold = ADVANCE ? D.wmask[a] : 0u;
+    unsigned wnew = 0;
+    for (int wall = 0; wall < kWalls; ++wall) {
+      const int ax = wall >> 1;
+      const double dist = (wall & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
+      if (!(ra - dist > 0.0)) continue;
+      double nrm[3] = {0.0, 0.0, 0.0}, vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
+      nrm[ax] = (wall & 1) ? 1.0 : -1.0;
+      const double dn = ra - dist;
+      const double rw0 = ra * wa0, rw1 = ra * wa1, rw2 = ra * wa2;
+      vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
+      vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
+      vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
+      if ((wold >> wall) & 1u)
+        for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
+      contact_law<R, ADVANCE>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, f, nxft, dtn);
+      for (int c = 0; c < 3; ++c) {
+        F[c] += f[c];
+        T[c] += ra * nxft[c];
+        D.whdt[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
+      }
+      wnew |= 1u << wall;
+    }
+    D.wmask[a] = (unsigned char)wnew;
+  }
+  for (int c = 0; c < 3; ++c) {
+    F[c] = group_sum<L>(F[c]);
+    T[c] = group_sum<L>(T[c]);
+  }
+  mask_new = group_or<L>(mask_new);
+  if (lane != 0) {
+    if (bits) atomicOr(D.err, bits);
+    return;
+  }
 
+  // ---- lane 0: store the step, open the next one
+  D.hmask[cur][a] = mask_new;
   for (int c = 0; c < 3; ++c) {
     D.Fc[c * n + a] = F[c];
     D.Tc[c * n + a] = T[c];
@@ -412,12 +447,13 @@ hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st) {
 template <typename R, bool ADVANCE, bool CONT>
 static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
-  const int grid = (D.n + kForceBlock - 1) / kForceBlock;
+  constexpr int L = kForceLanes;
+  const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
   if (e0)
-    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT>, dim3(grid), dim3(kForceBlock), 0, st, e0,
-                          e1, 0, D, p2, p3, src);
+    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L>, dim3(grid), dim3(kForceBlock), 0, st,
+                          e0, e1, 0, D, p2, p3, src);
   else
-    force_kick<R, ADVANCE, CONT><<<grid, kForceBlock, 0, st>>>(D, p2, p3, src);
+    force_kick<R, ADVANCE, CONT, L><<<grid, kForceBlock, 0, st>>>(D, p2, p3, src);
 }
 
 // e0/e1: when non-NULL, events recorded at the kernel's own start and end.
