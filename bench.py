@@ -8,10 +8,11 @@ step every 10 DEM steps).  A "step" is one DEM step; the coupling step that
 falls on every tenth step is inside the timed region.  Inputs are generated
 and copied to HBM before timing.
 
-Prints ONE JSON line: metric/value (particle-steps/s), the roofline of the
-dominant kernel (contact search + forces), measured with HIP events around
-each of its launches on the stream it runs on, and the CPU oracle timed on a
-bounded sample of the same workload.
+Prints ONE JSON line: metric/value (particle-steps/s) over K timed steps; the
+roofline of the dominant kernel (contact search + forces), measured with HIP
+events bound to each of its launches while the same K steps are replayed on a
+fresh bed (the runs are deterministic); and the CPU oracle timed on a bounded
+sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -42,8 +43,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_01185_amd", "csrc", "dem_kernels.
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=100)
     return ap.parse_args()
@@ -107,13 +108,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     wl = synth.fluidized()
-    bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, resort_every=RESORT_EVERY)
     U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
     P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
-    out = bed.couple(U, P)  # allocates the output tensors once
-    stream = bed.stream
 
-    def run(steps, start):
+    def make_bed():
+        bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, resort_every=RESORT_EVERY)
+        out = bed.couple(U, P)  # allocates the output tensors once; the run re-couples at step 0
+        return bed, out
+
+    def run(bed, out, steps, start):
         s = start
         end = start + steps
         while s < end:
@@ -124,20 +127,22 @@ def main():
             s += chunk
         return s
 
-    step = run(args.warmup, 0)
+    # throughput: W warmup steps, then exactly K timed steps without per-kernel
+    # instrumentation
+    bed, out = make_bed()
+    stream = bed.stream
+    step = run(bed, out, args.warmup, 0)
     torch.cuda.synchronize()
     err, _ = bed.poll()
     if err:
         raise SystemExit(f"device error after warmup: {cfddem.status_string(err)}")
     pairs0, walls0 = contact_counts(bed)
-
-    # timed region: exactly K steps, no per-kernel instrumentation
     start_ev = torch.cuda.Event(enable_timing=True)
     stop_ev = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start_ev.record(stream)
-    step = run(args.steps, step)
+    step = run(bed, out, args.steps, step)
     stop_ev.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -146,20 +151,26 @@ def main():
     if err:
         raise SystemExit(f"device error in the timed region: {cfddem.status_string(err)}")
     pairs1, walls1 = contact_counts(bed)
+    bed.close()
+    del bed, out
 
-    # roofline region: the next K steps with HIP events bound to every launch of
-    # the contact-force kernel on its stream (the events add launch latency, so
-    # this region is not used for the throughput)
+    # roofline: the same deterministic trajectory replayed on a fresh bed, with
+    # HIP events bound to every launch of the contact-force kernel on its
+    # stream during the same K steps (the events add launch latency, so this
+    # replay is not used for the throughput)
+    bed, out = make_bed()
+    step = run(bed, out, args.warmup, 0)
     bed.kernel_timing(True)
-    step = run(args.steps, step)
+    step = run(bed, out, args.steps, step)
     torch.cuda.synchronize()
     bed.kernel_timing(False)
     launches, force_ms = bed.kernel_timing_read()
     pairs2, walls2 = contact_counts(bed)
+    bed.close()
 
     elapsed = max(wall, gpu_ms / 1e3)
     value = wl.n * args.steps / elapsed
-    contacts = 0.5 * (pairs1 + walls1 + pairs2 + walls2)
+    contacts = 0.5 * (pairs0 + walls0 + pairs2 + walls2)
     force_avg_s = force_ms / 1e3 / max(launches, 1)
     alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
     achieved = alg_bytes / force_avg_s / 1e9

@@ -204,68 +204,88 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
   const size_t mn = (size_t)D.maxn * n;
   int bits = 0;
   unsigned long long mask_prev;
-  int m;  // list length (kept in registers: only lane 0 stores it)
+  int m = 0;  // list length (kept in registers: only lane 0 stores it)
+
+  // candidate list of this group while a broad search runs (lane 0 fills it)
+  extern __shared__ unsigned long long sh_list[];
+  constexpr int kGroups = kForceBlock / L;
+  unsigned long long *my_list = sh_list + threadIdx.x / L;  // stride kGroups
 
   if (rebuild) {
-    // ---- broad search over the 27-cell stencil, insertion-sorted by oid
-    const int ca = D.cell[p3][a];
-    const int el = ca / G.kk, sub = ca - el * G.kk;
-    const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
-    const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
-    const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
-    unsigned long long *lst = D.nbr[cur];
-    const int *cnt = D.cnt[p3];
-    const int *slot = D.slot[p2];
-    m = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int gz = g2 + dz;
-      if (gz < 0 || gz >= G.gc[2]) continue;
-      const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int gy = g1 + dy;
-        if (gy < 0 || gy >= G.gc[1]) continue;
-        const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int gx = g0 + dx;
-          if (gx < 0 || gx >= G.gc[0]) continue;
-          const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
-          const int c2 =
-              ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk + (sz * G.k[1] + sy) * G.k[0] + sx;
-          int cm = cnt[c2];
-          if (cm > D.cap) cm = D.cap;
-          const int *sl = slot + (size_t)c2 * D.cap;
-          for (int s = 0; s < cm; ++s) {
-            const int b = sl[s];
-            if (b == a) continue;
-            if (!within_cutoff(xa0, xa1, xa2, xs[b], xs[n + b], xs[2 * n + b],
-                               ra + D.rad[b] + D.skin))
-              continue;
-            const unsigned long long key =
-                ((unsigned long long)(unsigned)D.oid[b] << 32) | (unsigned)b;
-            if (m < D.maxn) {
-              int p = m;
-              while (p > 0 && lst[(size_t)(p - 1) * n + a] > key) {
-                lst[(size_t)p * n + a] = lst[(size_t)(p - 1) * n + a];
-                --p;
+    // ---- broad search over the 27-cell stencil (lane 0), insertion-sorted
+    //      by partner original ID in LDS
+    if (lane == 0) {
+      const int ca = D.cell[p3][a];
+      const int el = ca / G.kk, sub = ca - el * G.kk;
+      const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
+      const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
+      const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
+      const int *cnt = D.cnt[p3];
+      const int *slot = D.slot[p2];
+      m = 0;
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int gz = g2 + dz;
+        if (gz < 0 || gz >= G.gc[2]) continue;
+        const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int gy = g1 + dy;
+          if (gy < 0 || gy >= G.gc[1]) continue;
+          const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int gx = g0 + dx;
+            if (gx < 0 || gx >= G.gc[0]) continue;
+            const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
+            const int c2 = ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk +
+                           (sz * G.k[1] + sy) * G.k[0] + sx;
+            int cm = cnt[c2];
+            if (cm > D.cap) cm = D.cap;
+            const int *sl = slot + (size_t)c2 * D.cap;
+            for (int s = 0; s < cm; ++s) {
+              const int b = sl[s];
+              if (b == a) continue;
+              if (!within_cutoff(xa0, xa1, xa2, xs[b], xs[n + b], xs[2 * n + b],
+                                 ra + D.rad[b] + D.skin))
+                continue;
+              const unsigned long long key =
+                  ((unsigned long long)(unsigned)D.oid[b] << 32) | (unsigned)b;
+              if (m < D.maxn) {
+                int p = m;
+                while (p > 0 && my_list[(p - 1) * kGroups] > key) {
+                  my_list[p * kGroups] = my_list[(p - 1) * kGroups];
+                  --p;
+                }
+                my_list[p * kGroups] = key;
+                ++m;
+              } else {
+                bits |= kErrCapacity;
               }
-              lst[(size_t)p * n + a] = key;
-              ++m;
-            } else {
-              bits |= kErrCapacity;
             }
           }
         }
       }
+      D.ln[cur][a] = m;
+      D.xb[a] = xa0;
+      D.xb[n + a] = xa1;
+      D.xb[2 * n + a] = xa2;
     }
-    // ---- carry the tangential history of entries that were touching
+    // lane 0's LDS list and count become visible to the rest of the group
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    m = __shfl(m, (threadIdx.x & 63) & ~(L - 1), 64);
+    // ---- each lane stores its own entries and carries their tangential
+    //      history from the previous list (both sorted by partner oid)
     const int s = src ? src[a] : a;
     const int mo = D.ln[lold][s];
     const unsigned long long mask_old = D.hmask[lold][s];
     const unsigned long long *olst = D.nbr[lold];
+    unsigned long long *lst = D.nbr[cur];
     unsigned long long carried = 0;
     int q = 0;
-    for (int t = 0; t < m; ++t) {
-      const unsigned ot = (unsigned)(lst[(size_t)t * n + a] >> 32);
+    for (int t = lane; t < m; t += L) {
+      const unsigned long long key = my_list[t * kGroups];
+      lst[(size_t)t * n + a] = key;
+      const unsigned ot = (unsigned)(key >> 32);
       while (q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) < ot) ++q;
       if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot &&
           ((mask_old >> q) & 1ull)) {
@@ -275,13 +295,7 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
         carried |= 1ull << t;
       }
     }
-    if (lane == 0) {
-      D.ln[cur][a] = m;
-      D.xb[a] = xa0;
-      D.xb[n + a] = xa1;
-      D.xb[2 * n + a] = xa2;
-    }
-    mask_prev = carried;
+    mask_prev = carried;  // bits of this lane's entries
   } else {
     mask_prev = D.hmask[cur][a];
     m = D.ln[cur][a];
@@ -296,7 +310,7 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
   double *hdt = D.hdt[cur];
   unsigned long long mask_new = 0;
   for (int t = lane; t < m; t += L) {
-    const unsigned long long key = lst[(size_t)t * n + a];
+    const unsigned long long key = rebuild ? my_list[t * kGroups] : lst[(size_t)t * n + a];
     const int b = (int)(unsigned)(key & 0xffffffffu);
     const int ob = (int)(unsigned)(key >> 32);
     const double xb0 = xs[b], xb1 = xs[n + b], xb2 = xs[2 * n + b];
@@ -366,23 +380,28 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
       }
       wnew |= 1u << wall;
     }
-    D.wmask[a] = (unsigned char)wnew;
+    if (wnew != wold || !ADVANCE) D.wmask[a] = (unsigned char)wnew;
   }
   for (int c = 0; c < 3; ++c) {
     F[c] = group_sum<L>(F[c]);
     T[c] = group_sum<L>(T[c]);
   }
   mask_new = group_or<L>(mask_new);
+  mask_prev = group_or<L>(mask_prev);
   if (lane != 0) {
     if (bits) atomicOr(D.err, bits);
     return;
   }
 
-  // ---- lane 0: store the step, open the next one
-  D.hmask[cur][a] = mask_new;
-  for (int c = 0; c < 3; ++c) {
-    D.Fc[c * n + a] = F[c];
-    D.Tc[c * n + a] = T[c];
+  // ---- lane 0: store the step, open the next one.  Inside a run the
+  //      boundary velocities and the stored force/torque are never read, so
+  //      only the last step of a run stores them.
+  if (rebuild || mask_new != mask_prev) D.hmask[cur][a] = mask_new;
+  if (!CONT) {
+    for (int c = 0; c < 3; ++c) {
+      D.Fc[c * n + a] = F[c];
+      D.Tc[c * n + a] = T[c];
+    }
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
   // the grid of step s-1 is free: clear it for step s+2
@@ -397,8 +416,10 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
       alpha[c] = T[c] / inertia;
       vb[c] = vhs[i] + 0.5 * D.dt * acc[c];
       wb[c] = whs[i] + 0.5 * D.dt * alpha[c];
-      D.v[i] = vb[c];
-      D.w[i] = wb[c];
+      if (!CONT) {
+        D.v[i] = vb[c];
+        D.w[i] = wb[c];
+      }
     }
     if (vb[0] != vb[0] || vb[1] != vb[1] || vb[2] != vb[2]) bits |= kErrNan;
     if (CONT) {
@@ -449,11 +470,12 @@ static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t 
                       hipEvent_t e1) {
   constexpr int L = kForceLanes;
   const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
+  const size_t lds = sizeof(unsigned long long) * (size_t)D.maxn * (kForceBlock / L);
   if (e0)
-    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L>, dim3(grid), dim3(kForceBlock), 0, st,
+    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L>, dim3(grid), dim3(kForceBlock), lds, st,
                           e0, e1, 0, D, p2, p3, src);
   else
-    force_kick<R, ADVANCE, CONT, L><<<grid, kForceBlock, 0, st>>>(D, p2, p3, src);
+    force_kick<R, ADVANCE, CONT, L><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src);
 }
 
 // e0/e1: when non-NULL, events recorded at the kernel's own start and end.
