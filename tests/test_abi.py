@@ -39,7 +39,7 @@ def test_struct_layout_matches_header():
 #include "cfddem.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(dem_params), offsetof(dem_params, dt),
-         offsetof(dem_params, max_contacts), offsetof(dem_params, d_min), sizeof(cfd_params),
+         offsetof(dem_params, max_neighbors), offsetof(dem_params, skin), sizeof(cfd_params),
          offsetof(cfd_params, eps_min));
   return 0;
 }
@@ -50,8 +50,8 @@ int main(void) {
         open(c, "w").write(src)
         subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), "-o", exe, c], check=True)
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
-    want = [C.sizeof(cfddem.DemParams), cfddem.DemParams.dt.offset, cfddem.DemParams.max_contacts.offset,
-            cfddem.DemParams.d_min.offset, C.sizeof(cfddem.CfdParams), cfddem.CfdParams.eps_min.offset]
+    want = [C.sizeof(cfddem.DemParams), cfddem.DemParams.dt.offset, cfddem.DemParams.max_neighbors.offset,
+            cfddem.DemParams.skin.offset, C.sizeof(cfddem.CfdParams), cfddem.CfdParams.eps_min.offset]
     assert [int(v) for v in out] == want
 
 
