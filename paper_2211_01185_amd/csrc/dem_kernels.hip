@@ -146,6 +146,16 @@ __device__ inline void contact_law(const Material &M, const double n[3], double 
   nxft[2] = (double)(R(n[0]) * ft[1] - R(n[1]) * ft[0]);
 }
 
+// R_a w_a + R_b w_b without contraction, so that both particles of a pair
+// round it identically (an FMA would fuse a different product on each side).
+__device__ inline void lever_sum(double ra, double wa0, double wa1, double wa2, double rb,
+                                 double wb0, double wb1, double wb2, double rw[3]) {
+#pragma clang fp contract(off)
+  rw[0] = ra * wa0 + rb * wb0;
+  rw[1] = ra * wa1 + rb * wb1;
+  rw[2] = ra * wa2 + rb * wb2;
+}
+
 // Broad-search predicate: (R_i + R_j + skin)^2 - |x_j - x_i|^2 > 0.  Every
 // pair that satisfies the fine-search predicate satisfies this one.
 __device__ inline bool within_cutoff(double xi0, double xi1, double xi2, double xj0, double xj1,
@@ -182,7 +192,7 @@ __device__ inline unsigned long long group_or(unsigned long long v) {
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L>
-__global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3, const int *src) {
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
   const int gid = blockIdx.x * kForceBlock + threadIdx.x;
   const int a = gid / L;
   const int lane = gid % L;
@@ -223,15 +233,18 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
       const int *cnt = D.cnt[p3];
       const int *slot = D.slot[p2];
       m = 0;
+      #pragma unroll 1
       for (int dz = -1; dz <= 1; ++dz) {
         const int gz = g2 + dz;
         if (gz < 0 || gz >= G.gc[2]) continue;
         const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
-        for (int dy = -1; dy <= 1; ++dy) {
+      #pragma unroll 1
+      for (int dy = -1; dy <= 1; ++dy) {
           const int gy = g1 + dy;
           if (gy < 0 || gy >= G.gc[1]) continue;
           const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
-          for (int dx = -1; dx <= 1; ++dx) {
+      #pragma unroll 1
+      for (int dx = -1; dx <= 1; ++dx) {
             const int gx = g0 + dx;
             if (gx < 0 || gx >= G.gc[0]) continue;
             const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
@@ -300,6 +313,9 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
     mask_prev = D.hmask[cur][a];
     m = D.ln[cur][a];
   }
+  // keep the fast path's loads below the (rare) broad search, so that their
+  // registers are not live across it
+  __asm__ __volatile__("" ::: "memory");
 
   // ---- fine search and forces over this lane's list entries
   const double va0 = vhs[a], va1 = vhs[n + a], va2 = vhs[2 * n + a];
@@ -310,9 +326,8 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
   double *hdt = D.hdt[cur];
   unsigned long long mask_new = 0;
   for (int t = lane; t < m; t += L) {
-    const unsigned long long key = rebuild ? my_list[t * kGroups] : lst[(size_t)t * n + a];
+    const unsigned long long key = lst[(size_t)t * n + a];  // this lane stored its own entries
     const int b = (int)(unsigned)(key & 0xffffffffu);
-    const int ob = (int)(unsigned)(key >> 32);
     const double xb0 = xs[b], xb1 = xs[n + b], xb2 = xs[2 * n + b];
     const double rb = D.rad[b];
     if (!touching(xa0, xa1, xa2, xb0, xb1, xb2, ra, rb)) continue;
@@ -322,34 +337,27 @@ __global__ __launch_bounds__(kForceBlock) void force_kick(Dev D, int p2, int p3,
     const double vb0 = vhs[b], vb1 = vhs[n + b], vb2 = vhs[2 * n + b];
     const double wb0 = whs[b], wb1 = whs[n + b], wb2 = whs[2 * n + b];
     const double mb = D.mass[b];
-    const bool first = oa < ob;  // canonical: lower original ID is "i"
-    const double xi0 = first ? xa0 : xb0, xi1 = first ? xa1 : xb1, xi2 = first ? xa2 : xb2;
-    const double xj0 = first ? xb0 : xa0, xj1 = first ? xb1 : xa1, xj2 = first ? xb2 : xa2;
-    const double vi0 = first ? va0 : vb0, vi1 = first ? va1 : vb1, vi2 = first ? va2 : vb2;
-    const double vj0 = first ? vb0 : va0, vj1 = first ? vb1 : va1, vj2 = first ? vb2 : va2;
-    const double wi0 = first ? wa0 : wb0, wi1 = first ? wa1 : wb1, wi2 = first ? wa2 : wb2;
-    const double wj0 = first ? wb0 : wa0, wj1 = first ? wb1 : wa1, wj2 = first ? wb2 : wa2;
-    const double ri = first ? ra : rb, rj = first ? rb : ra;
-    const double mi = first ? ma : mb, mj = first ? mb : ma;
-    const double d0 = xj0 - xi0, d1 = xj1 - xi1, d2 = xj2 - xi2;
+    // Evaluated from this particle's side.  Every quantity the partner
+    // computes from its side is the exact negation (d, n, relative velocity,
+    // tangential overlap, force) or identical (|d|, dn, R_e, m_e, n x f_t), so
+    // the two sides stay bit-consistent: force on b = -force on a exactly.
+    const double d0 = xb0 - xa0, d1 = xb1 - xa1, d2 = xb2 - xa2;
     const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    double nrm[3], vij[3], f[3], nxft[3], dtn[3];
+    double nrm[3], vij[3], rw[3], f[3], nxft[3], dtn[3];
     nrm[0] = d0 / dist;
     nrm[1] = d1 / dist;
     nrm[2] = d2 / dist;
-    const double dn = (ri + rj) - dist;
-    const double rw0 = ri * wi0 + rj * wj0, rw1 = ri * wi1 + rj * wj1, rw2 = ri * wi2 + rj * wj2;
-    vij[0] = vi0 - vj0 + (rw1 * nrm[2] - rw2 * nrm[1]);
-    vij[1] = vi1 - vj1 + (rw2 * nrm[0] - rw0 * nrm[2]);
-    vij[2] = vi2 - vj2 + (rw0 * nrm[1] - rw1 * nrm[0]);
-    const double Re = 1.0 / (1.0 / ri + 1.0 / rj);
-    const double me = 1.0 / (1.0 / mi + 1.0 / mj);
+    const double dn = (ra + rb) - dist;
+    lever_sum(ra, wa0, wa1, wa2, rb, wb0, wb1, wb2, rw);
+    vij[0] = va0 - vb0 + (rw[1] * nrm[2] - rw[2] * nrm[1]);
+    vij[1] = va1 - vb1 + (rw[2] * nrm[0] - rw[0] * nrm[2]);
+    vij[2] = va2 - vb2 + (rw[0] * nrm[1] - rw[1] * nrm[0]);
+    const double Re = 1.0 / (1.0 / ra + 1.0 / rb);
+    const double me = 1.0 / (1.0 / ma + 1.0 / mb);
     contact_law<R, ADVANCE>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, f, nxft, dtn);
-    const double lever = first ? ri : rj;  // torque on i: R_i n x f_t, on j: R_j n x f_t
-    const double sgn = first ? 1.0 : -1.0;
     for (int c = 0; c < 3; ++c) {
-      F[c] += sgn * f[c];
-      T[c] += lever * nxft[c];
+      F[c] += f[c];
+      T[c] += ra * nxft[c];  // R_a n x f_t (n x f_t is the same from both sides)
       hdt[(size_t)c * mn + (size_t)t * n + a] = dtn[c];
     }
     mask_new |= 1ull << t;

@@ -221,3 +221,21 @@ def test_garbage_workspace_is_harmless():
         assert got == set(zip(pi.tolist(), pj.tolist()))
     err, _ = gb.poll()
     assert err == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pair_forces_are_exactly_opposite(precision):
+    """Each particle evaluates its pairs from its own side; the partner's
+    evaluation must be the exact negation, so the total contact force of a
+    wall-free, gravity-free bed vanishes to summation rounding."""
+    wl = synth.lattice(n_side=(7, 7, 7), seed_index=2)
+    wl.x[2] += 0.005
+    wl.dem["gravity"] = [0.0, 0.0, 0.0]
+    gb = gpu_bed(wl, precision)
+    for _ in range(3):
+        gb.step(4)
+        F, _ = gb.read_forces()
+        F = F.cpu().numpy()
+        i, j, _ = gb.read_contacts()
+        assert np.all(j >= 0) and i.size > 500
+        assert np.all(np.abs(F.sum(axis=1)) <= 1e-13 * np.abs(F).sum())
