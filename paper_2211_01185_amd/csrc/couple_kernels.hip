@@ -1,6 +1,7 @@
 // couple_kernels.hip -- one coupling step on gfx950 (Section 2.3 of El
 // Geitani, Golshan & Blais, arXiv 2211.01185), fused into one element-centric
-// kernel.  One 64-lane wavefront owns one mesh element:
+// kernel.  One 64-lane wavefront owns one mesh element (four per block, each
+// with its own LDS region, synchronized at wavefront scope only):
 //   1. gathers the element's particles from its nested DEM cells (the grid
 //      built at the current positions), sorts their indices in LDS so that
 //      every sum below has a fixed order,
@@ -20,6 +21,14 @@
 namespace cfddem {
 
 constexpr int kWave = 64;
+constexpr int kElemPerBlock = 4;  // one wavefront per element
+
+// LDS written by some lanes of a wavefront becomes visible to the others.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 constexpr double kPi = 3.14159265358979323846;
 
 template <typename R>
@@ -68,19 +77,24 @@ __device__ inline void basis1d(int order, double t, double L[3]) {
 }
 
 template <typename R>
-__global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, int p3,
+__global__ __launch_bounds__(kWave * kElemPerBlock) void couple_elements(Dev D, Cpl C, int p2, int p3,
                                                          const double *__restrict__ U,
                                                          const double *__restrict__ P,
                                                          double *__restrict__ eps_q,
                                                          double *__restrict__ beta_q,
                                                          double *__restrict__ fpf_q,
                                                          double *__restrict__ esums) {
-  __shared__ int ids[kElemMaxParticles];
-  __shared__ double sU[3][27];
-  __shared__ double sP[8];
-  const int lane = threadIdx.x;
-  const int e = blockIdx.x;
+  __shared__ int ids_all[kElemPerBlock][kElemMaxParticles];
+  __shared__ double sU_all[kElemPerBlock][3][27];
+  __shared__ double sP_all[kElemPerBlock][8];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int e = blockIdx.x * kElemPerBlock + wave;
   const Grid &G = D.grid;
+  if (e >= G.n_elem) return;  // whole wavefront
+  int *ids = ids_all[wave];
+  double(*sU)[27] = sU_all[wave];
+  double *sP = sP_all[wave];
   const int n = D.n;
   const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
   const int nqtot = G.n_elem * C.nq;
@@ -125,7 +139,7 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, i
   int np2 = 1;
   while (np2 < total) np2 <<= 1;
   for (int t = total + lane; t < np2; t += kWave) ids[t] = 0x7fffffff;
-  __syncthreads();
+  wave_sync();
   for (int size = 2; size <= np2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = lane; t < np2; t += kWave) {
@@ -139,7 +153,7 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, i
           }
         }
       }
-      __syncthreads();
+      wave_sync();
     }
   }
 
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, i
       const int ia = lane & 1, ib = (lane >> 1) & 1, ic = lane >> 2;
       sP[lane] = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
     }
-    __syncthreads();
+    wave_sync();
     const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
     for (int t = lane; t < total; t += kWave) {
       const int k = ids[t];
@@ -280,12 +294,14 @@ __global__ __launch_bounds__(kWave) void couple_elements(Dev D, Cpl C, int p2, i
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, const double *U, const double *P,
                          double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
                          hipStream_t st) {
-  const int grid = D.grid.n_elem;
+  const int grid = (D.grid.n_elem + kElemPerBlock - 1) / kElemPerBlock;
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   if (fp32)
-    couple_elements<float><<<grid, kWave, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q, fpf_q, esums);
+    couple_elements<float><<<grid, kWave * kElemPerBlock, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q,
+                                                                    fpf_q, esums);
   else
-    couple_elements<double><<<grid, kWave, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q, fpf_q, esums);
+    couple_elements<double><<<grid, kWave * kElemPerBlock, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q,
+                                                                     fpf_q, esums);
   return hipGetLastError();
 }
 
