@@ -17,9 +17,9 @@ hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_fl
 hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st);
 hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
                              bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, const double *U, const double *P,
-                         double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
-                         hipStream_t st);
+hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
+                         const double *P, double *eps_q, double *beta_q, double *fpf_q,
+                         double *esums, bool fp32, hipStream_t st);
 }  // namespace cfddem
 
 using namespace cfddem;
@@ -158,10 +158,10 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   Carver c{base};
   const size_t n = (size_t)S.n, mn = (size_t)S.maxn;
   Dev &D = B.D;
-  D.err = c.take<int>(64);  // [0] error bits, [16..18] flags, [32..34] list buffer
+  D.err = c.take<int>(64);
   if (base) {
-    D.flag = D.err + 16;
-    D.lbuf = D.err + 32;
+    D.flag = D.err + kFlagWord;
+    D.lbuf = D.err + kLbufWord;
   }
   B.scalars = c.take<unsigned long long>(8);
   for (int b = 0; b < 2; ++b) {
@@ -191,6 +191,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   }
   D.wmask = c.take<unsigned char>(n);
   D.whdt = c.take<double>(3 * kWalls * n);
+  D.occ = c.take<int>((size_t)S.grid.n_elem);
   B.x2 = c.take<double>(3 * n);
   B.v2 = c.take<double>(3 * n);
   B.w2 = c.take<double>(3 * n);
@@ -466,6 +467,7 @@ struct dem_ctx {
   long long s = 0;  // index of the last completed step (0 = creation)
   const int *pending_src = nullptr;  // permutation to apply at the next broad search
   int since_sort = 0;
+  long long n_couple = 0;  // coupling steps issued
   dem_status poisoned = DEM_OK;
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
@@ -688,8 +690,9 @@ dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_n
                           void *stream) {
   if (!ctx || !u_nodes || !p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
   if (ctx->poisoned) return ctx->poisoned;
-  HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->s, u_nodes, p_nodes, eps_q, beta_q, fpf_q,
-                        elem_sums, ctx->fp32, (hipStream_t)stream));
+  HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->s, ctx->n_couple, u_nodes, p_nodes, eps_q, beta_q,
+                        fpf_q, elem_sums, ctx->fp32, (hipStream_t)stream));
+  ++ctx->n_couple;
   return DEM_OK;
 }
 

@@ -1,27 +1,42 @@
 // couple_kernels.hip -- one coupling step on gfx950 (Section 2.3 of El
-// Geitani, Golshan & Blais, arXiv 2211.01185), fused into one element-centric
-// kernel.  One 64-lane wavefront owns one mesh element (four per block, each
-// with its own LDS region, synchronized at wavefront scope only):
+// Geitani, Golshan & Blais, arXiv 2211.01185) in two kernels.  A fluidized or
+// settled bed fills a small fraction of the mesh, so the step is a
+// bandwidth-bound write of the outputs of every empty element (eps = 1, no
+// drag, nothing handed to the fluid) and a few long, latency-bound element
+// computations.
+//
+// couple_classify: one wavefront per kClassElems consecutive elements reads
+// their cell counts (coalesced), writes the outputs of the empty ones as
+// contiguous runs and appends the occupied ones to a list.
+//
+// couple_occupied: one block of kCplThreads threads per listed element:
 //   1. gathers the element's particles from its nested DEM cells (the grid
-//      built at the current positions), sorts their indices in LDS so that
-//      every sum below has a fixed order,
+//      built at the current positions); each thread orders the particles of
+//      its own cells by index, so that every sum below has an order fixed by
+//      the set of particles alone,
 //   2. particle-centroid void fraction eps_e = 1 - sum V_p / V_e
 //      (Eq. "void_fraction"),
-//   3. per particle: Q_n interpolation of the fluid velocity and the Q1
-//      pressure gradient from the element's nodal values staged in LDS, Di
-//      Felice closure, f_fp = f_D + f_B + f_gradp (held by the DEM steps),
-//   4. element sums reduced across the wave (fixed butterfly order), then the
+//   3. per particle (one per thread): Q_n interpolation of the fluid
+//      velocity and the Q1 pressure gradient from the element's nodal values
+//      staged in LDS, Di Felice closure, f_fp = f_D + f_B + f_gradp (held by
+//      the DEM steps),
+//   4. element sums reduced across the block (fixed order), then the
 //      quadrature-point outputs eps_q, beta_q and the force density on the
 //      fluid F_pf,q = -beta_q (u_q - u_bar) [- sum f_gradp / V_e for model B]
-//      (Eqs. "fa", "fb").
-// No float atomics: every output element is written by exactly one wave and
-// every f_fp by the wave of the particle's element.
+//      (Eqs. "fa", "fb"), one (point, component) per thread.
+// No float atomics: every output element is written by exactly one thread and
+// every f_fp by the block of the particle's element.
 #include "device.h"
 
 namespace cfddem {
 
 constexpr int kWave = 64;
-constexpr int kElemPerBlock = 4;  // one wavefront per element
+constexpr int kCplThreads = 128;    // threads per occupied element
+constexpr int kCplWaves = kCplThreads / kWave;
+constexpr int kClassElems = 8;      // elements per wavefront of the classify pass
+constexpr int kClassBlock = 256;
+constexpr int kMaxCoupleBlocks = 4096;  // grid of the occupied-element pass
+constexpr int kSlotPre = 4;         // slot entries per cell loaded with the counts
 
 // LDS written by some lanes of a wavefront becomes visible to the others.
 __device__ inline void wave_sync() {
@@ -48,19 +63,53 @@ __device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
   return R(0.5) * rho_f * lim * pow(eps, R(2.0 - 3.7)) * area;
 }
 
+// FP32 closure on the hardware transcendentals (log2, exp2, 1/sqrt and 1/x,
+// each within about 1 ulp): the same expression as above, with
+// log10 x = log2 x log10 2, e^x = 2^(x log2 e) and a^b = 2^(b log2 a).
+template <>
+__device__ inline float difelice_beta<float>(float rho_f, float mu_f, float eps, float d, float slip) {
+  constexpr float kLog10of2 = 0.30102999566398119521f;
+  constexpr float kLog2e = 1.44269504088896340736f;
+  const float r = 0.5f * d;
+  const float area = float(kPi) * r * r;
+  const float log2_eps = __builtin_amdgcn_logf(eps);
+  if (slip > 0.0f) {
+    const float Re = rho_f * eps * slip * d * __builtin_amdgcn_rcpf(mu_f);
+    const float lg = 1.5f - __builtin_amdgcn_logf(Re) * kLog10of2;
+    const float chi = 3.7f - 0.65f * __builtin_amdgcn_exp2f(-(lg * lg) * (0.5f * kLog2e));
+    const float root = 0.63f + 4.8f * __builtin_amdgcn_rsqf(Re);
+    const float CD = root * root * __builtin_amdgcn_exp2f((2.0f - chi) * log2_eps);
+    return 0.5f * rho_f * CD * area * slip;
+  }
+  const float lim = float(4.8 * 4.8) * mu_f * __builtin_amdgcn_rcpf(rho_f * eps * d);
+  return 0.5f * rho_f * lim * __builtin_amdgcn_exp2f(float(2.0 - 3.7) * log2_eps) * area;
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
 }
 
-__device__ inline int wave_excl_scan(int v, int lane, int &total) {
-  int incl = v;
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int t = __shfl_up(incl, off, kWave);
-    if (lane >= off) incl += t;
+// N butterfly sums at once, level by level, so that the lane exchanges of a
+// level are in flight together rather than N dependent chains.
+template <int N>
+__device__ inline void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double t[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) t[j] = __shfl_xor(v[j], off, kWave);
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += t[j];
   }
-  total = __shfl(incl, kWave - 1, kWave);
-  return incl - v;
+}
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int t = __shfl_up(v, off, kWave);
+    if (lane >= off) v += t;
+  }
+  return v;
 }
 
 // 1D Lagrange basis on equispaced nodes of [0,1] and its derivative (Q1).
@@ -76,232 +125,410 @@ __device__ inline void basis1d(int order, double t, double L[3]) {
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kWave * kElemPerBlock) void couple_elements(Dev D, Cpl C, int p2, int p3,
-                                                         const double *__restrict__ U,
-                                                         const double *__restrict__ P,
-                                                         double *__restrict__ eps_q,
-                                                         double *__restrict__ beta_q,
-                                                         double *__restrict__ fpf_q,
-                                                         double *__restrict__ esums) {
-  __shared__ int ids_all[kElemPerBlock][kElemMaxParticles];
-  __shared__ double sU_all[kElemPerBlock][3][27];
-  __shared__ double sP_all[kElemPerBlock][8];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int e = blockIdx.x * kElemPerBlock + wave;
+
+// Per-particle step 3 of one element: interpolation, closure, f_fp, and the
+// thread's running element sums.
+template <typename R, int ORD>
+__device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const int ee[3],
+                                      const double xp[3], const double up[3], double r,
+                                      double eps_c, const double (*sU)[27], const double *sP,
+                                      double sums[10]) {
   const Grid &G = D.grid;
-  if (e >= G.n_elem) return;  // whole wavefront
-  int *ids = ids_all[wave];
-  double(*sU)[27] = sU_all[wave];
-  double *sP = sP_all[wave];
   const int n = D.n;
-  const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
-  const int nqtot = G.n_elem * C.nq;
-
-  // ---- 1. particles of this element: counts of its cells, scan, gather
-  const int *cnt = D.cnt[p3];
-  const int *slot = D.slot[p2];
-  const double *X = D.xs[p2];
-  const int base = e * G.kk;
-  int mine = 0;
-  for (int c = lane; c < G.kk; c += kWave) {
-    int m = cnt[base + c];
-    mine += m < D.cap ? m : D.cap;
-  }
-  int total;
-  const int off = wave_excl_scan(mine, lane, total);
-  if (total > kElemMaxParticles) {
-    if (lane == 0) atomicOr(D.err, kErrCapacity);
-    total = 0;
-  }
-  if (total == 0) {
-    // empty element: eps = 1, no drag, nothing handed to the fluid
-    for (int q = lane; q < C.nq; q += kWave) {
-      const long qg = (long)e * C.nq + q;
-      eps_q[qg] = 1.0;
-      beta_q[qg] = 0.0;
-      for (int c = 0; c < 3; ++c) fpf_q[(long)c * nqtot + qg] = 0.0;
-    }
-    if (esums && lane < 12) esums[lane * G.n_elem + e] = 0.0;
-    return;
-  }
-  {
-    int w = off;
-    for (int c = lane; c < G.kk; c += kWave) {
-      int m = cnt[base + c];
-      if (m > D.cap) m = D.cap;
-      const int *sl = slot + (size_t)(base + c) * D.cap;
-      for (int s = 0; s < m; ++s) ids[w++] = sl[s];
-    }
-  }
-  // pad to a power of two for the bitonic sort
-  int np2 = 1;
-  while (np2 < total) np2 <<= 1;
-  for (int t = total + lane; t < np2; t += kWave) ids[t] = 0x7fffffff;
-  wave_sync();
-  for (int size = 2; size <= np2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = lane; t < np2; t += kWave) {
-        const int partner = t ^ stride;
-        if (partner > t) {
-          const int u = ids[t], v = ids[partner];
-          const bool up = (t & size) == 0;
-          if ((u > v) == up) {
-            ids[t] = v;
-            ids[partner] = u;
-          }
-        }
-      }
-      wave_sync();
-    }
-  }
-
-  // ---- 2. void fraction
-  double vsum = 0.0;
-  for (int t = lane; t < total; t += kWave) {
-    const double r = D.rad[ids[t]];
-    vsum += 4.0 / 3.0 * kPi * r * r * r;
-  }
-  vsum = wave_sum(vsum);
-  const double eps = 1.0 - vsum / C.Ve;
-
-  // ---- 3. per-particle forces
-  const int p1 = C.order + 1;
-  const int nnode = p1 * p1 * p1;
-  double s_beta = 0.0, s_bu[3] = {0, 0, 0}, s_fd[3] = {0, 0, 0}, s_fg[3] = {0, 0, 0};
-  if (total > 0) {
-    for (int t = lane; t < nnode; t += kWave) {
-      const int ia = t % p1, ib = (t / p1) % p1, ic = t / (p1 * p1);
-      const long gx = (long)C.order * ex + ia, gy = (long)C.order * ey + ib, gz = (long)C.order * ez + ic;
-      const long node = (gz * C.nvy + gy) * C.nvx + gx;
-      const long nv = (long)C.nvx * C.nvy * ((long)C.order * G.n_el[2] + 1);
-      sU[0][t] = U[node];
-      sU[1][t] = U[nv + node];
-      sU[2][t] = U[2 * nv + node];
-    }
-    if (lane < 8) {
-      const int ia = lane & 1, ib = (lane >> 1) & 1, ic = lane >> 2;
-      sP[lane] = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
-    }
-    wave_sync();
-    const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
-    for (int t = lane; t < total; t += kWave) {
-      const int k = ids[t];
-      double xp[3], up[3], xi[3];
-      for (int c = 0; c < 3; ++c) {
-        xp[c] = X[c * n + k];
-        up[c] = D.v[c * n + k];
-      }
-      const int ee[3] = {ex, ey, ez};
-      for (int a = 0; a < 3; ++a) xi[a] = (xp[a] - (G.lo[a] + (double)ee[a] * G.he[a])) * G.inv_he[a];
-      double Lx[3], Ly[3], Lz[3];
-      basis1d(C.order, xi[0], Lx);
-      basis1d(C.order, xi[1], Ly);
-      basis1d(C.order, xi[2], Lz);
-      double uf[3] = {0.0, 0.0, 0.0};
-      for (int ic = 0; ic < p1; ++ic)
-        for (int ib = 0; ib < p1; ++ib) {
-          const double wyz = Ly[ib] * Lz[ic];
-          for (int ia = 0; ia < p1; ++ia) {
-            const double N = Lx[ia] * wyz;
-            const int t2 = (ic * p1 + ib) * p1 + ia;
-            uf[0] += N * sU[0][t2];
-            uf[1] += N * sU[1][t2];
-            uf[2] += N * sU[2][t2];
-          }
-        }
-      // Q1 pressure gradient: d/dx = inv_he d/dxi
-      double gp[3] = {0.0, 0.0, 0.0};
-      {
-        const double q0[2] = {1.0 - xi[0], xi[0]}, q1[2] = {1.0 - xi[1], xi[1]}, q2[2] = {1.0 - xi[2], xi[2]};
-        const double dq[2] = {-1.0, 1.0};
-        for (int c8 = 0; c8 < 8; ++c8) {
-          const int ia = c8 & 1, ib = (c8 >> 1) & 1, ic = c8 >> 2;
-          const double Pk = sP[c8];
-          gp[0] += dq[ia] * q1[ib] * q2[ic] * G.inv_he[0] * Pk;
-          gp[1] += q0[ia] * dq[ib] * q2[ic] * G.inv_he[1] * Pk;
-          gp[2] += q0[ia] * q1[ib] * dq[ic] * G.inv_he[2] * Pk;
-        }
-      }
-      const double r = D.rad[k];
-      const double Vp = 4.0 / 3.0 * kPi * r * r * r;
-      const double sl[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
-      const double slip = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + sl[2] * sl[2]);
-      const double beta =
-          (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
-      for (int c = 0; c < 3; ++c) {
-        const double fD = beta * sl[c];
-        const double fB = -C.rho_f * Vp * D.g[c];
-        const double fG = -Vp * gp[c];
-        D.ffp[c * n + k] = fD + fB + fG;
-        s_bu[c] += beta * up[c];
-        s_fd[c] += fD;
-        s_fg[c] += fG;
-      }
-      s_beta += beta;
-    }
-  }
-  s_beta = wave_sum(s_beta);
+  constexpr int p1 = ORD + 1;
+  double xi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xi[a] = (xp[a] - (G.lo[a] + (double)ee[a] * G.he[a])) * G.inv_he[a];
+  double Lx[3], Ly[3], Lz[3];
+  basis1d(ORD, xi[0], Lx);
+  basis1d(ORD, xi[1], Ly);
+  basis1d(ORD, xi[2], Lz);
+  double uf[3] = {0.0, 0.0, 0.0};
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s_bu[c] = wave_sum(s_bu[c]);
-    s_fd[c] = wave_sum(s_fd[c]);
-    s_fg[c] = wave_sum(s_fg[c]);
-  }
-
-  // ---- 4. quadrature-point outputs
-  const double bq = s_beta / C.Ve;
-  double ubar[3] = {0.0, 0.0, 0.0};
-  if (total > 0 && s_beta > 0.0)
-    for (int c = 0; c < 3; ++c) ubar[c] = s_bu[c] / s_beta;
-  for (int q = lane; q < C.nq; q += kWave) {
-    const long qg = (long)e * C.nq + q;
-    const int qx = q % C.nq1, qy = (q / C.nq1) % C.nq1, qz = q / (C.nq1 * C.nq1);
-    double F[3] = {0.0, 0.0, 0.0};
-    if (total > 0) {
-      double uq[3] = {0.0, 0.0, 0.0};
-      for (int ic = 0; ic < p1; ++ic)
-        for (int ib = 0; ib < p1; ++ib)
-          for (int ia = 0; ia < p1; ++ia) {
-            const double N = C.Lq[ia][qx] * C.Lq[ib][qy] * C.Lq[ic][qz];
-            const int t2 = (ic * p1 + ib) * p1 + ia;
-            uq[0] += N * sU[0][t2];
-            uq[1] += N * sU[1][t2];
-            uq[2] += N * sU[2][t2];
-          }
-      for (int c = 0; c < 3; ++c) {
-        F[c] = -bq * (uq[c] - ubar[c]);
-        if (C.model == 1) F[c] -= s_fg[c] / C.Ve;
+#pragma unroll
+    for (int ic = 0; ic < p1; ++ic) {
+      double acc_c = 0.0;
+#pragma unroll
+      for (int ib = 0; ib < p1; ++ib) {
+        double acc_b = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < p1; ++ia) acc_b += Lx[ia] * sU[c][(ic * p1 + ib) * p1 + ia];
+        acc_c += Ly[ib] * acc_b;
       }
+      uf[c] += Lz[ic] * acc_c;
+      // one layer of nodal values in flight at a time (bounds the registers)
+      __asm__ volatile("" ::: "memory");
     }
-    eps_q[qg] = eps;
-    beta_q[qg] = bq;
-    for (int c = 0; c < 3; ++c) fpf_q[(long)c * nqtot + qg] = F[c];
   }
-  if (esums && lane == 0) {
-    const int ne = G.n_elem;
-    esums[0 * ne + e] = (double)total;
-    esums[1 * ne + e] = vsum;
-    esums[2 * ne + e] = s_beta;
-    for (int c = 0; c < 3; ++c) {
-      esums[(3 + c) * ne + e] = s_bu[c];
-      esums[(6 + c) * ne + e] = s_fd[c];
-      esums[(9 + c) * ne + e] = s_fg[c];
+  // Q1 pressure gradient, d/dx = inv_he d/dxi, from the differences of the
+  // corner values along each axis
+  double gp[3];
+  {
+    const double q0[2] = {1.0 - xi[0], xi[0]}, q1[2] = {1.0 - xi[1], xi[1]}, q2[2] = {1.0 - xi[2], xi[2]};
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        g0 += q1[i] * q2[j] * (sP[1 + 2 * i + 4 * j] - sP[2 * i + 4 * j]);
+        g1 += q0[i] * q2[j] * (sP[i + 2 + 4 * j] - sP[i + 4 * j]);
+        g2 += q0[i] * q1[j] * (sP[i + 2 * j + 4] - sP[i + 2 * j]);
+      }
+    gp[0] = g0 * G.inv_he[0];
+    gp[1] = g1 * G.inv_he[1];
+    gp[2] = g2 * G.inv_he[2];
+  }
+  const double Vp = 4.0 / 3.0 * kPi * r * r * r;
+  const double sl[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
+  const double slip = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + sl[2] * sl[2]);
+  const double beta = (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double fD = beta * sl[c];
+    const double fB = -C.rho_f * Vp * D.g[c];
+    const double fG = -Vp * gp[c];
+    D.ffp[c * n + k] = fD + fB + fG;
+    sums[1 + c] += beta * up[c];
+    sums[4 + c] += fD;
+    sums[7 + c] += fG;
+  }
+  sums[0] += beta;
+}
+
+// Sorts a few register values ascending (odd-even transposition).
+template <int N>
+__device__ inline void sort_small(int (&v)[N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int i = r & 1; i + 1 < N; i += 2) {
+      const int a = v[i], b = v[i + 1];
+      v[i] = a < b ? a : b;
+      v[i + 1] = a < b ? b : a;
     }
+}
+
+// Inserts the slot entries [from, m) of a cell into the sorted run ids[w, w+from).
+__device__ inline void insert_rest(int *ids, int w, const int *sl, int from, int m) {
+  for (int s = from; s < m; ++s) {
+    const int v = sl[s];
+    int k = w + s;
+    while (k > w && ids[k - 1] > v) {
+      ids[k] = ids[k - 1];
+      --k;
+    }
+    ids[k] = v;
   }
 }
 
-hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, const double *U, const double *P,
-                         double *eps_q, double *beta_q, double *fpf_q, double *esums, bool fp32,
-                         hipStream_t st) {
-  const int grid = (D.grid.n_elem + kElemPerBlock - 1) / kElemPerBlock;
-  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
-  if (fp32)
-    couple_elements<float><<<grid, kWave * kElemPerBlock, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q,
-                                                                    fpf_q, esums);
+struct CplShared {
+  int ids[kElemMaxParticles];
+  double sU[3][27];
+  double sP[8];
+  double sLq[3][3];  // 1D velocity basis at the Gauss points (kernel constants)
+  double red[kCplWaves][11];
+  int scan[kCplWaves];
+};
+
+// One occupied element, computed by the whole block.  The latency is a short
+// chain of memory round trips: counts, slot entries and nodal values are
+// loaded together, then the particles' state, then the outputs are stored.
+template <typename R, int ORD>
+__device__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
+                               const double *__restrict__ P, double *__restrict__ eps_q,
+                               double *__restrict__ beta_q, double *__restrict__ fpf_q,
+                               double *__restrict__ esums, int p2, int p3, CplShared &sh) {
+  const Grid &G = D.grid;
+  const int n = D.n;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
+  const int ee[3] = {ex, ey, ez};
+  constexpr int p1 = ORD + 1;
+  constexpr int nnode = p1 * p1 * p1;
+  constexpr int nq = p1 * p1 * p1;  // Gauss points: order + 1 per axis
+  const long nqtot = (long)G.n_elem * nq;
+
+  // ---- nodal values of the element (at most 27): velocity on wave 0,
+  // pressure corners on wave 1
+  double un[3] = {0.0, 0.0, 0.0}, pk = 0.0;
+  if (tid < nnode) {
+    const long nv = (long)C.nvx * C.nvy * ((long)ORD * G.n_el[2] + 1);
+    const int ia = tid % p1, ib = (tid / p1) % p1, ic = tid / (p1 * p1);
+    const long node = (((long)ORD * ez + ic) * C.nvy + (long)ORD * ey + ib) * C.nvx + (long)ORD * ex + ia;
+    un[0] = U[node];
+    un[1] = U[nv + node];
+    un[2] = U[2 * nv + node];
+  }
+  const int pc = tid - kWave;  // pressure corner of this thread
+  if (pc >= 0 && pc < 8) {
+    const int ia = pc & 1, ib = (pc >> 1) & 1, ic = pc >> 2;
+    pk = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
+  }
+
+  // ---- 1. particles of this element.  The thread owning cell c of the
+  // element (c = tid first) loads its count and its first slot entries at once.
+  const int *cnt = D.cnt[p3];
+  const int *slot = D.slot[p2];
+  const int base = e * G.kk;
+  const int pre = D.cap < kSlotPre ? D.cap : kSlotPre;
+  int m0 = 0;
+  int v0[kSlotPre] = {0, 0, 0, 0};
+  if (tid < G.kk) {
+    m0 = cnt[base + tid];
+    const int *sl = slot + (size_t)(base + tid) * D.cap;
+#pragma unroll
+    for (int s = 0; s < kSlotPre; ++s) v0[s] = s < pre ? sl[s] : 0;
+  }
+  if (m0 > D.cap) m0 = D.cap;
+  int mine = m0;
+  for (int c = tid + kCplThreads; c < G.kk; c += kCplThreads) {
+    const int m = cnt[base + c];
+    mine += m < D.cap ? m : D.cap;
+  }
+  // block exclusive scan of the per-thread counts
+  const int incl = wave_incl_scan(mine, lane);
+  if (lane == kWave - 1) sh.scan[wave] = incl;
+  if (tid < nnode) {
+    sh.sU[0][tid] = un[0];
+    sh.sU[1][tid] = un[1];
+    sh.sU[2][tid] = un[2];
+  }
+  if (pc >= 0 && pc < 8) sh.sP[pc] = pk;
+  __syncthreads();
+  int off = incl - mine, total = 0;
+#pragma unroll
+  for (int w = 0; w < kCplWaves; ++w) {
+    if (w < wave) off += sh.scan[w];
+    total += sh.scan[w];
+  }
+  const bool over = total > kElemMaxParticles;
+  if (over && tid == 0) atomicOr(D.err, kErrCapacity);
+  if (over) total = 0;
+  if (total > 0) {
+    // each thread writes its cells' particles ordered by index, so the order
+    // of ids depends on the set of particles alone
+    int w = off;
+    if (tid < G.kk) {
+#pragma unroll
+      for (int s = 0; s < kSlotPre; ++s)
+        if (s >= m0) v0[s] = 0x7fffffff;
+      sort_small(v0);
+#pragma unroll
+      for (int s = 0; s < kSlotPre; ++s)
+        if (s < m0) sh.ids[w + s] = v0[s];
+      insert_rest(sh.ids, w, slot + (size_t)(base + tid) * D.cap, kSlotPre, m0);
+      w += m0;
+    }
+    for (int c = tid + kCplThreads; c < G.kk; c += kCplThreads) {
+      int m = cnt[base + c];
+      if (m > D.cap) m = D.cap;
+      insert_rest(sh.ids, w, slot + (size_t)(base + c) * D.cap, 0, m);
+      w += m;
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. void fraction; the state of the thread's first particle is
+  // loaded in the same round trip as its radius
+  const double *X = D.xs[p2];
+  const int k0 = tid < total ? sh.ids[tid] : -1;
+  double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, r0 = 0.0;
+  if (k0 >= 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x0[c] = X[c * n + k0];
+      u0[c] = D.v[c * n + k0];
+    }
+    r0 = D.rad[k0];
+  }
+  double vsum = k0 >= 0 ? 4.0 / 3.0 * kPi * r0 * r0 * r0 : 0.0;
+  for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
+    const double r = D.rad[sh.ids[t]];
+    vsum += 4.0 / 3.0 * kPi * r * r * r;
+  }
+  vsum = wave_sum(vsum);
+  if (lane == 0) sh.red[wave][10] = vsum;
+  __syncthreads();
+  vsum = 0.0;
+#pragma unroll
+  for (int w = 0; w < kCplWaves; ++w) vsum += sh.red[w][10];
+  const double eps = 1.0 - vsum / C.Ve;
+
+  // ---- 3. per-particle forces
+  double sums[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // beta, beta u_p, f_D, f_gradp
+  const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
+  if (k0 >= 0) particle_force<R, ORD>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
+  for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
+    const int k = sh.ids[t];
+    double xp[3], up[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xp[c] = X[c * n + k];
+      up[c] = D.v[c * n + k];
+    }
+    particle_force<R, ORD>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
+  }
+  wave_sum_n(sums);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 10; ++j) sh.red[wave][j] = sums[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 10; ++j) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCplWaves; ++w) v += sh.red[w][j];
+    sums[j] = v;
+  }
+
+  // ---- 4. quadrature-point outputs: thread t < 3 nq computes component
+  // t / nq of F at point t % nq; the next nq threads write eps and beta
+  const double s_beta = sums[0];
+  const double bq = s_beta / C.Ve;
+  if (tid < 3 * nq) {
+    const int c = tid / nq, q = tid % nq;
+    const int qi[3] = {q % p1, (q / p1) % p1, q / (p1 * p1)};
+    // basis values at this thread's Gauss point (staged in LDS: a
+    // per-thread index into the kernel arguments would turn every use into a
+    // memory round trip)
+    double Lg[3][p1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < p1; ++b) Lg[a][b] = sh.sLq[b][qi[a]];
+    double F = 0.0;
+    if (total > 0) {
+      double uq = 0.0;
+#pragma unroll
+      for (int ic = 0; ic < p1; ++ic) {
+        double acc_c = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < p1; ++ib) {
+          double acc_b = 0.0;
+#pragma unroll
+          for (int ia = 0; ia < p1; ++ia) acc_b += Lg[0][ia] * sh.sU[c][(ic * p1 + ib) * p1 + ia];
+          acc_c += Lg[1][ib] * acc_b;
+        }
+        uq += Lg[2][ic] * acc_c;
+        __asm__ volatile("" ::: "memory");
+      }
+      const double ubar = s_beta > 0.0 ? sums[1 + c] / s_beta : 0.0;
+      F = -bq * (uq - ubar);
+      if (C.model == 1) F -= sums[7 + c] / C.Ve;
+    }
+    fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
+  } else if (tid < 4 * nq) {
+    const long qg = (long)e * nq + (tid - 3 * nq);
+    eps_q[qg] = eps;
+    beta_q[qg] = bq;
+  } else if (esums && tid == 4 * nq) {
+    const int ne = G.n_elem;
+    esums[0 * ne + e] = (double)total;
+    esums[1 * ne + e] = vsum;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) esums[(2 + j) * ne + e] = sums[j];
+  }
+  __syncthreads();  // the block's LDS is reused for its next element
+}
+
+// Occupied-element counts live in two words selected by the parity of the
+// coupling call: call k appends to word k&1 and clears word (k+1)&1 for the
+// next call, which nothing reads during call k.
+__global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int p3, int parity,
+                                                               double *__restrict__ eps_q,
+                                                               double *__restrict__ beta_q,
+                                                               double *__restrict__ fpf_q,
+                                                               double *__restrict__ esums) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gw = (blockIdx.x * kClassBlock + threadIdx.x) / kWave;
+  const Grid &G = D.grid;
+  if (gw == 0 && lane == 0) D.err[kOccWord + (parity ^ 1)] = 0;
+  const int e0 = gw * kClassElems;
+  if (e0 >= G.n_elem) return;  // whole wavefront
+  const int ne = G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems;
+  const int *cnt = D.cnt[p3];
+  unsigned occupied = 0;
+  for (int c = lane; c - lane < G.kk; c += kWave) {
+    int m[kClassElems];
+#pragma unroll
+    for (int j = 0; j < kClassElems; ++j)
+      m[j] = (j < ne && c < G.kk) ? cnt[(size_t)(e0 + j) * G.kk + c] : 0;
+#pragma unroll
+    for (int j = 0; j < kClassElems; ++j)
+      if (__ballot(m[j] != 0)) occupied |= 1u << j;
+  }
+  // empty elements: eps = 1, no drag, nothing handed to the fluid; their
+  // quadrature points form contiguous runs
+  const int nq = C.nq;
+  const long nqtot = (long)G.n_elem * nq;
+  const long q0 = (long)e0 * nq;
+  for (int t = lane; t < ne * nq; t += kWave) {
+    if ((occupied >> (t / nq)) & 1u) continue;
+    const long qg = q0 + t;
+    eps_q[qg] = 1.0;
+    beta_q[qg] = 0.0;
+    fpf_q[qg] = 0.0;
+    fpf_q[nqtot + qg] = 0.0;
+    fpf_q[2 * nqtot + qg] = 0.0;
+  }
+  if (esums && lane < ne && !((occupied >> lane) & 1u))
+    for (int k = 0; k < 12; ++k) esums[(long)k * G.n_elem + e0 + lane] = 0.0;
+  if (occupied) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(D.err + kOccWord + parity, __popc(occupied));
+    base = __shfl(base, 0, kWave);
+    if (lane < ne && ((occupied >> lane) & 1u))
+      D.occ[base + __popc(occupied & ((1u << lane) - 1u))] = e0 + lane;
+  }
+}
+
+// One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
+// list exit at once; dispatching one block per mesh element would cost more
+// than the work).  Longer lists are strided over the grid.
+template <typename R, int ORD>
+__global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
+                                                                    int parity,
+                                                                    const double *__restrict__ U,
+                                                                    const double *__restrict__ P,
+                                                                    double *__restrict__ eps_q,
+                                                                    double *__restrict__ beta_q,
+                                                                    double *__restrict__ fpf_q,
+                                                                    double *__restrict__ esums) {
+  __shared__ CplShared sh;
+  // the list entry is read in the same round trip as the list length (every
+  // entry below n_elem is in bounds)
+  const int nocc = D.err[kOccWord + parity];
+  const int e = D.occ[blockIdx.x];
+  __asm__ volatile("" ::: "memory");
+  if ((int)blockIdx.x >= nocc) return;  // whole block
+  const int tid = threadIdx.x;
+  if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
+  couple_element<R, ORD>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+  // more occupied elements than blocks: the rest, strided over the grid
+  for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
+    couple_element<R, ORD>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+}
+
+hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
+                         const double *P, double *eps_q, double *beta_q, double *fpf_q,
+                         double *esums, bool fp32, hipStream_t st) {
+  const int p2 = (int)(s & 1), p3 = (int)(s % 3), parity = (int)(call & 1);
+  const int ne = D.grid.n_elem;
+  const int waves_c = (ne + kClassElems - 1) / kClassElems;
+  const int grid_c = (waves_c + kClassBlock / kWave - 1) / (kClassBlock / kWave);
+  couple_classify<<<grid_c, kClassBlock, 0, st>>>(D, C, p3, parity, eps_q, beta_q, fpf_q, esums);
+  const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks), b(kCplThreads);
+  if (fp32 && C.order == 2)
+    couple_occupied<float, 2><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
+  else if (fp32)
+    couple_occupied<float, 1><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
+  else if (C.order == 2)
+    couple_occupied<double, 2><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
   else
-    couple_elements<double><<<grid, kWave * kElemPerBlock, 0, st>>>(D, C, p2, p3, U, P, eps_q, beta_q,
-                                                                     fpf_q, esums);
+    couple_occupied<double, 1><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
   return hipGetLastError();
 }
 

@@ -15,6 +15,9 @@ constexpr int kWalls = 6;          // partner codes 0..5 are the box faces
 
 // sticky device error bits
 enum : int { kErrDomain = 1, kErrCapacity = 2, kErrNan = 4 };
+// word offsets in the int block at err: [0] error bits, [16..18] broad-search
+// flags, [32..34] list buffer, [48..49] occupied-element counts by call parity
+enum : int { kFlagWord = 16, kLbufWord = 32, kOccWord = 48 };
 
 struct Material {
   double Ye;        // effective Young's modulus
@@ -72,6 +75,7 @@ struct Dev {
   double *hdt[2];                // 3 x maxn x n tangential overlap of each entry
   unsigned char *wmask;          // bit w: wall w touched at the last evaluation
   double *whdt;                  // 3 x 6 x n tangential overlap against each wall
+  int *occ;              // mesh elements holding particles (coupling step)
   int *err;              // sticky error bits
 };
 
