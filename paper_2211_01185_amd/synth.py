@@ -97,76 +97,64 @@ def rsa_monodisperse(rng, n, d, lo, hi, max_tries=2000000):
 
 
 def rsa_polydisperse(rng, radius, lo, hi):
-    """Random sequential addition of spheres with the given radii (placed in the
-    given order) inside [lo, hi], wall distance >= r, centre distance > r_i + r_j.
-    Batched with a k-d tree over the accepted spheres."""
+    """Random sequential addition of spheres with the given radii inside
+    [lo, hi], wall distance >= r, centre distance > r_i + r_j.  The radii are
+    placed largest first (the small ones then fill the gaps; in the drawn order
+    the last large spheres find no room long before the target fraction), and
+    the returned centres are listed in the order of ``radius`` on return, which
+    the caller shuffles.  Candidates come in batches; clashes with accepted
+    spheres are found with one vectorized k-d tree distance query per batch,
+    clashes inside a batch keep the earlier candidate, and rejected radii are
+    retried in the next batch."""
     from scipy.spatial import cKDTree
 
     n = radius.shape[0]
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
+    radius[:] = np.sort(radius)[::-1]
     rmax = float(radius.max())
     pts = np.zeros((n, 3))
     placed = 0
     tree = None
-    tree_pts = np.zeros((0, 3))
-    tree_r = np.zeros(0)
-    pending = np.zeros((0, 3))
-    pending_r = np.zeros(0)
     while placed < n:
-        batch = min(n - placed, 20000)
-        rb = radius[placed:placed + batch]
-        cand = lo + rb[:, None] + (hi - lo - 2 * rb[:, None]) * rng.random((batch, 3))
-        ok = np.ones(batch, dtype=bool)
-        # against accepted spheres in the tree and in the not-yet-indexed list
+        left = n - placed
+        batch = min(left, 50000)
+        # few spheres left: several candidate positions for each, copy c of
+        # every sphere before copy c + 1
+        copies = max(1, 20000 // batch)
+        sid = np.tile(np.arange(batch), copies)
+        rb = radius[placed:placed + batch][sid]
+        cand = lo + rb[:, None] + (hi - lo - 2 * rb[:, None]) * rng.random((sid.shape[0], 3))
+        ok = np.ones(sid.shape[0], dtype=bool)
+        ctree = cKDTree(cand)
         if tree is not None:
-            nb = tree.query_ball_point(cand, rb + rmax)
-            for k in range(batch):
-                idx = nb[k]
-                if idx:
-                    dd = np.sum((tree_pts[idx] - cand[k]) ** 2, axis=1)
-                    if np.any(dd <= (tree_r[idx] + rb[k]) ** 2):
-                        ok[k] = False
-        if pending.shape[0]:
-            ptree = cKDTree(pending)
-            nb = ptree.query_ball_point(cand, rb + rmax)
-            for k in range(batch):
-                if not ok[k] or not nb[k]:
-                    continue
-                idx = nb[k]
-                dd = np.sum((pending[idx] - cand[k]) ** 2, axis=1)
-                if np.any(dd <= (pending_r[idx] + rb[k]) ** 2):
-                    ok[k] = False
-        # within the batch, in order: a candidate is dropped if it overlaps an
-        # earlier accepted candidate of the same batch
-        btree = cKDTree(cand)
-        pairs = btree.query_pairs(2 * rmax, output_type="ndarray")
+            m = tree.sparse_distance_matrix(ctree, 2 * rmax, output_type="ndarray")
+            if m.shape[0]:
+                clash = m["v"] <= radius[m["i"]] + rb[m["j"]]
+                ok[m["j"][clash]] = False
+        # inside the batch, in order: a candidate is dropped if it overlaps an
+        # earlier candidate of the batch that is still accepted
+        pairs = ctree.query_pairs(2 * rmax, output_type="ndarray")
         if pairs.shape[0]:
-            a, b = pairs[:, 0], pairs[:, 1]
-            lo_i = np.minimum(a, b)
-            hi_i = np.maximum(a, b)
-            dd = np.sum((cand[lo_i] - cand[hi_i]) ** 2, axis=1)
-            clash = dd <= (rb[lo_i] + rb[hi_i]) ** 2
-            lo_i, hi_i = lo_i[clash], hi_i[clash]
-            order = np.argsort(hi_i, kind="stable")
-            for p in order:
-                if ok[lo_i[p]]:
-                    ok[hi_i[p]] = False
-        # accepted candidates keep their radii order; rejected radii retry
-        acc = np.nonzero(ok)[0]
-        rej = np.nonzero(~ok)[0]
-        new_r = np.concatenate([rb[acc], rb[rej]])
-        radius[placed:placed + batch] = new_r
-        pts[placed:placed + acc.shape[0]] = cand[acc]
-        pending = np.vstack([pending, cand[acc]])
-        pending_r = np.concatenate([pending_r, rb[acc]])
+            a, b = pairs.min(axis=1), pairs.max(axis=1)
+            dd = np.sqrt(np.sum((cand[a] - cand[b]) ** 2, axis=1))
+            keep = (dd <= rb[a] + rb[b]) | (sid[a] == sid[b])
+            a, b = a[keep], b[keep]
+            for p in np.argsort(b, kind="stable"):
+                if ok[a[p]]:
+                    ok[b[p]] = False
+        # the first surviving copy of each sphere is placed
+        first = np.full(batch, -1)
+        cand_ok = np.nonzero(ok)[0]
+        u, at = np.unique(sid[cand_ok], return_index=True)
+        first[u] = cand_ok[at]
+        acc = np.nonzero(first >= 0)[0]
+        rej = np.nonzero(first < 0)[0]
+        r_here = radius[placed:placed + batch].copy()
+        radius[placed:placed + batch] = np.concatenate([r_here[acc], r_here[rej]])
+        pts[placed:placed + acc.shape[0]] = cand[first[acc]]
         placed += acc.shape[0]
-        if pending.shape[0] > 50000 or placed == n:
-            tree_pts = np.vstack([tree_pts, pending])
-            tree_r = np.concatenate([tree_r, pending_r])
-            tree = cKDTree(tree_pts)
-            pending = np.zeros((0, 3))
-            pending_r = np.zeros(0)
+        tree = cKDTree(pts[:placed])
     return pts.T.copy()
 
 
@@ -269,6 +257,9 @@ def spouted(n=500_000, seed_index=0, box=(0.15, 0.15, 0.6), fill_height=0.45, n_
     radius = 0.5 * d
     lo, hi = [0.0, 0.0, 0.0], list(box)
     x = rsa_polydisperse(rng, radius, lo, [hi[0], hi[1], fill_height])
+    perm = rng.permutation(n)  # particle IDs independent of size
+    x = x[:, perm].copy()
+    radius = radius[perm].copy()
     v = rng.normal(0.0, 0.01, size=(3, n))
     fluid = dict(order=2, n_el=list(n_el), rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
     nodes = node_grid(lo, hi, fluid["n_el"], 2)

@@ -1,0 +1,97 @@
+"""Parity at the full sizes of the benchmark workloads, against the FP64 oracle
+on every particle, contact and quadrature point (the oracle takes about a
+second per coupling step at these sizes).
+
+* The 100,000-sphere fluidized bed in the exact launch configuration that
+  bench.py times (FP32 force and drag arithmetic, re-sort every 100 steps, a
+  coupling step every 10 DEM steps): 110 steps, crossing a re-sort and
+  several neighbour-list rebuilds; also with the FP64 path.
+* The 500,000-sphere polydisperse spouted bed: priming, one coupling step and
+  ten DEM steps.
+
+Contact sets must match bit for bit at every check.  Coupling outputs, which
+depend on the current state only, are held to the single-step bar (1e-5 FP32,
+1e-10 FP64); the DEM state after many steps to ten times that bar, the same
+allowance as the short coupled sequence in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+import bench
+from paper_2211_01185_amd import cfddem, synth
+from tests.parity_util import TOL, assert_close, compare_contacts, compare_states, oracle_bed
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fields(wl):
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device="cuda").contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device="cuda").contiguous()
+    return U, P
+
+
+def _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums):
+    out = gb.couple(U, P, elem_sums=elem_sums)
+    ref = ob.couple(fl, wl.U, wl.P)
+    assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-12)
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    if elem_sums:
+        es = out["elem_sums"].cpu().numpy()
+        assert np.array_equal(es[0], ref["elem_sums"][0])  # particles per element
+        assert_close("elem_sums", es[1:], ref["elem_sums"][1:], tol)
+    assert_close("f_fp", gb.read_state()["ffp"].cpu().numpy(), ob.state()["ffp"], tol)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fluidized_bed_bench_configuration(precision):
+    wl = synth.fluidized()
+    # the bed exactly as bench.py builds it
+    gb = cfddem.bed_from_workload(wl, precision=precision, device=torch.device("cuda:0"),
+                                  resort_every=bench.RESORT_EVERY)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    tol = TOL[precision]
+    compare_contacts(gb, ob, tol)
+    compare_states(gb, ob, tol, keys=("Fc", "Tc"))
+    s = 0
+    while s < 110:
+        if s % bench.COUPLING_EVERY == 0:
+            _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums=(s // bench.COUPLING_EVERY) % 2 == 0)
+        k = 1 if s == 0 else bench.COUPLING_EVERY - s % bench.COUPLING_EVERY
+        gb.step(k)
+        ob.step(k)
+        s += k
+        n = compare_contacts(gb, ob, 10 * tol)
+        compare_states(gb, ob, tol if s == 1 else 10 * tol)
+    assert n > 1000  # contacts have formed by the end
+    err, ncont = gb.poll()
+    assert err == 0 and ncont == n
+
+
+@pytest.fixture(scope="module")
+def spouted():
+    return synth.spouted()
+
+
+def test_spouted_bed_full_size(spouted):
+    wl = spouted
+    gb = cfddem.bed_from_workload(wl, precision="fp32", device=torch.device("cuda:0"),
+                                  resort_every=bench.RESORT_EVERY)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    tol = TOL["fp32"]
+    compare_contacts(gb, ob, tol)
+    _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums=True)
+    gb.step(1)
+    ob.step(1)
+    compare_contacts(gb, ob, tol)
+    compare_states(gb, ob, tol)
+    gb.step(9)
+    ob.step(9)
+    compare_contacts(gb, ob, 10 * tol)
+    compare_states(gb, ob, 10 * tol)
+    _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums=False)
+    err, _ = gb.poll()
+    assert err == 0
