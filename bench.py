@@ -11,10 +11,20 @@ and copied to HBM before timing.
 Prints ONE JSON line: metric/value (particle-steps/s) over K timed steps; the
 roofline of the dominant kernel (contact search + forces), measured with HIP
 events bound to each of its launches while the same K steps are replayed on a
-fresh bed (the runs are deterministic); and the CPU oracle timed on a bounded
-sample of the same workload.
+fresh bed (the runs are deterministic); the CPU oracle timed on a bounded
+sample of the same workload; and the two other parts of the metric:
+
+  batched: 64 independent column beds (5k-80k spheres each, their own
+           diameter, restitution, inlet velocity and Q1 mesh) advanced 1,000
+           steps by shared launches replayed from a HIP graph (FP32 forces),
+           next to the same beds run one by one through the single-bed FP64
+           path;
+  served:  a Poisson stream (20 jobs/s) of sedimentation / fluidization jobs of
+           1k-200k spheres, served by continuous batching; p50/p99 latency and
+           aggregate particle-steps/s over the jobs after the warm-up ones.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--no-batched] [--no-served] [--served-jobs J]
 """
 import argparse
 import hashlib
@@ -47,6 +57,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-served", action="store_true", help="skip the served stream")
+    ap.add_argument("--batched-beds", type=int, default=64)
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--served-jobs", type=int, default=650)
+    ap.add_argument("--served-warmup", type=int, default=50)
     return ap.parse_args()
 
 
@@ -94,13 +110,93 @@ def cpu_baseline(wl, dem_steps):
                       f"{wl.n}-sphere bed, single-threaded FP64 C oracle, {dt:.1f} s"}
 
 
+def batched_ensemble(n_beds, steps, dev):
+    """The batched ensemble: every bed advanced by shared launches from one
+    graph per chunk (coupling + 10 steps), FP32 forces; then the plain
+    per-bed FP64 path on the same beds (single-bed entry points, one bed after
+    another) over a tenth of the steps."""
+    import torch
+
+    from paper_2211_01185_amd import cfddem, synth
+
+    wls = synth.batched(n_beds)
+    n_total = sum(w.n for w in wls)
+    fields = [(torch.as_tensor(w.U, dtype=torch.float64, device=dev).contiguous(),
+               torch.as_tensor(w.P, dtype=torch.float64, device=dev).contiguous()) for w in wls]
+    beds = [cfddem.bed_from_workload(w, precision="fp32", device=dev, resort_every=RESORT_EVERY) for w in wls]
+    batch = cfddem.Batch(beds, fields)
+    chunks = steps // COUPLING_EVERY
+    batch.run(2, COUPLING_EVERY, couple=True)  # warm-up, graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(chunks, COUPLING_EVERY, couple=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    errors = sum(1 for b in beds if b.poll()[0])
+    contacts = sum(b.poll()[1] for b in beds)
+    batch.close()
+    for b in beds:
+        b.close()
+    del batch, beds
+    # plain per-bed FP64 path
+    plain_steps = max(COUPLING_EVERY, steps // 10)
+    t_plain = 0.0
+    for w, (U, P) in zip(wls, fields):
+        bed = cfddem.bed_from_workload(w, precision="fp64", device=dev, resort_every=RESORT_EVERY)
+        out = bed.couple(U, P)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(plain_steps // COUPLING_EVERY):
+            bed.couple(U, P, out=out)
+            bed.step(COUPLING_EVERY)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+        errors += 1 if bed.poll()[0] else 0
+        bed.close()
+    return {
+        "workload": f"{n_beds} independent column beds, {n_total} spheres in total (5k-80k per bed, "
+                    f"d 1-3 mm, e 0.7-0.95, inlet 0.5-2 m/s, Q1 meshes), coupling every {COUPLING_EVERY} steps",
+        "beds": n_beds, "particles": n_total, "steps": chunks * COUPLING_EVERY,
+        "value": n_total * chunks * COUPLING_EVERY / dt, "unit": "particle-steps/s",
+        "jobs_per_s": n_beds / (dt * steps / (chunks * COUPLING_EVERY)),
+        "ms_per_step": dt * 1e3 / (chunks * COUPLING_EVERY),
+        "dtype": "f32 forces / f64 state", "launch": "shared launches per step, one HIP graph per chunk",
+        "contacts_end": int(contacts), "errors": int(errors),
+        "per_bed_fp64_path": {"value": n_total * plain_steps / t_plain, "unit": "particle-steps/s",
+                              "steps": plain_steps, "dtype": "f64",
+                              "launch": "single-bed entry points, one bed after another"},
+    }
+
+
+def served_stream(n_jobs, warmup, dev):
+    """The served stream: Poisson arrivals, continuous batching; statistics
+    over the jobs after the first `warmup` ones."""
+    from paper_2211_01185_amd import serve, synth
+
+    jobs = synth.job_stream(n_jobs)
+    server = serve.Server(device=dev)
+    results, wall = server.run(jobs)
+    measured = [r for r in results if r.index >= warmup]
+    t_first = min(r.arrival for r in measured)
+    t_last = max(r.finished for r in measured)
+    s = serve.summarize(measured, t_last - t_first)
+    offered = sum(j.n * j.steps for j in jobs) / jobs[-1].arrival
+    return {
+        "workload": f"{n_jobs} jobs ({warmup} warm-up), Poisson arrivals 20 jobs/s, sedimentation or "
+                    "fluidization column beds of 1k-200k spheres, 200-2000 steps, coupling every 10",
+        "jobs": s["jobs"], "latency_p50_s": s["latency_p50_s"], "latency_p99_s": s["latency_p99_s"],
+        "value": s["particle_steps_per_s"], "unit": "particle-steps/s", "jobs_per_s": s["jobs_per_s"],
+        "offered_particle_steps_per_s": offered, "errors": s["errors"], "chunks": server.chunks,
+        "batch_rebuilds": server.rebuilds, "wall_s": wall, "dtype": "f32 forces / f64 state",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(beds shard by bed or by z-slab, see the design notes)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2211_01185_amd import cfddem, synth
@@ -213,6 +309,10 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    if not args.no_batched:
+        result["batched"] = batched_ensemble(args.batched_beds, args.batched_steps, dev)
+    if not args.no_served:
+        result["served"] = served_stream(args.served_jobs, args.served_warmup, dev)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(result), flush=True)

@@ -201,6 +201,64 @@ dem_status dem_kernel_timing_read(dem_ctx *ctx, int64_t *launches, double *total
  * that the caller synchronizes before freeing the workspace. */
 dem_status dem_destroy(dem_ctx *ctx);
 
+/* ---- Batches: many independent beds advanced by the same launches ----
+ *
+ * A batch groups beds already created with dem_create (each with its own
+ * particles, box, materials, time step, mesh and fluid parameters) so that
+ * every DEM step and coupling step of all of them runs as one launch per
+ * kernel: each block of a batched kernel finds its bed and its block within
+ * the bed in a block map, and the bed's arrays and constants in device
+ * tables.  The arithmetic of a bed does not depend on the other beds of the
+ * batch.  Requirements: 1..4096 beds, all of the same precision; for
+ * coupling, all of the same velocity order and each with fewer than 2^20
+ * elements.  While a bed belongs to a batch it must be advanced only through
+ * the batch (dem_read_*, dem_poll and dem_kernel_timing stay valid; errors
+ * are reported per bed by dem_poll).  Destroying the batch leaves every bed
+ * usable on its own.  The same algorithm as dem_step / cfd_dem_couple
+ * (Sections 2.2 and 2.3) runs on every bed. */
+typedef struct dem_batch dem_batch;
+
+/* Device workspace of a batch of these beds (host function; 0 on invalid
+ * arguments).  beds: host array of n_beds contexts. */
+size_t dem_batch_workspace_bytes(int32_t n_beds, dem_ctx *const *beds);
+
+/* Build the batch.  The coupling buffers are host arrays of n_beds device
+ * pointers with the meaning and layout of cfd_dem_couple's arguments, bed by
+ * bed; u_nodes == NULL builds a batch without coupling (the other five
+ * arrays are then ignored), elem_sums may be NULL or hold NULL entries.
+ * The buffers stay registered for the batch's lifetime: dem_batch_couple
+ * reads the current contents of u_nodes/p_nodes and overwrites the outputs.
+ * workspace: >= dem_batch_workspace_bytes, 256-byte aligned, caller-owned.
+ * Synchronizes the stream (the tables are uploaded once).  *out (host)
+ * receives the batch. */
+dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *const *u_nodes,
+                            const double *const *p_nodes, double *const *eps_q,
+                            double *const *beta_q, double *const *fpf_q,
+                            double *const *elem_sums, void *workspace, size_t ws_bytes,
+                            void *stream, dem_batch **out);
+
+/* dem_step(bed, n_steps) for every bed of the batch, as one drift launch, one
+ * contact-force launch per step and one bookkeeping launch; beds whose
+ * re-sort is due are re-sorted first (per bed). */
+dem_status dem_batch_step(dem_batch *batch, int32_t n_steps, void *stream);
+
+/* cfd_dem_couple on every bed of the batch with its registered buffers: one
+ * classify launch over all beds' elements and one launch over the occupied
+ * elements of all beds. */
+dem_status dem_batch_couple(dem_batch *batch, void *stream);
+
+/* n_chunks times: [dem_batch_couple if couple != 0] then
+ * dem_batch_step(steps_per_chunk), with the same results.  The coupling step
+ * and the run of steps_per_chunk steps are each replayed from a HIP graph
+ * captured at their first use (the step graph again when steps_per_chunk
+ * changes); due re-sorts run between the two, outside the graphs. */
+dem_status dem_batch_run(dem_batch *batch, int32_t n_chunks, int32_t steps_per_chunk,
+                         int32_t couple, void *stream);
+
+/* Release the batch (host memory, its graph and capture stream); the beds
+ * and the workspace stay the caller's. */
+dem_status dem_batch_destroy(dem_batch *batch);
+
 /* Static description of a status code. */
 const char *dem_status_string(dem_status s);
 

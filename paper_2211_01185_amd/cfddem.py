@@ -31,7 +31,9 @@ FP32_FORCES = 1
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kernel_timing",
-           "dem_kernel_timing_read", "dem_destroy", "dem_status_string")
+           "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
+           "dem_batch_step", "dem_batch_couple", "dem_batch_run", "dem_batch_destroy",
+           "dem_status_string")
 
 
 class DemParams(C.Structure):
@@ -97,6 +99,18 @@ def load():
     lib.dem_kernel_timing_read.argtypes = [vp, C.POINTER(i64), C.POINTER(dbl), vp]
     lib.dem_destroy.restype = i32
     lib.dem_destroy.argtypes = [vp]
+    lib.dem_batch_workspace_bytes.restype = C.c_size_t
+    lib.dem_batch_workspace_bytes.argtypes = [i32, vp]
+    lib.dem_batch_create.restype = i32
+    lib.dem_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.dem_batch_step.restype = i32
+    lib.dem_batch_step.argtypes = [vp, i32, vp]
+    lib.dem_batch_couple.restype = i32
+    lib.dem_batch_couple.argtypes = [vp, vp]
+    lib.dem_batch_run.restype = i32
+    lib.dem_batch_run.argtypes = [vp, i32, i32, i32, vp]
+    lib.dem_batch_destroy.restype = i32
+    lib.dem_batch_destroy.argtypes = [vp]
     lib.dem_status_string.restype = C.c_char_p
     lib.dem_status_string.argtypes = [i32]
     _lib = lib
@@ -288,6 +302,86 @@ class Bed:
         _check(self._lib.dem_kernel_timing_read(self._h, C.byref(launches), C.byref(ms), self._st),
                "dem_kernel_timing_read")
         return int(launches.value), float(ms.value)
+
+
+class Batch:
+    """Beds advanced together by shared launches (dem_batch_*).
+
+    fields: None (no coupling) or one (U, P) pair of float64 device tensors per
+    bed; the coupling outputs are allocated here, one dict per bed, and
+    rewritten by every couple() / run(couple=True)."""
+
+    def __init__(self, beds, fields=None, elem_sums=False, stream=None):
+        import torch
+
+        self._torch = torch
+        lib = load()
+        self.beds = list(beds)
+        nb = len(self.beds)
+        self.stream = stream if stream is not None else self.beds[0].stream
+        self.device = self.beds[0].device
+        handles = (C.c_void_p * nb)(*[b._h.value for b in self.beds])
+        nbytes = int(lib.dem_batch_workspace_bytes(nb, handles))
+        if nbytes == 0:
+            raise CfddemError(DEM_E_ARG, "dem_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        ws = C.c_void_p(self.workspace.data_ptr() + off)
+        self.out = None
+        arrays = [None] * 6
+        if fields is not None:
+            if len(fields) != nb:
+                raise ValueError("one (U, P) pair per bed")
+            self.fields = [(U.contiguous(), P.contiguous()) for U, P in fields]
+            self.out = []
+            for bed in self.beds:
+                m = bed.n_elem * bed.nq
+                o = dict(eps_q=torch.empty(m, dtype=torch.float64, device=self.device),
+                         beta_q=torch.empty(m, dtype=torch.float64, device=self.device),
+                         fpf_q=torch.empty((3, m), dtype=torch.float64, device=self.device))
+                if elem_sums:
+                    o["elem_sums"] = torch.empty((12, bed.n_elem), dtype=torch.float64, device=self.device)
+                self.out.append(o)
+
+            def ptrs(ts):
+                return (C.c_void_p * nb)(*[t.data_ptr() if t is not None else None for t in ts])
+
+            arrays = [ptrs([f[0] for f in self.fields]), ptrs([f[1] for f in self.fields]),
+                      ptrs([o["eps_q"] for o in self.out]), ptrs([o["beta_q"] for o in self.out]),
+                      ptrs([o["fpf_q"] for o in self.out]),
+                      ptrs([o.get("elem_sums") for o in self.out]) if elem_sums else None]
+        self._h = C.c_void_p()
+        _check(lib.dem_batch_create(nb, handles, *arrays, ws, C.c_size_t(nbytes), self._st, C.byref(self._h)),
+               "dem_batch_create")
+        self._lib = lib
+
+    @property
+    def _st(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def step(self, n_steps: int = 1):
+        _check(self._lib.dem_batch_step(self._h, int(n_steps), self._st), "dem_batch_step")
+
+    def couple(self):
+        _check(self._lib.dem_batch_couple(self._h, self._st), "dem_batch_couple")
+        return self.out
+
+    def run(self, n_chunks: int, steps_per_chunk: int, couple: bool = True):
+        """n_chunks x [couple] + steps_per_chunk steps, replayed from one HIP graph."""
+        _check(self._lib.dem_batch_run(self._h, int(n_chunks), int(steps_per_chunk), 1 if couple else 0,
+                                       self._st), "dem_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.stream.synchronize()
+            self._lib.dem_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def bed_from_workload(wl, precision=None, device="cuda", **kw) -> Bed:

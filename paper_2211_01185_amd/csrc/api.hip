@@ -20,6 +20,18 @@ hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool adv
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,
                          double *esums, bool fp32, hipStream_t st);
+hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                  hipStream_t st);
+hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                   int i, bool cont, bool fp32, int maxn, hipStream_t st);
+hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
+hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
+                                hipStream_t st);
+hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
+                               const unsigned *map_class, int blocks_class, int *cnt_word,
+                               unsigned *list, long long total_elems, int order, bool fp32,
+                               hipStream_t st);
+int couple_class_elems_per_block();
 }  // namespace cfddem
 
 using namespace cfddem;
@@ -808,6 +820,312 @@ dem_status dem_destroy(dem_ctx *ctx) {
   if (!ctx) return DEM_E_ARG;
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
+  return DEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct dem_batch {
+  std::vector<dem_ctx *> beds;
+  bool fp32 = false;
+  bool couples = false;
+  int order = 2;
+  int maxn = 1;
+  // device tables and maps (carved from the caller's workspace)
+  Dev *tab = nullptr;
+  Cpl *ctab = nullptr;
+  CplIO *iot = nullptr;
+  BedRun *run = nullptr;
+  unsigned *map_drift = nullptr, *map_force = nullptr, *map_class = nullptr, *list = nullptr;
+  int *cnt = nullptr;
+  int nb_drift = 0, nb_force = 0, nb_class = 0;
+  long long total_elems = 0;
+  // graphs of a chunk: the coupling step, and g_steps DEM steps
+  hipStream_t cap = nullptr;
+  hipGraphExec_t g_cpl = nullptr;
+  hipGraphExec_t g_step = nullptr;
+  int g_steps = -1;
+};
+
+namespace {
+
+struct BatchLayout {
+  int nb_drift = 0, nb_force = 0, nb_class = 0;
+  long long total_elems = 0;
+};
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Validates the beds and counts the blocks of each batched launch.
+dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, BatchLayout &L) {
+  if (n_beds < 1 || n_beds > kMaxBeds || !beds) return DEM_E_ARG;
+  const long long max_blocks = 0x7fffffffLL;
+  long long d = 0, f = 0, c = 0, e = 0;
+  for (int b = 0; b < n_beds; ++b) {
+    const dem_ctx *x = beds[b];
+    if (!x) return DEM_E_ARG;
+    for (int j = 0; j < b; ++j)
+      if (beds[j] == x) return DEM_E_ARG;
+    if (x->fp32 != beds[0]->fp32) return DEM_E_UNSUPPORTED;
+    const long long n = x->S.n;
+    const int bd = ceil_div(n, 256), bf = ceil_div(n * kForceLanes, kForceBlock);
+    const int ne = x->S.grid.n_elem;
+    const int bc = ceil_div(ne, couple_class_elems_per_block());
+    if (bd > (int)kBlockMask || bf > (int)kBlockMask || bc > (int)kBlockMask) return DEM_E_UNSUPPORTED;
+    if (couples) {
+      if (x->cp.order != beds[0]->cp.order) return DEM_E_UNSUPPORTED;
+      if (ne > (int)kBlockMask) return DEM_E_UNSUPPORTED;
+    }
+    d += bd;
+    f += bf;
+    c += bc;
+    e += ne;
+  }
+  if (d > max_blocks || f > max_blocks || c > max_blocks) return DEM_E_UNSUPPORTED;
+  L.nb_drift = (int)d;
+  L.nb_force = (int)f;
+  L.nb_class = couples ? (int)c : 0;
+  L.total_elems = couples ? e : 0;
+  return DEM_OK;
+}
+
+size_t batch_carve(int32_t n_beds, const BatchLayout &L, char *base, dem_batch *B) {
+  Carver c{base};
+  Dev *tab = c.take<Dev>((size_t)n_beds);
+  Cpl *ctab = c.take<Cpl>((size_t)n_beds);
+  CplIO *iot = c.take<CplIO>((size_t)n_beds);
+  BedRun *run = c.take<BedRun>((size_t)n_beds);
+  unsigned *md = c.take<unsigned>((size_t)L.nb_drift);
+  unsigned *mf = c.take<unsigned>((size_t)L.nb_force);
+  unsigned *mc = c.take<unsigned>((size_t)(L.nb_class > 0 ? L.nb_class : 1));
+  unsigned *list = c.take<unsigned>((size_t)(L.total_elems > 0 ? L.total_elems : 1));
+  int *cnt = c.take<int>(64);
+  if (B) {
+    B->tab = tab;
+    B->ctab = ctab;
+    B->iot = iot;
+    B->run = run;
+    B->map_drift = md;
+    B->map_force = mf;
+    B->map_class = mc;
+    B->list = list;
+    B->cnt = cnt;
+  }
+  return c.off + kAlign;
+}
+
+void fill_map(std::vector<unsigned> &m, int bed, int blocks) {
+  for (int k = 0; k < blocks; ++k) m.push_back(((unsigned)bed << kBedShift) | (unsigned)k);
+}
+
+// Re-sorts the beds whose re-sort is due and refreshes their table entries.
+dem_status batch_resorts(dem_batch *B, hipStream_t st) {
+  for (size_t b = 0; b < B->beds.size(); ++b) {
+    dem_ctx *ctx = B->beds[b];
+    if (ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
+      dem_status r = resort(ctx, st);
+      if (r != DEM_OK) return r;
+      HIP_TRY(launch_batch_set_bed(B->tab, B->run, (int)b, ctx->B.D, ctx->s, ctx->pending_src, st));
+    }
+  }
+  return DEM_OK;
+}
+
+// Enqueues n steps of every bed (no re-sorts).
+dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
+  HIP_TRY(launch_drift_bin_batch(B->tab, B->run, B->map_drift, B->nb_drift, st));
+  for (int i = 1; i <= n; ++i)
+    HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force, i, i < n, B->fp32,
+                                    B->maxn, st));
+  HIP_TRY(launch_batch_advance(B->run, (int)B->beds.size(), n, st));
+  return DEM_OK;
+}
+
+dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
+  HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
+                              B->list, B->total_elems, B->order, B->fp32, st));
+  return DEM_OK;
+}
+
+void batch_mirror_steps(dem_batch *B, int n) {
+  for (dem_ctx *ctx : B->beds) {
+    ctx->s += n;
+    ctx->since_sort += n;
+    ctx->pending_src = nullptr;
+  }
+}
+
+dem_status batch_poisoned(const dem_batch *B) {
+  for (const dem_ctx *ctx : B->beds)
+    if (ctx->poisoned) return ctx->poisoned;
+  return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dem_batch_workspace_bytes(int32_t n_beds, dem_ctx *const *beds) {
+  // sized for coupling when the beds allow it, else for stepping only
+  BatchLayout L;
+  if (batch_layout(n_beds, beds, true, L) != DEM_OK && batch_layout(n_beds, beds, false, L) != DEM_OK)
+    return 0;
+  return batch_carve(n_beds, L, nullptr, nullptr);
+}
+
+dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *const *u_nodes,
+                            const double *const *p_nodes, double *const *eps_q,
+                            double *const *beta_q, double *const *fpf_q,
+                            double *const *elem_sums, void *workspace, size_t ws_bytes,
+                            void *stream, dem_batch **out) {
+  if (!out) return DEM_E_ARG;
+  *out = nullptr;
+  const bool couples = u_nodes != nullptr;
+  BatchLayout L;
+  dem_status r = batch_layout(n_beds, beds, couples, L);
+  if (r != DEM_OK) return r;
+  if (couples) {
+    if (!p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
+    for (int b = 0; b < n_beds; ++b)
+      if (!u_nodes[b] || !p_nodes[b] || !eps_q[b] || !beta_q[b] || !fpf_q[b]) return DEM_E_ARG;
+  }
+  for (int b = 0; b < n_beds; ++b)
+    if (beds[b]->poisoned) return beds[b]->poisoned;
+  const size_t need = batch_carve(n_beds, L, nullptr, nullptr);
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need) return DEM_E_WORKSPACE;
+  dem_batch *B = new (std::nothrow) dem_batch();
+  if (!B) return DEM_E_ARG;
+  batch_carve(n_beds, L, (char *)workspace, B);
+  B->beds.assign(beds, beds + n_beds);
+  B->fp32 = beds[0]->fp32;
+  B->couples = couples;
+  B->order = beds[0]->cp.order;
+  B->nb_drift = L.nb_drift;
+  B->nb_force = L.nb_force;
+  B->nb_class = L.nb_class;
+  B->total_elems = L.total_elems;
+  std::vector<Dev> tab;
+  std::vector<Cpl> ctab;
+  std::vector<CplIO> iot;
+  std::vector<BedRun> run;
+  std::vector<unsigned> md, mf, mc;
+  for (int b = 0; b < n_beds; ++b) {
+    const dem_ctx *ctx = beds[b];
+    tab.push_back(ctx->B.D);
+    ctab.push_back(ctx->C);
+    CplIO io{};
+    if (couples)
+      io = CplIO{u_nodes[b], p_nodes[b], eps_q[b], beta_q[b], fpf_q[b], elem_sums ? elem_sums[b] : nullptr};
+    iot.push_back(io);
+    run.push_back(BedRun{ctx->s, ctx->pending_src});
+    if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
+    fill_map(md, b, ceil_div(ctx->S.n, 256));
+    fill_map(mf, b, ceil_div((long long)ctx->S.n * kForceLanes, kForceBlock));
+    if (couples) fill_map(mc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto fail = [&](dem_status code) {
+    delete B;
+    return code;
+  };
+  bool ok = hipMemcpyAsync(B->tab, tab.data(), sizeof(Dev) * tab.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(B->ctab, ctab.data(), sizeof(Cpl) * ctab.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(B->iot, iot.data(), sizeof(CplIO) * iot.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(B->run, run.data(), sizeof(BedRun) * run.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(B->map_drift, md.data(), sizeof(unsigned) * md.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(B->map_force, mf.data(), sizeof(unsigned) * mf.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+            (mc.empty() || hipMemcpyAsync(B->map_class, mc.data(), sizeof(unsigned) * mc.size(), hipMemcpyHostToDevice, st) == hipSuccess) &&
+            hipMemsetAsync(B->cnt, 0, sizeof(int) * 64, st) == hipSuccess &&
+            hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) return fail(DEM_E_HIP);
+  if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) return fail(DEM_E_HIP);
+  *out = B;
+  return DEM_OK;
+}
+
+dem_status dem_batch_step(dem_batch *B, int32_t n_steps, void *stream) {
+  if (!B || n_steps < 0) return DEM_E_ARG;
+  dem_status r = batch_poisoned(B);
+  if (r != DEM_OK) return r;
+  if (n_steps == 0) return DEM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  r = batch_resorts(B, st);
+  if (r != DEM_OK) return r;
+  r = batch_enqueue_steps(B, n_steps, st);
+  if (r != DEM_OK) return r;
+  batch_mirror_steps(B, n_steps);
+  return DEM_OK;
+}
+
+dem_status dem_batch_couple(dem_batch *B, void *stream) {
+  if (!B) return DEM_E_ARG;
+  if (!B->couples) return DEM_E_ARG;
+  dem_status r = batch_poisoned(B);
+  if (r != DEM_OK) return r;
+  return batch_enqueue_couple(B, (hipStream_t)stream);
+}
+
+dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk, int32_t couple,
+                         void *stream) {
+  if (!B || n_chunks < 0 || steps_per_chunk < 0 || (couple && !B->couples)) return DEM_E_ARG;
+  dem_status r = batch_poisoned(B);
+  if (r != DEM_OK) return r;
+  if (n_chunks == 0 || (steps_per_chunk == 0 && !couple)) return DEM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // capture what this call needs and is not captured yet
+  auto capture = [&](bool cpl, int steps, hipGraphExec_t *exec) -> dem_status {
+    HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    const dem_status cr = cpl ? batch_enqueue_couple(B, B->cap) : batch_enqueue_steps(B, steps, B->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(B->cap, &g);
+    if (cr != DEM_OK || ec != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return cr != DEM_OK ? cr : DEM_E_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      *exec = nullptr;
+      return DEM_E_HIP;
+    }
+    return DEM_OK;
+  };
+  if (couple && !B->g_cpl) {
+    r = capture(true, 0, &B->g_cpl);
+    if (r != DEM_OK) return r;
+  }
+  if (steps_per_chunk > 0 && (!B->g_step || B->g_steps != steps_per_chunk)) {
+    if (B->g_step) {
+      HIP_TRY(hipGraphExecDestroy(B->g_step));
+      B->g_step = nullptr;
+    }
+    r = capture(false, steps_per_chunk, &B->g_step);
+    if (r != DEM_OK) return r;
+    B->g_steps = steps_per_chunk;
+  }
+  // per chunk, the order of dem_batch_couple + dem_batch_step: couple, due
+  // re-sorts, steps
+  for (int c = 0; c < n_chunks; ++c) {
+    if (couple) HIP_TRY(hipGraphLaunch(B->g_cpl, st));
+    if (steps_per_chunk > 0) {
+      r = batch_resorts(B, st);
+      if (r != DEM_OK) return r;
+      HIP_TRY(hipGraphLaunch(B->g_step, st));
+      batch_mirror_steps(B, steps_per_chunk);
+    }
+  }
+  return DEM_OK;
+}
+
+dem_status dem_batch_destroy(dem_batch *B) {
+  if (!B) return DEM_E_ARG;
+  if (B->g_cpl) (void)hipGraphExecDestroy(B->g_cpl);
+  if (B->g_step) (void)hipGraphExecDestroy(B->g_step);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  delete B;
   return DEM_OK;
 }
 

@@ -235,7 +235,7 @@ struct CplShared {
 // chain of memory round trips: counts, slot entries and nodal values are
 // loaded together, then the particles' state, then the outputs are stored.
 template <typename R, int ORD>
-__device__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
+__device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
                                const double *__restrict__ P, double *__restrict__ eps_q,
                                double *__restrict__ beta_q, double *__restrict__ fpf_q,
                                double *__restrict__ esums, int p2, int p3, CplShared &sh) {
@@ -434,19 +434,17 @@ __device__ void couple_element(const Dev &D, const Cpl &C, int e, const double *
   __syncthreads();  // the block's LDS is reused for its next element
 }
 
-// Occupied-element counts live in two words selected by the parity of the
-// coupling call: call k appends to word k&1 and clears word (k+1)&1 for the
-// next call, which nothing reads during call k.
-__global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int p3, int parity,
-                                                               double *__restrict__ eps_q,
-                                                               double *__restrict__ beta_q,
-                                                               double *__restrict__ fpf_q,
-                                                               double *__restrict__ esums) {
+// Classification of kClassElems consecutive elements starting at e0 by one
+// wavefront: empty ones get their outputs, occupied ones are appended to
+// list (entries tag | element) through the counter at cnt_word.
+__device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C, int e0, int p3,
+                                                     int *cnt_word, unsigned *list, unsigned tag,
+                                                     double *__restrict__ eps_q,
+                                                     double *__restrict__ beta_q,
+                                                     double *__restrict__ fpf_q,
+                                                     double *__restrict__ esums) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int gw = (blockIdx.x * kClassBlock + threadIdx.x) / kWave;
   const Grid &G = D.grid;
-  if (gw == 0 && lane == 0) D.err[kOccWord + (parity ^ 1)] = 0;
-  const int e0 = gw * kClassElems;
   if (e0 >= G.n_elem) return;  // whole wavefront
   const int ne = G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems;
   const int *cnt = D.cnt[p3];
@@ -478,11 +476,25 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
     for (int k = 0; k < 12; ++k) esums[(long)k * G.n_elem + e0 + lane] = 0.0;
   if (occupied) {
     int base = 0;
-    if (lane == 0) base = atomicAdd(D.err + kOccWord + parity, __popc(occupied));
+    if (lane == 0) base = atomicAdd(cnt_word, __popc(occupied));
     base = __shfl(base, 0, kWave);
     if (lane < ne && ((occupied >> lane) & 1u))
-      D.occ[base + __popc(occupied & ((1u << lane) - 1u))] = e0 + lane;
+      list[base + __popc(occupied & ((1u << lane) - 1u))] = tag | (unsigned)(e0 + lane);
   }
+}
+
+// Single bed.  Occupied-element counts live in two words selected by the
+// parity of the coupling call: call k appends to word k&1 and clears word
+// (k+1)&1 for the next call, which nothing reads during call k.
+__global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int p3, int parity,
+                                                               double *__restrict__ eps_q,
+                                                               double *__restrict__ beta_q,
+                                                               double *__restrict__ fpf_q,
+                                                               double *__restrict__ esums) {
+  const int gw = (blockIdx.x * kClassBlock + threadIdx.x) / kWave;
+  if (gw == 0 && threadIdx.x == 0) D.err[kOccWord + (parity ^ 1)] = 0;
+  couple_classify_body(D, C, gw * kClassElems, p3, D.err + kOccWord + parity, (unsigned *)D.occ, 0u,
+                       eps_q, beta_q, fpf_q, esums);
 }
 
 // One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
@@ -511,6 +523,85 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
   for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
     couple_element<R, ORD>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
 }
+
+// ---------------------------------------------------------------------------
+// batched coupling: every bed of a batch, one occupied-element list
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
+    const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
+    const BedRun *__restrict__ run, const unsigned *__restrict__ map, int *cnt_word, unsigned *list) {
+  const unsigned mb = map[blockIdx.x];
+  const int b = (int)(mb >> kBedShift), blk = (int)(mb & kBlockMask);
+  const Dev &D = tab[b];
+  const Cpl &C = ctab[b];
+  const CplIO &io = iot[b];
+  const int p3 = (int)(run[b].s % 3);
+  const int gw = blk * (kClassBlock / kWave) + (int)(threadIdx.x / kWave);
+  couple_classify_body(D, C, gw * kClassElems, p3, cnt_word, list, (unsigned)b << kBedShift,
+                       io.eps_q, io.beta_q, io.fpf_q, io.esums);
+}
+
+template <typename R, int ORD>
+__device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const Cpl *__restrict__ ctab,
+                                              const CplIO *__restrict__ iot,
+                                              const BedRun *__restrict__ run, unsigned ent,
+                                              CplShared &sh) {
+  const int b = (int)(ent >> kBedShift), e = (int)(ent & kBlockMask);
+  const Dev &D = tab[b];
+  const Cpl &C = ctab[b];
+  const CplIO &io = iot[b];
+  const long long s = run[b].s;
+  const int tid = threadIdx.x;
+  if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
+  couple_element<R, ORD>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
+                         (int)(s % 3), sh);
+}
+
+template <typename R, int ORD>
+__global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
+    const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
+    const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list) {
+  __shared__ CplShared sh;
+  const int nocc = *cnt_word;
+  unsigned ent = list[blockIdx.x];
+  __asm__ volatile("" ::: "memory");
+  // one call site (the element computation is inlined once); the first entry
+  // is read in the same round trip as the list length
+  for (int i = blockIdx.x; i < nocc; i += gridDim.x) {
+    if (i != (int)blockIdx.x) ent = list[i];
+    couple_listed<R, ORD>(tab, ctab, iot, run, ent, sh);
+  }
+}
+
+__global__ void reset_count(int *cnt_word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_word = 0;
+}
+
+// Every bed of a batch (all of velocity order `order`).  The list has room
+// for total_elems entries (at least one); the counter is zero on entry and
+// on return.
+hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
+                               const unsigned *map_class, int blocks_class, int *cnt_word,
+                               unsigned *list, long long total_elems, int order, bool fp32,
+                               hipStream_t st) {
+  if (blocks_class <= 0) return hipGetLastError();
+  couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_word,
+                                                              list);
+  const dim3 g(total_elems < kMaxCoupleBlocks ? (int)total_elems : kMaxCoupleBlocks), b(kCplThreads);
+  if (fp32 && order == 2)
+    couple_occupied_batch<float, 2><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
+  else if (fp32)
+    couple_occupied_batch<float, 1><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
+  else if (order == 2)
+    couple_occupied_batch<double, 2><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
+  else
+    couple_occupied_batch<double, 1><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
+  reset_count<<<1, 64, 0, st>>>(cnt_word);
+  return hipGetLastError();
+}
+
+// Elements of one bed covered by one block of the classify pass.
+int couple_class_elems_per_block() { return kClassElems * (kClassBlock / kWave); }
 
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,

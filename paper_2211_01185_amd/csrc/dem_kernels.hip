@@ -13,10 +13,15 @@
 //                 limit, per-particle gather of force and torque (no float
 //                 atomics), second half kick; when another step follows, also
 //                 its half kick, drift, binning and displacement test
-// One thread per particle over SoA FP64 arrays.  A pair is evaluated by both
-// of its particles in the canonical orientation (lower original ID first), so
-// both sides compute bit-identical forces and tangential overlaps and each
-// keeps its own copy of the history in its own list slot.
+// Two lanes per particle over SoA FP64 arrays.  A pair is evaluated by both of
+// its particles, each from its own side; every quantity one side computes is
+// the exact negation of, or identical to, the other side's, so the forces are
+// exactly opposite and each particle keeps its own copy of the tangential
+// history in its own list slot.
+//
+// Each kernel body takes the bed's Dev and the block index explicitly: the
+// single-bed kernels pass their argument and blockIdx.x, the batched kernels
+// (many independent beds in one launch) look both up in device tables.
 #include <hip/hip_ext.h>
 
 #include "device.h"
@@ -50,8 +55,7 @@ __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], int
 // p2 = s & 1, p3 = s % 3 of the step being opened.  DRIFT = false bins the
 // positions already in xs[p2] (creation).
 template <bool DRIFT>
-__global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int force_flag) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int p3, int force_flag) {
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
@@ -83,6 +87,11 @@ __global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int forc
   int bits = 0;
   bin_and_test(D, k, xp, D.cnt[p3], D.slot[p2], D.cell[p3], D.flag + p3, force_flag != 0, bits);
   if (bits) atomicOr(D.err, bits);
+}
+
+template <bool DRIFT>
+__global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int force_flag) {
+  drift_bin_body<DRIFT>(D, blockIdx.x * 256 + threadIdx.x, p2, p3, force_flag);
 }
 
 // Clear the counts of grid p3 at the cells its particles were binned into.
@@ -192,8 +201,8 @@ __device__ inline unsigned long long group_or(unsigned long long v) {
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L>
-__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
-  const int gid = blockIdx.x * kForceBlock + threadIdx.x;
+__device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src) {
+  const int gid = blk * kForceBlock + threadIdx.x;
   const int a = gid / L;
   const int lane = gid % L;
   if (a >= D.n) return;  // whole groups leave together
@@ -455,9 +464,103 @@ __global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int 
   if (bits) atomicOr(D.err, bits);
 }
 
+template <typename R, bool ADVANCE, bool CONT, int L>
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
+  force_kick_body<R, ADVANCE, CONT, L>(D, blockIdx.x, p2, p3, src);
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels: one launch over every bed of a batch
+// ---------------------------------------------------------------------------
+__device__ inline void bed_of_block(const unsigned *__restrict__ map, int &bed, int &blk) {
+  const unsigned m = map[blockIdx.x];
+  bed = (int)(m >> kBedShift);
+  blk = (int)(m & kBlockMask);
+}
+
+// Opens step run.s + 1 of every bed.
+__global__ __launch_bounds__(256) void drift_bin_batch(const Dev *__restrict__ tab,
+                                                       const BedRun *__restrict__ run,
+                                                       const unsigned *__restrict__ map) {
+  int b, blk;
+  bed_of_block(map, b, blk);
+  const Dev &D = tab[b];
+  const long long s = run[b].s + 1;
+  drift_bin_body<true>(D, blk * 256 + threadIdx.x, (int)(s & 1), (int)(s % 3),
+                       run[b].src != nullptr);
+}
+
+// Step run.s + i of every bed (i = 1 applies the bed's pending permutation).
+template <typename R, bool CONT, int L>
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__restrict__ tab,
+                                                                   const BedRun *__restrict__ run,
+                                                                   const unsigned *__restrict__ map,
+                                                                   int i) {
+  int b, blk;
+  bed_of_block(map, b, blk);
+  const Dev &D = tab[b];
+  const long long s = run[b].s + i;
+  force_kick_body<R, true, CONT, L>(D, blk, (int)(s & 1), (int)(s % 3),
+                                    i == 1 ? run[b].src : nullptr);
+}
+
+// After a run of n steps: every bed's step index advances, pending
+// permutations have been applied.
+__global__ void batch_advance(BedRun *run, int nb, int n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  run[b].s += n;
+  run[b].src = nullptr;
+}
+
+// Writes one bed's table entries (stream-ordered, so that a re-sort's new
+// arrays take effect exactly at the next batched launch).
+__global__ void batch_set_bed(Dev *tab, BedRun *run, int b, Dev D, long long s, const int *src) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  tab[b] = D;
+  run[b].s = s;
+  run[b].src = src;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                  hipStream_t st) {
+  if (blocks > 0) drift_bin_batch<<<blocks, 256, 0, st>>>(tab, run, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                   int i, bool cont, bool fp32, int maxn, hipStream_t st) {
+  constexpr int L = kForceLanes;
+  const size_t lds = sizeof(unsigned long long) * (size_t)maxn * (kForceBlock / L);
+  if (blocks <= 0) return hipGetLastError();
+  if (fp32) {
+    if (cont)
+      force_kick_batch<float, true, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+    else
+      force_kick_batch<float, false, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+  } else {
+    if (cont)
+      force_kick_batch<double, true, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+    else
+      force_kick_batch<double, false, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st) {
+  batch_advance<<<(nb + 255) / 256, 256, 0, st>>>(run, nb, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
+                                hipStream_t st) {
+  batch_set_bed<<<1, 64, 0, st>>>(tab, run, b, D, s, src);
+  return hipGetLastError();
+}
+
 hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st) {
   const int grid = (D.n + 255) / 256;
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);

@@ -79,6 +79,26 @@ struct Dev {
   int *err;              // sticky error bits
 };
 
+// Batched launches: many independent beds in one launch.  Each block of a
+// batched kernel looks up (bed << kBedShift) | block-of-the-bed in a block
+// map, and the bed's Dev, Cpl, run state and coupling buffers in device
+// tables indexed by bed.
+constexpr int kBedShift = 20;
+constexpr unsigned kBlockMask = (1u << kBedShift) - 1u;
+constexpr int kMaxBeds = 4096;
+
+// Run state of one bed of a batch, advanced on the device.
+struct BedRun {
+  long long s;     // index of the last completed step
+  const int *src;  // after a re-sort: index each particle had when its list was built
+};
+
+// Coupling buffers of one bed of a batch.
+struct CplIO {
+  const double *U, *P;
+  double *eps_q, *beta_q, *fpf_q, *esums;
+};
+
 // Coupling constants.
 struct Cpl {
   int order;        // 1 or 2

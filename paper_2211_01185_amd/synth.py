@@ -19,6 +19,10 @@ available):
                   peak 20 m/s and width 0.01 m decaying as exp(-z/0.2).
   * ``lattice``   the plain geometry on a simple-cubic lattice of spacing
                   0.98 d: every neighbour overlaps (contact-heavy parity case).
+  * ``batched``   64 independent column beds of 5k-80k spheres with their own
+                  diameter, restitution and inlet velocity and their own Q1 mesh.
+  * ``job_stream`` Poisson arrivals of sedimentation / fluidization column beds
+                  of 1k-200k spheres (the served workload).
 """
 from __future__ import annotations
 
@@ -271,6 +275,90 @@ def spouted(n=500_000, seed_index=0, box=(0.15, 0.15, 0.6), fill_height=0.45, n_
     dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
     return Workload("spouted", x, v, np.zeros((3, n)), radius, np.full(n, 2500.0), dem, fluid,
                     dict(steps=500, coupling_every=10, precision="fp32"), U, P)
+
+
+def column_bed(rng, n, d, e, u_in, name="column", precision="fp32", steps=1000, rho=2500.0) -> Workload:
+    """A bed of the batched and served workloads: n spheres of diameter d in a
+    square column of width W = (n V_p / (0.4 * 2))^(1/3) (a packed height of
+    2 W at solid fraction 0.4) and height 4 W, packed as the fluidized bed
+    (jittered simple-cubic lattice); restitution e for particle-particle and
+    particle-wall contacts; Q1 mesh of h = W / round(W / (4 d)).  u_in > 0:
+    fluidization, U = (0, 0, u_in) + N(0, 0.05) per node and the linear
+    pressure carrying the bed's buoyant weight (Eq. "dpf"); u_in == 0:
+    sedimentation in still fluid (U = 0, P = 0)."""
+    vp = math.pi / 6.0 * d ** 3
+    W = (n * vp / 0.8) ** (1.0 / 3.0)
+    lo, hi = [0.0, 0.0, 0.0], [W, W, 4.0 * W]
+    x = jittered_lattice(rng, n, d, lo, hi, 0.4)
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    m = max(1, int(round(W / (4.0 * d))))
+    n_el = [m, m, 4 * m]
+    fluid = dict(order=1, n_el=n_el, rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, n_el, 1)
+    if u_in > 0.0:
+        U = rng.normal(0.0, 0.05, size=(3, nodes.shape[1]))
+        U[2] += u_in
+        dp = n * vp * (rho - fluid["rho_f"]) * G / (W * W)
+        P = dp * (1.0 - nodes[2] / hi[2])
+    else:
+        U = np.zeros((3, nodes.shape[1]))
+        P = np.zeros(nodes.shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material(e=e))
+    return Workload(name, x, v, np.zeros((3, n)), np.full(n, 0.5 * d), np.full(n, rho), dem, fluid,
+                    dict(steps=steps, coupling_every=10, precision=precision), U, P)
+
+
+def batched_bed(index: int) -> Workload:
+    """Bed `index` of the batched ensemble: n ~ U{5k..80k}, d ~ U[1, 3] mm,
+    e ~ U[0.7, 0.95], inlet velocity ~ U[0.5, 2] m/s, 1,000 steps."""
+    rng = rng_for(4, index)
+    n = int(rng.integers(5_000, 80_001))
+    d = float(rng.uniform(1e-3, 3e-3))
+    e = float(rng.uniform(0.7, 0.95))
+    u_in = float(rng.uniform(0.5, 2.0))
+    return column_bed(rng, n, d, e, u_in, name=f"batched{index}")
+
+
+def batched(n_beds: int = 64):
+    """The batched ensemble: n_beds independent beds (see batched_bed)."""
+    return [batched_bed(b) for b in range(n_beds)]
+
+
+@dataclass
+class Job:
+    index: int
+    arrival: float   # s after the start of the stream
+    kind: str        # "sedimentation" | "fluidization"
+    n: int
+    steps: int       # a multiple of the coupling period (10 DEM steps)
+
+    def workload(self) -> Workload:
+        rng = rng_for(5, self.index)
+        rng.random(3)  # the draws that fixed kind, n and steps
+        d = float(rng.uniform(1e-3, 3e-3))
+        e = float(rng.uniform(0.7, 0.95))
+        u_in = float(rng.uniform(0.5, 2.0)) if self.kind == "fluidization" else 0.0
+        return column_bed(rng, self.n, d, e, u_in, name=f"job{self.index}", steps=self.steps)
+
+
+def job_stream(n_jobs: int, rate: float = 20.0, n_min: int = 1_000, n_max: int = 200_000):
+    """The served stream: Poisson arrivals at `rate` jobs/s; each job is a
+    sedimentation or fluidization bed (50/50) of n log-uniform in
+    [n_min, n_max] spheres run for U{200..2000} steps rounded up to whole
+    coupling periods.  Geometry and parameters are drawn per job as in the
+    batched ensemble."""
+    arr = rng_for(5, 100_000)
+    t = np.cumsum(arr.exponential(1.0 / rate, size=n_jobs))
+    jobs = []
+    for j in range(n_jobs):
+        rng = rng_for(5, j)
+        u = rng.random(3)
+        kind = "sedimentation" if u[0] < 0.5 else "fluidization"
+        n = int(round(math.exp(math.log(n_min) + u[1] * (math.log(n_max) - math.log(n_min)))))
+        steps = 200 + int(u[2] * 1801)
+        steps = 10 * ((steps + 9) // 10)
+        jobs.append(Job(j, float(t[j]), kind, n, steps))
+    return jobs
 
 
 WORKLOADS = {"plain": plain, "lattice": lattice, "fluidized": fluidized, "spouted": spouted}

@@ -1,0 +1,158 @@
+"""Batches (dem_batch_*): many beds advanced by shared launches.
+
+* Each bed of a mixed batch against its own FP64 oracle (contact sets bit
+  for bit, states and coupling outputs within the stated tolerances), with
+  re-sorts due at different steps on different beds.
+* A bed's result alone (a batch of one) equals its result in a mixed batch
+  bit for bit: a bed's arithmetic does not depend on the other beds.
+* The graph-replayed chunks (dem_batch_run) equal the same launches issued
+  one by one, bit for bit.
+* A batch of one agrees with the single-bed entry points."""
+import numpy as np
+import pytest
+
+from paper_2211_01185_amd import cfddem, synth
+from tests.parity_util import TOL, assert_close, compare_contacts, compare_states, gpu_state, oracle_bed
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fields(wl):
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device="cuda").contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device="cuda").contiguous()
+    return U, P
+
+
+def _q1_beds():
+    """Three column beds of different sizes, diameters, restitutions and
+    meshes (Q1); the second one is sedimentation (U = 0, P = 0)."""
+    out = []
+    for j, (n, d, e, u) in enumerate([(3000, 2.0e-3, 0.9, 1.0), (1700, 1.3e-3, 0.75, 0.0),
+                                      (5200, 2.6e-3, 0.85, 1.6)]):
+        out.append(synth.column_bed(synth.rng_for(4, 500 + j), n, d, e, u, name=f"t{j}", precision="fp64"))
+    return out
+
+
+def _q2_beds():
+    """Contact-heavy lattices (every neighbour overlaps) with their own
+    restitution and friction (Q2 meshes)."""
+    a = synth.lattice(n_side=(8, 8, 9), seed_index=7)
+    b = synth.lattice(n_side=(7, 9, 11), seed_index=8)
+    b.dem.update(e=0.7, e_w=0.7, mu=0.5, mu_w=0.5)
+    c = synth.lattice(n_side=(10, 6, 5), seed_index=9)
+    c.dem.update(e=0.95, e_w=0.95)
+    return [a, b, c]
+
+
+def _make(wls, precision, resort=(0, 0, 0)):
+    beds = [cfddem.bed_from_workload(w, precision=precision, resort_every=r) for w, r in zip(wls, resort)]
+    fields = [_fields(w) for w in wls]
+    return beds, fields
+
+
+def _snapshot(bed):
+    st = gpu_state(bed)
+    i, j, dt = bed.read_contacts()
+    st["pairs_i"], st["pairs_j"], st["dt"] = i, j, dt
+    return st
+
+
+def _same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed_batch_matches_oracle(precision):
+    wls = _q2_beds()
+    beds, fields = _make(wls, precision, resort=(0, 3, 7))
+    batch = cfddem.Batch(beds, fields, elem_sums=True)
+    refs = [oracle_bed(w) for w in wls]
+    tol = TOL[precision]
+    for _ in range(2):
+        outs = batch.couple()
+        for w, (ob, fl), o in zip(wls, refs, outs):
+            ref = ob.couple(fl, w.U, w.P)
+            assert np.array_equal(o["elem_sums"][0].cpu().numpy(), ref["elem_sums"][0])
+            assert_close("eps_q", o["eps_q"].cpu().numpy(), ref["eps_q"], 1e-12)
+            assert_close("beta_q", o["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+            assert_close("fpf_q", o["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+            assert_close("elem_sums", o["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+        batch.step(10)
+        for ob, _ in refs:
+            ob.step(10)
+        for bed, (ob, _) in zip(beds, refs):
+            compare_contacts(bed, ob, 10 * tol)
+            compare_states(bed, ob, 10 * tol)
+    for bed in beds:
+        err, _ = bed.poll()
+        assert err == 0
+    batch.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_alone_equals_mixed(precision):
+    wls = _q1_beds()
+    beds, fields = _make(wls, precision, resort=(5, 0, 20))
+    mixed = cfddem.Batch(beds, fields)
+    mixed.run(3, 10, couple=True)
+    mixed_out = [{k: v.cpu().numpy() for k, v in o.items()} for o in mixed.couple()]
+    mixed_state = [_snapshot(b) for b in beds]
+    mixed.close()
+    for j, w in enumerate(wls):
+        bed, fld = _make([w], precision, resort=((5, 0, 20)[j],))
+        alone = cfddem.Batch(bed, fld)
+        alone.run(3, 10, couple=True)
+        out = {k: v.cpu().numpy() for k, v in alone.couple()[0].items()}
+        _same(out, mixed_out[j])
+        _same(_snapshot(bed[0]), mixed_state[j])
+        alone.close()
+
+
+def test_graph_replay_equals_launches():
+    wls = _q1_beds()
+    beds_a, fields_a = _make(wls, "fp32", resort=(4, 4, 4))
+    beds_b, fields_b = _make(wls, "fp32", resort=(4, 4, 4))
+    a = cfddem.Batch(beds_a, fields_a)
+    b = cfddem.Batch(beds_b, fields_b)
+    a.run(4, 5, couple=True)
+    for _ in range(4):
+        b.couple()
+        b.step(5)
+    # a second graph (other chunk length), then direct launches again
+    a.run(2, 3, couple=False)
+    b.step(3)
+    b.step(3)
+    for x, y in zip(beds_a, beds_b):
+        _same(_snapshot(x), _snapshot(y))
+    a.close()
+    b.close()
+
+
+def test_batch_of_one_agrees_with_single_bed_path():
+    w = _q2_beds()[1]
+    (single,), (fld,) = _make([w], "fp64", resort=(3,))
+    single.couple(*fld)
+    single.step(10)
+    (bed,), fields = _make([w], "fp64", resort=(3,))
+    batch = cfddem.Batch([bed], fields)
+    batch.couple()
+    batch.step(10)
+    i0, j0, _ = single.read_contacts()
+    i1, j1, _ = bed.read_contacts()
+    assert np.array_equal(i0, i1) and np.array_equal(j0, j1)
+    g0, g1 = gpu_state(single), gpu_state(bed)
+    for k in g0:
+        assert_close(k, g1[k], g0[k], TOL["fp64"])
+    batch.close()
+
+
+def test_batch_rejects_mixed_precision():
+    wls = _q1_beds()[:2]
+    beds = [cfddem.bed_from_workload(wls[0], precision="fp64"),
+            cfddem.bed_from_workload(wls[1], precision="fp32")]
+    with pytest.raises(cfddem.CfddemError) as ei:
+        cfddem.Batch(beds)
+    assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)
