@@ -117,13 +117,15 @@ def batched_ensemble(n_beds, steps, dev):
     another) over a tenth of the steps."""
     import torch
 
-    from paper_2211_01185_amd import cfddem, synth
+    from paper_2211_01185_amd import autotune, cfddem, synth
 
     wls = synth.batched(n_beds)
     n_total = sum(w.n for w in wls)
     fields = [(torch.as_tensor(w.U, dtype=torch.float64, device=dev).contiguous(),
                torch.as_tensor(w.P, dtype=torch.float64, device=dev).contiguous()) for w in wls]
-    beds = [cfddem.bed_from_workload(w, precision="fp32", device=dev, resort_every=RESORT_EVERY) for w in wls]
+    cfg, tune_report = autotune.tune(wls, "fp32", device=dev, use_cache=False)
+    beds = [cfddem.bed_from_workload(w, precision="fp32", device=dev, **autotune.bed_kwargs(w, cfg))
+            for w in wls]
     batch = cfddem.Batch(beds, fields)
     chunks = steps // COUPLING_EVERY
     batch.run(2, COUPLING_EVERY, couple=True)  # warm-up, graph capture
@@ -161,7 +163,7 @@ def batched_ensemble(n_beds, steps, dev):
         "jobs_per_s": n_beds / (dt * steps / (chunks * COUPLING_EVERY)),
         "ms_per_step": dt * 1e3 / (chunks * COUPLING_EVERY),
         "dtype": "f32 forces / f64 state", "launch": "shared launches per step, one HIP graph per chunk",
-        "contacts_end": int(contacts), "errors": int(errors),
+        "contacts_end": int(contacts), "errors": int(errors), "autotune": tune_report,
         "per_bed_fp64_path": {"value": n_total * plain_steps / t_plain, "unit": "particle-steps/s",
                               "steps": plain_steps, "dtype": "f64",
                               "launch": "single-bed entry points, one bed after another"},

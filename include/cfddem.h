@@ -85,7 +85,11 @@ typedef struct {
   int32_t cell_capacity; /* particles per DEM cell, 1..1024; 0 = derived from sizes */
   int32_t resort_every;  /* DEM steps between re-sorts of the particle arrays by
                             cell; 0 = never (order of creation) */
-  int32_t reserved;      /* must be 0 */
+  int32_t lanes;         /* lanes of a wavefront sharing one particle in the
+                            contact-force kernel (each walks every lanes-th
+                            list entry): 1, 2 or 4; 0 = 2.  A tuning choice:
+                            contact sets do not depend on it, force sums only
+                            in their rounding */
   double d_max;          /* largest particle diameter (sizes the DEM cells:
                             cells are at least this wide) */
   double d_min;          /* smallest particle diameter (sizes cell_capacity);

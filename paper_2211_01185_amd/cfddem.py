@@ -44,7 +44,7 @@ class DemParams(C.Structure):
         ("E", C.c_double), ("nu", C.c_double), ("e", C.c_double), ("mu", C.c_double),
         ("E_w", C.c_double), ("nu_w", C.c_double), ("e_w", C.c_double), ("mu_w", C.c_double),
         ("max_neighbors", C.c_int32), ("cell_capacity", C.c_int32), ("resort_every", C.c_int32),
-        ("reserved", C.c_int32), ("d_max", C.c_double), ("d_min", C.c_double), ("skin", C.c_double),
+        ("lanes", C.c_int32), ("d_max", C.c_double), ("d_min", C.c_double), ("skin", C.c_double),
     ]
 
 
@@ -127,7 +127,7 @@ def _check(status: int, where: str):
 
 
 def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, precision="fp64",
-                max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0):
+                max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0):
     """Fill the two C parameter structs from plain dicts (see synth.Workload)."""
     dp = DemParams()
     dp.abi_version = ABI_VERSION
@@ -143,7 +143,7 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     dp.max_neighbors = int(max_neighbors)
     dp.cell_capacity = int(cell_capacity)
     dp.resort_every = int(resort_every)
-    dp.reserved = 0
+    dp.lanes = int(lanes)
     dp.d_max = float(d_max)
     dp.d_min = float(d_min)
     dp.skin = float(skin)
@@ -170,7 +170,8 @@ class Bed:
     """One bed on the GPU: a dem_ctx plus the torch-owned workspace."""
 
     def __init__(self, dem: dict, fluid: dict, x, v, w, radius, density, precision="fp64",
-                 max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, device="cuda", stream=None):
+                 max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0, device="cuda",
+                 stream=None):
         import torch
 
         self._torch = torch
@@ -190,7 +191,7 @@ class Bed:
             raise ValueError("radius and density must be (n,)")
         rr = r.detach().cpu().numpy()
         self.dp, self.cp = make_params(dem, fluid, self.n, 2.0 * float(rr.max()), 2.0 * float(rr.min()),
-                                       precision, max_neighbors, cell_capacity, resort_every, skin)
+                                       precision, max_neighbors, cell_capacity, resort_every, skin, lanes)
         nbytes = workspace_bytes(self.dp, self.cp)
         if nbytes == 0:
             raise CfddemError(DEM_E_ARG, "dem_workspace_bytes")

@@ -16,14 +16,14 @@ namespace cfddem {
 hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st);
 hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st);
 hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
-                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+                             bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,
                          double *esums, bool fp32, hipStream_t st);
 hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
                                   hipStream_t st);
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, hipStream_t st);
+                                   int i, bool cont, bool fp32, int maxn, int lanes, hipStream_t st);
 hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
 hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
                                 hipStream_t st);
@@ -49,6 +49,7 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 // ---------------------------------------------------------------------------
 struct Sizes {
   int n, maxn, cap;
+  int lanes;  // lanes per particle in the contact-force kernel
   double skin;
   Grid grid;
   int scan_blocks;  // blocks of the device scan over max(ncells, n) items
@@ -70,7 +71,9 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (dp->max_neighbors < 0 || dp->max_neighbors > kMaxNeighbors) return DEM_E_ARG;
   if (!(dp->skin >= 0.0) || !isfinite(dp->skin)) return DEM_E_ARG;
   if (dp->cell_capacity < 0 || dp->cell_capacity > 1024) return DEM_E_ARG;
-  if (dp->resort_every < 0 || dp->reserved != 0) return DEM_E_ARG;
+  if (dp->resort_every < 0) return DEM_E_ARG;
+  if (dp->lanes != 0 && dp->lanes != 1 && dp->lanes != 2 && dp->lanes != 4) return DEM_E_ARG;
+  S.lanes = dp->lanes ? dp->lanes : kForceLanes;
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(dp->box_lo[a]) || !isfinite(dp->box_hi[a]) || !(dp->box_hi[a] > dp->box_lo[a]))
       return DEM_E_ARG;
@@ -540,7 +543,7 @@ static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool con
     e1 = ctx->ev[ctx->ev_used + 1];
     ctx->ev_used += 2;
   }
-  HIP_TRY(launch_force_kick(ctx->B.D, s, src, advance, cont, ctx->fp32, st, e0, e1));
+  HIP_TRY(launch_force_kick(ctx->B.D, s, src, advance, cont, ctx->fp32, ctx->S.lanes, st, e0, e1));
   return DEM_OK;
 }
 
@@ -834,6 +837,7 @@ struct dem_batch {
   bool couples = false;
   int order = 2;
   int maxn = 1;
+  int lanes = kForceLanes;
   // device tables and maps (carved from the caller's workspace)
   Dev *tab = nullptr;
   Cpl *ctab = nullptr;
@@ -869,9 +873,9 @@ dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, Batc
     if (!x) return DEM_E_ARG;
     for (int j = 0; j < b; ++j)
       if (beds[j] == x) return DEM_E_ARG;
-    if (x->fp32 != beds[0]->fp32) return DEM_E_UNSUPPORTED;
+    if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes) return DEM_E_UNSUPPORTED;
     const long long n = x->S.n;
-    const int bd = ceil_div(n, 256), bf = ceil_div(n * kForceLanes, kForceBlock);
+    const int bd = ceil_div(n, 256), bf = ceil_div(n * x->S.lanes, kForceBlock);
     const int ne = x->S.grid.n_elem;
     const int bc = ceil_div(ne, couple_class_elems_per_block());
     if (bd > (int)kBlockMask || bf > (int)kBlockMask || bc > (int)kBlockMask) return DEM_E_UNSUPPORTED;
@@ -939,7 +943,7 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
   HIP_TRY(launch_drift_bin_batch(B->tab, B->run, B->map_drift, B->nb_drift, st));
   for (int i = 1; i <= n; ++i)
     HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force, i, i < n, B->fp32,
-                                    B->maxn, st));
+                                    B->maxn, B->lanes, st));
   HIP_TRY(launch_batch_advance(B->run, (int)B->beds.size(), n, st));
   return DEM_OK;
 }
@@ -1001,6 +1005,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
   batch_carve(n_beds, L, (char *)workspace, B);
   B->beds.assign(beds, beds + n_beds);
   B->fp32 = beds[0]->fp32;
+  B->lanes = beds[0]->S.lanes;
   B->couples = couples;
   B->order = beds[0]->cp.order;
   B->nb_drift = L.nb_drift;
@@ -1023,7 +1028,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
     run.push_back(BedRun{ctx->s, ctx->pending_src});
     if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
     fill_map(md, b, ceil_div(ctx->S.n, 256));
-    fill_map(mf, b, ceil_div((long long)ctx->S.n * kForceLanes, kForceBlock));
+    fill_map(mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
     if (couples) fill_map(mc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));
   }
   hipStream_t st = (hipStream_t)stream;

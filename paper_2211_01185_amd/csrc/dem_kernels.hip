@@ -531,11 +531,10 @@ hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsig
   return hipGetLastError();
 }
 
-hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, hipStream_t st) {
-  constexpr int L = kForceLanes;
+template <int L>
+static void launch_fkb(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
+                       bool cont, bool fp32, int maxn, hipStream_t st) {
   const size_t lds = sizeof(unsigned long long) * (size_t)maxn * (kForceBlock / L);
-  if (blocks <= 0) return hipGetLastError();
   if (fp32) {
     if (cont)
       force_kick_batch<float, true, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
@@ -547,6 +546,18 @@ hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsi
     else
       force_kick_batch<double, false, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
   }
+}
+
+// lanes: 1, 2 or 4 (the same for every bed of the batch)
+hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                   int i, bool cont, bool fp32, int maxn, int lanes, hipStream_t st) {
+  if (blocks <= 0) return hipGetLastError();
+  if (lanes == 1)
+    launch_fkb<1>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+  else if (lanes == 4)
+    launch_fkb<4>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+  else
+    launch_fkb<2>(tab, run, map, blocks, i, cont, fp32, maxn, st);
   return hipGetLastError();
 }
 
@@ -576,10 +587,9 @@ hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename R, bool ADVANCE, bool CONT>
+template <typename R, bool ADVANCE, bool CONT, int L>
 static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
-  constexpr int L = kForceLanes;
   const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
   const size_t lds = sizeof(unsigned long long) * (size_t)D.maxn * (kForceBlock / L);
   if (e0)
@@ -589,26 +599,38 @@ static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t 
     force_kick<R, ADVANCE, CONT, L><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src);
 }
 
-// e0/e1: when non-NULL, events recorded at the kernel's own start and end.
-hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
-                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
+template <int L>
+static void launch_fk_lanes(const Dev &D, int p2, int p3, const int *src, bool advance, bool cont,
+                            bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!advance) {
     if (fp32)
-      launch_fk<float, false, false>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, false, false, L>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<double, false, false>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, false, false, L>(D, p2, p3, src, st, e0, e1);
   } else if (fp32) {
     if (cont)
-      launch_fk<float, true, true>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, true, L>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<float, true, false>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, false, L>(D, p2, p3, src, st, e0, e1);
   } else {
     if (cont)
-      launch_fk<double, true, true>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, true, L>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<double, true, false>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, false, L>(D, p2, p3, src, st, e0, e1);
   }
+}
+
+// e0/e1: when non-NULL, events recorded at the kernel's own start and end.
+// lanes: 1, 2 or 4.
+hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
+                             bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const int p2 = (int)(s & 1), p3 = (int)(s % 3);
+  if (lanes == 1)
+    launch_fk_lanes<1>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+  else if (lanes == 4)
+    launch_fk_lanes<4>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+  else
+    launch_fk_lanes<2>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
   return hipGetLastError();
 }
 

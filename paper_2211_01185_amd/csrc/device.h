@@ -9,7 +9,7 @@ namespace cfddem {
 
 constexpr int kMaxNeighbors = 64;  // bound of dem_params.max_neighbors (one 64-bit mask)
 constexpr int kForceBlock = 128;   // threads per block of the contact-force kernel
-constexpr int kForceLanes = 2;     // lanes sharing one particle in the contact-force kernel
+constexpr int kForceLanes = 2;     // default lanes sharing one particle in the contact-force kernel
 constexpr int kElemMaxParticles = 1024;  // particles one coupling wave can hold
 constexpr int kWalls = 6;          // partner codes 0..5 are the box faces
 

@@ -64,7 +64,7 @@ def test_workspace_query_validates_parameters():
     dp2, _ = cfddem.make_params(wl.dem, wl.fluid, 10 * wl.n, 3e-3, 3e-3)
     assert cfddem.workspace_bytes(dp2, cp) > good
     bad = [("abi_version", 99), ("n", 0), ("dt", -1.0), ("e", 0.0), ("e", 1.5), ("nu", 0.5),
-           ("max_neighbors", 65), ("skin", -1.0), ("d_max", 0.0), ("reserved", 1)]
+           ("max_neighbors", 65), ("skin", -1.0), ("d_max", 0.0), ("lanes", 3)]
     for field, value in bad:
         dpb, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
         setattr(dpb, field, value)

@@ -239,3 +239,22 @@ def test_pair_forces_are_exactly_opposite(precision):
         i, j, _ = gb.read_contacts()
         assert np.all(j >= 0) and i.size > 500
         assert np.all(np.abs(F.sum(axis=1)) <= 1e-13 * np.abs(F).sum())
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lanes_per_particle(lanes, precision):
+    """The lanes sharing a particle in the contact-force kernel change no
+    contact and forces only in their rounding."""
+    wl = _workload("lattice_ragged")
+    gb = gpu_bed(wl, precision, lanes=lanes, resort_every=4)
+    ob, _ = oracle_bed(wl)
+    compare_contacts(gb, ob, TOL[precision])
+    gb.step(1)
+    ob.step(1)
+    compare_contacts(gb, ob, TOL[precision])
+    compare_states(gb, ob, TOL[precision])
+    gb.step(9)
+    ob.step(9)
+    compare_contacts(gb, ob, 10 * TOL[precision])
+    compare_states(gb, ob, 10 * TOL[precision])
