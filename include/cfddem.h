@@ -9,8 +9,9 @@
  * limit, velocity-Verlet integration of Eqs. "newton_law" and
  * "angular_momentum".  One coupling step (Section 2.3): particle-centroid
  * void fraction (Eq. "void_fraction") at the quadrature points of a given
- * Q1/Q2 hex mesh, Di Felice drag (Eq. "drag" and the per-particle drag
- * expression), buoyancy and pressure-gradient forces on the particles, and the
+ * Q1/Q2 hex mesh, drag (Eq. "drag" and the per-particle drag expression,
+ * with the Di Felice, Dallavalle, Rong, Koch-Hill, Beetstra or Gidaspow
+ * closure), buoyancy and pressure-gradient forces on the particles, and the
  * drag (plus, for model B, the pressure-gradient force) reduced back to the
  * quadrature points (Eqs. "fa" / "fb").
  *
@@ -60,7 +61,19 @@ enum {
 };
 
 enum { DEM_FP64 = 0, DEM_FP32_FORCES = 1 };
-enum { DEM_DRAG_DIFELICE = 0 };
+/* Drag closures of Section 2.3.2 (cfd_params.drag).  DEM_DRAG_BETA_OVER_EPS
+ * may be OR-ed in: the coefficient is divided by the fluid fraction,
+ * beta_B = beta_A / eps (Eq. "beta"); without it both models use the same
+ * coefficient. */
+enum {
+  DEM_DRAG_DIFELICE = 0,
+  DEM_DRAG_DALLAVALLE = 1,
+  DEM_DRAG_RONG = 2,
+  DEM_DRAG_KOCH_HILL = 3,
+  DEM_DRAG_BEETSTRA = 4,  /* the printed force multiplies the fluid velocity: the slip is read */
+  DEM_DRAG_GIDASPOW = 5,  /* per-particle coefficient = mixture coefficient x V_p / (1 - eps) */
+  DEM_DRAG_BETA_OVER_EPS = 0x100
+};
 enum { DEM_MODEL_A = 0, DEM_MODEL_B = 1 };
 
 /* DEM parameters (host struct).  Material constants follow Table
@@ -112,7 +125,7 @@ typedef struct {
   int32_t n_el[3]; /* >= 1 each */
   double rho_f;    /* fluid density, > 0 */
   double mu_f;     /* fluid DYNAMIC viscosity (Pa s), > 0 */
-  int32_t drag;    /* DEM_DRAG_DIFELICE */
+  int32_t drag;    /* DEM_DRAG_* closure, optionally | DEM_DRAG_BETA_OVER_EPS */
   int32_t model;   /* DEM_MODEL_A or DEM_MODEL_B (decides what is handed to
                       the fluid, Eqs. "fa" / "fb") */
   double eps_min;  /* the drag closure sees clamp(eps, eps_min, 1); (0, 1] */

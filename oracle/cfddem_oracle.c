@@ -18,7 +18,8 @@
  *   5. F_c, T_c = sums over contacts; v = v_h + dt/2 a', w = w_h + dt/2 alpha'
  * One coupling step (Section 2.3): particle-centroid void fraction per element
  * (Eq. "void_fraction"), Q_n interpolation of the fluid velocity and the Q1
- * pressure gradient at each particle, the Di Felice drag closure, buoyancy and
+ * pressure gradient at each particle, a drag closure (Di Felice, Dallavalle,
+ * Rong, Koch-Hill, Beetstra or Gidaspow; optionally beta_B = beta_A / eps), buoyancy and
  * pressure-gradient forces on the particles, and the per-element reduction of
  * the drag back onto the quadrature points (Eqs. "fa", "fb").
  *
@@ -38,10 +39,20 @@
  *                             (0.2328 m/s) and its closed form; 0.96 x Stokes at
  *                             vanishing Reynolds number; voidage exponent 3.7 in
  *                             both Reynolds limits
+ *   other closures            Stokes' 3 pi mu d for a lone sphere at vanishing
+ *                             Reynolds number (Koch-Hill, Beetstra, Gidaspow;
+ *                             0.96 of it for Dallavalle and Rong); Di Felice and
+ *                             Rong equal Dallavalle at eps = 1; Gidaspow's dense
+ *                             branch equals the textbook Ergun pressure drop;
+ *                             near-continuity of the Gidaspow (Re = 1000) and
+ *                             Koch-Hill (eps_p = 0.4) branch joins
  *   qpt reduction             momentum balance of the drag (and pressure force
- *                             for model B) over the quadrature weights
+ *                             for model B) over the quadrature weights, for
+ *                             every closure; beta_B = beta_A / eps per element
  * Parity unpinned: the middle-Reynolds shape of the Di Felice voidage exponent
- * (no printed value exercises it) and long chaotic trajectories.
+ * (no printed value exercises it), the eps-dependence of Rong's exponent and of
+ * Beetstra's Reynolds term away from the limits above, and long chaotic
+ * trajectories.
  */
 #include "cfddem_oracle.h"
 
@@ -649,6 +660,100 @@ double orc_difelice_beta(double rho_f, double mu_f, double eps, double d, double
   return 0.5 * rho_f * lim * pow(eps, 2.0 - 3.7) * area;
 }
 
+/* The other closures of Section 2.3.2, with eps the fluid fraction,
+ * eps_p = 1 - eps, Re = rho_f eps |slip| d / mu_f (the particle Reynolds
+ * number of the section) and V_p = pi d^3 / 6:
+ *  Dallavalle  C_D = (0.63 + 4.8/sqrt(Re))^2, beta = 1/2 rho_f C_D pi r^2 |slip|
+ *  Rong        C_D = (0.63 + 4.8/sqrt(Re))^2 eps^(2 - [2.65 (eps + 1)
+ *                    - (5.3 - 3.5 eps) eps^2 exp(-(1.5 - log10 Re)^2 / 2)])
+ *  Koch-Hill   beta = 18 mu_f eps^2 eps_p / d^2 (F0 + F3 Re / 2) V_p / eps_p,
+ *              F0 = (1 + 3 sqrt(eps_p/2) + 135/64 eps_p ln eps_p + 16.14 eps_p)
+ *                   / (1 + 0.681 eps_p - 8.48 eps_p^2 + 8.14 eps_p^3) (eps_p < 0.4),
+ *                   10 eps_p / eps^3 (eps_p >= 0.4);
+ *              F3 = 0.0673 + 0.212 eps_p + 0.0232 / eps^5
+ *  Beetstra    f_D = 3 pi mu_f d eps F slip, i.e. beta = 3 pi mu_f d eps F, with
+ *              F = 10 eps_p / eps^2 + eps^2 (1 + 1.5 sqrt(eps_p))
+ *                  + 0.413 Re / (24 eps^2) (1/eps + 3 eps_p eps + 8.4 Re^-0.343)
+ *                    / (1 + 10^(3 eps_p) Re^(-(1 + 4 eps_p)/2))
+ *              (the printed force multiplies the fluid velocity; the slip is
+ *              read, as in every other closure)
+ *  Gidaspow    per unit mixture volume: eps < 0.8 (Ergun)
+ *              150 eps_p^2 mu_f / (eps d^2) + 1.75 eps_p rho_f |slip| / d,
+ *              eps >= 0.8 (Wen-Yu) 3/4 C_D eps |slip| rho_f eps_p / d eps^-2.65,
+ *              C_D = 24/Re (1 + 0.15 Re^0.687) (Re < 1000), 0.44 (Re >= 1000);
+ *              per particle times V_p / eps_p (as the Koch-Hill expression
+ *              writes out), the |slip| of the Ergun term read as a magnitude.
+ * Zero slip: every product C_D |slip| or Re-dependent factor is replaced by
+ * its limit. */
+static double koch_hill_F0(double ep, double ef) {
+  if (ep < 0.4) {
+    double lnterm = ep > 0.0 ? 135.0 / 64.0 * ep * log(ep) : 0.0;
+    return (1.0 + 3.0 * sqrt(ep / 2.0) + lnterm + 16.14 * ep) /
+           (1.0 + 0.681 * ep - 8.48 * ep * ep + 8.14 * ep * ep * ep);
+  }
+  return 10.0 * ep / (ef * ef * ef);
+}
+
+double orc_drag_beta(int drag, double rho_f, double mu_f, double eps, double d, double slip) {
+  double r = 0.5 * d;
+  double area = PI * r * r;
+  double Vp = PI * d * d * d / 6.0;
+  double ep = 1.0 - eps;
+  double Re = rho_f * eps * slip * d / mu_f;
+  switch (drag) {
+    case ORC_DRAG_DIFELICE:
+      return orc_difelice_beta(rho_f, mu_f, eps, d, slip);
+    case ORC_DRAG_DALLAVALLE:
+    case ORC_DRAG_RONG: {
+      double cds; /* C_D |slip| without the voidage factor */
+      double expo = 0.0;
+      if (slip > 0.0) {
+        double root = 0.63 + 4.8 / sqrt(Re);
+        cds = root * root * slip;
+      } else {
+        cds = 4.8 * 4.8 * mu_f / (rho_f * eps * d);
+      }
+      if (drag == ORC_DRAG_RONG) {
+        double bump = 0.0;
+        if (slip > 0.0) {
+          double lg = 1.5 - log10(Re);
+          bump = exp(-(lg * lg) / 2.0);
+        }
+        expo = 2.0 - (2.65 * (eps + 1.0) - (5.3 - 3.5 * eps) * eps * eps * bump);
+      }
+      return 0.5 * rho_f * cds * pow(eps, expo) * area;
+    }
+    case ORC_DRAG_KOCH_HILL: {
+      double F0 = koch_hill_F0(ep, eps);
+      double F3 = 0.0673 + 0.212 * ep + 0.0232 / pow(eps, 5.0);
+      return 18.0 * mu_f * eps * eps / (d * d) * (F0 + 0.5 * F3 * Re) * Vp;
+    }
+    case ORC_DRAG_BEETSTRA: {
+      double F = 10.0 * ep / (eps * eps) + eps * eps * (1.0 + 1.5 * sqrt(ep));
+      if (slip > 0.0) {
+        double num = 1.0 / eps + 3.0 * ep * eps + 8.4 * pow(Re, -0.343);
+        double den = 1.0 + pow(10.0, 3.0 * ep) * pow(Re, -(1.0 + 4.0 * ep) / 2.0);
+        F += 0.413 * Re / (24.0 * eps * eps) * num / den;
+      }
+      return 3.0 * PI * mu_f * d * eps * F;
+    }
+    case ORC_DRAG_GIDASPOW: {
+      if (eps < 0.8)
+        return Vp * (150.0 * ep * mu_f / (eps * d * d) + 1.75 * rho_f * slip / d);
+      double cds; /* C_D |slip| */
+      if (slip > 0.0) {
+        double CD = Re < 1000.0 ? 24.0 / Re * (1.0 + 0.15 * pow(Re, 0.687)) : 0.44;
+        cds = CD * slip;
+      } else {
+        cds = 24.0 * mu_f / (rho_f * eps * d);
+      }
+      return Vp * 0.75 * cds * eps * rho_f / d * pow(eps, -2.65);
+    }
+    default:
+      return NAN;
+  }
+}
+
 /* Gauss-Legendre points and weights mapped to [0,1]. */
 static void gauss_rule(int npts, double *pt, double *wt) {
   if (npts == 2) {
@@ -716,7 +821,8 @@ int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double
     double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
     double d = 2.0 * s->r[i];
     double Vp = 4.0 / 3.0 * PI * s->r[i] * s->r[i] * s->r[i];
-    double beta = orc_difelice_beta(f->rho_f, f->mu_f, eps_c, d, norm3(slip));
+    double beta = orc_drag_beta(f->drag, f->rho_f, f->mu_f, eps_c, d, norm3(slip));
+    if (f->beta_over_eps) beta /= eps_c; /* beta_B = beta_A / eps (Eq. "beta") */
     for (int c = 0; c < 3; ++c) {
       double fD = beta * slip[c];
       double fB = -f->rho_f * Vp * g[c];

@@ -44,7 +44,17 @@ typedef struct {
   double mu_f;    /* fluid DYNAMIC viscosity (Pa s) */
   int model;      /* 0 = VANS model A, 1 = model B */
   double eps_min; /* lower clamp of the void fraction seen by the drag closure */
+  int drag;       /* ORC_DRAG_*: closure of the momentum-exchange coefficient */
+  int beta_over_eps; /* 1: beta_B = beta_A / eps (Eq. "beta"), 0: the same beta for both models */
 } orc_fluid;
+
+/* Drag closures of Section 2.3.2. */
+#define ORC_DRAG_DIFELICE 0
+#define ORC_DRAG_DALLAVALLE 1
+#define ORC_DRAG_RONG 2
+#define ORC_DRAG_KOCH_HILL 3
+#define ORC_DRAG_BEETSTRA 4
+#define ORC_DRAG_GIDASPOW 5
 
 typedef struct orc_dem orc_dem;
 
@@ -79,6 +89,12 @@ void orc_interpolate(const orc_fluid *f, const double lo[3], const double hi[3],
 /* Di Felice momentum-exchange coefficient of one particle:
  * beta_p = 0.5 rho_f C_D pi r^2 |slip|. */
 double orc_difelice_beta(double rho_f, double mu_f, double eps, double d, double slip);
+
+/* Momentum-exchange coefficient beta_p of one particle (f_D = beta_p slip)
+ * for closure `drag` (ORC_DRAG_*) at fluid fraction eps, diameter d and slip
+ * speed |slip| >= 0; finite limits at zero slip.  Returns NaN for an unknown
+ * closure. */
+double orc_drag_beta(int drag, double rho_f, double mu_f, double eps, double d, double slip);
 
 /* ---- whole-step routines ---- */
 

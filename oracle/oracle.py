@@ -31,8 +31,11 @@ class OrcParams(C.Structure):
 class OrcFluid(C.Structure):
     _fields_ = [
         ("order", C.c_int), ("n_el", C.c_int * 3), ("rho_f", C.c_double), ("mu_f", C.c_double),
-        ("model", C.c_int), ("eps_min", C.c_double),
+        ("model", C.c_int), ("eps_min", C.c_double), ("drag", C.c_int), ("beta_over_eps", C.c_int),
     ]
+
+
+DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4, "gidaspow": 5}
 
 
 _lib = None
@@ -61,6 +64,8 @@ def _load():
     lib.orc_interpolate.argtypes = [C.POINTER(OrcFluid), _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp]
     lib.orc_difelice_beta.restype = C.c_double
     lib.orc_difelice_beta.argtypes = [C.c_double] * 5
+    lib.orc_drag_beta.restype = C.c_double
+    lib.orc_drag_beta.argtypes = [C.c_int] + [C.c_double] * 5
     lib.orc_dem_create.restype = C.c_void_p
     lib.orc_dem_create.argtypes = [C.POINTER(OrcParams), C.c_long, _dp, _dp, _dp, _dp, _dp]
     lib.orc_dem_step.restype = C.c_int
@@ -109,13 +114,15 @@ def make_params(box_lo, box_hi, gravity, dt, E, nu, e, mu, E_w=None, nu_w=None, 
     return p
 
 
-def make_fluid(order, n_el, rho_f, mu_f, model=0, eps_min=0.1) -> OrcFluid:
+def make_fluid(order, n_el, rho_f, mu_f, model=0, eps_min=0.1, drag=0, beta_over_eps=0) -> OrcFluid:
     f = OrcFluid()
     f.order = int(order)
     f.n_el[:] = [int(v) for v in n_el]
     f.rho_f, f.mu_f = float(rho_f), float(mu_f)
     f.model = int(model)
     f.eps_min = float(eps_min)
+    f.drag = DRAG[drag] if isinstance(drag, str) else int(drag)
+    f.beta_over_eps = int(beta_over_eps)
     return f
 
 
@@ -172,6 +179,13 @@ def interpolate(fluid: OrcFluid, lo, hi, x, U, P):
 
 def difelice_beta(rho_f, mu_f, eps, d, slip):
     return _load().orc_difelice_beta(float(rho_f), float(mu_f), float(eps), float(d), float(slip))
+
+
+def drag_beta(drag, rho_f, mu_f, eps, d, slip):
+    """Momentum-exchange coefficient of one particle for closure `drag`
+    (a name of DRAG or its number)."""
+    k = DRAG[drag] if isinstance(drag, str) else int(drag)
+    return _load().orc_drag_beta(k, float(rho_f), float(mu_f), float(eps), float(d), float(slip))
 
 
 class OracleBed:

@@ -29,6 +29,8 @@ DEM_E_ABI = -8
 FP64 = 0
 FP32_FORCES = 1
 
+DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4, "gidaspow": 5}
+
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
@@ -152,7 +154,8 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     cp.n_el[:] = [int(v) for v in fluid["n_el"]]
     cp.rho_f = float(fluid["rho_f"])
     cp.mu_f = float(fluid["mu_f"])
-    cp.drag = 0
+    drag = fluid.get("drag", 0)
+    cp.drag = (DRAG[drag] if isinstance(drag, str) else int(drag)) | (0x100 if fluid.get("beta_over_eps") else 0)
     cp.model = int(fluid.get("model", 0))
     cp.eps_min = float(fluid.get("eps_min", 0.1))
     return dp, cp

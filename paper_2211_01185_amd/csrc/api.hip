@@ -29,7 +29,7 @@ hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long
                                 hipStream_t st);
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
                                const unsigned *map_class, int blocks_class, int *cnt_word,
-                               unsigned *list, long long total_elems, int order, bool fp32,
+                               unsigned *list, long long total_elems, int order, bool fp32, bool gen,
                                hipStream_t st);
 int couple_class_elems_per_block();
 }  // namespace cfddem
@@ -84,7 +84,8 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!finite_pos(cp->rho_f) || !finite_pos(cp->mu_f)) return DEM_E_ARG;
   if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
   if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
-  if (cp->drag != DEM_DRAG_DIFELICE) return DEM_E_UNSUPPORTED;
+  if ((cp->drag & ~(0xff | DEM_DRAG_BETA_OVER_EPS)) != 0 || (cp->drag & 0xff) > DEM_DRAG_GIDASPOW)
+    return DEM_E_UNSUPPORTED;
 
   S.n = (int)dp->n;
   S.maxn = dp->max_neighbors ? dp->max_neighbors : 32;
@@ -610,6 +611,8 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   C.mu_f = cp->mu_f;
   C.eps_min = cp->eps_min;
   C.model = cp->model;
+  C.drag = cp->drag & 0xff;
+  C.beta_over_eps = (cp->drag & DEM_DRAG_BETA_OVER_EPS) ? 1 : 0;
   C.Ve = S.grid.he[0] * S.grid.he[1] * S.grid.he[2];
   {
     double gp[3];
@@ -838,6 +841,7 @@ struct dem_batch {
   int order = 2;
   int maxn = 1;
   int lanes = kForceLanes;
+  bool gen_drag = false;  // some bed uses a closure other than Di Felice
   // device tables and maps (carved from the caller's workspace)
   Dev *tab = nullptr;
   Cpl *ctab = nullptr;
@@ -950,7 +954,7 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
 
 dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
   HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
-                              B->list, B->total_elems, B->order, B->fp32, st));
+                              B->list, B->total_elems, B->order, B->fp32, B->gen_drag, st));
   return DEM_OK;
 }
 
@@ -1027,6 +1031,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
     iot.push_back(io);
     run.push_back(BedRun{ctx->s, ctx->pending_src});
     if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
+    if (ctx->C.drag != 0) B->gen_drag = true;
     fill_map(md, b, ceil_div(ctx->S.n, 256));
     fill_map(mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
     if (couples) fill_map(mc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));

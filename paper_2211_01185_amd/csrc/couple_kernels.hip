@@ -18,7 +18,7 @@
 //      (Eq. "void_fraction"),
 //   3. per particle (one per thread): Q_n interpolation of the fluid
 //      velocity and the Q1 pressure gradient from the element's nodal values
-//      staged in LDS, Di Felice closure, f_fp = f_D + f_B + f_gradp (held by
+//      staged in LDS, drag closure, f_fp = f_D + f_B + f_gradp (held by
 //      the DEM steps),
 //   4. element sums reduced across the block (fixed order), then the
 //      quadrature-point outputs eps_q, beta_q and the force density on the
@@ -46,43 +46,116 @@ __device__ inline void wave_sync() {
 }
 constexpr double kPi = 3.14159265358979323846;
 
+// Transcendentals of the drag closures: the library functions in FP64; in
+// FP32 the hardware log2, exp2, 1/sqrt and 1/x (each within about 1 ulp),
+// with log10 x = log2 x log10 2, e^x = 2^(x log2 e) and a^b = 2^(b log2 a).
 template <typename R>
-__device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
+struct Tr;
+template <>
+struct Tr<double> {
+  static __device__ inline double log10_(double x) { return log10(x); }
+  static __device__ inline double log_(double x) { return log(x); }
+  static __device__ inline double exp_(double x) { return exp(x); }
+  static __device__ inline double pow_(double a, double b) { return pow(a, b); }
+  static __device__ inline double rsqrt_(double x) { return 1.0 / sqrt(x); }
+  static __device__ inline double rcp_(double x) { return 1.0 / x; }
+};
+template <>
+struct Tr<float> {
+  static constexpr float kLog10of2 = 0.30102999566398119521f;
+  static constexpr float kLn2 = 0.69314718055994530942f;
+  static constexpr float kLog2e = 1.44269504088896340736f;
+  static __device__ inline float log10_(float x) { return __builtin_amdgcn_logf(x) * kLog10of2; }
+  static __device__ inline float log_(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+  static __device__ inline float exp_(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+  static __device__ inline float pow_(float a, float b) { return __builtin_amdgcn_exp2f(b * __builtin_amdgcn_logf(a)); }
+  static __device__ inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+  static __device__ inline float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+// Momentum-exchange coefficient beta_p of one particle (f_D = beta_p slip) for
+// the closures of Section 2.3.2 (Eq. "drag" and the per-particle drag
+// expression), fluid fraction eps, diameter d, slip speed >= 0.  Re is the
+// section's particle Reynolds number rho_f eps |slip| d / mu_f.  At zero slip
+// every Re-dependent factor takes its limit.
+//   0 Di Felice   C_D = (0.63 + 4.8 Re^-1/2)^2 eps^(2 - chi),
+//                 chi = 3.7 - 0.65 exp(-(1.5 - log10 Re)^2 / 2)
+//   1 Dallavalle  C_D = (0.63 + 4.8 Re^-1/2)^2
+//   2 Rong        C_D = (0.63 + 4.8 Re^-1/2)^2 eps^(2 - [2.65 (eps + 1)
+//                       - (5.3 - 3.5 eps) eps^2 exp(-(1.5 - log10 Re)^2 / 2)])
+//                 (these three: beta = 1/2 rho_f C_D pi r^2 |slip|)
+//   3 Koch-Hill   beta = 18 mu_f eps^2 / d^2 (F0 + F3 Re / 2) V_p
+//   4 Beetstra    beta = 3 pi mu_f d eps F (the slip read for the printed
+//                 fluid velocity)
+//   5 Gidaspow    Ergun (eps < 0.8) or Wen-Yu (eps >= 0.8) per unit mixture
+//                 volume, times V_p / (1 - eps)
+template <typename R>
+__device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
+  using T = Tr<R>;
   const R r = R(0.5) * d;
   const R area = R(kPi) * r * r;
-  if (slip > R(0)) {
-    const R Re = rho_f * eps * slip * d / mu_f;
-    const R lg = R(1.5) - log10(Re);
-    const R chi = R(3.7) - R(0.65) * exp(-(lg * lg) / R(2));
-    const R root = R(0.63) + R(4.8) / sqrt(Re);
-    const R CD = root * root * pow(eps, R(2) - chi);
-    return R(0.5) * rho_f * CD * area * slip;
+  const R vp = R(kPi / 6.0) * d * d * d;
+  const R ep = R(1) - eps;
+  const R inv_mu = T::rcp_(mu_f);
+  const R Re = rho_f * eps * slip * d * inv_mu;
+  const bool moving = slip > R(0);
+  switch (drag) {
+    case 0:
+    case 1:
+    case 2: {
+      // C_D |slip| without the voidage factor; zero slip: 4.8^2 mu_f / (rho_f eps d)
+      R cds;
+      if (moving) {
+        const R root = R(0.63) + R(4.8) * T::rsqrt_(Re);
+        cds = root * root * slip;
+      } else {
+        cds = R(4.8 * 4.8) * mu_f * T::rcp_(rho_f * eps * d);
+      }
+      R expo = R(0);
+      if (drag != 1) {
+        R bump = R(0);  // exp(-(1.5 - log10 Re)^2 / 2), 0 at zero slip
+        if (moving) {
+          const R lg = R(1.5) - T::log10_(Re);
+          bump = T::exp_(-(lg * lg) * R(0.5));
+        }
+        expo = drag == 0 ? R(2) - (R(3.7) - R(0.65) * bump)
+                         : R(2) - (R(2.65) * (eps + R(1)) - (R(5.3) - R(3.5) * eps) * eps * eps * bump);
+      }
+      return R(0.5) * rho_f * cds * (drag == 1 ? R(1) : T::pow_(eps, expo)) * area;
+    }
+    case 3: {
+      R F0;
+      if (ep < R(0.4)) {
+        const R lnterm = ep > R(0) ? R(135.0 / 64.0) * ep * T::log_(ep) : R(0);
+        F0 = (R(1) + R(3) * sqrt(ep * R(0.5)) + lnterm + R(16.14) * ep) /
+             (R(1) + R(0.681) * ep - R(8.48) * ep * ep + R(8.14) * ep * ep * ep);
+      } else {
+        F0 = R(10) * ep / (eps * eps * eps);
+      }
+      const R e2 = eps * eps;
+      const R F3 = R(0.0673) + R(0.212) * ep + R(0.0232) / (e2 * e2 * eps);
+      return R(18) * mu_f * e2 / (d * d) * (F0 + R(0.5) * F3 * Re) * vp;
+    }
+    case 4: {
+      const R e2 = eps * eps;
+      R F = R(10) * ep / e2 + e2 * (R(1) + R(1.5) * sqrt(ep));
+      if (moving) {
+        const R num = R(1) / eps + R(3) * ep * eps + R(8.4) * T::pow_(Re, R(-0.343));
+        const R den = R(1) + T::pow_(R(10), R(3) * ep) * T::pow_(Re, -(R(1) + R(4) * ep) * R(0.5));
+        F += R(0.413) * Re / (R(24) * e2) * num / den;
+      }
+      return R(3.0 * kPi) * mu_f * d * eps * F;
+    }
+    default: {  // 5
+      if (eps < R(0.8)) return vp * (R(150) * ep * mu_f / (eps * d * d) + R(1.75) * rho_f * slip / d);
+      R cds;  // C_D |slip|; zero slip: 24 mu_f / (rho_f eps d)
+      if (moving)
+        cds = (Re < R(1000) ? R(24) * T::rcp_(Re) * (R(1) + R(0.15) * T::pow_(Re, R(0.687))) : R(0.44)) * slip;
+      else
+        cds = R(24) * mu_f * T::rcp_(rho_f * eps * d);
+      return vp * R(0.75) * cds * eps * rho_f / d * T::pow_(eps, R(-2.65));
+    }
   }
-  // zero slip: C_D |slip| -> 4.8^2 mu_f / (rho_f eps d), chi -> 3.7
-  const R lim = R(4.8 * 4.8) * mu_f / (rho_f * eps * d);
-  return R(0.5) * rho_f * lim * pow(eps, R(2.0 - 3.7)) * area;
-}
-
-// FP32 closure on the hardware transcendentals (log2, exp2, 1/sqrt and 1/x,
-// each within about 1 ulp): the same expression as above, with
-// log10 x = log2 x log10 2, e^x = 2^(x log2 e) and a^b = 2^(b log2 a).
-template <>
-__device__ inline float difelice_beta<float>(float rho_f, float mu_f, float eps, float d, float slip) {
-  constexpr float kLog10of2 = 0.30102999566398119521f;
-  constexpr float kLog2e = 1.44269504088896340736f;
-  const float r = 0.5f * d;
-  const float area = float(kPi) * r * r;
-  const float log2_eps = __builtin_amdgcn_logf(eps);
-  if (slip > 0.0f) {
-    const float Re = rho_f * eps * slip * d * __builtin_amdgcn_rcpf(mu_f);
-    const float lg = 1.5f - __builtin_amdgcn_logf(Re) * kLog10of2;
-    const float chi = 3.7f - 0.65f * __builtin_amdgcn_exp2f(-(lg * lg) * (0.5f * kLog2e));
-    const float root = 0.63f + 4.8f * __builtin_amdgcn_rsqf(Re);
-    const float CD = root * root * __builtin_amdgcn_exp2f((2.0f - chi) * log2_eps);
-    return 0.5f * rho_f * CD * area * slip;
-  }
-  const float lim = float(4.8 * 4.8) * mu_f * __builtin_amdgcn_rcpf(rho_f * eps * d);
-  return 0.5f * rho_f * lim * __builtin_amdgcn_exp2f(float(2.0 - 3.7) * log2_eps) * area;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -126,9 +199,31 @@ __device__ inline void basis1d(int order, double t, double L[3]) {
 }
 
 
+// Di Felice (closure 0), the default.  The element kernels are instantiated
+// with GEN = false when every bed uses it, so that the other closures' code
+// and registers stay out of that path.
+template <typename R>
+__device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
+  using T = Tr<R>;
+  const R r = R(0.5) * d;
+  const R area = R(kPi) * r * r;
+  R cds, expo;
+  if (slip > R(0)) {
+    const R Re = rho_f * eps * slip * d * T::rcp_(mu_f);
+    const R root = R(0.63) + R(4.8) * T::rsqrt_(Re);
+    const R lg = R(1.5) - T::log10_(Re);
+    cds = root * root * slip;
+    expo = R(2) - (R(3.7) - R(0.65) * T::exp_(-(lg * lg) * R(0.5)));
+  } else {
+    cds = R(4.8 * 4.8) * mu_f * T::rcp_(rho_f * eps * d);
+    expo = R(2.0 - 3.7);
+  }
+  return R(0.5) * rho_f * cds * T::pow_(eps, expo) * area;
+}
+
 // Per-particle step 3 of one element: interpolation, closure, f_fp, and the
 // thread's running element sums.
-template <typename R, int ORD>
+template <typename R, int ORD, bool GEN>
 __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const int ee[3],
                                       const double xp[3], const double up[3], double r,
                                       double eps_c, const double (*sU)[27], const double *sP,
@@ -182,7 +277,9 @@ __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const i
   const double Vp = 4.0 / 3.0 * kPi * r * r * r;
   const double sl[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
   const double slip = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + sl[2] * sl[2]);
-  const double beta = (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
+  double beta = GEN ? (double)drag_beta<R>(C.drag, R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip))
+                    : (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
+  if (C.beta_over_eps) beta /= eps_c;  // beta_B = beta_A / eps (Eq. "beta")
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double fD = beta * sl[c];
@@ -234,7 +331,7 @@ struct CplShared {
 // One occupied element, computed by the whole block.  The latency is a short
 // chain of memory round trips: counts, slot entries and nodal values are
 // loaded together, then the particles' state, then the outputs are stored.
-template <typename R, int ORD>
+template <typename R, int ORD, bool GEN>
 __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
                                const double *__restrict__ P, double *__restrict__ eps_q,
                                double *__restrict__ beta_q, double *__restrict__ fpf_q,
@@ -360,7 +457,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   // ---- 3. per-particle forces
   double sums[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // beta, beta u_p, f_D, f_gradp
   const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
-  if (k0 >= 0) particle_force<R, ORD>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
+  if (k0 >= 0) particle_force<R, ORD, GEN>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
     const int k = sh.ids[t];
     double xp[3], up[3];
@@ -369,7 +466,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       xp[c] = X[c * n + k];
       up[c] = D.v[c * n + k];
     }
-    particle_force<R, ORD>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
+    particle_force<R, ORD, GEN>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
   }
   wave_sum_n(sums);
   if (lane == 0)
@@ -500,7 +597,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
 // One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
 // list exit at once; dispatching one block per mesh element would cost more
 // than the work).  Longer lists are strided over the grid.
-template <typename R, int ORD>
+template <typename R, int ORD, bool GEN>
 __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
                                                                     int parity,
                                                                     const double *__restrict__ U,
@@ -518,10 +615,10 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
   if ((int)blockIdx.x >= nocc) return;  // whole block
   const int tid = threadIdx.x;
   if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+  couple_element<R, ORD, GEN>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
   // more occupied elements than blocks: the rest, strided over the grid
   for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
-    couple_element<R, ORD>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+    couple_element<R, ORD, GEN>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -541,7 +638,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
                        io.eps_q, io.beta_q, io.fpf_q, io.esums);
 }
 
-template <typename R, int ORD>
+template <typename R, int ORD, bool GEN>
 __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const Cpl *__restrict__ ctab,
                                               const CplIO *__restrict__ iot,
                                               const BedRun *__restrict__ run, unsigned ent,
@@ -553,11 +650,11 @@ __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const
   const long long s = run[b].s;
   const int tid = threadIdx.x;
   if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
+  couple_element<R, ORD, GEN>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
                          (int)(s % 3), sh);
 }
 
-template <typename R, int ORD>
+template <typename R, int ORD, bool GEN>
 __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list) {
@@ -569,7 +666,7 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
   // is read in the same round trip as the list length
   for (int i = blockIdx.x; i < nocc; i += gridDim.x) {
     if (i != (int)blockIdx.x) ent = list[i];
-    couple_listed<R, ORD>(tab, ctab, iot, run, ent, sh);
+    couple_listed<R, ORD, GEN>(tab, ctab, iot, run, ent, sh);
   }
 }
 
@@ -577,25 +674,27 @@ __global__ void reset_count(int *cnt_word) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_word = 0;
 }
 
-// Every bed of a batch (all of velocity order `order`).  The list has room
+// Every bed of a batch (all of velocity order `order`; gen: some bed uses a
+// closure other than Di Felice).  The list has room
 // for total_elems entries (at least one); the counter is zero on entry and
 // on return.
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
                                const unsigned *map_class, int blocks_class, int *cnt_word,
-                               unsigned *list, long long total_elems, int order, bool fp32,
+                               unsigned *list, long long total_elems, int order, bool fp32, bool gen,
                                hipStream_t st) {
   if (blocks_class <= 0) return hipGetLastError();
   couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_word,
                                                               list);
   const dim3 g(total_elems < kMaxCoupleBlocks ? (int)total_elems : kMaxCoupleBlocks), b(kCplThreads);
-  if (fp32 && order == 2)
-    couple_occupied_batch<float, 2><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
-  else if (fp32)
-    couple_occupied_batch<float, 1><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
-  else if (order == 2)
-    couple_occupied_batch<double, 2><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
-  else
-    couple_occupied_batch<double, 1><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list);
+#define CFDDEM_OCCB(RT, O, GN) couple_occupied_batch<RT, O, GN><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list)
+  if (fp32) {
+    if (order == 2) { if (gen) CFDDEM_OCCB(float, 2, true); else CFDDEM_OCCB(float, 2, false); }
+    else { if (gen) CFDDEM_OCCB(float, 1, true); else CFDDEM_OCCB(float, 1, false); }
+  } else {
+    if (order == 2) { if (gen) CFDDEM_OCCB(double, 2, true); else CFDDEM_OCCB(double, 2, false); }
+    else { if (gen) CFDDEM_OCCB(double, 1, true); else CFDDEM_OCCB(double, 1, false); }
+  }
+#undef CFDDEM_OCCB
   reset_count<<<1, 64, 0, st>>>(cnt_word);
   return hipGetLastError();
 }
@@ -612,14 +711,16 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
   const int grid_c = (waves_c + kClassBlock / kWave - 1) / (kClassBlock / kWave);
   couple_classify<<<grid_c, kClassBlock, 0, st>>>(D, C, p3, parity, eps_q, beta_q, fpf_q, esums);
   const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks), b(kCplThreads);
-  if (fp32 && C.order == 2)
-    couple_occupied<float, 2><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
-  else if (fp32)
-    couple_occupied<float, 1><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
-  else if (C.order == 2)
-    couple_occupied<double, 2><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
-  else
-    couple_occupied<double, 1><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums);
+#define CFDDEM_OCC(RT, O, GN) couple_occupied<RT, O, GN><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)
+  const bool gen = C.drag != 0;
+  if (fp32) {
+    if (C.order == 2) { if (gen) CFDDEM_OCC(float, 2, true); else CFDDEM_OCC(float, 2, false); }
+    else { if (gen) CFDDEM_OCC(float, 1, true); else CFDDEM_OCC(float, 1, false); }
+  } else {
+    if (C.order == 2) { if (gen) CFDDEM_OCC(double, 2, true); else CFDDEM_OCC(double, 2, false); }
+    else { if (gen) CFDDEM_OCC(double, 1, true); else CFDDEM_OCC(double, 1, false); }
+  }
+#undef CFDDEM_OCC
   return hipGetLastError();
 }
 

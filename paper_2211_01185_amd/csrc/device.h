@@ -108,6 +108,8 @@ struct Cpl {
   int npx, npy;     // pressure node lattice
   double rho_f, mu_f, eps_min;
   int model;
+  int drag;           // closure (DEM_DRAG_* without the flag bits)
+  int beta_over_eps;  // 1: beta divided by the fluid fraction
   double Ve;        // element volume
   double Lq[3][3];  // Lq[a][i]: 1D velocity basis a at Gauss point i
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)

@@ -14,7 +14,8 @@ def oracle_bed(wl, model=None):
                       d["E_w"], d["nu_w"], d["e_w"], d["mu_w"])
     f = wl.fluid
     fl = O.make_fluid(f["order"], f["n_el"], f["rho_f"], f["mu_f"],
-                      f.get("model", 0) if model is None else model, f["eps_min"])
+                      f.get("model", 0) if model is None else model, f["eps_min"],
+                      f.get("drag", 0), f.get("beta_over_eps", 0))
     return O.OracleBed(p, wl.x, wl.v, wl.w, wl.radius, wl.density), fl
 
 

@@ -258,3 +258,26 @@ def test_lanes_per_particle(lanes, precision):
     ob.step(9)
     compare_contacts(gb, ob, 10 * TOL[precision])
     compare_states(gb, ob, 10 * TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("drag", ["dallavalle", "rong", "koch_hill", "beetstra", "gidaspow"])
+@pytest.mark.parametrize("beta_over_eps", [0, 1])
+def test_coupling_step_other_closures(drag, beta_over_eps, precision):
+    """Every drag closure of Section 2.3.2 (and beta_B = beta_A / eps)
+    against the oracle on one coupling step; the lattice spans fluid fractions
+    on both sides of the Gidaspow (0.8) and Koch-Hill (eps_p = 0.4) joins."""
+    wl = _workload("lattice")
+    wl.fluid.update(drag=drag, beta_over_eps=beta_over_eps, model=1)
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    out = gb.couple(U, P, elem_sums=True)
+    ref = ob.couple(fl, wl.U, wl.P)
+    tol = TOL[precision]
+    eps = ref["eps_q"]
+    assert eps[eps < 1].min() < 0.6 and eps.max() >= 0.8  # both branches exercised
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+    assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
