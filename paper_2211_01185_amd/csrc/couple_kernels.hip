@@ -367,8 +367,8 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
   // ---- 1. particles of this element.  The thread owning cell c of the
   // element (c = tid first) loads its count and its first slot entries at once.
-  const int *cnt = D.cnt[p3];
-  const int *slot = D.slot[p2];
+  const int *cnt = sel(D.cnt, p3);
+  const int *slot = sel(D.slot, p2);
   const int base = e * G.kk;
   const int pre = D.cap < kSlotPre ? D.cap : kSlotPre;
   int m0 = 0;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
   // ---- 2. void fraction; the state of the thread's first particle is
   // loaded in the same round trip as its radius
-  const double *X = D.xs[p2];
+  const double *X = sel(D.xs, p2);
   const int k0 = tid < total ? sh.ids[tid] : -1;
   double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, r0 = 0.0;
   if (k0 >= 0) {
@@ -544,7 +544,7 @@ __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C,
   const Grid &G = D.grid;
   if (e0 >= G.n_elem) return;  // whole wavefront
   const int ne = G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems;
-  const int *cnt = D.cnt[p3];
+  const int *cnt = sel(D.cnt, p3);
   unsigned occupied = 0;
   for (int c = lane; c - lane < G.kk; c += kWave) {
     int m[kClassElems];

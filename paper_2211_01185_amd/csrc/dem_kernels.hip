@@ -59,8 +59,8 @@ __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int 
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
-  const double *x0 = D.xs[p2 ^ 1];
-  double *x1 = D.xs[p2], *vh = D.vhs[p2], *wh = D.whs[p2];
+  const double *x0 = sel(D.xs, p2 ^ 1);
+  double *x1 = sel(D.xs, p2), *vh = sel(D.vhs, p2), *wh = sel(D.whs, p2);
   if (DRIFT) {
     const double m = D.mass[k];
     const double r = D.rad[k];
@@ -85,7 +85,7 @@ __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int 
     }
   }
   int bits = 0;
-  bin_and_test(D, k, xp, D.cnt[p3], D.slot[p2], D.cell[p3], D.flag + p3, force_flag != 0, bits);
+  bin_and_test(D, k, xp, sel(D.cnt, p3), sel(D.slot, p2), sel(D.cell, p3), D.flag + p3, force_flag != 0, bits);
   if (bits) atomicOr(D.err, bits);
 }
 
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int forc
 __global__ void clear_grid(Dev D, int p3) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
-  D.cnt[p3][D.cell[p3][k]] = 0;
+  sel(D.cnt, p3)[sel(D.cell, p3)[k]] = 0;
   if (k == 0) D.flag[p3] = 0;
 }
 
@@ -210,9 +210,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const Grid &G = D.grid;
   const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
   const int r3 = p3 == 0 ? 2 : p3 - 1;  // (s - 1) % 3
-  const double *xs = D.xs[p2];
-  const double *vhs = D.vhs[p2];
-  const double *whs = D.whs[p2];
+  const double *xs = sel(D.xs, p2);
+  const double *vhs = sel(D.vhs, p2);
+  const double *whs = sel(D.whs, p2);
   const int lold = D.lbuf[p3];
   const bool rebuild = !ADVANCE || src != nullptr || D.flag[p3] != 0;
   const int cur = rebuild ? (lold ^ 1) : lold;
@@ -234,13 +234,13 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     // ---- broad search over the 27-cell stencil (lane 0), insertion-sorted
     //      by partner original ID in LDS
     if (lane == 0) {
-      const int ca = D.cell[p3][a];
+      const int ca = sel(D.cell, p3)[a];
       const int el = ca / G.kk, sub = ca - el * G.kk;
       const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
       const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
       const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
-      const int *cnt = D.cnt[p3];
-      const int *slot = D.slot[p2];
+      const int *cnt = sel(D.cnt, p3);
+      const int *slot = sel(D.slot, p2);
       m = 0;
       #pragma unroll 1
       for (int dz = -1; dz <= 1; ++dz) {
@@ -285,7 +285,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
           }
         }
       }
-      D.ln[cur][a] = m;
+      sel(D.ln, cur)[a] = m;
       D.xb[a] = xa0;
       D.xb[n + a] = xa1;
       D.xb[2 * n + a] = xa2;
@@ -298,10 +298,10 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     // ---- each lane stores its own entries and carries their tangential
     //      history from the previous list (both sorted by partner oid)
     const int s = src ? src[a] : a;
-    const int mo = D.ln[lold][s];
-    const unsigned long long mask_old = D.hmask[lold][s];
-    const unsigned long long *olst = D.nbr[lold];
-    unsigned long long *lst = D.nbr[cur];
+    const int mo = sel(D.ln, lold)[s];
+    const unsigned long long mask_old = sel(D.hmask, lold)[s];
+    const unsigned long long *olst = sel(D.nbr, lold);
+    unsigned long long *lst = sel(D.nbr, cur);
     unsigned long long carried = 0;
     int q = 0;
     for (int t = lane; t < m; t += L) {
@@ -312,15 +312,15 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot &&
           ((mask_old >> q) & 1ull)) {
         for (int c = 0; c < 3; ++c)
-          D.hdt[cur][(size_t)c * mn + (size_t)t * n + a] =
-              D.hdt[lold][(size_t)c * mn + (size_t)q * n + s];
+          sel(D.hdt, cur)[(size_t)c * mn + (size_t)t * n + a] =
+              sel(D.hdt, lold)[(size_t)c * mn + (size_t)q * n + s];
         carried |= 1ull << t;
       }
     }
     mask_prev = carried;  // bits of this lane's entries
   } else {
-    mask_prev = D.hmask[cur][a];
-    m = D.ln[cur][a];
+    mask_prev = sel(D.hmask, cur)[a];
+    m = sel(D.ln, cur)[a];
   }
   // keep the fast path's loads below the (rare) broad search, so that their
   // registers are not live across it
@@ -331,8 +331,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
   const double ma = D.mass[a];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-  const unsigned long long *lst = D.nbr[cur];
-  double *hdt = D.hdt[cur];
+  const unsigned long long *lst = sel(D.nbr, cur);
+  double *hdt = sel(D.hdt, cur);
   unsigned long long mask_new = 0;
   for (int t = lane; t < m; t += L) {
     const unsigned long long key = lst[(size_t)t * n + a];  // this lane stored its own entries
@@ -373,15 +373,21 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   }
   // ---- walls (last lane of the group)
   if (lane == L - 1) {
-    const double xa[3] = {xa0, xa1, xa2};
     const unsigned wold = ADVANCE ? D.wmask[a] : 0u;
     unsigned wnew = 0;
     for (int wall = 0; wall < kWalls; ++wall) {
+      // axis quantities by selection (no run-time index into the grid)
       const int ax = wall >> 1;
-      const double dist = (wall & 1) ? G.hi[ax] - xa[ax] : xa[ax] - G.lo[ax];
+      const double xax = ax == 0 ? xa0 : (ax == 1 ? xa1 : xa2);
+      const double face = (wall & 1) ? (ax == 0 ? G.hi[0] : (ax == 1 ? G.hi[1] : G.hi[2]))
+                                     : (ax == 0 ? G.lo[0] : (ax == 1 ? G.lo[1] : G.lo[2]));
+      const double dist = (wall & 1) ? face - xax : xax - face;
       if (!(ra - dist > 0.0)) continue;
-      double nrm[3] = {0.0, 0.0, 0.0}, vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
-      nrm[ax] = (wall & 1) ? 1.0 : -1.0;
+      const double sgn = (wall & 1) ? 1.0 : -1.0;
+      double nrm[3], vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
+      nrm[0] = ax == 0 ? sgn : 0.0;
+      nrm[1] = ax == 1 ? sgn : 0.0;
+      nrm[2] = ax == 2 ? sgn : 0.0;
       const double dn = ra - dist;
       const double rw0 = ra * wa0, rw1 = ra * wa1, rw2 = ra * wa2;
       vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
@@ -413,7 +419,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   // ---- lane 0: store the step, open the next one.  Inside a run the
   //      boundary velocities and the stored force/torque are never read, so
   //      only the last step of a run stores them.
-  if (rebuild || mask_new != mask_prev) D.hmask[cur][a] = mask_new;
+  if (rebuild || mask_new != mask_prev) sel(D.hmask, cur)[a] = mask_new;
   if (!CONT) {
     for (int c = 0; c < 3; ++c) {
       D.Fc[c * n + a] = F[c];
@@ -422,7 +428,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
   // the grid of step s-1 is free: clear it for step s+2
-  D.cnt[r3][D.cell[r3][a]] = 0;
+  sel(D.cnt, r3)[sel(D.cell, r3)[a]] = 0;
 
   if (ADVANCE) {
     const double inertia = 0.4 * ma * ra * ra;
@@ -442,7 +448,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     if (CONT) {
       // open step s+1 with the same held fluid force
       double xp[3];
-      double *x1 = D.xs[p2 ^ 1], *vh1 = D.vhs[p2 ^ 1], *wh1 = D.whs[p2 ^ 1];
+      double *x1 = sel(D.xs, p2 ^ 1), *vh1 = sel(D.vhs, p2 ^ 1), *wh1 = sel(D.whs, p2 ^ 1);
       const double xa[3] = {xa0, xa1, xa2};
       for (int c = 0; c < 3; ++c) {
         const int i = c * n + a;
@@ -453,7 +459,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
         wh1[i] = whc;
         x1[i] = xp[c];
       }
-      bin_and_test(D, a, xp, D.cnt[q3], D.slot[p2 ^ 1], D.cell[q3], D.flag + q3, false, bits);
+      bin_and_test(D, a, xp, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.cell, q3), D.flag + q3, false, bits);
     }
   }
   if (a == 0) {

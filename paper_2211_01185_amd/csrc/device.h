@@ -115,6 +115,17 @@ struct Cpl {
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)
 };
 
+// Buffer i of a double- or triple-buffered array, with constant indices only
+// (so that a Dev copied into registers stays in registers).
+template <typename T>
+__device__ __forceinline__ T *sel(T *const (&a)[2], int i) {
+  return i ? a[1] : a[0];
+}
+template <typename T>
+__device__ __forceinline__ T *sel(T *const (&a)[3], int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
 __device__ inline int floor_clamp(double t, int n) {
   double f = floor(t);
   if (!(f >= 0.0)) return 0;
