@@ -201,16 +201,20 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_2211_01185_amd import cfddem, synth
+    from paper_2211_01185_amd import autotune, cfddem, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     wl = synth.fluidized()
     U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
     P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    # skin (DEM cell size), re-sort interval and lanes per particle: tuned on
+    # short runs of this bed before the measurement (results do not depend on them)
+    tuned, tune_report = autotune.tune([wl], "fp32", steps=300, device=dev, use_cache=False)
+    bed_kw = autotune.bed_kwargs(wl, tuned)
 
     def make_bed():
-        bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, resort_every=RESORT_EVERY)
+        bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, **bed_kw)
         out = bed.couple(U, P)  # allocates the output tensors once; the run re-couples at step 0
         return bed, out
 
@@ -295,7 +299,8 @@ def main():
             "coupling_every": COUPLING_EVERY,
             "precision": "FP32 pair-force and drag arithmetic, FP64 positions/velocities/history/sums",
             "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
-            "resort_every": RESORT_EVERY,
+            "tuned": dict(bed_kw, trials=tune_report["trials"],
+                          default_ms_per_step=tune_report["default_ms_per_step"]),
             "parallelism": "1 GPU",
         },
         "roofline": {

@@ -78,9 +78,38 @@ def signature(wls, precision) -> str:
     return f"{precision}|beds={len(wls)}|n~{float(f'{n:.1g}')}|d~{float(f'{d:.1g}')}|u~{u:.1f}"
 
 
+def _time_single(wl, field, cfg, precision, steps, device):
+    """One bed through the single-bed entry points (the path such a bed runs on)."""
+    import torch
+
+    bed = cfddem.bed_from_workload(wl, precision=precision, device=device, **bed_kwargs(wl, cfg))
+    try:
+        U, P = field
+        out = bed.couple(U, P)
+        chunks = max(1, steps // COUPLING_EVERY)
+
+        def run(k):
+            for _ in range(k):
+                bed.couple(U, P, out=out)
+                bed.step(COUPLING_EVERY)
+
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(chunks)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = bed.poll()[0] == 0
+    finally:
+        bed.close()
+    return dt / (chunks * COUPLING_EVERY) if ok else float("inf")
+
+
 def _time_batch(wls, fields, cfg, precision, steps, device):
     import torch
 
+    if len(wls) == 1:
+        return _time_single(wls[0], fields[0], cfg, precision, steps, device)
     beds = [cfddem.bed_from_workload(w, precision=precision, device=device, **bed_kwargs(w, cfg)) for w in wls]
     try:
         batch = cfddem.Batch(beds, fields)
@@ -100,8 +129,9 @@ def _time_batch(wls, fields, cfg, precision, steps, device):
 
 
 def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample=8):
-    """Best configuration for running these beds (one bed, or a batch of
-    them), tuned on up to `sample` of the beds.  Returns (config, report)."""
+    """Best configuration for running these beds, tuned on up to `sample` of
+    them: one bed is timed through the single-bed entry points, several as a
+    batch.  Returns (config, report)."""
     import torch
 
     key = signature(wls, precision)

@@ -2,10 +2,11 @@
 on every particle, contact and quadrature point (the oracle takes about a
 second per coupling step at these sizes).
 
-* The 100,000-sphere fluidized bed in the exact launch configuration that
-  bench.py times (FP32 force and drag arithmetic, re-sort every 100 steps, a
-  coupling step every 10 DEM steps): 110 steps, crossing a re-sort and
-  several neighbour-list rebuilds; also with the FP64 path.
+* The 100,000-sphere fluidized bed in the launch configuration that bench.py
+  times (FP32 force and drag arithmetic, a coupling step every 10 DEM steps;
+  skin, re-sort interval and lanes at the defaults and at tuned values):
+  110 steps, crossing re-sorts and neighbour-list rebuilds; also with the
+  FP64 path.
 * The 500,000-sphere polydisperse spouted bed: priming, one coupling step and
   ten DEM steps.
 
@@ -17,7 +18,7 @@ import numpy as np
 import pytest
 
 import bench
-from paper_2211_01185_amd import cfddem, synth
+from paper_2211_01185_amd import autotune, cfddem, synth
 from tests.parity_util import TOL, assert_close, compare_contacts, compare_states, oracle_bed
 
 pytestmark = pytest.mark.gpu
@@ -44,12 +45,14 @@ def _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums):
     assert_close("f_fp", gb.read_state()["ffp"].cpu().numpy(), ob.state()["ffp"], tol)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_fluidized_bed_bench_configuration(precision):
+@pytest.mark.parametrize("precision,cfg", [("fp32", autotune.DEFAULT),
+                                           ("fp32", {"skin_factor": 0.2, "resort_every": 200, "lanes": 4}),
+                                           ("fp64", autotune.DEFAULT)])
+def test_fluidized_bed_bench_configuration(precision, cfg):
     wl = synth.fluidized()
-    # the bed exactly as bench.py builds it
+    # the bed as bench.py builds it, with the default and a tuned configuration
     gb = cfddem.bed_from_workload(wl, precision=precision, device=torch.device("cuda:0"),
-                                  resort_every=bench.RESORT_EVERY)
+                                  **autotune.bed_kwargs(wl, cfg))
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     tol = TOL[precision]
