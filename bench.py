@@ -123,7 +123,8 @@ def batched_ensemble(n_beds, steps, dev):
     n_total = sum(w.n for w in wls)
     fields = [(torch.as_tensor(w.U, dtype=torch.float64, device=dev).contiguous(),
                torch.as_tensor(w.P, dtype=torch.float64, device=dev).contiguous()) for w in wls]
-    cfg, tune_report = autotune.tune(wls, "fp32", device=dev, use_cache=False)
+    # tuned over as many steps as the measurement runs, from the same start
+    cfg, tune_report = autotune.tune(wls, "fp32", steps=steps, device=dev, use_cache=False)
     beds = [cfddem.bed_from_workload(w, precision="fp32", device=dev, **autotune.bed_kwargs(w, cfg))
             for w in wls]
     batch = cfddem.Batch(beds, fields)
@@ -209,8 +210,11 @@ def main():
     U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
     P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
     # skin (DEM cell size), re-sort interval and lanes per particle: tuned on
-    # short runs of this bed before the measurement (results do not depend on them)
-    tuned, tune_report = autotune.tune([wl], "fp32", steps=300, device=dev, use_cache=False)
+    # runs of this bed from its start over as many steps as are measured (the
+    # rate of list rebuilds grows as the bed fluidizes); results do not depend
+    # on them
+    tuned, tune_report = autotune.tune([wl], "fp32", steps=args.warmup + args.steps, device=dev,
+                                       use_cache=False)
     bed_kw = autotune.bed_kwargs(wl, tuned)
 
     def make_bed():

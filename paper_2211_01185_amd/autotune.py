@@ -12,10 +12,12 @@ Knobs (each a dem_params field):
 
 None of them changes a contact set, and forces only at the rounding level
 (the order of a particle's contact sums depends on its list layout), which the
-invariance tests check.  The tuner times short coupled runs (a coupling step
-every 10 DEM steps, as the workloads run) on the device for candidate values,
-one knob at a time starting from the defaults (coordinate descent), and keeps
-the fastest.  Results are cached in a JSON file keyed by a signature of the
+invariance tests check.  The tuner times coupled runs (a coupling step every
+10 DEM steps, as the workloads run) from the beds' initial state on the device
+for candidate values, one knob at a time starting from the defaults
+(coordinate descent), and keeps the fastest.  Runs should be as long as the
+runs being tuned for: a bed that starts at rest rebuilds its lists rarely at
+first, which favours small skins on short runs.  Results are cached in a JSON file keyed by a signature of the
 workload.
 """
 from __future__ import annotations

@@ -185,6 +185,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
     D.vhs[b] = c.take<double>(3 * n);
     D.whs[b] = c.take<double>(3 * n);
     D.slot[b] = c.take<int>((size_t)S.grid.ncells * S.cap);
+    D.srec[b] = c.take<float4>((size_t)S.grid.ncells * S.cap);
   }
   for (int b = 0; b < 3; ++b) {
     D.cell[b] = c.take<int>(n);
@@ -583,6 +584,15 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   D.maxn = S.maxn;
   D.skin = S.skin;
   D.trig2 = (0.499 * S.skin) * (0.499 * S.skin);
+  {
+    // single-precision coordinates are off by at most 2^-24 of the largest
+    // coordinate magnitude; the broad-search test widens its cutoff by 2^-20
+    // of it (and by 2^-18 relative), so that it keeps every pair that the
+    // exact test would
+    double xm = 0.0;
+    for (int a = 0; a < 3; ++a) xm = fmax(xm, fmax(fabs(S.grid.lo[a]), fabs(S.grid.hi[a])));
+    D.marg = (float)ldexp(xm, -20);
+  }
   D.dt = dp->dt;
   for (int a = 0; a < 3; ++a) D.g[a] = dp->gravity[a];
   D.grid = S.grid;

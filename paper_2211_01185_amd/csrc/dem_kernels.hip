@@ -2,11 +2,15 @@
 // & Blais, arXiv 2211.01185), one kernel launch per step:
 //   drift_bin   : opens a run of steps: half kick + drift from the boundary
 //                 state, binning of the new centres into the nested cell grid
-//                 (atomic slot insertion), displacement test that requests a
+//                 (atomic slot insertion, with a single-precision record of
+//                 position and radius per slot), displacement test that requests a
 //                 new broad search
 //   force_kick  : step s: broad search when requested (cell-list neighbour
-//                 list within R_i + R_j + skin over the 27-cell stencil,
-//                 sorted by partner original ID, history carried by a merge),
+//                 list over the 27-cell stencil: every pair within
+//                 R_i + R_j + skin, found by a single-precision test against
+//                 the cells' slot records whose cutoff is widened to cover
+//                 its rounding; sorted by partner original ID, history carried
+//                 by a merge),
 //                 fine search (exact overlap test over the list and the six
 //                 walls), Hertz-Mindlin contact law (Table "tab:viscoelastic",
 //                 contact-force equation) with tangential history and Coulomb
@@ -28,10 +32,12 @@
 
 namespace cfddem {
 
-// Binning of x into the grid of a step (counts cnt, slots sl, cells cl) and
-// the displacement test against the last broad-search positions.
-__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], int *cnt, int *sl,
-                                    int *cl, int *flag, bool force_flag, int &bits) {
+// Binning of x into the grid of a step (counts cnt, slots sl with their
+// single-precision records rec, cells cl) and the displacement test against
+// the last broad-search positions.
+__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], double r, int *cnt,
+                                    int *sl, float4 *rec, int *cl, int *flag, bool force_flag,
+                                    int &bits) {
   int elem, cell;
   bool inside;
   bin_point(D.grid, xp, elem, cell, inside);
@@ -39,9 +45,10 @@ __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], int
   if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
   cl[k] = cell;
   const int s = atomicAdd(&cnt[cell], 1);
-  if (s >= 0 && s < D.cap)
+  if (s >= 0 && s < D.cap) {
     sl[(size_t)cell * D.cap + s] = k;
-  else
+    rec[(size_t)cell * D.cap + s] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)r);
+  } else
     bits |= kErrCapacity;
   // a list built at xb stays complete while every particle is within skin/2
   const int n = D.n;
@@ -85,7 +92,8 @@ __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int 
     }
   }
   int bits = 0;
-  bin_and_test(D, k, xp, sel(D.cnt, p3), sel(D.slot, p2), sel(D.cell, p3), D.flag + p3, force_flag != 0, bits);
+  bin_and_test(D, k, xp, D.rad[k], sel(D.cnt, p3), sel(D.slot, p2), sel(D.srec, p2), sel(D.cell, p3),
+               D.flag + p3, force_flag != 0, bits);
   if (bits) atomicOr(D.err, bits);
 }
 
@@ -167,20 +175,14 @@ __device__ inline void lever_sum(double ra, double wa0, double wa1, double wa2, 
 
 // Broad-search predicate: (R_i + R_j + skin)^2 - |x_j - x_i|^2 > 0.  Every
 // pair that satisfies the fine-search predicate satisfies this one.
-__device__ inline bool within_cutoff(double xi0, double xi1, double xi2, double xj0, double xj1,
-                                     double xj2, double cut) {
-  const double dx = xj0 - xi0, dy = xj1 - xi1, dz = xj2 - xi2;
-  return cut * cut - (dx * dx + dy * dy + dz * dz) > 0.0;
-}
-
 // ---------------------------------------------------------------------------
 // one DEM step (plus the opening of the next one when CONT)
 // ---------------------------------------------------------------------------
 // L consecutive lanes of a wavefront share one particle: lane l walks the list
 // entries t = l, l + L, ..., lane L-1 also the walls, and the partial force
-// and torque are summed over the L lanes in a fixed butterfly order.  A broad
-// search is done by every lane of the group (identical work, identical
-// writes), so no lane waits for another.  Lane 0 finishes the step.
+// and torque are summed over the L lanes in a fixed butterfly order.  Lane 0
+// does a broad search, when one is due, into the group's list in LDS; every
+// lane then stores its own entries.  Lane 0 finishes the step.
 // p2 = s & 1, p3 = s % 3.  The grid p3 / slot buffer p2 hold x_s.
 // ADVANCE = false: creation-time evaluation (no history advance, no kick).
 // src: after a re-sort, the index each particle had when its list was built
@@ -219,7 +221,6 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
 
   const double xa0 = xs[a], xa1 = xs[n + a], xa2 = xs[2 * n + a];
   const double ra = D.rad[a];
-  const int oa = D.oid[a];
   const size_t mn = (size_t)D.maxn * n;
   int bits = 0;
   unsigned long long mask_prev;
@@ -239,48 +240,90 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
       const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
       const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
+      // the index of a stencil cell is a sum of one term per axis (element
+      // part plus sub-cell part); -1 marks a term outside the grid
+      int tx[3], ty[3], tz[3];
+      #pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int gx = g0 + d - 1, gy = g1 + d - 1, gz = g2 + d - 1;
+        tx[d] = (gx >= 0 && gx < G.gc[0]) ? (gx / G.k[0]) * G.kk + gx % G.k[0] : -1;
+        ty[d] = (gy >= 0 && gy < G.gc[1]) ? (gy / G.k[1]) * G.n_el[0] * G.kk + (gy % G.k[1]) * G.k[0] : -1;
+        tz[d] = (gz >= 0 && gz < G.gc[2])
+                    ? (gz / G.k[2]) * G.n_el[1] * G.n_el[0] * G.kk + (gz % G.k[2]) * G.k[1] * G.k[0]
+                    : -1;
+      }
       const int *cnt = sel(D.cnt, p3);
       const int *slot = sel(D.slot, p2);
+      const float4 *rec = sel(D.srec, p2);
+      // single-precision prefilter against the slot records, its cutoff
+      // widened so that it keeps every pair within ra + rb + skin exactly
+      const float xf0 = (float)xa0, xf1 = (float)xa1, xf2 = (float)xa2;
+      const float rsk = (float)ra + (float)D.skin;
+      constexpr float kCutRel = 1.0f + 0x1p-18f;
+      constexpr int kCand = 8;
       m = 0;
       #pragma unroll 1
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int gz = g2 + dz;
-        if (gz < 0 || gz >= G.gc[2]) continue;
-        const int ez = gz / G.k[2], sz = gz - ez * G.k[2];
-      #pragma unroll 1
-      for (int dy = -1; dy <= 1; ++dy) {
-          const int gy = g1 + dy;
-          if (gy < 0 || gy >= G.gc[1]) continue;
-          const int ey = gy / G.k[1], sy = gy - ey * G.k[1];
-      #pragma unroll 1
-      for (int dx = -1; dx <= 1; ++dx) {
-            const int gx = g0 + dx;
-            if (gx < 0 || gx >= G.gc[0]) continue;
-            const int ex = gx / G.k[0], sx = gx - ex * G.k[0];
-            const int c2 = ((ez * G.n_el[1] + ey) * G.n_el[0] + ex) * G.kk +
-                           (sz * G.k[1] + sy) * G.k[0] + sx;
-            int cm = cnt[c2];
-            if (cm > D.cap) cm = D.cap;
-            const int *sl = slot + (size_t)c2 * D.cap;
-            for (int s = 0; s < cm; ++s) {
-              const int b = sl[s];
-              if (b == a) continue;
-              if (!within_cutoff(xa0, xa1, xa2, xs[b], xs[n + b], xs[2 * n + b],
-                                 ra + D.rad[b] + D.skin))
-                continue;
-              const unsigned long long key =
-                  ((unsigned long long)(unsigned)D.oid[b] << 32) | (unsigned)b;
-              if (m < D.maxn) {
-                int p = m;
-                while (p > 0 && my_list[(p - 1) * kGroups] > key) {
-                  my_list[p * kGroups] = my_list[(p - 1) * kGroups];
-                  --p;
-                }
-                my_list[p * kGroups] = key;
-                ++m;
-              } else {
-                bits |= kErrCapacity;
+      for (int dz = 0; dz < 3; ++dz) {
+        const int z = dz == 0 ? tz[0] : (dz == 1 ? tz[1] : tz[2]);
+        if (z < 0) continue;
+        // the nine counts of this plane are loaded together; their prefix
+        // sums number the plane's candidates 0 .. tot-1 across its cells
+        int cc[9], pf[10];
+        pf[0] = 0;
+        #pragma unroll
+        for (int j = 0; j < 9; ++j) {
+          const int y = ty[j / 3], x = tx[j % 3];
+          const bool in = y >= 0 && x >= 0;
+          cc[j] = in ? z + y + x : 0;
+          pf[j + 1] = pf[j] + (in ? min(cnt[cc[j]], D.cap) : 0);
+        }
+        const int tot = pf[9];
+        // eight candidates at a time, whatever cells they are in: slot
+        // indices and records loaded together, then the original IDs of the
+        // candidates that pass
+        #pragma unroll 1
+        for (int q0 = 0; q0 < tot; q0 += kCand) {
+          int bq[kCand];
+          float4 rq[kCand];
+          bool ok[kCand];
+          #pragma unroll
+          for (int i = 0; i < kCand; ++i) {
+            const int q = q0 + i;
+            ok[i] = q < tot;
+            // the last cell whose first candidate is at or before q holds q
+            int c = cc[0], first = 0;
+            #pragma unroll
+            for (int j = 1; j < 9; ++j)
+              if (q >= pf[j]) {
+                c = cc[j];
+                first = pf[j];
               }
+            const size_t at = (size_t)c * D.cap + (q - first);
+            bq[i] = ok[i] ? slot[at] : a;
+            rq[i] = ok[i] ? rec[at] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+          unsigned oq[kCand];
+          #pragma unroll
+          for (int i = 0; i < kCand; ++i) {
+            const float d0 = rq[i].x - xf0, d1 = rq[i].y - xf1, d2 = rq[i].z - xf2;
+            const float cut = (rsk + rq[i].w) * kCutRel + D.marg;
+            ok[i] = ok[i] && bq[i] != a && d0 * d0 + d1 * d1 + d2 * d2 < cut * cut;
+            oq[i] = ok[i] ? (unsigned)D.oid[bq[i]] : 0u;
+          }
+          #pragma unroll
+          for (int i = 0; i < kCand; ++i) {
+            if (!ok[i]) continue;
+            const unsigned long long key = ((unsigned long long)oq[i] << 32) | (unsigned)bq[i];
+            if (m < D.maxn) {
+              int p = m;
+              while (p > 0 && my_list[(p - 1) * kGroups] > key) {
+                my_list[p * kGroups] = my_list[(p - 1) * kGroups];
+                --p;
+              }
+              my_list[p * kGroups] = key;
+              ++m;
+            } else {
+              bits |= kErrCapacity;
             }
           }
         }
@@ -459,7 +502,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
         wh1[i] = whc;
         x1[i] = xp[c];
       }
-      bin_and_test(D, a, xp, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.cell, q3), D.flag + q3, false, bits);
+      bin_and_test(D, a, xp, ra, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.srec, p2 ^ 1), sel(D.cell, q3),
+                   D.flag + q3, false, bits);
     }
   }
   if (a == 0) {

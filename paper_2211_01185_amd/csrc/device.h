@@ -53,6 +53,7 @@ struct Dev {
   double g[3];
   double skin;        // neighbour-list skin
   double trig2;       // squared displacement that triggers a new broad search
+  float marg;         // absolute margin of the single-precision broad-search test
   Material pp, pw;
   Grid grid;
   double *xs[2];         // positions x_s, by step parity
@@ -66,6 +67,8 @@ struct Dev {
   int *cell[3];          // cell of x_s, by step mod 3
   int *cnt[3];           // particles per cell, by step mod 3
   int *slot[2];          // ncells x cap particle indices, by step parity
+  float4 *srec[2];       // ncells x cap: position and radius of each slot's particle
+                         // in single precision (broad-search prefilter), by parity
   int *flag;             // [3] broad search requested, by step mod 3
   int *lbuf;             // [3] neighbour-list buffer in use, by step mod 3
   // neighbour lists (buffer lbuf): entries sorted by partner original ID
