@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--bed-config", default=None,
+                    help="JSON of the main bed's skin, resort_every and lanes, used instead of tuning "
+                         "(to repeat a tuned run under a counter profiler)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-served", action="store_true", help="skip the served stream")
     ap.add_argument("--batched-beds", type=int, default=64)
@@ -66,21 +69,29 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_sha():
     with open(KERNEL_SOURCE, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_entry(n_contacts):
+def traffic_entry(bed_kw):
     """HBM bytes per launch of the force kernel from the committed rocprofv3
-    counter summary, or None if it is absent or the kernel changed since."""
+    counter summary, or None if it is absent, the kernel changed since, or it
+    was taken with another tuned configuration."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha256") != kernel_source_sha():
         return None
-    return float(t["hbm_bytes_per_launch"])
+    cfg = t.get("config") or {}
+    same = (cfg.get("lanes") == bed_kw["lanes"] and cfg.get("resort_every") == bed_kw["resort_every"]
+            and abs(float(cfg.get("skin", -1.0)) - bed_kw["skin"]) <= 1e-9 * bed_kw["skin"])
+    return float(t["hbm_bytes_per_launch"]) if same else None
 
 
 def contact_counts(bed):
@@ -213,9 +224,14 @@ def main():
     # runs of this bed from its start over as many steps as are measured (the
     # rate of list rebuilds grows as the bed fluidizes); results do not depend
     # on them
-    tuned, tune_report = autotune.tune([wl], "fp32", steps=args.warmup + args.steps, device=dev,
-                                       use_cache=False)
-    bed_kw = autotune.bed_kwargs(wl, tuned)
+    if args.bed_config:
+        bed_kw = {k: json.loads(args.bed_config)[k] for k in ("skin", "resort_every", "lanes")}
+        tune_report = {"trials": 0, "default_ms_per_step": None}
+    else:
+        tuned, tune_report = autotune.tune([wl], "fp32", steps=args.warmup + args.steps, device=dev,
+                                           use_cache=False)
+        bed_kw = autotune.bed_kwargs(wl, tuned)
+    progress(f"tuned {bed_kw} in {tune_report['trials']} trials")
 
     def make_bed():
         bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, **bed_kw)
@@ -259,6 +275,7 @@ def main():
     pairs1, walls1 = contact_counts(bed)
     bed.close()
     del bed, out
+    progress(f"timed region: {wall * 1e3 / args.steps:.4f} ms per step")
 
     # roofline: the same deterministic trajectory replayed on a fresh bed, with
     # HIP events bound to every launch of the contact-force kernel on its
@@ -273,6 +290,7 @@ def main():
     launches, force_ms = bed.kernel_timing_read()
     pairs2, walls2 = contact_counts(bed)
     bed.close()
+    progress(f"replayed region: {launches} force-kernel launches, {force_ms * 1e3 / max(launches, 1):.2f} us each")
 
     elapsed = max(wall, gpu_ms / 1e3)
     value = wl.n * args.steps / elapsed
@@ -280,7 +298,7 @@ def main():
     force_avg_s = force_ms / 1e3 / max(launches, 1)
     alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
     achieved = alg_bytes / force_avg_s / 1e9
-    traffic = traffic_entry(contacts)
+    traffic = traffic_entry(bed_kw)
 
     result = {
         "metric": METRIC,
@@ -309,7 +327,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "force_kick (contact search + Hertz-Mindlin forces + second half kick)",
+            "kernel": f"force_kick<float, true, *, {bed_kw['lanes']}> (contact search + Hertz-Mindlin "
+                      "forces + second half kick)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -322,9 +341,13 @@ def main():
     }
     if not args.no_batched:
         result["batched"] = batched_ensemble(args.batched_beds, args.batched_steps, dev)
+        progress(f"batched: {result['batched']['value']:.4g} particle-steps/s")
     if not args.no_served:
+        progress("served stream: starting")
         result["served"] = served_stream(args.served_jobs, args.served_warmup, dev)
+        progress(f"served: p99 {result['served']['latency_p99_s']:.4f} s")
     if not args.no_cpu:
+        progress("oracle sample: starting")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(result), flush=True)
 

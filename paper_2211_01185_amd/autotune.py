@@ -130,10 +130,12 @@ def _time_batch(wls, fields, cfg, precision, steps, device):
     return dt / (chunks * COUPLING_EVERY) if ok else float("inf")
 
 
-def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample=8):
+def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample=8, min_gain=0.01):
     """Best configuration for running these beds, tuned on up to `sample` of
     them: one bed is timed through the single-bed entry points, several as a
-    batch.  Returns (config, report)."""
+    batch.  A candidate replaces the current best only when it is faster by
+    more than `min_gain` (relative), so that timing noise does not move the
+    choice.  Returns (config, report)."""
     import torch
 
     key = signature(wls, precision)
@@ -158,7 +160,7 @@ def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample
         for v in values:
             cfg = dict(best, **{knob: v})
             t = timed(cfg)
-            if t < t_best:
+            if t < t_best * (1.0 - min_gain):
                 best, t_best = cfg, t
     report = {"config": best, "ms_per_step": t_best * 1e3, "default_ms_per_step": trials[json.dumps(DEFAULT, sort_keys=True)] * 1e3,
               "trials": len(trials), "tuned_on_beds": len(sub), "signature": key, "cached": False}
