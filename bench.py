@@ -40,11 +40,12 @@ METRIC = "DEM+coupling particle-steps/s @100k spheres; batched jobs/s + p99 late
 HBM_PEAK_GBS = 8000.0
 COUPLING_EVERY = 10
 RESORT_EVERY = 100
-# algorithmic bytes of the contact-force kernel: per particle it must read
-# x, v_half, w_half (72 B), radius and mass (16 B), the held fluid force (24 B)
-# and write v, w (48 B); per contact (pair or wall) read + write the tangential
-# overlap (48 B) and the partner index (8 B).
-FORCE_BYTES_PER_PARTICLE = 160
+# algorithmic bytes of one DEM step (one launch of the contact-force kernel):
+# per particle it must read x, v_half, w_half (72 B), radius and mass (16 B) and
+# the held fluid force (24 B), and write the next step's x, v_half, w_half
+# (72 B); per contact (pair or wall) read + write the tangential overlap (48 B)
+# and read the partner index (8 B).
+FORCE_BYTES_PER_PARTICLE = 184
 BYTES_PER_CONTACT = 56
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kick_fluidized_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_01185_amd", "csrc", "dem_kernels.hip")
