@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CFDDEM_ABI_VERSION 1
+#define CFDDEM_ABI_VERSION 2
 
 typedef struct dem_ctx dem_ctx;
 typedef int32_t dem_status;
@@ -111,6 +111,15 @@ typedef struct {
                             broad search lists partners within R_i + R_j + skin
                             and is redone on the device as soon as a particle
                             has moved more than skin/2 since the last one */
+  double mu_r, mu_r_w;   /* rolling friction coefficients, particle-particle and
+                            particle-wall, >= 0 (0 = no rolling torque).  The
+                            rolling torque M^r of Eq. "angular_momentum" (its
+                            form is not given in the paper) is the constant
+                            torque -mu_r R_e |f_n| w/|w| with w = w_i - w_j the
+                            relative angular velocity at the half step (w_i
+                            against a wall) and f_n the full normal force; it
+                            acts on i, its negation on j, and is zero when
+                            w = 0 */
 } dem_params;
 
 /* Coupling parameters (host struct).  The structured hex mesh spans the DEM
@@ -129,6 +138,12 @@ typedef struct {
   int32_t model;   /* DEM_MODEL_A or DEM_MODEL_B (decides what is handed to
                       the fluid, Eqs. "fa" / "fb") */
   double eps_min;  /* the drag closure sees clamp(eps, eps_min, 1); (0, 1] */
+  int32_t shear;   /* 1: add the shear force f = -V_p div(tau_f) (Section 2.3.2,
+                      Eqs. "fa" / "fb"), with tau_f the stress of Eq. "stress"
+                      evaluated from the Q_n velocity field at the particle
+                      (div tau = mu_f (lap u + grad(div u) / 3)); model B also
+                      hands it to the fluid.  0: no shear force */
+  int32_t reserved; /* must be 0 */
 } cfd_params;
 
 /* Bytes of device workspace dem_create needs for these parameters.  Pure host
@@ -160,7 +175,10 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
  * forces at the half-step velocities, second half kick. */
 dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream);
 
-/* One coupling step at the current particle state with the given fluid field.
+/* One coupling step at the current particle state with the given fluid field
+ * (Section 2.3: locate and PCM void fraction, Q_n interpolation at the
+ * particles, drag closure, particle forces, reduction to quadrature points;
+ * F_pf of Eqs. "fa" / "fb").
  *   u_nodes: 3 x n_v nodal velocity (component-major over velocity nodes)
  *   p_nodes: n_p nodal pressure (Q1); must not contain the hydrostatic part
  *            rho_f g.x, since buoyancy is applied to the particles explicitly
@@ -168,9 +186,10 @@ dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream);
  *   fpf_q: 3 x (n_el*n_q) force density on the fluid (component-major)
  *   elem_sums: NULL, or 12 x n_el (component-major over elements):
  *     0 particle count, 1 sum V_p, 2 sum beta_p, 3-5 sum beta_p u_p,
- *     6-8 sum f_D, 9-11 sum f_gradp
- * Also stores f_fp = f_D + f_B + f_gradp per particle, held by the following
- * dem_step calls. */
+ *     6-8 sum f_D, 9-11 sum of the undisturbed-flow forces f_gradp (+ f_shear
+ *     when cfd_params.shear is set)
+ * Also stores f_fp = f_D + f_B + f_gradp (+ f_shear) per particle, held by the
+ * following dem_step calls. */
 dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_nodes,
                           double *eps_q, double *beta_q, double *fpf_q, double *elem_sums,
                           void *stream);

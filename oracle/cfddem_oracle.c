@@ -228,6 +228,7 @@ long orc_find_pairs(long n, const double *x, const double *r, const double lo[3]
 /* ------------------------------------------------------------------------- */
 typedef struct {
   double Ye, Ge, beta, mu; /* effective Young, effective shear, beta(e), Coulomb */
+  double mu_r;             /* rolling friction coefficient */
 } material_t;
 
 /* 1/Y_e = (1-nu_i^2)/Y_i + (1-nu_j^2)/Y_j */
@@ -251,10 +252,11 @@ static double restitution_beta(double e) {
  *   Re, me  effective radius and mass
  *   dt_old  stored tangential overlap (canonical orientation), or zeros
  *   advance 1: project onto the tangent plane and add v_rt*dt; 0: use dt_old
- * Outputs f (normal + tangential), ft, and the updated tangential overlap. */
+ * Outputs f (normal + tangential), ft, the updated tangential overlap and the
+ * magnitude of the normal force. */
 static void contact_law(const material_t *mat, const double n[3], double dn, const double vij[3],
                         double Re, double me, double dt, const double dt_old[3], int advance,
-                        double f[3], double ft[3], double dt_new[3]) {
+                        double f[3], double ft[3], double dt_new[3], double *fn_out) {
   double sq = sqrt(Re * dn);
   double kn = 4.0 / 3.0 * mat->Ye * sq;
   double kt = 8.0 * mat->Ge * sq;
@@ -290,6 +292,19 @@ static void contact_law(const material_t *mat, const double n[3], double dn, con
     }
   }
   for (int c = 0; c < 3; ++c) f[c] = fn[c] + ft[c];
+  *fn_out = fn_mag;
+}
+
+/* Rolling friction torque on the first body of a contact (Eq.
+ * "angular_momentum" names M^r_ij without giving its form): the constant
+ * torque -mu_r R_e |f_n| w/|w| opposing the relative angular velocity
+ * w = w_i - w_j (w_i against a wall), zero when w = 0.  The second body
+ * receives its negation. */
+static void rolling_torque(double mu_r, double Re, double fn_mag, const double w[3], double M[3]) {
+  double wm = norm3(w);
+  for (int c = 0; c < 3; ++c) M[c] = 0.0;
+  if (mu_r > 0.0 && wm > 0.0)
+    for (int c = 0; c < 3; ++c) M[c] = -mu_r * Re * fn_mag * w[c] / wm;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -401,16 +416,19 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
       for (int k = 0; k < 3; ++k) vij[k] = vi[k] - vj[k] + cr[k];
       double Re = 1.0 / (1.0 / Ri + 1.0 / Rj);
       double me = 1.0 / (1.0 / s->m[i] + 1.0 / s->m[j]);
-      contact_law(&s->pp, nrm, dn, vij, Re, me, s->p.dt, dt_old, advance, f, ft, dt_new);
-      double ti[3], tj[3], nxft[3];
+      double fn_mag;
+      contact_law(&s->pp, nrm, dn, vij, Re, me, s->p.dt, dt_old, advance, f, ft, dt_new, &fn_mag);
+      double ti[3], tj[3], nxft[3], Mr[3];
+      double wrel[3] = {wi[0] - wj[0], wi[1] - wj[1], wi[2] - wj[2]};
+      rolling_torque(s->pp.mu_r, Re, fn_mag, wrel, Mr);
       cross3(nrm, ft, nxft);
       for (int k = 0; k < 3; ++k) {
         ti[k] = Ri * nxft[k];
         tj[k] = Rj * nxft[k];
         s->Fc[k * n + i] += f[k];
         s->Fc[k * n + j] -= f[k];
-        s->Tc[k * n + i] += ti[k];
-        s->Tc[k * n + j] += tj[k];
+        s->Tc[k * n + i] += ti[k] + Mr[k];
+        s->Tc[k * n + j] += tj[k] - Mr[k];
       }
     } else {
       int wall = -1 - (int)j;
@@ -422,12 +440,14 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
       double rw[3] = {Ri * wi[0], Ri * wi[1], Ri * wi[2]};
       cross3(rw, nrm, cr);
       for (int k = 0; k < 3; ++k) vij[k] = vi[k] + cr[k];
-      contact_law(&s->pw, nrm, dn, vij, Ri, s->m[i], s->p.dt, dt_old, advance, f, ft, dt_new);
-      double nxft[3];
+      double fn_mag;
+      contact_law(&s->pw, nrm, dn, vij, Ri, s->m[i], s->p.dt, dt_old, advance, f, ft, dt_new, &fn_mag);
+      double nxft[3], Mr[3];
+      rolling_torque(s->pw.mu_r, Ri, fn_mag, wi, Mr);
       cross3(nrm, ft, nxft);
       for (int k = 0; k < 3; ++k) {
         s->Fc[k * n + i] += f[k];
-        s->Tc[k * n + i] += Ri * nxft[k];
+        s->Tc[k * n + i] += Ri * nxft[k] + Mr[k];
       }
     }
     na[c] = i;
@@ -470,10 +490,12 @@ orc_dem *orc_dem_create(const orc_params *p, long n, const double *x, const doub
   s->pp.Ge = effective_shear(p->E, p->nu, p->E, p->nu);
   s->pp.beta = restitution_beta(p->e);
   s->pp.mu = p->mu;
+  s->pp.mu_r = p->mu_r;
   s->pw.Ye = effective_young(p->E, p->nu, p->E_w, p->nu_w);
   s->pw.Ge = effective_shear(p->E, p->nu, p->E_w, p->nu_w);
   s->pw.beta = restitution_beta(p->e_w);
   s->pw.mu = p->mu_w;
+  s->pw.mu_r = p->mu_r_w;
   size_t v3 = sizeof(double) * 3 * (n ? n : 1);
   s->x = (double *)xmalloc(v3);
   s->v = (double *)xmalloc(v3);
@@ -566,6 +588,26 @@ double orc_lagrange_deriv(int p, int k, double t) {
   return sum;
 }
 
+/* Second derivative: sum over ordered pairs (q, r) of dropped factors. */
+double orc_lagrange_deriv2(int p, int k, double t) {
+  double tk = (double)k / p;
+  double sum = 0.0;
+  for (int q = 0; q <= p; ++q) {
+    if (q == k) continue;
+    for (int r = 0; r <= p; ++r) {
+      if (r == k || r == q) continue;
+      double term = 1.0 / (tk - (double)q / p) / (tk - (double)r / p);
+      for (int m = 0; m <= p; ++m) {
+        if (m == k || m == q || m == r) continue;
+        double tm = (double)m / p;
+        term *= (t - tm) / (tk - tm);
+      }
+      sum += term;
+    }
+  }
+  return sum;
+}
+
 /* Element of a point and its reference coordinates xi in [0,1]^3. */
 static void locate(const orc_fluid *f, const double lo[3], const double hi[3], const double xp[3],
                    long e[3], double xi[3]) {
@@ -621,6 +663,70 @@ static void interp_pressure_gradient(const orc_fluid *f, const double lo[3], con
 static long velocity_node_count(const orc_fluid *f) {
   long p = f->order;
   return (p * f->n_el[0] + 1) * (p * f->n_el[1] + 1) * (p * f->n_el[2] + 1);
+}
+
+/* d^0, d^1 or d^2 of the 1D basis k at t. */
+static double lagrange_d(int p, int k, int order, double t) {
+  if (order == 0) return orc_lagrange(p, k, t);
+  if (order == 1) return orc_lagrange_deriv(p, k, t);
+  return orc_lagrange_deriv2(p, k, t);
+}
+
+/* div(tau_f) at a point (Eq. "stress"):
+ *   tau_cj = mu_f (d_j u_c + d_c u_j) - 2/3 mu_f (div u) delta_cj,
+ *   (div tau)_c = sum_j d_j tau_cj,
+ * from the Hessians H[c][a][b] = d_a d_b u_c of the Q_n field. */
+static void stress_divergence(const orc_fluid *f, const double lo[3], const double hi[3],
+                              const long e[3], const double xi[3], const double *U, long n_v,
+                              double out[3]) {
+  int p = f->order;
+  double inv_he[3];
+  for (int a = 0; a < 3; ++a) inv_he[a] = (double)f->n_el[a] / (hi[a] - lo[a]);
+  double H[3][3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) H[c][a][b] = 0.0;
+  for (int ic = 0; ic <= p; ++ic)
+    for (int ib = 0; ib <= p; ++ib)
+      for (int ia = 0; ia <= p; ++ia) {
+        long node = node_index(p, f->n_el, e, ia, ib, ic);
+        int loc[3] = {ia, ib, ic};
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            int ord[3] = {0, 0, 0};
+            ord[a] += 1;
+            ord[b] += 1;
+            double d2N = inv_he[a] * inv_he[b];
+            for (int ax = 0; ax < 3; ++ax) d2N *= lagrange_d(p, loc[ax], ord[ax], xi[ax]);
+            for (int c = 0; c < 3; ++c) H[c][a][b] += d2N * U[c * n_v + node];
+          }
+      }
+  double mu = f->mu_f;
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double d_tau = mu * (H[c][j][j] + H[j][c][j]); /* d_j of mu (d_j u_c + d_c u_j) */
+      if (j == c) {
+        double d_div = 0.0; /* d_c (div u) */
+        for (int k = 0; k < 3; ++k) d_div += H[k][k][c];
+        d_tau -= 2.0 / 3.0 * mu * d_div;
+      }
+      s += d_tau;
+    }
+    out[c] = s;
+  }
+}
+
+void orc_stress_divergence(const orc_fluid *f, const double lo[3], const double hi[3], long n,
+                           const double *x, const double *U, double *out) {
+  long n_v = velocity_node_count(f);
+  for (long i = 0; i < n; ++i) {
+    double xp[3] = {x[i], x[n + i], x[2 * n + i]}, xi[3], dv[3];
+    long e[3];
+    locate(f, lo, hi, xp, e, xi);
+    stress_divergence(f, lo, hi, e, xi, U, n_v, dv);
+    for (int c = 0; c < 3; ++c) out[c * n + i] = dv[c];
+  }
 }
 
 void orc_interpolate(const orc_fluid *f, const double lo[3], const double hi[3], long n,
@@ -773,7 +879,7 @@ static void gauss_rule(int npts, double *pt, double *wt) {
 
 /* Element sums layout (component-major over elements, 12 rows):
  *   0 count, 1 sum V_p, 2 sum beta_p, 3-5 sum beta_p u_p, 6-8 sum f_D,
- *   9-11 sum f_gradp. */
+ *   9-11 sum of the undisturbed-flow forces f_gradp (+ f_shear when enabled). */
 #define ES_ROWS 12
 
 int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double *P,
@@ -823,14 +929,17 @@ int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double
     double Vp = 4.0 / 3.0 * PI * s->r[i] * s->r[i] * s->r[i];
     double beta = orc_drag_beta(f->drag, f->rho_f, f->mu_f, eps_c, d, norm3(slip));
     if (f->beta_over_eps) beta /= eps_c; /* beta_B = beta_A / eps (Eq. "beta") */
+    double dtau[3] = {0.0, 0.0, 0.0};
+    if (f->shear) stress_divergence(f, lo, hi, e, xi, U, n_v, dtau);
     for (int c = 0; c < 3; ++c) {
       double fD = beta * slip[c];
       double fB = -f->rho_f * Vp * g[c];
       double fG = -Vp * gp[c];
-      s->ffp[c * n + i] = fD + fB + fG;
+      double fS = -Vp * dtau[c]; /* shear force (zero unless enabled) */
+      s->ffp[c * n + i] = fD + fB + fG + fS;
       sums[(3 + c) * nel + el] += beta * up[c];
       sums[(6 + c) * nel + el] += fD;
-      sums[(9 + c) * nel + el] += fG;
+      sums[(9 + c) * nel + el] += fG + fS; /* undisturbed-flow forces */
     }
     sums[2 * nel + el] += beta;
   }

@@ -33,6 +33,7 @@ typedef struct {
   double dt;                   /* DEM time step */
   double E, nu, e, mu;         /* particle-particle: Young, Poisson, restitution, Coulomb */
   double E_w, nu_w, e_w, mu_w; /* particle-wall: wall Young, wall Poisson, restitution, Coulomb */
+  double mu_r, mu_r_w;         /* rolling friction, particle-particle and particle-wall (0: none) */
 } orc_params;
 
 /* Fluid / mesh parameters of the coupling (Section 2.3).  The structured hex
@@ -46,6 +47,7 @@ typedef struct {
   double eps_min; /* lower clamp of the void fraction seen by the drag closure */
   int drag;       /* ORC_DRAG_*: closure of the momentum-exchange coefficient */
   int beta_over_eps; /* 1: beta_B = beta_A / eps (Eq. "beta"), 0: the same beta for both models */
+  int shear;      /* 1: shear force -V_p div(tau_f) on the particles (Eqs. "fa", "fb") */
 } orc_fluid;
 
 /* Drag closures of Section 2.3.2. */
@@ -95,6 +97,12 @@ double orc_difelice_beta(double rho_f, double mu_f, double eps, double d, double
  * speed |slip| >= 0; finite limits at zero slip.  Returns NaN for an unknown
  * closure. */
 double orc_drag_beta(int drag, double rho_f, double mu_f, double eps, double d, double slip);
+/* Second derivative of Lagrange polynomial k of degree p on nodes m/p. */
+double orc_lagrange_deriv2(int p, int k, double t);
+/* div(tau_f) of Eq. "stress" at each of n points x (3 x n) from the nodal
+ * velocities U (3 x n_v); out: 3 x n. */
+void orc_stress_divergence(const orc_fluid *f, const double lo[3], const double hi[3], long n,
+                           const double *x, const double *U, double *out);
 
 /* ---- whole-step routines ---- */
 

@@ -25,6 +25,7 @@ class OrcParams(C.Structure):
         ("dt", C.c_double),
         ("E", C.c_double), ("nu", C.c_double), ("e", C.c_double), ("mu", C.c_double),
         ("E_w", C.c_double), ("nu_w", C.c_double), ("e_w", C.c_double), ("mu_w", C.c_double),
+        ("mu_r", C.c_double), ("mu_r_w", C.c_double),
     ]
 
 
@@ -32,6 +33,7 @@ class OrcFluid(C.Structure):
     _fields_ = [
         ("order", C.c_int), ("n_el", C.c_int * 3), ("rho_f", C.c_double), ("mu_f", C.c_double),
         ("model", C.c_int), ("eps_min", C.c_double), ("drag", C.c_int), ("beta_over_eps", C.c_int),
+        ("shear", C.c_int),
     ]
 
 
@@ -60,6 +62,10 @@ def _load():
     lib.orc_lagrange.argtypes = [C.c_int, C.c_int, C.c_double]
     lib.orc_lagrange_deriv.restype = C.c_double
     lib.orc_lagrange_deriv.argtypes = [C.c_int, C.c_int, C.c_double]
+    lib.orc_lagrange_deriv2.restype = C.c_double
+    lib.orc_lagrange_deriv2.argtypes = [C.c_int, C.c_int, C.c_double]
+    lib.orc_stress_divergence.restype = None
+    lib.orc_stress_divergence.argtypes = [C.POINTER(OrcFluid), _dp, _dp, C.c_long, _dp, _dp, _dp]
     lib.orc_interpolate.restype = None
     lib.orc_interpolate.argtypes = [C.POINTER(OrcFluid), _dp, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp]
     lib.orc_difelice_beta.restype = C.c_double
@@ -100,7 +106,7 @@ def _f64(a, shape=None):
 
 
 def make_params(box_lo, box_hi, gravity, dt, E, nu, e, mu, E_w=None, nu_w=None, e_w=None,
-                mu_w=None) -> OrcParams:
+                mu_w=None, mu_r=0.0, mu_r_w=None) -> OrcParams:
     p = OrcParams()
     p.box_lo[:] = [float(v) for v in box_lo]
     p.box_hi[:] = [float(v) for v in box_hi]
@@ -111,10 +117,13 @@ def make_params(box_lo, box_hi, gravity, dt, E, nu, e, mu, E_w=None, nu_w=None, 
     p.nu_w = nu if nu_w is None else nu_w
     p.e_w = e if e_w is None else e_w
     p.mu_w = mu if mu_w is None else mu_w
+    p.mu_r = float(mu_r)
+    p.mu_r_w = float(mu_r if mu_r_w is None else mu_r_w)
     return p
 
 
-def make_fluid(order, n_el, rho_f, mu_f, model=0, eps_min=0.1, drag=0, beta_over_eps=0) -> OrcFluid:
+def make_fluid(order, n_el, rho_f, mu_f, model=0, eps_min=0.1, drag=0, beta_over_eps=0,
+               shear=0) -> OrcFluid:
     f = OrcFluid()
     f.order = int(order)
     f.n_el[:] = [int(v) for v in n_el]
@@ -123,7 +132,23 @@ def make_fluid(order, n_el, rho_f, mu_f, model=0, eps_min=0.1, drag=0, beta_over
     f.eps_min = float(eps_min)
     f.drag = DRAG[drag] if isinstance(drag, str) else int(drag)
     f.beta_over_eps = int(beta_over_eps)
+    f.shear = int(shear)
     return f
+
+
+def stress_divergence(f: OrcFluid, lo, hi, x, U):
+    """div(tau_f) of Eq. "stress" at the points x (3, n) of the field U (3, n_v)."""
+    lib = _load()
+    x = _f64(x)
+    n = x.shape[1]
+    U = _f64(U)
+    out = np.zeros((3, n))
+    lib.orc_stress_divergence(C.byref(f), _d(_f64(lo)), _d(_f64(hi)), n, _d(x), _d(U), _d(out))
+    return out
+
+
+def lagrange_deriv2(p, k, t):
+    return _load().orc_lagrange_deriv2(int(p), int(k), float(t))
 
 
 def bin_particles(x, lo, hi, n_el, k):

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libcfddem.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 DEM_OK = 0
 DEM_E_ARG = -1
@@ -47,6 +47,7 @@ class DemParams(C.Structure):
         ("E_w", C.c_double), ("nu_w", C.c_double), ("e_w", C.c_double), ("mu_w", C.c_double),
         ("max_neighbors", C.c_int32), ("cell_capacity", C.c_int32), ("resort_every", C.c_int32),
         ("lanes", C.c_int32), ("d_max", C.c_double), ("d_min", C.c_double), ("skin", C.c_double),
+        ("mu_r", C.c_double), ("mu_r_w", C.c_double),
     ]
 
 
@@ -54,6 +55,7 @@ class CfdParams(C.Structure):
     _fields_ = [
         ("order", C.c_int32), ("n_el", C.c_int32 * 3), ("rho_f", C.c_double), ("mu_f", C.c_double),
         ("drag", C.c_int32), ("model", C.c_int32), ("eps_min", C.c_double),
+        ("shear", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -149,6 +151,8 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     dp.d_max = float(d_max)
     dp.d_min = float(d_min)
     dp.skin = float(skin)
+    dp.mu_r = float(dem.get("mu_r", 0.0))
+    dp.mu_r_w = float(dem.get("mu_r_w", dem.get("mu_r", 0.0)))
     cp = CfdParams()
     cp.order = int(fluid["order"])
     cp.n_el[:] = [int(v) for v in fluid["n_el"]]
@@ -158,6 +162,7 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     cp.drag = (DRAG[drag] if isinstance(drag, str) else int(drag)) | (0x100 if fluid.get("beta_over_eps") else 0)
     cp.model = int(fluid.get("model", 0))
     cp.eps_min = float(fluid.get("eps_min", 0.1))
+    cp.shear = 1 if fluid.get("shear") else 0
     return dp, cp
 
 

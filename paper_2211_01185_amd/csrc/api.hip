@@ -23,13 +23,14 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
 hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
                                   hipStream_t st);
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, int lanes, hipStream_t st);
+                                   int i, bool cont, bool fp32, int maxn, int lanes, bool roll,
+                                   hipStream_t st);
 hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
 hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
                                 hipStream_t st);
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
-                               const unsigned *map_class, int blocks_class, int *cnt_word,
-                               unsigned *list, long long total_elems, int order, bool fp32, bool gen,
+                               const unsigned *map_class, int blocks_class, int *cnt_words,
+                               unsigned *list, const long long mode_elems[3], int order, bool fp32,
                                hipStream_t st);
 int couple_class_elems_per_block();
 }  // namespace cfddem
@@ -67,6 +68,8 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!(dp->nu > -1.0 && dp->nu < 0.5) || !(dp->nu_w > -1.0 && dp->nu_w < 0.5)) return DEM_E_ARG;
   if (!(dp->e > 0.0 && dp->e <= 1.0) || !(dp->e_w > 0.0 && dp->e_w <= 1.0)) return DEM_E_ARG;
   if (!(dp->mu >= 0.0) || !(dp->mu_w >= 0.0)) return DEM_E_ARG;
+  if (!(dp->mu_r >= 0.0) || !(dp->mu_r_w >= 0.0) || !isfinite(dp->mu_r) || !isfinite(dp->mu_r_w))
+    return DEM_E_ARG;
   if (!finite_pos(dp->d_max) || !finite_pos(dp->d_min) || dp->d_min > dp->d_max) return DEM_E_ARG;
   if (dp->max_neighbors < 0 || dp->max_neighbors > kMaxNeighbors) return DEM_E_ARG;
   if (!(dp->skin >= 0.0) || !isfinite(dp->skin)) return DEM_E_ARG;
@@ -84,6 +87,7 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!finite_pos(cp->rho_f) || !finite_pos(cp->mu_f)) return DEM_E_ARG;
   if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
   if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
+  if ((cp->shear != 0 && cp->shear != 1) || cp->reserved != 0) return DEM_E_ARG;
   if ((cp->drag & ~(0xff | DEM_DRAG_BETA_OVER_EPS)) != 0 || (cp->drag & 0xff) > DEM_DRAG_GIDASPOW)
     return DEM_E_UNSUPPORTED;
 
@@ -608,6 +612,8 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   };
   D.pp = material(dp->E, dp->nu, dp->E, dp->nu, dp->e, dp->mu);
   D.pw = material(dp->E, dp->nu, dp->E_w, dp->nu_w, dp->e_w, dp->mu_w);
+  D.pp.mu_r = dp->mu_r;
+  D.pw.mu_r = dp->mu_r_w;
   // coupling constants
   Cpl &C = ctx->C;
   C.order = cp->order;
@@ -623,6 +629,7 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   C.model = cp->model;
   C.drag = cp->drag & 0xff;
   C.beta_over_eps = (cp->drag & DEM_DRAG_BETA_OVER_EPS) ? 1 : 0;
+  C.shear = cp->shear;
   C.Ve = S.grid.he[0] * S.grid.he[1] * S.grid.he[2];
   {
     double gp[3];
@@ -851,7 +858,14 @@ struct dem_batch {
   int order = 2;
   int maxn = 1;
   int lanes = kForceLanes;
-  bool gen_drag = false;  // some bed uses a closure other than Di Felice
+  // beds are grouped by kernel variant, each group with its own launches, so
+  // that a bed's arithmetic never depends on the other beds: the force map
+  // holds the blocks of the beds without rolling friction first
+  // (nb_force_plain of them), then those of the beds with it; the coupling
+  // lists occupied elements per element-kernel variant (mode_elems[m]
+  // elements of the beds in mode m)
+  int nb_force_plain = 0;
+  long long mode_elems[3] = {0, 0, 0};
   // device tables and maps (carved from the caller's workspace)
   Dev *tab = nullptr;
   Cpl *ctab = nullptr;
@@ -955,16 +969,22 @@ dem_status batch_resorts(dem_batch *B, hipStream_t st) {
 // Enqueues n steps of every bed (no re-sorts).
 dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
   HIP_TRY(launch_drift_bin_batch(B->tab, B->run, B->map_drift, B->nb_drift, st));
-  for (int i = 1; i <= n; ++i)
-    HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force, i, i < n, B->fp32,
-                                    B->maxn, B->lanes, st));
+  const int nb_roll = B->nb_force - B->nb_force_plain;
+  for (int i = 1; i <= n; ++i) {
+    if (B->nb_force_plain > 0)
+      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force_plain, i, i < n, B->fp32,
+                                      B->maxn, B->lanes, false, st));
+    if (nb_roll > 0)
+      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force + B->nb_force_plain, nb_roll, i, i < n,
+                                      B->fp32, B->maxn, B->lanes, true, st));
+  }
   HIP_TRY(launch_batch_advance(B->run, (int)B->beds.size(), n, st));
   return DEM_OK;
 }
 
 dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
   HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
-                              B->list, B->total_elems, B->order, B->fp32, B->gen_drag, st));
+                              B->list, B->mode_elems, B->order, B->fp32, st));
   return DEM_OK;
 }
 
@@ -1030,7 +1050,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
   std::vector<Cpl> ctab;
   std::vector<CplIO> iot;
   std::vector<BedRun> run;
-  std::vector<unsigned> md, mf, mc;
+  std::vector<unsigned> md, mf, mf_roll, mc;
   for (int b = 0; b < n_beds; ++b) {
     const dem_ctx *ctx = beds[b];
     tab.push_back(ctx->B.D);
@@ -1041,11 +1061,14 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
     iot.push_back(io);
     run.push_back(BedRun{ctx->s, ctx->pending_src});
     if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
-    if (ctx->C.drag != 0) B->gen_drag = true;
+    if (couples) B->mode_elems[cpl_mode_of(ctx->C.drag, ctx->C.shear)] += ctx->S.grid.n_elem;
+    const bool roll = ctx->B.D.pp.mu_r > 0.0 || ctx->B.D.pw.mu_r > 0.0;
     fill_map(md, b, ceil_div(ctx->S.n, 256));
-    fill_map(mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
+    fill_map(roll ? mf_roll : mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
     if (couples) fill_map(mc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));
   }
+  B->nb_force_plain = (int)mf.size();
+  mf.insert(mf.end(), mf_roll.begin(), mf_roll.end());
   hipStream_t st = (hipStream_t)stream;
   auto fail = [&](dem_status code) {
     delete B;

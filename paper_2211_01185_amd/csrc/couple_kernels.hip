@@ -198,10 +198,92 @@ __device__ inline void basis1d(int order, double t, double L[3]) {
   }
 }
 
+// First and second derivatives of the 1D basis with respect to t.
+__device__ inline void basis1d_deriv(int order, double t, double d1[3], double d2[3]) {
+  if (order == 2) {
+    d1[0] = 4.0 * t - 3.0;
+    d1[1] = 4.0 - 8.0 * t;
+    d1[2] = 4.0 * t - 1.0;
+    d2[0] = 4.0;
+    d2[1] = -8.0;
+    d2[2] = 4.0;
+  } else {
+    d1[0] = -1.0;
+    d1[1] = 1.0;
+    d1[2] = 0.0;
+    d2[0] = d2[1] = d2[2] = 0.0;
+  }
+}
+
+// Divergence of the fluid stress (Eq. "stress") at local coordinates xi of an
+// element whose nodal velocities are sU:
+//   div tau = mu_f (lap u + grad(div u) / 3),
+// from the second derivatives of the Q_n field, sum-factorized axis by axis.
+template <int ORD>
+__device__ inline void div_tau(const double xi[3], const double (*sU)[27], const double inv_he[3],
+                               double mu_f, double out[3]) {
+  constexpr int p1 = ORD + 1;
+  double V[3][3], D1[3][3], D2[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    basis1d(ORD, xi[a], V[a]);
+    basis1d_deriv(ORD, xi[a], D1[a], D2[a]);
+  }
+  // per component c the second derivatives of u_c; kept are its Laplacian
+  // and its terms of grad(div u) (d_a d_c u_c for each axis a)
+  double lap[3], gdiv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double hxx = 0.0, hyy = 0.0, hzz = 0.0, hxy = 0.0, hxz = 0.0, hyz = 0.0;
+#pragma unroll
+    for (int ic = 0; ic < p1; ++ic) {
+      double sxx = 0.0, syy = 0.0, s00 = 0.0, sxy = 0.0, s10 = 0.0, s01 = 0.0;
+#pragma unroll
+      for (int ib = 0; ib < p1; ++ib) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < p1; ++ia) {
+          const double u = sU[c][(ic * p1 + ib) * p1 + ia];
+          a0 += V[0][ia] * u;
+          a1 += D1[0][ia] * u;
+          a2 += D2[0][ia] * u;
+        }
+        sxx += V[1][ib] * a2;
+        syy += D2[1][ib] * a0;
+        s00 += V[1][ib] * a0;
+        sxy += D1[1][ib] * a1;
+        s10 += V[1][ib] * a1;
+        s01 += D1[1][ib] * a0;
+      }
+      hxx += V[2][ic] * sxx;
+      hyy += V[2][ic] * syy;
+      hzz += D2[2][ic] * s00;
+      hxy += V[2][ic] * sxy;
+      hxz += D1[2][ic] * s10;
+      hyz += D1[2][ic] * s01;
+    }
+    hxx *= inv_he[0] * inv_he[0];
+    hyy *= inv_he[1] * inv_he[1];
+    hzz *= inv_he[2] * inv_he[2];
+    hxy *= inv_he[0] * inv_he[1];
+    hxz *= inv_he[0] * inv_he[2];
+    hyz *= inv_he[1] * inv_he[2];
+    lap[c] = hxx + hyy + hzz;
+    gdiv[0] += c == 0 ? hxx : (c == 1 ? hxy : hxz);
+    gdiv[1] += c == 0 ? hxy : (c == 1 ? hyy : hyz);
+    gdiv[2] += c == 0 ? hxz : (c == 1 ? hyz : hzz);
+    // one component's nodal values in flight at a time (bounds the registers)
+    __asm__ volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = mu_f * (lap[c] + gdiv[c] / 3.0);
+}
+
 
 // Di Felice (closure 0), the default.  The element kernels are instantiated
-// with GEN = false when every bed uses it, so that the other closures' code
-// and registers stay out of that path.
+// per MODE: 0 when every bed uses Di Felice without the shear force, 1 for
+// any closure, 2 for any closure with the shear force, so that each path
+// keeps only the code and registers it needs.
 template <typename R>
 __device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
   using T = Tr<R>;
@@ -223,7 +305,7 @@ __device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
 
 // Per-particle step 3 of one element: interpolation, closure, f_fp, and the
 // thread's running element sums.
-template <typename R, int ORD, bool GEN>
+template <typename R, int ORD, int MODE>
 __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const int ee[3],
                                       const double xp[3], const double up[3], double r,
                                       double eps_c, const double (*sU)[27], const double *sP,
@@ -277,18 +359,32 @@ __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const i
   const double Vp = 4.0 / 3.0 * kPi * r * r * r;
   const double sl[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
   const double slip = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + sl[2] * sl[2]);
+  constexpr bool GEN = MODE >= 1;
   double beta = GEN ? (double)drag_beta<R>(C.drag, R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip))
                     : (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
   if (C.beta_over_eps) beta /= eps_c;  // beta_B = beta_A / eps (Eq. "beta")
+  // shear force -V_p div tau (Eqs. "fa", "fb"), when enabled; added as a
+  // separate term, so that a bed without it computes the same arithmetic in
+  // every instantiation
+  const bool shear = MODE == 2 && C.shear;
+  double dtau[3] = {0.0, 0.0, 0.0};
+  if (shear) div_tau<ORD>(xi, sU, G.inv_he, C.mu_f, dtau);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double fD = beta * sl[c];
     const double fB = -C.rho_f * Vp * D.g[c];
     const double fG = -Vp * gp[c];
-    D.ffp[c * n + k] = fD + fB + fG;
+    double f = fD + fB + fG;
+    double g = sums[7 + c] + fG;  // undisturbed-flow forces
+    if (shear) {
+      const double fS = -Vp * dtau[c];
+      f += fS;
+      g += fS;
+    }
+    D.ffp[c * n + k] = f;
     sums[1 + c] += beta * up[c];
     sums[4 + c] += fD;
-    sums[7 + c] += fG;
+    sums[7 + c] = g;
   }
   sums[0] += beta;
 }
@@ -331,7 +427,7 @@ struct CplShared {
 // One occupied element, computed by the whole block.  The latency is a short
 // chain of memory round trips: counts, slot entries and nodal values are
 // loaded together, then the particles' state, then the outputs are stored.
-template <typename R, int ORD, bool GEN>
+template <typename R, int ORD, int MODE>
 __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
                                const double *__restrict__ P, double *__restrict__ eps_q,
                                double *__restrict__ beta_q, double *__restrict__ fpf_q,
@@ -457,7 +553,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   // ---- 3. per-particle forces
   double sums[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // beta, beta u_p, f_D, f_gradp
   const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
-  if (k0 >= 0) particle_force<R, ORD, GEN>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
+  if (k0 >= 0) particle_force<R, ORD, MODE>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
     const int k = sh.ids[t];
     double xp[3], up[3];
@@ -466,7 +562,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       xp[c] = X[c * n + k];
       up[c] = D.v[c * n + k];
     }
-    particle_force<R, ORD, GEN>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
+    particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
   }
   wave_sum_n(sums);
   if (lane == 0)
@@ -597,7 +693,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
 // One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
 // list exit at once; dispatching one block per mesh element would cost more
 // than the work).  Longer lists are strided over the grid.
-template <typename R, int ORD, bool GEN>
+template <typename R, int ORD, int MODE>
 __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
                                                                     int parity,
                                                                     const double *__restrict__ U,
@@ -615,10 +711,10 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
   if ((int)blockIdx.x >= nocc) return;  // whole block
   const int tid = threadIdx.x;
   if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD, GEN>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+  couple_element<R, ORD, MODE>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
   // more occupied elements than blocks: the rest, strided over the grid
   for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
-    couple_element<R, ORD, GEN>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+    couple_element<R, ORD, MODE>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,7 +722,8 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
-    const BedRun *__restrict__ run, const unsigned *__restrict__ map, int *cnt_word, unsigned *list) {
+    const BedRun *__restrict__ run, const unsigned *__restrict__ map, int *cnt_words, unsigned *list,
+    ModeLists ml) {
   const unsigned mb = map[blockIdx.x];
   const int b = (int)(mb >> kBedShift), blk = (int)(mb & kBlockMask);
   const Dev &D = tab[b];
@@ -634,11 +731,13 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
   const CplIO &io = iot[b];
   const int p3 = (int)(run[b].s % 3);
   const int gw = blk * (kClassBlock / kWave) + (int)(threadIdx.x / kWave);
-  couple_classify_body(D, C, gw * kClassElems, p3, cnt_word, list, (unsigned)b << kBedShift,
+  // occupied elements go to the list of the bed's element-kernel variant
+  const int m = cpl_mode_of(C.drag, C.shear);
+  couple_classify_body(D, C, gw * kClassElems, p3, cnt_words + m, list + ml.off[m], (unsigned)b << kBedShift,
                        io.eps_q, io.beta_q, io.fpf_q, io.esums);
 }
 
-template <typename R, int ORD, bool GEN>
+template <typename R, int ORD, int MODE>
 __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const Cpl *__restrict__ ctab,
                                               const CplIO *__restrict__ iot,
                                               const BedRun *__restrict__ run, unsigned ent,
@@ -650,11 +749,11 @@ __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const
   const long long s = run[b].s;
   const int tid = threadIdx.x;
   if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD, GEN>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
+  couple_element<R, ORD, MODE>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
                          (int)(s % 3), sh);
 }
 
-template <typename R, int ORD, bool GEN>
+template <typename R, int ORD, int MODE>
 __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list) {
@@ -666,36 +765,48 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
   // is read in the same round trip as the list length
   for (int i = blockIdx.x; i < nocc; i += gridDim.x) {
     if (i != (int)blockIdx.x) ent = list[i];
-    couple_listed<R, ORD, GEN>(tab, ctab, iot, run, ent, sh);
+    couple_listed<R, ORD, MODE>(tab, ctab, iot, run, ent, sh);
   }
 }
 
-__global__ void reset_count(int *cnt_word) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_word = 0;
+__global__ void reset_count(int *cnt_words) {
+  if (blockIdx.x == 0 && threadIdx.x < 3) cnt_words[threadIdx.x] = 0;
 }
 
-// Every bed of a batch (all of velocity order `order`; gen: some bed uses a
-// closure other than Di Felice).  The list has room
-// for total_elems entries (at least one); the counter is zero on entry and
-// on return.
+// Every bed of a batch (all of velocity order `order`).  Occupied elements
+// are listed per element-kernel variant (mode_elems[m] elements of beds in
+// mode m, region m of the list at ml.off[m], counted in cnt_words[m]), and
+// each variant present runs its own launch, so that every bed computes the
+// arithmetic of its own variant whatever the other beds are.  The counters
+// are zero on entry and on return.
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
-                               const unsigned *map_class, int blocks_class, int *cnt_word,
-                               unsigned *list, long long total_elems, int order, bool fp32, bool gen,
+                               const unsigned *map_class, int blocks_class, int *cnt_words,
+                               unsigned *list, const long long mode_elems[3], int order, bool fp32,
                                hipStream_t st) {
   if (blocks_class <= 0) return hipGetLastError();
-  couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_word,
-                                                              list);
-  const dim3 g(total_elems < kMaxCoupleBlocks ? (int)total_elems : kMaxCoupleBlocks), b(kCplThreads);
-#define CFDDEM_OCCB(RT, O, GN) couple_occupied_batch<RT, O, GN><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_word, list)
-  if (fp32) {
-    if (order == 2) { if (gen) CFDDEM_OCCB(float, 2, true); else CFDDEM_OCCB(float, 2, false); }
-    else { if (gen) CFDDEM_OCCB(float, 1, true); else CFDDEM_OCCB(float, 1, false); }
-  } else {
-    if (order == 2) { if (gen) CFDDEM_OCCB(double, 2, true); else CFDDEM_OCCB(double, 2, false); }
-    else { if (gen) CFDDEM_OCCB(double, 1, true); else CFDDEM_OCCB(double, 1, false); }
+  ModeLists ml;
+  ml.off[0] = 0;
+  ml.off[1] = mode_elems[0];
+  ml.off[2] = mode_elems[0] + mode_elems[1];
+  couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_words,
+                                                              list, ml);
+  const dim3 b(kCplThreads);
+#define CFDDEM_OCCB(RT, O, M)                                                                   \
+  couple_occupied_batch<RT, O, M><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_words + M, list + ml.off[M])
+#define CFDDEM_OCCB_MODE(RT, O) \
+  do { if (m == 2) CFDDEM_OCCB(RT, O, 2); else if (m == 1) CFDDEM_OCCB(RT, O, 1); else CFDDEM_OCCB(RT, O, 0); } while (0)
+  for (int m = 0; m < 3; ++m) {
+    if (mode_elems[m] <= 0) continue;
+    const dim3 g(mode_elems[m] < kMaxCoupleBlocks ? (int)mode_elems[m] : kMaxCoupleBlocks);
+    if (fp32) {
+      if (order == 2) CFDDEM_OCCB_MODE(float, 2); else CFDDEM_OCCB_MODE(float, 1);
+    } else {
+      if (order == 2) CFDDEM_OCCB_MODE(double, 2); else CFDDEM_OCCB_MODE(double, 1);
+    }
   }
+#undef CFDDEM_OCCB_MODE
 #undef CFDDEM_OCCB
-  reset_count<<<1, 64, 0, st>>>(cnt_word);
+  reset_count<<<1, 64, 0, st>>>(cnt_words);
   return hipGetLastError();
 }
 
@@ -711,15 +822,16 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
   const int grid_c = (waves_c + kClassBlock / kWave - 1) / (kClassBlock / kWave);
   couple_classify<<<grid_c, kClassBlock, 0, st>>>(D, C, p3, parity, eps_q, beta_q, fpf_q, esums);
   const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks), b(kCplThreads);
-#define CFDDEM_OCC(RT, O, GN) couple_occupied<RT, O, GN><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)
-  const bool gen = C.drag != 0;
+#define CFDDEM_OCC(RT, O, M) couple_occupied<RT, O, M><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)
+#define CFDDEM_OCC_MODE(RT, O) \
+  do { if (mode == 2) CFDDEM_OCC(RT, O, 2); else if (mode == 1) CFDDEM_OCC(RT, O, 1); else CFDDEM_OCC(RT, O, 0); } while (0)
+  const int mode = cpl_mode_of(C.drag, C.shear);
   if (fp32) {
-    if (C.order == 2) { if (gen) CFDDEM_OCC(float, 2, true); else CFDDEM_OCC(float, 2, false); }
-    else { if (gen) CFDDEM_OCC(float, 1, true); else CFDDEM_OCC(float, 1, false); }
+    if (C.order == 2) CFDDEM_OCC_MODE(float, 2); else CFDDEM_OCC_MODE(float, 1);
   } else {
-    if (C.order == 2) { if (gen) CFDDEM_OCC(double, 2, true); else CFDDEM_OCC(double, 2, false); }
-    else { if (gen) CFDDEM_OCC(double, 1, true); else CFDDEM_OCC(double, 1, false); }
+    if (C.order == 2) CFDDEM_OCC_MODE(double, 2); else CFDDEM_OCC_MODE(double, 1);
   }
+#undef CFDDEM_OCC_MODE
 #undef CFDDEM_OCC
   return hipGetLastError();
 }

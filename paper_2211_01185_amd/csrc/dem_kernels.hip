@@ -118,12 +118,15 @@ __global__ void clear_grid(Dev D, int p3) {
 // tangential history are FP64; the spring-dashpot arithmetic runs in R.
 //   dn   normal overlap, vij relative contact-point velocity (first - second)
 //   dto  stored tangential overlap (zeros for a new contact)
-// Outputs: f = f_n + f_t, nxft = n x f_t, dtn = updated tangential overlap.
-template <typename R, bool ADVANCE>
+//   wr   relative angular velocity (first - second; the first's against a wall)
+// Outputs: f = f_n + f_t, nxft = n x f_t, dtn = updated tangential overlap,
+// mr = rolling torque on the first body, -mu_r R_e |f_n| wr/|wr| (zero when
+// mu_r = 0 or wr = 0; Eq. "angular_momentum" names it without a form).
+template <typename R, bool ADVANCE, bool ROLL>
 __device__ inline void contact_law(const Material &M, const double n[3], double dn,
                                    const double vij[3], double Re, double me, double dt,
-                                   const double dto[3], double f[3], double nxft[3],
-                                   double dtn[3]) {
+                                   const double dto[3], const double wr[3], double f[3],
+                                   double nxft[3], double dtn[3], double mr[3]) {
   const double vn = vij[0] * n[0] + vij[1] * n[1] + vij[2] * n[2];
   double vrn[3], vrt[3];
   for (int c = 0; c < 3; ++c) {
@@ -161,6 +164,17 @@ __device__ inline void contact_law(const Material &M, const double n[3], double 
   nxft[0] = (double)(R(n[1]) * ft[2] - R(n[2]) * ft[1]);
   nxft[1] = (double)(R(n[2]) * ft[0] - R(n[0]) * ft[2]);
   nxft[2] = (double)(R(n[0]) * ft[1] - R(n[1]) * ft[0]);
+  mr[0] = mr[1] = mr[2] = 0.0;
+  if (ROLL && M.mu_r > 0.0) {
+    const R w0 = R(wr[0]), w1 = R(wr[1]), w2 = R(wr[2]);
+    const R wm = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    if (wm > R(0.0)) {
+      const R s = -R(M.mu_r) * R(Re) * fn_mag / wm;
+      mr[0] = (double)(s * w0);
+      mr[1] = (double)(s * w1);
+      mr[2] = (double)(s * w2);
+    }
+  }
 }
 
 // R_a w_a + R_b w_b without contraction, so that both particles of a pair
@@ -173,8 +187,6 @@ __device__ inline void lever_sum(double ra, double wa0, double wa1, double wa2, 
   rw[2] = ra * wa2 + rb * wb2;
 }
 
-// Broad-search predicate: (R_i + R_j + skin)^2 - |x_j - x_i|^2 > 0.  Every
-// pair that satisfies the fine-search predicate satisfies this one.
 // ---------------------------------------------------------------------------
 // one DEM step (plus the opening of the next one when CONT)
 // ---------------------------------------------------------------------------
@@ -202,7 +214,9 @@ __device__ inline unsigned long long group_or(unsigned long long v) {
   return v;
 }
 
-template <typename R, bool ADVANCE, bool CONT, int L>
+// ROLL: some rolling friction coefficient is nonzero (a separate
+// instantiation, so that the kernels without it keep their registers).
+template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
 __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src) {
   const int gid = blk * kForceBlock + threadIdx.x;
   const int a = gid / L;
@@ -374,6 +388,10 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
   const double ma = D.mass[a];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+  // rolling torques, summed apart and added to T only for a bed with rolling
+  // friction, so that a bed without it gets the same arithmetic in either
+  // instantiation
+  double Tr[3] = {0.0, 0.0, 0.0};
   const unsigned long long *lst = sel(D.nbr, cur);
   double *hdt = sel(D.hdt, cur);
   unsigned long long mask_new = 0;
@@ -395,7 +413,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     // the two sides stay bit-consistent: force on b = -force on a exactly.
     const double d0 = xb0 - xa0, d1 = xb1 - xa1, d2 = xb2 - xa2;
     const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    double nrm[3], vij[3], rw[3], f[3], nxft[3], dtn[3];
+    double nrm[3], vij[3], rw[3], f[3], nxft[3], dtn[3], mr[3];
     nrm[0] = d0 / dist;
     nrm[1] = d1 / dist;
     nrm[2] = d2 / dist;
@@ -406,10 +424,12 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     vij[2] = va2 - vb2 + (rw[0] * nrm[1] - rw[1] * nrm[0]);
     const double Re = 1.0 / (1.0 / ra + 1.0 / rb);
     const double me = 1.0 / (1.0 / ma + 1.0 / mb);
-    contact_law<R, ADVANCE>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, f, nxft, dtn);
+    const double wr[3] = {wa0 - wb0, wa1 - wb1, wa2 - wb2};
+    contact_law<R, ADVANCE, ROLL>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, wr, f, nxft, dtn, mr);
     for (int c = 0; c < 3; ++c) {
       F[c] += f[c];
       T[c] += ra * nxft[c];  // R_a n x f_t (n x f_t is the same from both sides)
+      if (ROLL) Tr[c] += mr[c];  // the partner's is the exact negation
       hdt[(size_t)c * mn + (size_t)t * n + a] = dtn[c];
     }
     mask_new |= 1ull << t;
@@ -427,7 +447,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       const double dist = (wall & 1) ? face - xax : xax - face;
       if (!(ra - dist > 0.0)) continue;
       const double sgn = (wall & 1) ? 1.0 : -1.0;
-      double nrm[3], vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3];
+      double nrm[3], vij[3], dto[3] = {0.0, 0.0, 0.0}, f[3], nxft[3], dtn[3], mr[3];
       nrm[0] = ax == 0 ? sgn : 0.0;
       nrm[1] = ax == 1 ? sgn : 0.0;
       nrm[2] = ax == 2 ? sgn : 0.0;
@@ -438,10 +458,12 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
       if ((wold >> wall) & 1u)
         for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
-      contact_law<R, ADVANCE>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, f, nxft, dtn);
+      const double wr[3] = {wa0, wa1, wa2};
+      contact_law<R, ADVANCE, ROLL>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, wr, f, nxft, dtn, mr);
       for (int c = 0; c < 3; ++c) {
         F[c] += f[c];
         T[c] += ra * nxft[c];
+        if (ROLL) Tr[c] += mr[c];
         D.whdt[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
       }
       wnew |= 1u << wall;
@@ -452,6 +474,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     F[c] = group_sum<L>(F[c]);
     T[c] = group_sum<L>(T[c]);
   }
+  if (ROLL && (D.pp.mu_r > 0.0 || D.pw.mu_r > 0.0))
+    for (int c = 0; c < 3; ++c) T[c] += group_sum<L>(Tr[c]);
   mask_new = group_or<L>(mask_new);
   mask_prev = group_or<L>(mask_prev);
   if (lane != 0) {
@@ -514,9 +538,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   if (bits) atomicOr(D.err, bits);
 }
 
-template <typename R, bool ADVANCE, bool CONT, int L>
+template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
 __global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
-  force_kick_body<R, ADVANCE, CONT, L>(D, blockIdx.x, p2, p3, src);
+  force_kick_body<R, ADVANCE, CONT, L, ROLL>(D, blockIdx.x, p2, p3, src);
 }
 
 // ---------------------------------------------------------------------------
@@ -541,7 +565,7 @@ __global__ __launch_bounds__(256) void drift_bin_batch(const Dev *__restrict__ t
 }
 
 // Step run.s + i of every bed (i = 1 applies the bed's pending permutation).
-template <typename R, bool CONT, int L>
+template <typename R, bool CONT, int L, bool ROLL>
 __global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__restrict__ tab,
                                                                    const BedRun *__restrict__ run,
                                                                    const unsigned *__restrict__ map,
@@ -550,8 +574,8 @@ __global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__
   bed_of_block(map, b, blk);
   const Dev &D = tab[b];
   const long long s = run[b].s + i;
-  force_kick_body<R, true, CONT, L>(D, blk, (int)(s & 1), (int)(s % 3),
-                                    i == 1 ? run[b].src : nullptr);
+  force_kick_body<R, true, CONT, L, ROLL>(D, blk, (int)(s & 1), (int)(s % 3),
+                                          i == 1 ? run[b].src : nullptr);
 }
 
 // After a run of n steps: every bed's step index advances, pending
@@ -581,33 +605,44 @@ hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsig
   return hipGetLastError();
 }
 
-template <int L>
+template <int L, bool ROLL>
 static void launch_fkb(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
                        bool cont, bool fp32, int maxn, hipStream_t st) {
   const size_t lds = sizeof(unsigned long long) * (size_t)maxn * (kForceBlock / L);
   if (fp32) {
     if (cont)
-      force_kick_batch<float, true, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<float, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
     else
-      force_kick_batch<float, false, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<float, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
   } else {
     if (cont)
-      force_kick_batch<double, true, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<double, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
     else
-      force_kick_batch<double, false, L><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<double, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
   }
 }
 
-// lanes: 1, 2 or 4 (the same for every bed of the batch)
-hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, int lanes, hipStream_t st) {
-  if (blocks <= 0) return hipGetLastError();
+template <bool ROLL>
+static void launch_fkb_lanes(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
+                             bool cont, bool fp32, int maxn, int lanes, hipStream_t st) {
   if (lanes == 1)
-    launch_fkb<1>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<1, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
   else if (lanes == 4)
-    launch_fkb<4>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<4, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
   else
-    launch_fkb<2>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<2, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+}
+
+// lanes: 1, 2 or 4 (the same for every bed of the batch); roll: some bed has
+// a nonzero rolling friction coefficient
+hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+                                   int i, bool cont, bool fp32, int maxn, int lanes, bool roll,
+                                   hipStream_t st) {
+  if (blocks <= 0) return hipGetLastError();
+  if (roll)
+    launch_fkb_lanes<true>(tab, run, map, blocks, i, cont, fp32, maxn, lanes, st);
+  else
+    launch_fkb_lanes<false>(tab, run, map, blocks, i, cont, fp32, maxn, lanes, st);
   return hipGetLastError();
 }
 
@@ -637,37 +672,48 @@ hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename R, bool ADVANCE, bool CONT, int L>
+template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
 static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
   const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
   const size_t lds = sizeof(unsigned long long) * (size_t)D.maxn * (kForceBlock / L);
   if (e0)
-    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L>, dim3(grid), dim3(kForceBlock), lds, st,
+    hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L, ROLL>, dim3(grid), dim3(kForceBlock), lds, st,
                           e0, e1, 0, D, p2, p3, src);
   else
-    force_kick<R, ADVANCE, CONT, L><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src);
+    force_kick<R, ADVANCE, CONT, L, ROLL><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src);
 }
 
-template <int L>
+template <int L, bool ROLL>
 static void launch_fk_lanes(const Dev &D, int p2, int p3, const int *src, bool advance, bool cont,
                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!advance) {
     if (fp32)
-      launch_fk<float, false, false, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, false, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<double, false, false, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, false, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
   } else if (fp32) {
     if (cont)
-      launch_fk<float, true, true, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, true, L, ROLL>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<float, true, false, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
   } else {
     if (cont)
-      launch_fk<double, true, true, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, true, L, ROLL>(D, p2, p3, src, st, e0, e1);
     else
-      launch_fk<double, true, false, L>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
   }
+}
+
+template <bool ROLL>
+static void launch_fk_roll(const Dev &D, int p2, int p3, const int *src, bool advance, bool cont,
+                           bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (lanes == 1)
+    launch_fk_lanes<1, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+  else if (lanes == 4)
+    launch_fk_lanes<4, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+  else
+    launch_fk_lanes<2, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
 }
 
 // e0/e1: when non-NULL, events recorded at the kernel's own start and end.
@@ -675,12 +721,10 @@ static void launch_fk_lanes(const Dev &D, int p2, int p3, const int *src, bool a
 hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
                              bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
-  if (lanes == 1)
-    launch_fk_lanes<1>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
-  else if (lanes == 4)
-    launch_fk_lanes<4>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+  if (D.pp.mu_r > 0.0 || D.pw.mu_r > 0.0)
+    launch_fk_roll<true>(D, p2, p3, src, advance, cont, fp32, lanes, st, e0, e1);
   else
-    launch_fk_lanes<2>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+    launch_fk_roll<false>(D, p2, p3, src, advance, cont, fp32, lanes, st, e0, e1);
   return hipGetLastError();
 }
 

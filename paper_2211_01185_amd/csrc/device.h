@@ -24,6 +24,7 @@ struct Material {
   double Ge;        // effective shear modulus
   double eta_coef;  // -2 sqrt(5/6) beta(e)  (>= 0)
   double mu;        // Coulomb coefficient
+  double mu_r;      // rolling friction coefficient (0: no rolling torque)
 };
 
 // Structured grid: mesh elements split into k[a] DEM cells per axis.
@@ -96,6 +97,16 @@ struct BedRun {
   const int *src;  // after a re-sort: index each particle had when its list was built
 };
 
+// Occupied-element lists of a batched coupling step, one per element-kernel
+// variant (mode 0: Di Felice, 1: other closures, 2: shear force): region m
+// starts at off[m] of the list, its length is counted in word m.
+struct ModeLists {
+  long long off[3];
+};
+
+// Element-kernel variant of a bed's coupling step.
+__host__ __device__ inline int cpl_mode_of(int drag, int shear) { return shear ? 2 : (drag != 0 ? 1 : 0); }
+
 // Coupling buffers of one bed of a batch.
 struct CplIO {
   const double *U, *P;
@@ -113,6 +124,7 @@ struct Cpl {
   int model;
   int drag;           // closure (DEM_DRAG_* without the flag bits)
   int beta_over_eps;  // 1: beta divided by the fluid fraction
+  int shear;          // 1: shear force -V_p div(tau) added to the particle force
   double Ve;        // element volume
   double Lq[3][3];  // Lq[a][i]: 1D velocity basis a at Gauss point i
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)

@@ -11,11 +11,12 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5}
 def oracle_bed(wl, model=None):
     d = wl.dem
     p = O.make_params(d["box_lo"], d["box_hi"], d["gravity"], d["dt"], d["E"], d["nu"], d["e"], d["mu"],
-                      d["E_w"], d["nu_w"], d["e_w"], d["mu_w"])
+                      d["E_w"], d["nu_w"], d["e_w"], d["mu_w"], d.get("mu_r", 0.0),
+                      d.get("mu_r_w", d.get("mu_r", 0.0)))
     f = wl.fluid
     fl = O.make_fluid(f["order"], f["n_el"], f["rho_f"], f["mu_f"],
                       f.get("model", 0) if model is None else model, f["eps_min"],
-                      f.get("drag", 0), f.get("beta_over_eps", 0))
+                      f.get("drag", 0), f.get("beta_over_eps", 0), 1 if f.get("shear") else 0)
     return O.OracleBed(p, wl.x, wl.v, wl.w, wl.radius, wl.density), fl
 
 

@@ -38,9 +38,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "cfddem.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(dem_params), offsetof(dem_params, dt),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dem_params), offsetof(dem_params, dt),
          offsetof(dem_params, max_neighbors), offsetof(dem_params, skin), sizeof(cfd_params),
-         offsetof(cfd_params, eps_min));
+         offsetof(cfd_params, eps_min), offsetof(dem_params, mu_r), offsetof(dem_params, mu_r_w),
+         offsetof(cfd_params, shear));
   return 0;
 }
 """
@@ -51,7 +52,8 @@ int main(void) {
         subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), "-o", exe, c], check=True)
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
     want = [C.sizeof(cfddem.DemParams), cfddem.DemParams.dt.offset, cfddem.DemParams.max_neighbors.offset,
-            cfddem.DemParams.skin.offset, C.sizeof(cfddem.CfdParams), cfddem.CfdParams.eps_min.offset]
+            cfddem.DemParams.skin.offset, C.sizeof(cfddem.CfdParams), cfddem.CfdParams.eps_min.offset,
+            cfddem.DemParams.mu_r.offset, cfddem.DemParams.mu_r_w.offset, cfddem.CfdParams.shear.offset]
     assert [int(v) for v in out] == want
 
 
@@ -64,7 +66,8 @@ def test_workspace_query_validates_parameters():
     dp2, _ = cfddem.make_params(wl.dem, wl.fluid, 10 * wl.n, 3e-3, 3e-3)
     assert cfddem.workspace_bytes(dp2, cp) > good
     bad = [("abi_version", 99), ("n", 0), ("dt", -1.0), ("e", 0.0), ("e", 1.5), ("nu", 0.5),
-           ("max_neighbors", 65), ("skin", -1.0), ("d_max", 0.0), ("lanes", 3)]
+           ("max_neighbors", 65), ("skin", -1.0), ("d_max", 0.0), ("lanes", 3), ("mu_r", -0.1),
+           ("mu_r_w", float("nan"))]
     for field, value in bad:
         dpb, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
         setattr(dpb, field, value)
@@ -72,6 +75,10 @@ def test_workspace_query_validates_parameters():
     _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
     cpb.order = 3
     assert cfddem.workspace_bytes(dp, cpb) == 0
+    for field, value in (("shear", 2), ("reserved", 1)):
+        _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
+        setattr(cpb, field, value)
+        assert cfddem.workspace_bytes(dp, cpb) == 0, field
     # elements narrower than one particle diameter are rejected
     dpb, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
     cpb.n_el[0] = 40

@@ -111,6 +111,56 @@ def test_alone_equals_mixed(precision):
         alone.close()
 
 
+def _feature_beds():
+    """Lattices with different contact and coupling features: one plain, one
+    with rolling friction and the shear force, one with the Gidaspow closure
+    and beta_B = beta_A / eps (the batch runs every bed in the instantiation
+    its most demanding bed needs)."""
+    a, b, c = _q2_beds()
+    rng = np.random.default_rng(5)
+    for w in (a, b, c):
+        w.U = w.U + rng.normal(0.0, 0.05, w.U.shape)
+    b.dem.update(mu_r=0.2, mu_r_w=0.3)
+    b.fluid.update(shear=1, model=1)
+    c.fluid.update(drag="gidaspow", beta_over_eps=1)
+    return [a, b, c]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed_features_match_oracle_and_alone(precision):
+    wls = _feature_beds()
+    beds, fields = _make(wls, precision, resort=(3, 0, 5))
+    mixed = cfddem.Batch(beds, fields, elem_sums=True)
+    refs = [oracle_bed(w) for w in wls]
+    tol = TOL[precision]
+    for _ in range(2):
+        outs = mixed.couple()
+        for w, (ob, fl), o in zip(wls, refs, outs):
+            ref = ob.couple(fl, w.U, w.P)
+            assert_close("fpf_q", o["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+            assert_close("elem_sums", o["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+        mixed.step(10)
+        for ob, _ in refs:
+            ob.step(10)
+    for bed, (ob, _) in zip(beds, refs):
+        compare_contacts(bed, ob, 10 * tol)
+        compare_states(bed, ob, 10 * tol)
+    mixed_out = [{k: v.cpu().numpy() for k, v in o.items()} for o in mixed.couple()]
+    mixed_state = [_snapshot(b) for b in beds]
+    mixed.close()
+    # each bed alone (a batch of one, in its own instantiation): bit for bit
+    for j, w in enumerate(wls):
+        bed, fld = _make([w], precision, resort=((3, 0, 5)[j],))
+        alone = cfddem.Batch(bed, fld, elem_sums=True)
+        for _ in range(2):
+            alone.couple()
+            alone.step(10)
+        out = {k: v.cpu().numpy() for k, v in alone.couple()[0].items()}
+        _same(out, mixed_out[j])
+        _same(_snapshot(bed[0]), mixed_state[j])
+        alone.close()
+
+
 def test_graph_replay_equals_launches():
     wls = _q1_beds()
     beds_a, fields_a = _make(wls, "fp32", resort=(4, 4, 4))

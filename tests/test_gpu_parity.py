@@ -281,3 +281,82 @@ def test_coupling_step_other_closures(drag, beta_over_eps, precision):
     assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
     assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
     assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
+
+
+def _noisy_field(wl, order, seed=11, amplitude=0.05):
+    """A fluid field with spatial variation in every component (its stress
+    divergence is nonzero), for velocity order 1 or 2 on the workload's mesh."""
+    rng = np.random.default_rng(seed)
+    n_el = np.array(wl.fluid["n_el"])
+    n_v = int(np.prod(order * n_el + 1))
+    wl.fluid["order"] = order
+    wl.U = rng.normal(0.0, amplitude, (3, n_v))
+    wl.U[2] += 0.5
+    return wl
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rolling_friction(lanes, precision):
+    """The rolling torque (Table "tab:setup1" coefficients: 0.2 between
+    particles, 0.3 against walls) on a contact-heavy bed with random spins:
+    creation-time torques, one step and ten steps against the oracle."""
+    wl = _workload("lattice_ragged")
+    wl.dem.update(mu_r=0.2, mu_r_w=0.3)
+    gb = gpu_bed(wl, precision, lanes=lanes, resort_every=4)
+    ob, _ = oracle_bed(wl)
+    tol = TOL[precision]
+    compare_contacts(gb, ob, tol)
+    compare_states(gb, ob, tol, keys=("Fc", "Tc"))
+    plain = _workload("lattice_ragged")
+    assert not np.allclose(gpu_state(gpu_bed(plain, precision))["Tc"], gpu_state(gb)["Tc"])
+    gb.step(1)
+    ob.step(1)
+    compare_contacts(gb, ob, tol)
+    compare_states(gb, ob, tol)
+    gb.step(9)
+    ob.step(9)
+    compare_contacts(gb, ob, 10 * tol)
+    compare_states(gb, ob, 10 * tol)
+    assert gb.poll()[0] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("drag", ["difelice", "gidaspow"])
+def test_coupling_step_with_shear_force(drag, order, model, precision):
+    """The shear force -V_p div(tau_f) (Eqs. "fa", "fb", "stress") on one
+    coupling step: particle forces, element sums and (model B) the force on
+    the fluid against the oracle, Q1 and Q2 fields.  A water-like fluid
+    (the paper's liquid cases) makes the shear force large enough to be seen
+    above the FP32 tolerance."""
+    wl = _noisy_field(_workload("lattice"), order, amplitude=0.3)
+    wl.fluid.update(shear=1, model=model, drag=drag, mu_f=1.0e-3, rho_f=1000.0)
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    out = gb.couple(U, P, elem_sums=True)
+    ref = ob.couple(fl, wl.U, wl.P)
+    tol = TOL[precision]
+    assert np.array_equal(out["elem_sums"][0].cpu().numpy(), ref["elem_sums"][0])
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+    assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
+    # the shear force is there: without it the particle force differs far
+    # beyond the FP64 tolerance (on the Q1 field, whose pure second
+    # derivatives vanish, only the grad(div u) part remains: ~4e-6 of f_fp,
+    # below the FP32 tolerance, so the FP64 case is the one that checks it)
+    ob2, fl2 = oracle_bed(wl)
+    fl2.shear = 0
+    ob2.couple(fl2, wl.U, wl.P)
+    diff = np.abs(ob2.state()["ffp"] - ob.state()["ffp"]).max() / np.abs(ob.state()["ffp"]).max()
+    assert diff > 100 * TOL["fp64"]
+    if order == 2:
+        assert diff > 5 * TOL["fp32"]
+    # and a coupled sequence with the held force
+    gb.step(10)
+    ob.step(10)
+    compare_contacts(gb, ob, 10 * tol)
+    compare_states(gb, ob, 10 * tol)
