@@ -21,10 +21,15 @@ sample of the same workload; and the two other parts of the metric:
            path;
   served:  a Poisson stream (20 jobs/s) of sedimentation / fluidization jobs of
            1k-200k spheres, served by continuous batching; p50/p99 latency and
-           aggregate particle-steps/s over the jobs after the warm-up ones.
+           aggregate particle-steps/s over the jobs after the warm-up ones;
+  settling: the DEM-only preparation of a bed, 100,000 spheres (d = 1 mm)
+           inserted at random above the floor of the same column and stepped
+           without coupling until at rest (kinetic energy below 1e-4 of
+           sum m g d, checked every 500 steps); steps to rest and
+           particle-steps/s.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--no-batched] [--no-served] [--served-jobs J]
+                       [--no-batched] [--no-served] [--no-settling] [--served-jobs J]
 """
 import argparse
 import hashlib
@@ -63,6 +68,7 @@ def parse():
                          "(to repeat a tuned run under a counter profiler)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-served", action="store_true", help="skip the served stream")
+    ap.add_argument("--no-settling", action="store_true", help="skip the DEM-only settling run")
     ap.add_argument("--batched-beds", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--served-jobs", type=int, default=650)
@@ -181,6 +187,28 @@ def batched_ensemble(n_beds, steps, dev):
                               "steps": plain_steps, "dtype": "f64",
                               "launch": "single-bed entry points, one bed after another"},
     }
+
+
+def settling_run(dev, max_steps=100_000):
+    """The filling workload stepped to rest (no coupling), FP32 forces."""
+    import torch
+
+    from paper_2211_01185_amd import cfddem, settle, synth
+
+    wl = synth.filling()
+    bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, resort_every=200)
+    torch.cuda.synchronize()
+    res = settle.settle(bed, settle.energy_scale(wl), rest=1e-4, every=500, max_steps=max_steps)
+    err, contacts = bed.poll()
+    bed.close()
+    return {"workload": "DEM-only filling: 100,000 spheres d=1 mm inserted at random (solid fraction 0.15) "
+                        "above the floor of the 0.1 x 0.1 x 0.4 m column, stepped without coupling to rest",
+            "particles": wl.n, "steps_to_rest": res.steps, "at_rest": res.at_rest,
+            "simulated_s": res.steps * wl.dem["dt"], "wall_s": res.wall_s,
+            "value": wl.n * res.steps / res.wall_s, "unit": "particle-steps/s",
+            "kinetic_energy_over_mgd": res.kinetic / settle.energy_scale(wl),
+            "contacts_at_rest": int(contacts), "errors": int(err),
+            "dtype": "f32 forces / f64 state", "check_every_steps": 500}
 
 
 def served_stream(n_jobs, warmup, dev):
@@ -347,6 +375,10 @@ def main():
         progress("served stream: starting")
         result["served"] = served_stream(args.served_jobs, args.served_warmup, dev)
         progress(f"served: p99 {result['served']['latency_p99_s']:.4f} s")
+    if not args.no_settling:
+        progress("settling: starting")
+        result["settling"] = settling_run(dev)
+        progress(f"settling: {result['settling']['steps_to_rest']} steps to rest")
     if not args.no_cpu:
         progress("oracle sample: starting")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

@@ -203,6 +203,16 @@ dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, dou
  * evaluation), 3 x n, original-ID order.  Either may be NULL. */
 dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream);
 
+/* Kinetic energy of the current (boundary) state: out[0] = sum 1/2 m v^2,
+ * out[1] = sum 1/2 I w^2 with I = 2/5 m R^2 (solid spheres, Eq.
+ * "angular_momentum"), host array of 2.  The sums are formed in a fixed order
+ * (per 256-particle block, then over blocks), so repeated calls on the same
+ * state agree bit for bit.  Used to detect a bed at rest, e.g. when a bed is
+ * filled and left to settle by DEM steps alone before coupled runs (Section
+ * 3.2).  Synchronizes the stream; returns the sticky error of a poisoned
+ * context without computing. */
+dem_status dem_kinetic_energy(dem_ctx *ctx, double *out, void *stream);
+
 /* Element and DEM-cell index of every particle at its last binning, original-ID
  * order.  Element index as in cfd_params; cell index
  * element*(kx*ky*kz) + (sz*ky+sy)*kx + sx with sub-cell s_a in [0, k_a).

@@ -32,7 +32,8 @@ FP32_FORCES = 1
 DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4, "gidaspow": 5}
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
-           "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kernel_timing",
+           "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
+           "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
            "dem_batch_step", "dem_batch_couple", "dem_batch_run", "dem_batch_destroy",
            "dem_status_string")
@@ -93,6 +94,8 @@ def load():
     lib.dem_read_forces.argtypes = [vp, vp, vp, vp]
     lib.dem_read_cells.restype = i32
     lib.dem_read_cells.argtypes = [vp, vp, vp, C.POINTER(i32), vp]
+    lib.dem_kinetic_energy.restype = i32
+    lib.dem_kinetic_energy.argtypes = [vp, C.POINTER(dbl), vp]
     lib.dem_read_contacts.restype = i32
     lib.dem_read_contacts.argtypes = [vp, vp, vp, i64, C.POINTER(i64), vp]
     lib.dem_poll.restype = i32
@@ -269,6 +272,13 @@ class Bed:
         T = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
         _check(self._lib.dem_read_forces(self._h, _ptr(F), _ptr(T), self._st), "dem_read_forces")
         return F, T
+
+    def kinetic_energy(self):
+        """(translational, rotational) kinetic energy of the current state;
+        synchronizes the bed's stream."""
+        out = (C.c_double * 2)()
+        _check(self._lib.dem_kinetic_energy(self._h, out, self._st), "dem_kinetic_energy")
+        return float(out[0]), float(out[1])
 
     def read_cells(self):
         torch = self._torch

@@ -172,6 +172,7 @@ struct Buffers {
   long long *cnt64, *off64;     // per-particle contact counts / offsets
   long long *bsum;              // per-block partial sums of the device scan
   unsigned long long *scalars;  // [0] contact count, [1] radius max bits, [2] radius min bits
+  double *energy;               // per-block kinetic energies, then the two totals
 };
 
 size_t carve(const Sizes &S, char *base, Buffers &B) {
@@ -184,6 +185,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
     D.lbuf = D.err + kLbufWord;
   }
   B.scalars = c.take<unsigned long long>(8);
+  B.energy = c.take<double>(2 * ((n + 255) / 256) + 2);
   for (int b = 0; b < 2; ++b) {
     D.xs[b] = c.take<double>(3 * n);
     D.vhs[b] = c.take<double>(3 * n);
@@ -418,6 +420,58 @@ __global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   d.cell[k] = s.cell[o];
   d.wmask[k] = s.wmask[o];
   for (int j = 0; j < 3 * kWalls; ++j) d.whdt[(size_t)j * n + k] = s.whdt[(size_t)j * n + o];
+}
+
+// Kinetic energy of the boundary state: translational sum 1/2 m v^2 and
+// rotational sum 1/2 I w^2 (I = 2/5 m R^2).  Each block adds its particles in
+// a fixed tree order into part[2 block], part[2 block + 1]; one wave then adds
+// the block partials (lane l takes blocks l, l + 64, ... in order, then a fixed
+// butterfly), so the totals do not depend on timing.
+__global__ __launch_bounds__(256) void k_energy_partials(Dev D, double *part) {
+  __shared__ double sh[2][256];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double et = 0.0, er = 0.0;
+  if (k < D.n) {
+    const int n = D.n;
+    const double m = D.mass[k], r = D.rad[k];
+    double v2 = 0.0, w2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      v2 += D.v[c * n + k] * D.v[c * n + k];
+      w2 += D.w[c * n + k] * D.w[c * n + k];
+    }
+    et = 0.5 * m * v2;
+    er = 0.5 * (0.4 * m * r * r) * w2;
+  }
+  sh[0][threadIdx.x] = et;
+  sh[1][threadIdx.x] = er;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + h];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_energy_total(int nb, const double *part, double *out) {
+  double et = 0.0, er = 0.0;
+  for (int i = (int)threadIdx.x; i < nb; i += 64) {
+    et += part[2 * i];
+    er += part[2 * i + 1];
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    et += __shfl_xor(et, off, 64);
+    er += __shfl_xor(er, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = et;
+    out[1] = er;
+  }
 }
 
 // Contacts of the last evaluation that particle k reports: its walls, and the
@@ -753,6 +807,21 @@ dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream)
   if (F_c) k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.Fc, F_c);
   if (T_c) k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.Tc, T_c);
   HIP_TRY(hipGetLastError());
+  return DEM_OK;
+}
+
+dem_status dem_kinetic_energy(dem_ctx *ctx, double *out, void *stream) {
+  if (!ctx || !out) return DEM_E_ARG;
+  if (ctx->poisoned) return ctx->poisoned;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev &D = ctx->B.D;
+  const int nb = blocks(D.n, 256);
+  double *part = ctx->B.energy;
+  k_energy_partials<<<nb, 256, 0, st>>>(D, part);
+  k_energy_total<<<1, 64, 0, st>>>(nb, part, part + 2 * nb);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return DEM_OK;
 }
 

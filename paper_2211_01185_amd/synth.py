@@ -23,6 +23,9 @@ available):
                   diameter, restitution and inlet velocity and their own Q1 mesh.
   * ``job_stream`` Poisson arrivals of sedimentation / fluidization column beds
                   of 1k-200k spheres (the served workload).
+  * ``filling``   DEM-only bed preparation: 100,000 spheres, d = 1 mm, at rest
+                  at solid fraction 0.15 in a layer above the floor of the
+                  fluidized-bed column, left to settle under gravity.
 """
 from __future__ import annotations
 
@@ -124,8 +127,10 @@ def rsa_polydisperse(rng, radius, lo, hi):
         left = n - placed
         batch = min(left, 50000)
         # few spheres left: several candidate positions for each, copy c of
-        # every sphere before copy c + 1
-        copies = max(1, 20000 // batch)
+        # every sphere before copy c + 1 (at most as many candidates as fill
+        # the box once, so that a small box is not flooded)
+        fill = float(np.prod(hi - lo)) / (batch * 4.0 / 3.0 * math.pi * rmax ** 3)
+        copies = max(1, min(20000 // batch, int(fill)))
         sid = np.tile(np.arange(batch), copies)
         rb = radius[placed:placed + batch][sid]
         cand = lo + rb[:, None] + (hi - lo - 2 * rb[:, None]) * rng.random((sid.shape[0], 3))
@@ -275,6 +280,35 @@ def spouted(n=500_000, seed_index=0, box=(0.15, 0.15, 0.6), fill_height=0.45, n_
     dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
     return Workload("spouted", x, v, np.zeros((3, n)), radius, np.full(n, 2500.0), dem, fluid,
                     dict(steps=500, coupling_every=10, precision="fp32"), U, P)
+
+
+def filling(n=100_000, d=1e-3, seed_index=0, width=0.1, height=0.4, solid_fraction=0.15, e=0.9) -> Workload:
+    """DEM-only filling of a square column (stand-in for the bed preparation
+    that precedes each coupled case of the paper, Sections 3.2 and 3.3): n
+    spheres of diameter d, rho = 2500, placed at random (random sequential
+    addition) at solid fraction `solid_fraction` in a layer that starts 2 d
+    above the floor, at rest, under gravity, to be stepped without coupling
+    until the bed is at rest.  The mesh (Q1, elements of about 5 d) only hosts
+    the cell grid; the fluid field is zero."""
+    rng = rng_for(6, seed_index)
+    vp = math.pi / 6.0 * d ** 3
+    layer = n * vp / (solid_fraction * width * width)
+    if 2.0 * d + layer > height:
+        raise ValueError("the insertion layer does not fit in the column")
+    radius = np.full(n, 0.5 * d)
+    x = rsa_polydisperse(rng, radius, [0.0, 0.0, 2.0 * d], [width, width, 2.0 * d + layer])
+    x = x[:, rng.permutation(n)].copy()
+    lo, hi = [0.0, 0.0, 0.0], [width, width, height]
+    m = max(1, int(round(width / (5.0 * d))))
+    h = width / m
+    n_el = [m, m, max(1, int(round(height / h)))]
+    fluid = dict(order=1, n_el=n_el, rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, n_el, 1)
+    U = np.zeros((3, nodes.shape[1]))
+    P = np.zeros(nodes.shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material(e=e))
+    return Workload("filling", x, np.zeros((3, n)), np.zeros((3, n)), np.full(n, 0.5 * d), np.full(n, 2500.0),
+                    dem, fluid, dict(steps=0, coupling_every=0, precision="fp32"), U, P)
 
 
 def column_bed(rng, n, d, e, u_in, name="column", precision="fp32", steps=1000, rho=2500.0) -> Workload:
