@@ -882,8 +882,27 @@ static void gauss_rule(int npts, double *pt, double *wt) {
  *   9-11 sum of the undisturbed-flow forces f_gradp (+ f_shear when enabled). */
 #define ES_ROWS 12
 
+/* Value of a scalar nodal field of order p at xi in element e. */
+static double interp_scalar(const orc_fluid *f, const long e[3], const double xi[3], const double *vals) {
+  int p = f->order;
+  double out = 0.0;
+  for (int ic = 0; ic <= p; ++ic)
+    for (int ib = 0; ib <= p; ++ib)
+      for (int ia = 0; ia <= p; ++ia) {
+        double N = orc_lagrange(p, ia, xi[0]) * orc_lagrange(p, ib, xi[1]) * orc_lagrange(p, ic, xi[2]);
+        out += N * vals[node_index(p, f->n_el, e, ia, ib, ic)];
+      }
+  return out;
+}
+
 int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double *P,
                    double *eps_q, double *beta_q, double *fpf_q, double *elem_sums) {
+  return orc_dem_couple_field(s, f, U, P, NULL, eps_q, beta_q, fpf_q, elem_sums);
+}
+
+int orc_dem_couple_field(orc_dem *s, const orc_fluid *f, const double *U, const double *P,
+                         const double *eps_nodes, double *eps_q, double *beta_q, double *fpf_q,
+                         double *elem_sums) {
   long n = s->n;
   const double *lo = s->p.box_lo, *hi = s->p.box_hi;
   const double *g = s->p.gravity;
@@ -920,7 +939,7 @@ int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double
     interp_velocity(f, e, xi, U, n_v, uf);
     interp_pressure_gradient(f, lo, hi, e, xi, P, gp);
     load3(s->v, n, i, up);
-    double eps = 1.0 - sums[1 * nel + el] / Ve;
+    double eps = eps_nodes ? interp_scalar(f, e, xi, eps_nodes) : 1.0 - sums[1 * nel + el] / Ve;
     double eps_c = eps;
     if (eps_c < f->eps_min) eps_c = f->eps_min;
     if (eps_c > 1.0) eps_c = 1.0;
@@ -960,7 +979,7 @@ int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double
           long q = el * nq + ((long)qz * nq1 + qy) * nq1 + qx;
           double xi[3] = {gpt[qx], gpt[qy], gpt[qz]}, uq[3];
           interp_velocity(f, e, xi, U, n_v, uq);
-          if (eps_q) eps_q[q] = eps;
+          if (eps_q) eps_q[q] = eps_nodes ? interp_scalar(f, e, xi, eps_nodes) : eps;
           if (beta_q) beta_q[q] = bq;
           for (int c = 0; c < 3; ++c) {
             double F = -bq * (uq[c] - ubar[c]);

@@ -113,6 +113,13 @@ orc_dem *orc_dem_create(const orc_params *p, long n, const double *x, const doub
 int orc_dem_step(orc_dem *s, long nsteps);
 int orc_dem_couple(orc_dem *s, const orc_fluid *f, const double *U, const double *P,
                    double *eps_q, double *beta_q, double *fpf_q, double *elem_sums);
+/* The same with a continuous void-fraction field: eps_nodes holds its values
+ * at the velocity nodes (the smoothed projection of the element PCM values);
+ * the closure sees it interpolated at each particle and eps_q is its value
+ * at each quadrature point.  eps_nodes = NULL is orc_dem_couple. */
+int orc_dem_couple_field(orc_dem *s, const orc_fluid *f, const double *U, const double *P,
+                         const double *eps_nodes, double *eps_q, double *beta_q, double *fpf_q,
+                         double *elem_sums);
 void orc_dem_get(const orc_dem *s, double *x, double *v, double *w, double *ffp,
                  double *Fc, double *Tc);
 void orc_dem_set_ffp(orc_dem *s, const double *ffp);

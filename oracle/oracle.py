@@ -78,6 +78,8 @@ def _load():
     lib.orc_dem_step.argtypes = [C.c_void_p, C.c_long]
     lib.orc_dem_couple.restype = C.c_int
     lib.orc_dem_couple.argtypes = [C.c_void_p, C.POINTER(OrcFluid), _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_dem_couple_field.restype = C.c_int
+    lib.orc_dem_couple_field.argtypes = [C.c_void_p, C.POINTER(OrcFluid), _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_dem_get.restype = None
     lib.orc_dem_get.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_dem_set_ffp.restype = None
@@ -149,6 +151,77 @@ def stress_divergence(f: OrcFluid, lo, hi, x, U):
 
 def lagrange_deriv2(p, k, t):
     return _load().orc_lagrange_deriv2(int(p), int(k), float(t))
+
+
+def element_matrices(order, he):
+    """Mass, stiffness and load of one element of size he (3,) in the Q_order
+    space: M_ij = int phi_i phi_j, K_ij = int grad phi_i . grad phi_j,
+    b_i = int phi_i, by (order+1)-point Gauss quadrature per axis (exact for
+    these polynomial integrands).  Local node l = (ic (p+1) + ib) (p+1) + ia."""
+    lib = _load()
+    p = int(order)
+    gx, gw = np.polynomial.legendre.leggauss(p + 1)
+    t, w = 0.5 * (gx + 1.0), 0.5 * gw
+    L = np.array([[lib.orc_lagrange(p, k, tq) for tq in t] for k in range(p + 1)])
+    dL = np.array([[lib.orc_lagrange_deriv(p, k, tq) for tq in t] for k in range(p + 1)])
+    loc = [(ia, ib, ic) for ic in range(p + 1) for ib in range(p + 1) for ia in range(p + 1)]
+    nl = len(loc)
+    M, K, b = np.zeros((nl, nl)), np.zeros((nl, nl)), np.zeros(nl)
+    J = float(np.prod(he))
+    for qz in range(p + 1):
+        for qy in range(p + 1):
+            for qx in range(p + 1):
+                wq = w[qx] * w[qy] * w[qz] * J
+                phi = np.array([L[a, qx] * L[bb, qy] * L[c, qz] for a, bb, c in loc])
+                grad = np.array([[dL[a, qx] * L[bb, qy] * L[c, qz] / he[0],
+                                  L[a, qx] * dL[bb, qy] * L[c, qz] / he[1],
+                                  L[a, qx] * L[bb, qy] * dL[c, qz] / he[2]] for a, bb, c in loc])
+                M += wq * np.outer(phi, phi)
+                K += wq * grad @ grad.T
+                b += wq * phi
+    return M, K, b
+
+
+def element_nodes(order, n_el):
+    """Global velocity-node index (x fastest) of local node l of element e,
+    shape (n_elements, (order+1)^3)."""
+    p = int(order)
+    n_el = [int(v) for v in n_el]
+    nx, ny = p * n_el[0] + 1, p * n_el[1] + 1
+    ez, ey, ex = np.meshgrid(np.arange(n_el[2]), np.arange(n_el[1]), np.arange(n_el[0]), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    cols = []
+    for ic in range(p + 1):
+        for ib in range(p + 1):
+            for ia in range(p + 1):
+                cols.append(((p * ez + ic) * ny + (p * ey + ib)) * nx + (p * ex + ia))
+    return np.stack(cols, axis=1)
+
+
+def smooth_void_fraction(fluid: OrcFluid, lo, hi, eps_e, L2):
+    """Continuous void fraction from the element PCM values eps_e: the field
+    eps_h of the velocity space Q_order with, for every basis function phi_i,
+        int eps_h phi_i + L2 int grad eps_h . grad phi_i = int eps_PCM phi_i
+    (natural boundary conditions; L2 = 0 is the L2 projection).  Global
+    assembly of the element matrices and a direct sparse solve.  Returns the
+    nodal values."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.linalg import spsolve
+
+    lo, hi = _f64(lo), _f64(hi)
+    n_el = np.array([int(v) for v in fluid.n_el])
+    he = (hi - lo) / n_el
+    M, K, be = element_matrices(fluid.order, he)
+    Ae = M + float(L2) * K
+    g = element_nodes(fluid.order, n_el)
+    nv = int(np.prod(int(fluid.order) * n_el + 1))
+    ne, nl = g.shape
+    rows = np.repeat(g, nl, axis=1).ravel()
+    cols = np.tile(g, (1, nl)).ravel()
+    A = coo_matrix((np.tile(Ae.ravel(), ne), (rows, cols)), shape=(nv, nv)).tocsc()
+    b = np.bincount(g.ravel(), weights=(np.asarray(eps_e, float)[:, None] * be[None, :]).ravel(),
+                    minlength=nv)
+    return spsolve(A, b)
 
 
 def bin_particles(x, lo, hi, n_el, k):
@@ -234,7 +307,9 @@ class OracleBed:
     def step(self, nsteps=1) -> int:
         return self._lib.orc_dem_step(self._h, int(nsteps))
 
-    def couple(self, fluid: OrcFluid, U, P):
+    def couple(self, fluid: OrcFluid, U, P, smooth_L2=None):
+        """One coupling step.  smooth_L2: None for the element PCM void
+        fraction, else the smoothing length L^2 of the continuous field."""
         n_el = int(fluid.n_el[0]) * int(fluid.n_el[1]) * int(fluid.n_el[2])
         nq = (fluid.order + 1) ** 3
         U = _f64(U)
@@ -245,7 +320,20 @@ class OracleBed:
         sums = np.zeros((12, n_el))
         err = self._lib.orc_dem_couple(self._h, C.byref(fluid), _d(U), _d(P), _d(eps_q), _d(beta_q),
                                        _d(fpf_q), _d(sums))
-        return dict(eps_q=eps_q, beta_q=beta_q, fpf_q=fpf_q, elem_sums=sums, err=err)
+        out = dict(eps_q=eps_q, beta_q=beta_q, fpf_q=fpf_q, elem_sums=sums, err=err)
+        if smooth_L2 is None:
+            return out
+        # smoothed void fraction: element PCM values, projection, then the
+        # coupling step again with the continuous field
+        hi = np.array(self.params.box_hi[:])
+        lo = np.array(self.params.box_lo[:])
+        Ve = float(np.prod((hi - lo) / np.array(fluid.n_el[:])))
+        eps_e = 1.0 - sums[1] / Ve
+        eps_nodes = smooth_void_fraction(fluid, lo, hi, eps_e, smooth_L2)
+        err = self._lib.orc_dem_couple_field(self._h, C.byref(fluid), _d(U), _d(P), _d(eps_nodes), _d(eps_q),
+                                             _d(beta_q), _d(fpf_q), _d(sums))
+        return dict(eps_q=eps_q, beta_q=beta_q, fpf_q=fpf_q, elem_sums=sums, err=err, eps_nodes=eps_nodes,
+                    eps_e=eps_e)
 
     def state(self):
         n = self.n
