@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CFDDEM_ABI_VERSION 2
+#define CFDDEM_ABI_VERSION 3
 
 typedef struct dem_ctx dem_ctx;
 typedef int32_t dem_status;
@@ -143,7 +143,21 @@ typedef struct {
                       evaluated from the Q_n velocity field at the particle
                       (div tau = mu_f (lap u + grad(div u) / 3)); model B also
                       hands it to the fluid.  0: no shear force */
-  int32_t reserved; /* must be 0 */
+  int32_t smooth;  /* 1: smoothed void fraction.  The element PCM values (Eq.
+                      "void_fraction") are projected onto the continuous
+                      velocity space: eps_h with int eps_h phi + smooth_L2 int
+                      grad eps_h . grad phi = int eps_PCM phi for every basis
+                      function phi (natural boundary conditions; the scheme
+                      with smoothing length L^2 of Tables "tab:setup2" and
+                      "tab:setup4" is described in a companion paper; this
+                      weak form is the reading).  eps_q is then eps_h at the
+                      quadrature points and the closure sees eps_h at each
+                      particle.  Solved by conjugate gradients to a relative
+                      residual of 1e-13 at every coupling step, starting from
+                      the previous field.  Not supported in batches.
+                      0: element PCM values (eps_q constant per element) */
+  double smooth_L2; /* smoothing length squared (m^2), >= 0 (0: the plain
+                       projection) */
 } cfd_params;
 
 /* Bytes of device workspace dem_create needs for these parameters.  Pure host
@@ -202,6 +216,10 @@ dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, dou
 /* Stored contact force and torque (sums over the contacts of the last
  * evaluation), 3 x n, original-ID order.  Either may be NULL. */
 dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream);
+
+/* Conjugate-gradient iterations of the smoothed void fraction at the last
+ * coupling step (cfd_params.smooth); -1 for a NULL context.  Host call. */
+int32_t dem_smoothing_iterations(const dem_ctx *ctx);
 
 /* Kinetic energy of the current (boundary) state: out[0] = sum 1/2 m v^2,
  * out[1] = sum 1/2 I w^2 with I = 2/5 m R^2 (solid spheres, Eq.

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libcfddem.so")
-SOURCES = ["api.hip", "dem_kernels.hip", "couple_kernels.hip"]
+SOURCES = ["api.hip", "dem_kernels.hip", "couple_kernels.hip", "smooth_kernels.hip"]
 ARCH = os.environ.get("CFDDEM_ARCH", "gfx950")
 
 

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libcfddem.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 DEM_OK = 0
 DEM_E_ARG = -1
@@ -33,6 +33,7 @@ DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
+           "dem_smoothing_iterations",
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
            "dem_batch_step", "dem_batch_couple", "dem_batch_run", "dem_batch_destroy",
@@ -56,7 +57,7 @@ class CfdParams(C.Structure):
     _fields_ = [
         ("order", C.c_int32), ("n_el", C.c_int32 * 3), ("rho_f", C.c_double), ("mu_f", C.c_double),
         ("drag", C.c_int32), ("model", C.c_int32), ("eps_min", C.c_double),
-        ("shear", C.c_int32), ("reserved", C.c_int32),
+        ("shear", C.c_int32), ("smooth", C.c_int32), ("smooth_L2", C.c_double),
     ]
 
 
@@ -94,6 +95,8 @@ def load():
     lib.dem_read_forces.argtypes = [vp, vp, vp, vp]
     lib.dem_read_cells.restype = i32
     lib.dem_read_cells.argtypes = [vp, vp, vp, C.POINTER(i32), vp]
+    lib.dem_smoothing_iterations.restype = i32
+    lib.dem_smoothing_iterations.argtypes = [vp]
     lib.dem_kinetic_energy.restype = i32
     lib.dem_kinetic_energy.argtypes = [vp, C.POINTER(dbl), vp]
     lib.dem_read_contacts.restype = i32
@@ -166,6 +169,9 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     cp.model = int(fluid.get("model", 0))
     cp.eps_min = float(fluid.get("eps_min", 0.1))
     cp.shear = 1 if fluid.get("shear") else 0
+    L2 = fluid.get("smooth_L2")
+    cp.smooth = 0 if L2 is None else 1
+    cp.smooth_L2 = 0.0 if L2 is None else float(L2)
     return dp, cp
 
 
@@ -272,6 +278,10 @@ class Bed:
         T = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
         _check(self._lib.dem_read_forces(self._h, _ptr(F), _ptr(T), self._st), "dem_read_forces")
         return F, T
+
+    def smoothing_iterations(self):
+        """CG iterations of the smoothed void fraction at the last coupling step."""
+        return int(self._lib.dem_smoothing_iterations(self._h))
 
     def kinetic_energy(self):
         """(translational, rotational) kinetic energy of the current state;

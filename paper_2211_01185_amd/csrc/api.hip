@@ -20,6 +20,15 @@ hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool adv
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,
                          double *esums, bool fp32, hipStream_t st);
+int smooth_blocks(long nv);
+hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *eps_e,
+                          double *b, hipStream_t st);
+hipError_t launch_smooth_init(const SmoothOp &S, const double *b, const double *x, double *r, double *z,
+                              double *p, double *part, double *sc, hipStream_t st);
+hipError_t launch_smooth_iteration(const SmoothOp &S, double *x, double *r, double *z, double *p, double *Ap,
+                                   double *part, double *sc, hipStream_t st);
+hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
+                              hipStream_t st);
 hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
                                   hipStream_t st);
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
@@ -51,6 +60,9 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 struct Sizes {
   int n, maxn, cap;
   int lanes;  // lanes per particle in the contact-force kernel
+  int smooth;     // smoothed void fraction
+  int nn[3];      // velocity nodes per axis
+  long nv;        // velocity nodes
   double skin;
   Grid grid;
   int scan_blocks;  // blocks of the device scan over max(ncells, n) items
@@ -87,11 +99,19 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!finite_pos(cp->rho_f) || !finite_pos(cp->mu_f)) return DEM_E_ARG;
   if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
   if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
-  if ((cp->shear != 0 && cp->shear != 1) || cp->reserved != 0) return DEM_E_ARG;
+  if (cp->shear != 0 && cp->shear != 1) return DEM_E_ARG;
+  if ((cp->smooth != 0 && cp->smooth != 1) || !(cp->smooth_L2 >= 0.0) || !isfinite(cp->smooth_L2))
+    return DEM_E_ARG;
   if ((cp->drag & ~(0xff | DEM_DRAG_BETA_OVER_EPS)) != 0 || (cp->drag & 0xff) > DEM_DRAG_GIDASPOW)
     return DEM_E_UNSUPPORTED;
 
   S.n = (int)dp->n;
+  S.smooth = cp->smooth;
+  S.nv = 1;
+  for (int a = 0; a < 3; ++a) {
+    S.nn[a] = cp->order * cp->n_el[a] + 1;
+    S.nv *= S.nn[a];
+  }
   S.maxn = dp->max_neighbors ? dp->max_neighbors : 32;
   S.skin = dp->skin > 0.0 ? dp->skin : 0.1 * dp->d_min;
   // the broad search needs cells at least d_max + skin wide; an element
@@ -173,6 +193,12 @@ struct Buffers {
   long long *bsum;              // per-block partial sums of the device scan
   unsigned long long *scalars;  // [0] contact count, [1] radius max bits, [2] radius min bits
   double *energy;               // per-block kinetic energies, then the two totals
+  // smoothed void fraction (only when enabled): element PCM values, the
+  // right-hand side, the field (kept between coupling steps as the start of
+  // the next solve), the CG vectors, the 1D band matrices, partial sums and
+  // scalars
+  double *eps_e, *sb, *sx, *sr, *sz, *sp, *sAp, *diag, *part, *sc;
+  double *band_m[3], *band_k[3];
 };
 
 size_t carve(const Sizes &S, char *base, Buffers &B) {
@@ -186,6 +212,23 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   }
   B.scalars = c.take<unsigned long long>(8);
   B.energy = c.take<double>(2 * ((n + 255) / 256) + 2);
+  if (S.smooth) {
+    const size_t nv = (size_t)S.nv;
+    B.eps_e = c.take<double>((size_t)S.grid.n_elem);
+    B.sb = c.take<double>(nv);
+    B.sx = c.take<double>(nv);
+    B.sr = c.take<double>(nv);
+    B.sz = c.take<double>(nv);
+    B.sp = c.take<double>(nv);
+    B.sAp = c.take<double>(nv);
+    B.diag = c.take<double>(nv);
+    B.part = c.take<double>(3 * (size_t)((S.nv + 255) / 256));
+    B.sc = c.take<double>(8);
+    for (int a = 0; a < 3; ++a) {
+      B.band_m[a] = c.take<double>(5 * (size_t)S.nn[a]);
+      B.band_k[a] = c.take<double>(5 * (size_t)S.nn[a]);
+    }
+  }
   for (int b = 0; b < 2; ++b) {
     D.xs[b] = c.take<double>(3 * n);
     D.vhs[b] = c.take<double>(3 * n);
@@ -545,6 +588,8 @@ struct dem_ctx {
   long long n_couple = 0;  // coupling steps issued
   dem_status poisoned = DEM_OK;
   bool timing = false;
+  SmoothOp SO{};           // smoothed void fraction operator (smooth = 1)
+  int smooth_iters = 0;    // CG iterations of the last coupling step
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   size_t ev_used = 0;
 };
@@ -684,6 +729,8 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   C.drag = cp->drag & 0xff;
   C.beta_over_eps = (cp->drag & DEM_DRAG_BETA_OVER_EPS) ? 1 : 0;
   C.shear = cp->shear;
+  C.smooth = cp->smooth;
+  C.eps_nodes = cp->smooth ? ctx->B.sx : nullptr;
   C.Ve = S.grid.he[0] * S.grid.he[1] * S.grid.he[2];
   {
     double gp[3];
@@ -719,6 +766,65 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
     return code;
   };
   if (hipMemsetAsync(D.err, 0, sizeof(int) * 64, st) != hipSuccess) return fail(DEM_E_HIP);
+  if (S.smooth) {
+    // 1D element matrices on an element of length h (Lagrange basis on
+    // equally spaced nodes): Q1 mass h/6 [2 1; 1 2], stiffness 1/h [1 -1; -1 1],
+    // load h/2 [1 1]; Q2 mass h/30 [4 2 -1; 2 16 2; -1 2 4], stiffness
+    // 1/(3h) [7 -8 1; -8 16 -8; 1 -8 7], load h [1/6 2/3 1/6].  Assembled per
+    // axis into 5-entry bands (offsets -2..2).
+    static const double m1[2][2] = {{2.0 / 6.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 6.0}};
+    static const double k1[2][2] = {{1.0, -1.0}, {-1.0, 1.0}};
+    static const double m2[3][3] = {{4.0 / 30.0, 2.0 / 30.0, -1.0 / 30.0},
+                                    {2.0 / 30.0, 16.0 / 30.0, 2.0 / 30.0},
+                                    {-1.0 / 30.0, 2.0 / 30.0, 4.0 / 30.0}};
+    static const double k2[3][3] = {{7.0 / 3.0, -8.0 / 3.0, 1.0 / 3.0},
+                                    {-8.0 / 3.0, 16.0 / 3.0, -8.0 / 3.0},
+                                    {1.0 / 3.0, -8.0 / 3.0, 7.0 / 3.0}};
+    static const double l1[2] = {0.5, 0.5}, l2[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    const int p = cp->order;
+    SmoothOp &SO = ctx->SO;
+    SO.order = p;
+    SO.nv = S.nv;
+    SO.L2 = cp->smooth_L2;
+    SO.diag = ctx->B.diag;
+    std::vector<double> bm[3], bk[3];
+    for (int a = 0; a < 3; ++a) {
+      SO.nn[a] = S.nn[a];
+      SO.n_el[a] = cp->n_el[a];
+      SO.band_m[a] = ctx->B.band_m[a];
+      SO.band_k[a] = ctx->B.band_k[a];
+      const double h = S.grid.he[a];
+      bm[a].assign(5 * (size_t)S.nn[a], 0.0);
+      bk[a].assign(5 * (size_t)S.nn[a], 0.0);
+      for (int e = 0; e < cp->n_el[a]; ++e)
+        for (int i = 0; i <= p; ++i)
+          for (int j = 0; j <= p; ++j) {
+            const int gi = p * e + i, gj = p * e + j;
+            bm[a][5 * (size_t)gi + (gj - gi + 2)] += h * (p == 1 ? m1[i][j] : m2[i][j]);
+            bk[a][5 * (size_t)gi + (gj - gi + 2)] += (p == 1 ? k1[i][j] : k2[i][j]) / h;
+          }
+      for (int l = 0; l < 3; ++l) SO.load[a][l] = l <= p ? h * (p == 1 ? l1[l] : l2[l]) : 0.0;
+    }
+    std::vector<double> dg((size_t)S.nv);
+    for (int gz = 0; gz < S.nn[2]; ++gz)
+      for (int gy = 0; gy < S.nn[1]; ++gy)
+        for (int gx = 0; gx < S.nn[0]; ++gx) {
+          const double mx = bm[0][5 * (size_t)gx + 2], my = bm[1][5 * (size_t)gy + 2], mz = bm[2][5 * (size_t)gz + 2];
+          const double kx = bk[0][5 * (size_t)gx + 2], ky = bk[1][5 * (size_t)gy + 2], kz = bk[2][5 * (size_t)gz + 2];
+          dg[((size_t)gz * S.nn[1] + gy) * S.nn[0] + gx] =
+              mx * my * mz + SO.L2 * (kx * my * mz + mx * ky * mz + mx * my * kz);
+        }
+    bool ok = true;
+    for (int a = 0; a < 3; ++a)
+      ok = ok && hipMemcpyAsync(ctx->B.band_m[a], bm[a].data(), sizeof(double) * bm[a].size(),
+                                hipMemcpyHostToDevice, st) == hipSuccess &&
+           hipMemcpyAsync(ctx->B.band_k[a], bk[a].data(), sizeof(double) * bk[a].size(),
+                          hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(ctx->B.diag, dg.data(), sizeof(double) * dg.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemsetAsync(ctx->B.sx, 0, sizeof(double) * (size_t)S.nv, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) return fail(DEM_E_HIP);
+  }
   k_fill_u64<<<1, 64, 0, st>>>(ctx->B.scalars, 0ULL, ~0ULL);
   if (hipGetLastError() != hipSuccess) return fail(DEM_E_HIP);
   for (int b = 0; b < 3; ++b)
@@ -774,16 +880,46 @@ dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
   return DEM_OK;
 }
 
+// Smoothed void fraction of the current state into B.sx: element PCM values,
+// right-hand side, then Jacobi-preconditioned CG from the previous field until
+// the residual norm is below 1e-13 of the right-hand side's (checked every 8
+// iterations; at most 4000).
+static dem_status smooth_solve(dem_ctx *ctx, hipStream_t st) {
+  Buffers &B = ctx->B;
+  const SmoothOp &S = ctx->SO;
+  HIP_TRY(launch_pcm_rhs(B.D, ctx->C, S, ctx->s, B.eps_e, B.sb, st));
+  HIP_TRY(launch_smooth_init(S, B.sb, B.sx, B.sr, B.sz, B.sp, B.part, B.sc, st));
+  const double tol2 = 1e-26;
+  int it = 0;
+  for (;;) {
+    double sc[8];
+    HIP_TRY(hipMemcpyAsync(sc, B.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (!(sc[3] > tol2 * sc[4]) || it >= 4000) break;
+    for (int k = 0; k < 8; ++k, ++it) HIP_TRY(launch_smooth_iteration(S, B.sx, B.sr, B.sz, B.sp, B.sAp, B.part, B.sc, st));
+  }
+  ctx->smooth_iters = it;
+  return DEM_OK;
+}
+
 dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_nodes,
                           double *eps_q, double *beta_q, double *fpf_q, double *elem_sums,
                           void *stream) {
   if (!ctx || !u_nodes || !p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
   if (ctx->poisoned) return ctx->poisoned;
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->C.smooth) {
+    dem_status r = smooth_solve(ctx, st);
+    if (r != DEM_OK) return r;
+  }
   HIP_TRY(launch_couple(ctx->B.D, ctx->C, ctx->s, ctx->n_couple, u_nodes, p_nodes, eps_q, beta_q,
-                        fpf_q, elem_sums, ctx->fp32, (hipStream_t)stream));
+                        fpf_q, elem_sums, ctx->fp32, st));
+  if (ctx->C.smooth) HIP_TRY(launch_eps_q_field(ctx->SO, ctx->C, ctx->B.sx, eps_q, st));
   ++ctx->n_couple;
   return DEM_OK;
 }
+
+int32_t dem_smoothing_iterations(const dem_ctx *ctx) { return ctx ? ctx->smooth_iters : -1; }
 
 dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, double *f_fp,
                           void *stream) {
@@ -971,6 +1107,7 @@ dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, Batc
     for (int j = 0; j < b; ++j)
       if (beds[j] == x) return DEM_E_ARG;
     if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes) return DEM_E_UNSUPPORTED;
+    if (x->C.smooth) return DEM_E_UNSUPPORTED;  // the smoothing solve runs per bed
     const long long n = x->S.n;
     const int bd = ceil_div(n, 256), bf = ceil_div(n * x->S.lanes, kForceBlock);
     const int ne = x->S.grid.n_elem;

@@ -309,6 +309,7 @@ template <typename R, int ORD, int MODE>
 __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const int ee[3],
                                       const double xp[3], const double up[3], double r,
                                       double eps_c, const double (*sU)[27], const double *sP,
+                                      const double *sE,
                                       double sums[10]) {
   const Grid &G = D.grid;
   const int n = D.n;
@@ -360,6 +361,23 @@ __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const i
   const double sl[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
   const double slip = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + sl[2] * sl[2]);
   constexpr bool GEN = MODE >= 1;
+  if (MODE == 2 && C.smooth) {
+    // smoothed void fraction: the continuous field at the particle
+    double ev = 0.0;
+#pragma unroll
+    for (int ic = 0; ic < p1; ++ic) {
+      double acc_c = 0.0;
+#pragma unroll
+      for (int ib = 0; ib < p1; ++ib) {
+        double acc_b = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < p1; ++ia) acc_b += Lx[ia] * sE[(ic * p1 + ib) * p1 + ia];
+        acc_c += Ly[ib] * acc_b;
+      }
+      ev += Lz[ic] * acc_c;
+    }
+    eps_c = fmin(1.0, fmax(ev, C.eps_min));
+  }
   double beta = GEN ? (double)drag_beta<R>(C.drag, R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip))
                     : (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
   if (C.beta_over_eps) beta /= eps_c;  // beta_B = beta_A / eps (Eq. "beta")
@@ -419,6 +437,7 @@ struct CplShared {
   int ids[kElemMaxParticles];
   double sU[3][27];
   double sP[8];
+  double sE[27];     // smoothed void fraction at the element's velocity nodes
   double sLq[3][3];  // 1D velocity basis at the Gauss points (kernel constants)
   double red[kCplWaves][11];
   int scan[kCplWaves];
@@ -454,6 +473,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     un[0] = U[node];
     un[1] = U[nv + node];
     un[2] = U[2 * nv + node];
+    if (MODE == 2 && C.smooth) sh.sE[tid] = C.eps_nodes[node];  // read after the barrier below
   }
   const int pc = tid - kWave;  // pressure corner of this thread
   if (pc >= 0 && pc < 8) {
@@ -553,7 +573,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   // ---- 3. per-particle forces
   double sums[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // beta, beta u_p, f_D, f_gradp
   const double eps_c = fmin(1.0, fmax(eps, C.eps_min));
-  if (k0 >= 0) particle_force<R, ORD, MODE>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sums);
+  if (k0 >= 0) particle_force<R, ORD, MODE>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sh.sE, sums);
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
     const int k = sh.ids[t];
     double xp[3], up[3];
@@ -562,7 +582,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       xp[c] = X[c * n + k];
       up[c] = D.v[c * n + k];
     }
-    particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sums);
+    particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sh.sE, sums);
   }
   wave_sum_n(sums);
   if (lane == 0)
@@ -732,7 +752,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
   const int p3 = (int)(run[b].s % 3);
   const int gw = blk * (kClassBlock / kWave) + (int)(threadIdx.x / kWave);
   // occupied elements go to the list of the bed's element-kernel variant
-  const int m = cpl_mode_of(C.drag, C.shear);
+  const int m = cpl_mode_of(C.drag, C.shear || C.smooth);
   couple_classify_body(D, C, gw * kClassElems, p3, cnt_words + m, list + ml.off[m], (unsigned)b << kBedShift,
                        io.eps_q, io.beta_q, io.fpf_q, io.esums);
 }
@@ -825,7 +845,7 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
 #define CFDDEM_OCC(RT, O, M) couple_occupied<RT, O, M><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)
 #define CFDDEM_OCC_MODE(RT, O) \
   do { if (mode == 2) CFDDEM_OCC(RT, O, 2); else if (mode == 1) CFDDEM_OCC(RT, O, 1); else CFDDEM_OCC(RT, O, 0); } while (0)
-  const int mode = cpl_mode_of(C.drag, C.shear);
+  const int mode = cpl_mode_of(C.drag, C.shear || C.smooth);
   if (fp32) {
     if (C.order == 2) CFDDEM_OCC_MODE(float, 2); else CFDDEM_OCC_MODE(float, 1);
   } else {

@@ -104,8 +104,23 @@ struct ModeLists {
   long long off[3];
 };
 
-// Element-kernel variant of a bed's coupling step.
-__host__ __device__ inline int cpl_mode_of(int drag, int shear) { return shear ? 2 : (drag != 0 ? 1 : 0); }
+// Element-kernel variant of a bed's coupling step: 2 for the shear force or
+// the smoothed void fraction, 1 for a closure other than Di Felice, else 0.
+__host__ __device__ inline int cpl_mode_of(int drag, int extended) { return extended ? 2 : (drag != 0 ? 1 : 0); }
+
+// Operator of the smoothed void fraction (smooth_kernels.hip): the global
+// matrix M + L^2 K of the velocity space as Kronecker products of 1D banded
+// matrices of each axis.
+struct SmoothOp {
+  int order;
+  int nn[3];     // velocity nodes per axis
+  int n_el[3];
+  long nv;       // velocity nodes
+  double L2;     // smoothing length squared
+  const double *band_m[3], *band_k[3];  // per axis: nn[a] rows of 5 entries (offsets -2..2)
+  const double *diag;                   // diagonal of the global matrix
+  double load[3][3];                    // integral of local basis l over an element of axis a
+};
 
 // Coupling buffers of one bed of a batch.
 struct CplIO {
@@ -125,6 +140,8 @@ struct Cpl {
   int drag;           // closure (DEM_DRAG_* without the flag bits)
   int beta_over_eps;  // 1: beta divided by the fluid fraction
   int shear;          // 1: shear force -V_p div(tau) added to the particle force
+  int smooth;         // 1: the closure sees the smoothed void-fraction field
+  const double *eps_nodes;  // that field at the velocity nodes (smooth = 1)
   double Ve;        // element volume
   double Lq[3][3];  // Lq[a][i]: 1D velocity basis a at Gauss point i
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)

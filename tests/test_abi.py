@@ -75,7 +75,7 @@ def test_workspace_query_validates_parameters():
     _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
     cpb.order = 3
     assert cfddem.workspace_bytes(dp, cpb) == 0
-    for field, value in (("shear", 2), ("reserved", 1)):
+    for field, value in (("shear", 2), ("smooth", 2), ("smooth_L2", -1.0)):
         _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
         setattr(cpb, field, value)
         assert cfddem.workspace_bytes(dp, cpb) == 0, field

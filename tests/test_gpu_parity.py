@@ -360,3 +360,47 @@ def test_coupling_step_with_shear_force(drag, order, model, precision):
     ob.step(10)
     compare_contacts(gb, ob, 10 * tol)
     compare_states(gb, ob, 10 * tol)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("L2", [0.0, 4 * 3e-3 ** 2, 5 * 3e-3 ** 2])  # 4 d^2, 5 d^2 of Tables 2, 4
+def test_coupling_step_with_smoothed_void_fraction(L2, order, precision):
+    """The smoothed void fraction (conjugate gradients on the GPU, a direct
+    sparse solve in the oracle): eps_q at every quadrature point, the closure
+    fed by the field at each particle, and the outputs of two coupling steps
+    (the second starting from the first's field) against the oracle."""
+    wl = _noisy_field(_workload("lattice"), order)
+    wl.fluid.update(smooth_L2=L2, model=1)
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    tol = TOL[precision]
+    for rep in range(2):
+        out = gb.couple(U, P, elem_sums=True)
+        ref = ob.couple(fl, wl.U, wl.P, smooth_L2=L2)
+        # the first solve starts from zero; the second from the first field,
+        # already converged when no sphere changed element in between
+        assert gb.smoothing_iterations() > 0 or rep > 0
+        assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-10)
+        assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+        assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+        assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+        assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
+        # a continuous field: not constant per element where the bed ends
+        eq = out["eps_q"].cpu().numpy().reshape(-1, (order + 1) ** 3)
+        assert np.abs(eq - eq[:, :1]).max() > 1e-3
+        gb.step(10)
+        ob.step(10)
+    assert gb.poll()[0] == 0
+
+
+def test_batches_reject_the_smoothed_void_fraction():
+    from paper_2211_01185_amd import cfddem
+    wl = _workload("lattice")
+    wl.fluid["smooth_L2"] = 5 * 3e-3 ** 2
+    gb = gpu_bed(wl, "fp64")
+    with pytest.raises(cfddem.CfddemError) as ei:
+        cfddem.Batch([gb], [_fields(wl)])
+    # refused by the workspace query (no size for such a batch) or by creation
+    assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)
