@@ -152,9 +152,10 @@ typedef struct {
                       "tab:setup4" is described in a companion paper; this
                       weak form is the reading).  eps_q is then eps_h at the
                       quadrature points and the closure sees eps_h at each
-                      particle.  Solved by conjugate gradients to a relative
-                      residual of 1e-13 at every coupling step, starting from
-                      the previous field.  Not supported in batches.
+                      particle.  Solved directly at every coupling step (the
+                      matrix is a Kronecker sum of 1D mass and stiffness
+                      matrices, diagonalized at creation by their generalized
+                      eigenvectors).  Not supported in batches.
                       0: element PCM values (eps_q constant per element) */
   double smooth_L2; /* smoothing length squared (m^2), >= 0 (0: the plain
                        projection) */
@@ -216,10 +217,6 @@ dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, dou
 /* Stored contact force and torque (sums over the contacts of the last
  * evaluation), 3 x n, original-ID order.  Either may be NULL. */
 dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream);
-
-/* Conjugate-gradient iterations of the smoothed void fraction at the last
- * coupling step (cfd_params.smooth); -1 for a NULL context.  Host call. */
-int32_t dem_smoothing_iterations(const dem_ctx *ctx);
 
 /* Kinetic energy of the current (boundary) state: out[0] = sum 1/2 m v^2,
  * out[1] = sum 1/2 I w^2 with I = 2/5 m R^2 (solid spheres, Eq.

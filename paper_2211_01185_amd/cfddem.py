@@ -33,7 +33,7 @@ DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
-           "dem_smoothing_iterations",
+
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
            "dem_batch_step", "dem_batch_couple", "dem_batch_run", "dem_batch_destroy",
@@ -95,8 +95,6 @@ def load():
     lib.dem_read_forces.argtypes = [vp, vp, vp, vp]
     lib.dem_read_cells.restype = i32
     lib.dem_read_cells.argtypes = [vp, vp, vp, C.POINTER(i32), vp]
-    lib.dem_smoothing_iterations.restype = i32
-    lib.dem_smoothing_iterations.argtypes = [vp]
     lib.dem_kinetic_energy.restype = i32
     lib.dem_kinetic_energy.argtypes = [vp, C.POINTER(dbl), vp]
     lib.dem_read_contacts.restype = i32
@@ -278,10 +276,6 @@ class Bed:
         T = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
         _check(self._lib.dem_read_forces(self._h, _ptr(F), _ptr(T), self._st), "dem_read_forces")
         return F, T
-
-    def smoothing_iterations(self):
-        """CG iterations of the smoothed void fraction at the last coupling step."""
-        return int(self._lib.dem_smoothing_iterations(self._h))
 
     def kinetic_energy(self):
         """(translational, rotational) kinetic energy of the current state;

@@ -21,12 +21,10 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,
                          double *esums, bool fp32, hipStream_t st);
 int smooth_blocks(long nv);
-hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *eps_e,
+hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *acc,
                           double *b, hipStream_t st);
-hipError_t launch_smooth_init(const SmoothOp &S, const double *b, const double *x, double *r, double *z,
-                              double *p, double *part, double *sc, hipStream_t st);
-hipError_t launch_smooth_iteration(const SmoothOp &S, double *x, double *r, double *z, double *p, double *Ap,
-                                   double *part, double *sc, hipStream_t st);
+hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
+                               hipStream_t st);
 hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
                               hipStream_t st);
 hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
@@ -69,6 +67,92 @@ struct Sizes {
 };
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// Generalized symmetric eigenproblem K v = lam M v, M positive definite (n x n
+// row-major, n up to a few hundred; set-up only): Cholesky M = L L^T, the
+// symmetric C = L^-1 K L^-T diagonalized by cyclic Jacobi rotations
+// (C = Q diag(lam) Q^T), then V = L^-T Q, so that V^T M V = I and
+// V^T K V = diag(lam).  V is returned row-major with the eigenvectors as
+// columns.  False if M is not positive definite.
+bool gen_eig(int n, const std::vector<double> &M, const std::vector<double> &K, std::vector<double> &V,
+             std::vector<double> &lam) {
+  const size_t N = (size_t)n;
+  std::vector<double> L(N * N, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = M[j * N + j];
+    for (int k = 0; k < j; ++k) d -= L[j * N + k] * L[j * N + k];
+    if (!(d > 0.0)) return false;
+    L[j * N + j] = sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = M[i * N + j];
+      for (int k = 0; k < j; ++k) v -= L[i * N + k] * L[j * N + k];
+      L[i * N + j] = v / L[j * N + j];
+    }
+  }
+  // W = L^-1 K (column by column), C^T = L^-1 W^T
+  std::vector<double> W(N * N), C(N * N);
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double v = K[i * N + c];
+      for (int k = 0; k < i; ++k) v -= L[i * N + k] * W[k * N + c];
+      W[i * N + c] = v / L[i * N + i];
+    }
+  for (int r = 0; r < n; ++r)
+    for (int i = 0; i < n; ++i) {
+      double v = W[r * N + i];
+      for (int k = 0; k < i; ++k) v -= L[i * N + k] * C[r * N + k];
+      C[r * N + i] = v / L[i * N + i];
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double v = 0.5 * (C[i * N + j] + C[j * N + i]);
+      C[i * N + j] = C[j * N + i] = v;
+    }
+  std::vector<double> Q(N * N, 0.0);
+  for (int i = 0; i < n; ++i) Q[i * N + i] = 1.0;
+  double norm = 0.0;
+  for (size_t i = 0; i < N * N; ++i) norm += C[i] * C[i];
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += C[i * N + j] * C[i * N + j];
+    if (off <= 1e-32 * norm) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = C[p * N + q];
+        if (apq == 0.0) continue;
+        const double theta = (C[q * N + q] - C[p * N + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double a = C[k * N + p], b = C[k * N + q];
+          C[k * N + p] = cs * a - sn * b;
+          C[k * N + q] = sn * a + cs * b;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double a = C[p * N + k], b = C[q * N + k];
+          C[p * N + k] = cs * a - sn * b;
+          C[q * N + k] = sn * a + cs * b;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double a = Q[k * N + p], b = Q[k * N + q];
+          Q[k * N + p] = cs * a - sn * b;
+          Q[k * N + q] = sn * a + cs * b;
+        }
+      }
+  }
+  lam.resize(N);
+  for (int i = 0; i < n; ++i) lam[i] = C[i * N + i];
+  // V = L^-T Q: back substitution, column by column
+  V.assign(N * N, 0.0);
+  for (int c = 0; c < n; ++c)
+    for (int i = n - 1; i >= 0; --i) {
+      double v = Q[i * N + c];
+      for (int k = i + 1; k < n; ++k) v -= L[k * N + i] * V[k * N + c];
+      V[i * N + c] = v / L[i * N + i];
+    }
+  return true;
+}
 
 // DEM_OK when the parameters are valid; fills the derived grid / capacity.
 dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
@@ -193,12 +277,11 @@ struct Buffers {
   long long *bsum;              // per-block partial sums of the device scan
   unsigned long long *scalars;  // [0] contact count, [1] radius max bits, [2] radius min bits
   double *energy;               // per-block kinetic energies, then the two totals
-  // smoothed void fraction (only when enabled): element PCM values, the
-  // right-hand side, the field (kept between coupling steps as the start of
-  // the next solve), the CG vectors, the 1D band matrices, partial sums and
-  // scalars
-  double *eps_e, *sb, *sx, *sr, *sz, *sp, *sAp, *diag, *part, *sc;
-  double *band_m[3], *band_k[3];
+  // smoothed void fraction (only when enabled): fixed-point element volume
+  // sums, the right-hand side, the field, two scratch vectors, and per axis
+  // the generalized eigenvectors (and transpose) and eigenvalues
+  double *eps_e, *sb, *sx, *st1, *st2;
+  double *fdV[3], *fdVt[3], *fdlam[3];
 };
 
 size_t carve(const Sizes &S, char *base, Buffers &B) {
@@ -217,16 +300,13 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
     B.eps_e = c.take<double>((size_t)S.grid.n_elem);
     B.sb = c.take<double>(nv);
     B.sx = c.take<double>(nv);
-    B.sr = c.take<double>(nv);
-    B.sz = c.take<double>(nv);
-    B.sp = c.take<double>(nv);
-    B.sAp = c.take<double>(nv);
-    B.diag = c.take<double>(nv);
-    B.part = c.take<double>(3 * (size_t)((S.nv + 255) / 256));
-    B.sc = c.take<double>(8);
+    B.st1 = c.take<double>(nv);
+    B.st2 = c.take<double>(nv);
     for (int a = 0; a < 3; ++a) {
-      B.band_m[a] = c.take<double>(5 * (size_t)S.nn[a]);
-      B.band_k[a] = c.take<double>(5 * (size_t)S.nn[a]);
+      const size_t m = (size_t)S.nn[a];
+      B.fdV[a] = c.take<double>(m * m);
+      B.fdVt[a] = c.take<double>(m * m);
+      B.fdlam[a] = c.take<double>(m);
     }
   }
   for (int b = 0; b < 2; ++b) {
@@ -589,7 +669,6 @@ struct dem_ctx {
   dem_status poisoned = DEM_OK;
   bool timing = false;
   SmoothOp SO{};           // smoothed void fraction operator (smooth = 1)
-  int smooth_iters = 0;    // CG iterations of the last coupling step
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   size_t ev_used = 0;
 };
@@ -771,7 +850,7 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
     // equally spaced nodes): Q1 mass h/6 [2 1; 1 2], stiffness 1/h [1 -1; -1 1],
     // load h/2 [1 1]; Q2 mass h/30 [4 2 -1; 2 16 2; -1 2 4], stiffness
     // 1/(3h) [7 -8 1; -8 16 -8; 1 -8 7], load h [1/6 2/3 1/6].  Assembled per
-    // axis into 5-entry bands (offsets -2..2).
+    // axis, then diagonalized together.
     static const double m1[2][2] = {{2.0 / 6.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 6.0}};
     static const double k1[2][2] = {{1.0, -1.0}, {-1.0, 1.0}};
     static const double m2[3][3] = {{4.0 / 30.0, 2.0 / 30.0, -1.0 / 30.0},
@@ -786,43 +865,39 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
     SO.order = p;
     SO.nv = S.nv;
     SO.L2 = cp->smooth_L2;
-    SO.diag = ctx->B.diag;
-    std::vector<double> bm[3], bk[3];
+    std::vector<double> V[3], Vt[3], lam[3];
     for (int a = 0; a < 3; ++a) {
-      SO.nn[a] = S.nn[a];
+      const int m = S.nn[a];
+      SO.nn[a] = m;
       SO.n_el[a] = cp->n_el[a];
-      SO.band_m[a] = ctx->B.band_m[a];
-      SO.band_k[a] = ctx->B.band_k[a];
+      SO.V[a] = ctx->B.fdV[a];
+      SO.Vt[a] = ctx->B.fdVt[a];
+      SO.lam[a] = ctx->B.fdlam[a];
       const double h = S.grid.he[a];
-      bm[a].assign(5 * (size_t)S.nn[a], 0.0);
-      bk[a].assign(5 * (size_t)S.nn[a], 0.0);
+      std::vector<double> M((size_t)m * m, 0.0), K((size_t)m * m, 0.0);
       for (int e = 0; e < cp->n_el[a]; ++e)
         for (int i = 0; i <= p; ++i)
           for (int j = 0; j <= p; ++j) {
-            const int gi = p * e + i, gj = p * e + j;
-            bm[a][5 * (size_t)gi + (gj - gi + 2)] += h * (p == 1 ? m1[i][j] : m2[i][j]);
-            bk[a][5 * (size_t)gi + (gj - gi + 2)] += (p == 1 ? k1[i][j] : k2[i][j]) / h;
+            const size_t at = (size_t)(p * e + i) * m + (p * e + j);
+            M[at] += h * (p == 1 ? m1[i][j] : m2[i][j]);
+            K[at] += (p == 1 ? k1[i][j] : k2[i][j]) / h;
           }
+      if (!gen_eig(m, M, K, V[a], lam[a])) return fail(DEM_E_ARG);
+      Vt[a].resize((size_t)m * m);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Vt[a][(size_t)j * m + i] = V[a][(size_t)i * m + j];
       for (int l = 0; l < 3; ++l) SO.load[a][l] = l <= p ? h * (p == 1 ? l1[l] : l2[l]) : 0.0;
     }
-    std::vector<double> dg((size_t)S.nv);
-    for (int gz = 0; gz < S.nn[2]; ++gz)
-      for (int gy = 0; gy < S.nn[1]; ++gy)
-        for (int gx = 0; gx < S.nn[0]; ++gx) {
-          const double mx = bm[0][5 * (size_t)gx + 2], my = bm[1][5 * (size_t)gy + 2], mz = bm[2][5 * (size_t)gz + 2];
-          const double kx = bk[0][5 * (size_t)gx + 2], ky = bk[1][5 * (size_t)gy + 2], kz = bk[2][5 * (size_t)gz + 2];
-          dg[((size_t)gz * S.nn[1] + gy) * S.nn[0] + gx] =
-              mx * my * mz + SO.L2 * (kx * my * mz + mx * ky * mz + mx * my * kz);
-        }
     bool ok = true;
     for (int a = 0; a < 3; ++a)
-      ok = ok && hipMemcpyAsync(ctx->B.band_m[a], bm[a].data(), sizeof(double) * bm[a].size(),
-                                hipMemcpyHostToDevice, st) == hipSuccess &&
-           hipMemcpyAsync(ctx->B.band_k[a], bk[a].data(), sizeof(double) * bk[a].size(),
-                          hipMemcpyHostToDevice, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(ctx->B.diag, dg.data(), sizeof(double) * dg.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-         hipMemsetAsync(ctx->B.sx, 0, sizeof(double) * (size_t)S.nv, st) == hipSuccess &&
-         hipStreamSynchronize(st) == hipSuccess;
+      ok = ok &&
+           hipMemcpyAsync(ctx->B.fdV[a], V[a].data(), sizeof(double) * V[a].size(), hipMemcpyHostToDevice, st) ==
+               hipSuccess &&
+           hipMemcpyAsync(ctx->B.fdVt[a], Vt[a].data(), sizeof(double) * Vt[a].size(), hipMemcpyHostToDevice,
+                          st) == hipSuccess &&
+           hipMemcpyAsync(ctx->B.fdlam[a], lam[a].data(), sizeof(double) * lam[a].size(), hipMemcpyHostToDevice,
+                          st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) return fail(DEM_E_HIP);
   }
   k_fill_u64<<<1, 64, 0, st>>>(ctx->B.scalars, 0ULL, ~0ULL);
@@ -880,25 +955,12 @@ dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
   return DEM_OK;
 }
 
-// Smoothed void fraction of the current state into B.sx: element PCM values,
-// right-hand side, then Jacobi-preconditioned CG from the previous field until
-// the residual norm is below 1e-13 of the right-hand side's (checked every 8
-// iterations; at most 4000).
+// Smoothed void fraction of the current state into B.sx: element PCM values
+// (fixed-point accumulators in B.eps_e), right-hand side, direct solve.
 static dem_status smooth_solve(dem_ctx *ctx, hipStream_t st) {
   Buffers &B = ctx->B;
-  const SmoothOp &S = ctx->SO;
-  HIP_TRY(launch_pcm_rhs(B.D, ctx->C, S, ctx->s, B.eps_e, B.sb, st));
-  HIP_TRY(launch_smooth_init(S, B.sb, B.sx, B.sr, B.sz, B.sp, B.part, B.sc, st));
-  const double tol2 = 1e-26;
-  int it = 0;
-  for (;;) {
-    double sc[8];
-    HIP_TRY(hipMemcpyAsync(sc, B.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (!(sc[3] > tol2 * sc[4]) || it >= 4000) break;
-    for (int k = 0; k < 8; ++k, ++it) HIP_TRY(launch_smooth_iteration(S, B.sx, B.sr, B.sz, B.sp, B.sAp, B.part, B.sc, st));
-  }
-  ctx->smooth_iters = it;
+  HIP_TRY(launch_pcm_rhs(B.D, ctx->C, ctx->SO, ctx->s, B.eps_e, B.sb, st));
+  HIP_TRY(launch_smooth_solve(ctx->SO, B.sb, B.sx, B.st1, B.st2, st));
   return DEM_OK;
 }
 
@@ -919,7 +981,6 @@ dem_status cfd_dem_couple(dem_ctx *ctx, const double *u_nodes, const double *p_n
   return DEM_OK;
 }
 
-int32_t dem_smoothing_iterations(const dem_ctx *ctx) { return ctx ? ctx->smooth_iters : -1; }
 
 dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, double *f_fp,
                           void *stream) {

@@ -108,18 +108,19 @@ struct ModeLists {
 // the smoothed void fraction, 1 for a closure other than Di Felice, else 0.
 __host__ __device__ inline int cpl_mode_of(int drag, int extended) { return extended ? 2 : (drag != 0 ? 1 : 0); }
 
-// Operator of the smoothed void fraction (smooth_kernels.hip): the global
-// matrix M + L^2 K of the velocity space as Kronecker products of 1D banded
-// matrices of each axis.
+// Solver of the smoothed void fraction (smooth_kernels.hip): the global
+// matrix M + L^2 K of the velocity space, a Kronecker sum of the 1D mass and
+// stiffness matrices of each axis, diagonalized by their generalized
+// eigenvectors.
 struct SmoothOp {
   int order;
   int nn[3];     // velocity nodes per axis
   int n_el[3];
   long nv;       // velocity nodes
   double L2;     // smoothing length squared
-  const double *band_m[3], *band_k[3];  // per axis: nn[a] rows of 5 entries (offsets -2..2)
-  const double *diag;                   // diagonal of the global matrix
-  double load[3][3];                    // integral of local basis l over an element of axis a
+  const double *V[3], *Vt[3];  // per axis: eigenvectors (columns) and their transpose, nn x nn
+  const double *lam[3];        // per axis: eigenvalues
+  double load[3][3];           // integral of local basis l over an element of axis a
 };
 
 // Coupling buffers of one bed of a batch.

@@ -9,16 +9,14 @@
 // structured mesh the global matrix is a sum of Kronecker products of 1D
 // banded matrices (mass M_a, stiffness K_a of each axis),
 //     A = Mx My Mz + L^2 (Kx My Mz + Mx Ky Mz + Mx My Kz),
-// so it is applied node by node as a (2 order + 1)^3 stencil whose weights
-// are products of 1D band entries; the system is solved by Jacobi-
-// preconditioned conjugate gradients.  Every reduction has a fixed order
-// (per 256-node block, then one wave over the blocks), so the iterates do not
-// depend on timing.
-//   pcm_elements   eps_e per element, the particle volumes summed exactly in
+// so it is diagonalized by the generalized eigenvectors of the 1D pairs
+// (K_a, M_a) (fast diagonalization): the solve is exact up to rounding, six
+// 1D transforms and a diagonal scaling, with no iteration and no history.
+//   pcm_cells      the particle volumes of each element summed exactly in
 //                  fixed point (2^-50 of the element volume), so the sum does
-//                  not depend on the order of the cell slots
+//                  not depend on the order of the cell slots or of the cells
 //   smooth_rhs     b_i = sum over the elements around node i of eps_e int phi_i
-//   smooth_*       the CG steps
+//   fd_transform   the 1D transforms of the solve
 //   eps_q_field    eps_h at every quadrature point
 #include "device.h"
 
@@ -36,67 +34,35 @@ __device__ inline void node_xyz(const SmoothOp &S, long i, int &gx, int &gy, int
   gz = (int)(r / S.nn[1]);
 }
 
-// y_i = (A x)_i over the stencil of node i.
-__device__ inline double apply_row(const SmoothOp &S, const double *__restrict__ x, int gx, int gy, int gz) {
-  const int b = S.order;
-  const double *mx = S.band_m[0] + (size_t)gx * 5, *kx = S.band_k[0] + (size_t)gx * 5;
-  const double *my = S.band_m[1] + (size_t)gy * 5, *ky = S.band_k[1] + (size_t)gy * 5;
-  const double *mz = S.band_m[2] + (size_t)gz * 5, *kz = S.band_k[2] + (size_t)gz * 5;
-  double y = 0.0;
-  for (int dz = -b; dz <= b; ++dz) {
-    const int jz = gz + dz;
-    if (jz < 0 || jz >= S.nn[2]) continue;
-    for (int dy = -b; dy <= b; ++dy) {
-      const int jy = gy + dy;
-      if (jy < 0 || jy >= S.nn[1]) continue;
-      const double m_yz = my[dy + 2] * mz[dz + 2];
-      const double k_yz = ky[dy + 2] * mz[dz + 2] + my[dy + 2] * kz[dz + 2];
-      const double *row = x + ((long)jz * S.nn[1] + jy) * S.nn[0];
-      for (int dx = -b; dx <= b; ++dx) {
-        const int jx = gx + dx;
-        if (jx < 0 || jx >= S.nn[0]) continue;
-        const double w = mx[dx + 2] * m_yz + S.L2 * (kx[dx + 2] * m_yz + mx[dx + 2] * k_yz);
-        y += w * row[jx];
-      }
-    }
-  }
-  return y;
-}
-
-// Fixed-order block sum of one value per thread; thread 0 gets the total.
-__device__ inline double block_sum(double v, double *sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = kSB / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double t = sh[0];
-  __syncthreads();
-  return t;
-}
 }  // namespace
 
-__global__ __launch_bounds__(256) void pcm_elements(Dev D, double Ve, int p2, int p3, double *eps_e) {
+// Zeroes the fixed-point solid-volume accumulators of the elements.
+__global__ __launch_bounds__(256) void pcm_clear(int n_elem, unsigned long long *acc) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  const Grid &G = D.grid;
-  if (e >= G.n_elem) return;
-  const int *cnt = sel(D.cnt, p3);
-  const int *slot = sel(D.slot, p2);
-  const double scale = 0x1p50 / Ve;
-  long long acc = 0;
-  for (int c = e * G.kk; c < (e + 1) * G.kk; ++c) {
-    int m = cnt[c];
-    if (m > D.cap) m = D.cap;
-    for (int s = 0; s < m; ++s) {
-      const double r = D.rad[slot[(size_t)c * D.cap + s]];
-      acc += llrint(4.0 / 3.0 * kPi * r * r * r * scale);
-    }
-  }
-  eps_e[e] = 1.0 - (double)acc * 0x1p-50;
+  if (e < n_elem) acc[e] = 0ull;
 }
 
-__global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const double *__restrict__ eps_e,
+// One thread per cell: the volumes of its particles in fixed point (2^-50 of
+// the element volume), added to its element's accumulator.  Integer sums do
+// not depend on the order of the additions.
+__global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const Grid &G = D.grid;
+  if (c >= G.ncells) return;
+  int m = sel(D.cnt, p3)[c];
+  if (m > D.cap) m = D.cap;
+  if (m == 0) return;
+  const int *sl = sel(D.slot, p2) + (size_t)c * D.cap;
+  const double scale = 0x1p50 / Ve;
+  unsigned long long sum = 0;
+  for (int s = 0; s < m; ++s) {
+    const double r = D.rad[sl[s]];
+    sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
+  }
+  atomicAdd(acc + c / G.kk, sum);
+}
+
+__global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned long long *__restrict__ acc,
                                                   double *__restrict__ b) {
   const long i = (long)blockIdx.x * kSB + threadIdx.x;
   if (i >= S.nv) return;
@@ -124,125 +90,40 @@ __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const double *__re
       }
     }
   }
-  double acc = 0.0;
+  double sum = 0.0;
   for (int kz = 0; kz < ne[2]; ++kz)
     for (int ky = 0; ky < ne[1]; ++ky)
       for (int kx = 0; kx < ne[0]; ++kx) {
         const long e = ((long)el[2][kz] * S.n_el[1] + el[1][ky]) * S.n_el[0] + el[0][kx];
-        acc += eps_e[e] * (S.load[0][lc[0][kx]] * S.load[1][lc[1][ky]] * S.load[2][lc[2][kz]]);
+        const double eps_e = 1.0 - (double)acc[e] * 0x1p-50;  // element PCM value
+        sum += eps_e * (S.load[0][lc[0][kx]] * S.load[1][lc[1][ky]] * S.load[2][lc[2][kz]]);
       }
-  b[i] = acc;
+  b[i] = sum;
 }
 
-// r = b - A x, z = r / diag, p = z; partial sums of r.z and r.r (and b.b).
-__global__ __launch_bounds__(kSB) void smooth_init(SmoothOp S, const double *__restrict__ b,
-                                                   const double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ z, double *__restrict__ p,
-                                                   double *__restrict__ part) {
-  __shared__ double sh[kSB];
+// Fast diagonalization.  Per axis a, V_a holds the generalized eigenvectors of
+// (K_a, M_a) (V^T M V = I, V^T K V = diag(lam_a)), so
+//     A^-1 = (Vx Vy Vz) diag(1 / (1 + L^2 (lam_x + lam_y + lam_z))) (Vx Vy Vz)^T
+// and the solve is three 1D transforms with V^T, the diagonal scaling, and
+// three with V.  One pass: out[.., i, ..] = sum_j T[i][j] in[.., j, ..] along
+// axis a (T = V^T or V, n_a x n_a row-major), optionally scaled by the
+// diagonal.
+__global__ __launch_bounds__(kSB) void fd_transform(SmoothOp S, int axis, const double *__restrict__ T,
+                                                    const double *__restrict__ in, double *__restrict__ out,
+                                                    int scale) {
   const long i = (long)blockIdx.x * kSB + threadIdx.x;
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  if (i < S.nv) {
-    int gx, gy, gz;
-    node_xyz(S, i, gx, gy, gz);
-    const double ri = b[i] - apply_row(S, x, gx, gy, gz);
-    const double zi = ri / S.diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    p[i] = zi;
-    rz = ri * zi;
-    rr = ri * ri;
-    bb = b[i] * b[i];
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  bb = block_sum(bb, sh);
-  if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = rz;
-    part[3 * blockIdx.x + 1] = rr;
-    part[3 * blockIdx.x + 2] = bb;
-  }
-}
-
-// Ap and the partial sums of p.Ap.
-__global__ __launch_bounds__(kSB) void smooth_apply(SmoothOp S, const double *__restrict__ p,
-                                                    double *__restrict__ Ap, double *__restrict__ part) {
-  __shared__ double sh[kSB];
-  const long i = (long)blockIdx.x * kSB + threadIdx.x;
-  double pAp = 0.0;
-  if (i < S.nv) {
-    int gx, gy, gz;
-    node_xyz(S, i, gx, gy, gz);
-    const double y = apply_row(S, p, gx, gy, gz);
-    Ap[i] = y;
-    pAp = p[i] * y;
-  }
-  pAp = block_sum(pAp, sh);
-  if (threadIdx.x == 0) part[3 * blockIdx.x] = pAp;
-}
-
-// Totals of the block partials (three slots per block, the first k used),
-// one wave in fixed order: out[j] = sum over blocks of part[3 blk + j].
-__global__ __launch_bounds__(64) void smooth_total(int nb, int k, const double *__restrict__ part,
-                                                   double *__restrict__ out) {
-  for (int j = 0; j < k; ++j) {
-    double v = 0.0;
-    for (int i = (int)threadIdx.x; i < nb; i += 64) v += part[(size_t)3 * i + j];
-    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if (threadIdx.x == 0) out[j] = v;
-  }
-}
-
-// alpha = rz / pAp; x += alpha p; r -= alpha Ap; z = r / diag; partial r.z
-// and r.r.  sc: [0] r.z of the current direction, [1] p.Ap.
-__global__ __launch_bounds__(kSB) void smooth_update(SmoothOp S, const double *__restrict__ sc,
-                                                     double *__restrict__ x, double *__restrict__ r,
-                                                     double *__restrict__ z, const double *__restrict__ p,
-                                                     const double *__restrict__ Ap, double *__restrict__ part) {
-  __shared__ double sh[kSB];
-  const long i = (long)blockIdx.x * kSB + threadIdx.x;
-  const double pAp = sc[1];
-  const double alpha = pAp != 0.0 ? sc[0] / pAp : 0.0;
-  double rz = 0.0, rr = 0.0;
-  if (i < S.nv) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    const double zi = ri / S.diag[i];
-    r[i] = ri;
-    z[i] = zi;
-    rz = ri * zi;
-    rr = ri * ri;
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    part[3 * blockIdx.x] = rz;
-    part[3 * blockIdx.x + 1] = rr;
-  }
-}
-
-// p = z + beta p, beta = rz_new / rz_old (sc[2] / sc[0]).
-__global__ __launch_bounds__(kSB) void smooth_direction(SmoothOp S, const double *__restrict__ sc,
-                                                        const double *__restrict__ z, double *__restrict__ p) {
-  const long i = (long)blockIdx.x * kSB + threadIdx.x;
-  const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
-  if (i < S.nv) p[i] = z[i] + beta * p[i];
-}
-
-// sc[0] = sc[2]: the new r.z becomes the current one (one thread, after the
-// direction update has read both).
-__global__ void smooth_shift(double *sc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc[0] = sc[2];
-}
-
-// After the initial residual: sc[0] = r.z, sc[3] = r.r, sc[4] = b.b from the
-// totals in sc[5..7].
-__global__ void smooth_init_scalars(double *sc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    sc[0] = sc[5];
-    sc[3] = sc[6];
-    sc[4] = sc[7];
-  }
+  if (i >= S.nv) return;
+  int g[3];
+  node_xyz(S, i, g[0], g[1], g[2]);
+  const int n = S.nn[axis];
+  const long stride = axis == 0 ? 1L : (axis == 1 ? (long)S.nn[0] : (long)S.nn[0] * S.nn[1]);
+  const int gi = axis == 0 ? g[0] : (axis == 1 ? g[1] : g[2]);
+  const double *line = in + (i - gi * stride);
+  const double *row = T + (size_t)gi * n;
+  double v = 0.0;
+  for (int j = 0; j < n; ++j) v += row[j] * line[j * stride];
+  if (scale) v /= 1.0 + S.L2 * (S.lam[0][g[0]] + S.lam[1][g[1]] + S.lam[2][g[2]]);
+  out[i] = v;
 }
 
 // eps_h at every quadrature point: thread per point, element-major numbering.
@@ -276,34 +157,27 @@ __global__ __launch_bounds__(256) void eps_q_field(SmoothOp S, Cpl C, const doub
 // ---------------------------------------------------------------------------
 int smooth_blocks(long nv) { return (int)((nv + kSB - 1) / kSB); }
 
-hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *eps_e,
+hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *acc,
                           double *b, hipStream_t st) {
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
-  pcm_elements<<<(D.grid.n_elem + 255) / 256, 256, 0, st>>>(D, C.Ve, p2, p3, eps_e);
-  smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, eps_e, b);
+  unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
+  pcm_clear<<<(D.grid.n_elem + 255) / 256, 256, 0, st>>>(D.grid.n_elem, a);
+  pcm_cells<<<(D.grid.ncells + 255) / 256, 256, 0, st>>>(D, C.Ve, p2, p3, a);
+  smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, a, b);
   return hipGetLastError();
 }
 
-// sc (device, 8 doubles): [0] r.z of the current direction, [1] p.Ap, [2] the
-// new r.z, [3] r.r, [4] b.b, [5..7] scratch of the initial totals
-hipError_t launch_smooth_init(const SmoothOp &S, const double *b, const double *x, double *r, double *z,
-                              double *p, double *part, double *sc, hipStream_t st) {
+// x = A^-1 b: transforms with V^T along x, y, z (the last one scaled by the
+// inverse diagonal), then with V along z, y, x; t1, t2 are scratch vectors.
+hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
+                               hipStream_t st) {
   const int nb = smooth_blocks(S.nv);
-  smooth_init<<<nb, kSB, 0, st>>>(S, b, x, r, z, p, part);
-  smooth_total<<<1, 64, 0, st>>>(nb, 3, part, sc + 5);
-  smooth_init_scalars<<<1, 64, 0, st>>>(sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_smooth_iteration(const SmoothOp &S, double *x, double *r, double *z, double *p, double *Ap,
-                                   double *part, double *sc, hipStream_t st) {
-  const int nb = smooth_blocks(S.nv);
-  smooth_apply<<<nb, kSB, 0, st>>>(S, p, Ap, part);
-  smooth_total<<<1, 64, 0, st>>>(nb, 1, part, sc + 1);
-  smooth_update<<<nb, kSB, 0, st>>>(S, sc, x, r, z, p, Ap, part);
-  smooth_total<<<1, 64, 0, st>>>(nb, 2, part, sc + 2);  // sc[2] = new r.z, sc[3] = r.r
-  smooth_direction<<<nb, kSB, 0, st>>>(S, sc, z, p);
-  smooth_shift<<<1, 64, 0, st>>>(sc);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 0, S.Vt[0], b, t1, 0);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 1, S.Vt[1], t1, t2, 0);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 2, S.Vt[2], t2, t1, 1);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 2, S.V[2], t1, t2, 0);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 1, S.V[1], t2, t1, 0);
+  fd_transform<<<nb, kSB, 0, st>>>(S, 0, S.V[0], t1, x, 0);
   return hipGetLastError();
 }
 
