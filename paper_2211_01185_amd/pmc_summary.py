@@ -52,8 +52,8 @@ def _scale(d, counter):
 def _region(d, counter, lanes, warmup, steps):
     """Counter values of the force-kernel step launches of the last bed the
     run created (the replayed region), after its warm-up."""
-    step_re = re.compile(rf"force_kick<float, true, (true|false), {lanes}>")
-    prime_re = re.compile(rf"force_kick<float, false, false, {lanes}>")
+    step_re = re.compile(rf"force_kick<float, true, (true|false), {lanes}, false>")
+    prime_re = re.compile(rf"force_kick<float, false, false, {lanes}, false>")
     rows = [r for r in _rows(d) if r["Counter_Name"] == counter]
     last_prime = max(i for i, r in enumerate(rows) if prime_re.search(r["Kernel_Name"]))
     launches = [r for r in rows[last_prime + 1:] if step_re.search(r["Kernel_Name"])]

@@ -8,9 +8,10 @@ kernel's launch durations over the main measurement's two regions: the timed
 steps of the first bed and the same steps replayed on a second bed (where the
 benchmark reads its per-launch HIP events).  A bed of the main measurement is
 recognised by its creation-time evaluation (force_kick<float, false, false,
-L>) at the main bed's grid size followed by at least warm-up + timed step
-launches of the single-bed kernel; the last two such beds are the
-measurement's (earlier ones are autotuner trials).
+L, false>: no rolling friction) at the main bed's grid size followed by step
+launches of the single-bed kernel: the measurement's two beds run exactly
+warm-up + timed steps (the autotuner's trials run two more coupling periods,
+the settling run thousands of steps, the smoothing run fewer).
 """
 from __future__ import annotations
 
@@ -58,8 +59,8 @@ def main(argv=None):
     rows = _one(args.trace, "kernel_trace.csv")
     key = "Kernel_Name" if "Kernel_Name" in rows[0] else "Name"
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    prime_re = re.compile(rf"cfddem::force_kick<float, false, false, {lanes}>")
-    step_re = re.compile(rf"cfddem::force_kick<float, true, (true|false), {lanes}>")
+    prime_re = re.compile(rf"cfddem::force_kick<float, false, false, {lanes}, false>")
+    step_re = re.compile(rf"cfddem::force_kick<float, true, (true|false), {lanes}, false>")
     beds, cur = [], None
     for r in rows:
         if int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0) != grid:
@@ -69,14 +70,14 @@ def main(argv=None):
             beds.append(cur)
         elif cur is not None and step_re.search(r[key]):
             cur.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    full = [b for b in beds if len(b) >= warmup + steps]
-    if len(full) < 2:
-        raise SystemExit(f"found {len(full)} beds with {warmup + steps} step launches at grid {grid}")
+    full = [b for b in beds if len(b) == warmup + steps]
+    if len(full) != 2:
+        raise SystemExit(f"found {len(full)} beds with exactly {warmup + steps} step launches at grid {grid}")
     print()
     print(f"Contact-force kernel `force_kick<float, true, *, {lanes}>` over the main measurement "
           f"({steps} launches after {warmup} warm-up steps; grid {grid}):")
     print()
-    for name, b in (("timed region (first bed)", full[-2]), ("replayed region (second bed)", full[-1])):
+    for name, b in (("timed region (first bed)", full[0]), ("replayed region (second bed)", full[1])):
         x = np.array(b[warmup:warmup + steps])
         med = float(np.median(x))
         print(f"- {name}: mean {x.mean():.2f} us, median {med:.2f} us, p90 {np.percentile(x, 90):.2f} us, "
