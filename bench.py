@@ -24,14 +24,24 @@ sample of the same workload; and the two other parts of the metric:
            aggregate particle-steps/s over the jobs after the warm-up ones;
   smoothing: the benchmark bed with the smoothed void fraction (L^2 = 5 d^2):
            200 coupled steps, and the first coupling step timed alone;
+  spouted: the 500,000-sphere polydisperse spouted bed (Q2 30x30x120, Gaussian
+           jet), tuned, 500 coupled steps after 20 warm-up ones, with the
+           contact-force kernel's launches timed on a replay;
   settling: the DEM-only preparation of a bed, 100,000 spheres (d = 1 mm)
            inserted at random above the floor of the same column and stepped
            without coupling until at rest (kinetic energy below 1e-4 of
            sum m g d, checked every 500 steps); steps to rest and
            particle-steps/s.
 
+Beside particle-steps/s the main line gives contacts/s (contact pairs and
+wall contacts resolved per second) and quadrature-points/s (points of the
+coupling steps per second).  The CPU leg also compares both GPU paths (FP32
+forces, all FP64) with the oracle on the main bed: the first coupling and DEM
+step, and the end of the oracle's sample.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--no-batched] [--no-served] [--no-settling] [--served-jobs J]
+                       [--no-batched] [--no-served] [--no-smoothing] [--no-spouted]
+                       [--no-settling] [--served-jobs J]
 """
 import argparse
 import hashlib
@@ -72,6 +82,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true", help="skip the served stream")
     ap.add_argument("--no-settling", action="store_true", help="skip the DEM-only settling run")
     ap.add_argument("--no-smoothing", action="store_true", help="skip the smoothed void-fraction run")
+    ap.add_argument("--no-spouted", action="store_true", help="skip the spouted-bed run")
     ap.add_argument("--batched-beds", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--served-jobs", type=int, default=650)
@@ -110,9 +121,38 @@ def contact_counts(bed):
     return len(i) - walls, walls
 
 
+def make_coupled_bed(wl, U, P, bed_kw, dev, precision="fp32"):
+    from paper_2211_01185_amd import cfddem
+
+    bed = cfddem.bed_from_workload(wl, precision=precision, device=dev, **bed_kw)
+    out = bed.couple(U, P)  # allocates the output tensors once; the run re-couples at step 0
+    return bed, out
+
+
+def run_coupled(bed, out, U, P, steps, start):
+    """Steps start .. start+steps-1, with a coupling step before every step
+    whose index is a multiple of COUPLING_EVERY."""
+    s = start
+    end = start + steps
+    while s < end:
+        if s % COUPLING_EVERY == 0:
+            bed.couple(U, P, out=out)
+        chunk = min(COUPLING_EVERY - s % COUPLING_EVERY, end - s)
+        bed.step(chunk)
+        s += chunk
+    return s
+
+
+def couplings_in(start, steps):
+    return sum(1 for s in range(start, start + steps) if s % COUPLING_EVERY == 0)
+
+
 def cpu_baseline(wl, dem_steps):
     """The FP64 oracle, as it stands, on the same bed: dem_steps DEM steps with
-    a coupling step every COUPLING_EVERY steps."""
+    a coupling step every COUPLING_EVERY steps.  Also returns what the GPU
+    paths are compared with: the first coupling step's outputs, the state
+    after the first step and the state at the end (copied outside the timed
+    steps)."""
     from oracle import oracle as O
 
     d, f = wl.dem, wl.fluid
@@ -120,15 +160,126 @@ def cpu_baseline(wl, dem_steps):
                       d["E_w"], d["nu_w"], d["e_w"], d["mu_w"])
     fl = O.make_fluid(f["order"], f["n_el"], f["rho_f"], f["mu_f"], f["model"], f["eps_min"])
     bed = O.OracleBed(p, wl.x, wl.v, wl.w, wl.radius, wl.density)
-    t0 = time.perf_counter()
+    ref = {}
+    dt = 0.0
     for s in range(dem_steps):
+        t0 = time.perf_counter()
         if s % COUPLING_EVERY == 0:
-            bed.couple(fl, wl.U, wl.P)
+            r = bed.couple(fl, wl.U, wl.P)
         bed.step(1)
-    dt = time.perf_counter() - t0
-    return {"value": wl.n * dem_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{dem_steps} DEM steps + {dem_steps // COUPLING_EVERY} coupling steps of the same "
-                      f"{wl.n}-sphere bed, single-threaded FP64 C oracle, {dt:.1f} s"}
+        dt += time.perf_counter() - t0
+        if s == 0:
+            ref["couple"] = r
+            ref["step1"] = bed.state()
+    ref["end"] = bed.state()
+    out = {"value": wl.n * dem_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{dem_steps} DEM steps + {dem_steps // COUPLING_EVERY} coupling steps of the same "
+                     f"{wl.n}-sphere bed, single-threaded FP64 C oracle, {dt:.1f} s"}
+    return out, ref
+
+
+def rel_max_err(got, want):
+    """max|got - want| / max|want| (the parity tests' measure)."""
+    import numpy as np
+
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    scale = float(np.max(np.abs(want)))
+    diff = float(np.max(np.abs(got - want)))
+    return diff / scale if scale > 0.0 else diff
+
+
+def errors_vs_oracle(wl, U, P, bed_kw, dev, ref, dem_steps):
+    """The GPU paths (FP32 forces / FP64 state, and all FP64) against the FP64
+    oracle on the main bed: the first coupling step and the first DEM step
+    (where the paths must agree to 1e-5 and 1e-10 relative), and the state
+    after the oracle's whole sample (a trajectory: reported, not bounded)."""
+    import numpy as np
+
+    res = {}
+    for precision in ("fp32", "fp64"):
+        bed, out = make_coupled_bed(wl, U, P, bed_kw, dev, precision)
+        c = {k: out[k].cpu().numpy() for k in ("eps_q", "beta_q", "fpf_q")}
+        bed.step(1)
+        st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
+        F, T = (t.cpu().numpy() for t in bed.read_forces())
+        o1 = ref["step1"]
+        e = {"eps_q": rel_max_err(c["eps_q"], ref["couple"]["eps_q"]),
+             "beta_q": rel_max_err(c["beta_q"], ref["couple"]["beta_q"]),
+             "fpf_q": rel_max_err(c["fpf_q"], ref["couple"]["fpf_q"]),
+             "f_fp": rel_max_err(st["ffp"], o1["ffp"]),
+             "contact_force": rel_max_err(F, o1["Fc"]), "contact_torque": rel_max_err(T, o1["Tc"]),
+             "x": rel_max_err(st["x"], o1["x"]), "v": rel_max_err(st["v"], o1["v"]),
+             "w": rel_max_err(st["w"], o1["w"])}
+        run_coupled(bed, out, U, P, dem_steps - 1, 1)
+        st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
+        err, _ = bed.poll()
+        bed.close()
+        d_min = 2.0 * float(wl.radius.min())
+        e[f"x_after_{dem_steps}_steps_over_d"] = float(np.max(np.abs(st["x"] - ref["end"]["x"]))) / d_min
+        e[f"v_after_{dem_steps}_steps"] = rel_max_err(st["v"], ref["end"]["v"])
+        e["errors"] = int(err)
+        res[precision] = e
+    return {"measure": "max|gpu - oracle| / max|oracle| per array after the first coupling step and the first "
+                       "DEM step; the end state of the oracle's sample as a trajectory deviation",
+            "bound_single_step": {"fp32": 1e-5, "fp64": 1e-10}, **res}
+
+
+def spouted_run(dev, steps=500, warmup=20):
+    """The spouted bed (500,000 polydisperse spheres, Q2 30x30x120, Gaussian
+    jet), FP32 forces: tuned as the main bed, then `warmup` + `steps` coupled
+    steps timed as the main measurement, and the same steps replayed on a
+    fresh bed with the contact-force kernel's launches timed."""
+    import torch
+
+    from paper_2211_01185_amd import autotune, synth
+
+    t0 = time.perf_counter()
+    wl = synth.spouted()
+    gen_s = time.perf_counter() - t0
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    tuned, tune_report = autotune.tune([wl], "fp32", steps=warmup + steps, device=dev, use_cache=False)
+    bed_kw = autotune.bed_kwargs(wl, tuned)
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    s = run_coupled(bed, out, U, P, warmup, 0)
+    torch.cuda.synchronize()
+    pairs0, walls0 = contact_counts(bed)
+    t0 = time.perf_counter()
+    run_coupled(bed, out, U, P, steps, s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    err, _ = bed.poll()
+    pairs1, walls1 = contact_counts(bed)
+    nq_total = bed.n_elem * bed.nq
+    bed.close()
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    s = run_coupled(bed, out, U, P, warmup, 0)
+    bed.kernel_timing(True)
+    run_coupled(bed, out, U, P, steps, s)
+    torch.cuda.synchronize()
+    bed.kernel_timing(False)
+    launches, force_ms = bed.kernel_timing_read()
+    err2, _ = bed.poll()
+    bed.close()
+    contacts = 0.5 * (pairs0 + walls0 + pairs1 + walls1)
+    force_avg_s = force_ms / 1e3 / max(launches, 1)
+    alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
+    achieved = alg_bytes / force_avg_s / 1e9
+    return {"workload": "spouted bed: 500,000 spheres, d lognormal (median 2 mm, sigma 0.2, clipped 1-4 mm), "
+                        "0.15 x 0.15 x 0.6 m, Q2 30x30x120 mesh (2,916,000 qpts), Gaussian inlet jet 20 m/s, "
+                        f"coupling every {COUPLING_EVERY} steps",
+            "particles": wl.n, "steps": steps, "warmup": warmup,
+            "value": wl.n * steps / wall, "unit": "particle-steps/s", "ms_per_step": wall * 1e3 / steps,
+            "contacts_per_s": contacts * steps / wall,
+            "quadrature_points_per_s": nq_total * couplings_in(warmup, steps) / wall,
+            "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
+            "tuned": dict(bed_kw, trials=tune_report["trials"],
+                          default_ms_per_step=tune_report["default_ms_per_step"]),
+            "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
+                             "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
+                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
+            "generation_s": gen_s, "errors": int(err or err2), "dtype": "f32 forces / f64 state"}
 
 
 def batched_ensemble(n_beds, steps, dev):
@@ -306,20 +457,10 @@ def main():
     progress(f"tuned {bed_kw} in {tune_report['trials']} trials")
 
     def make_bed():
-        bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, **bed_kw)
-        out = bed.couple(U, P)  # allocates the output tensors once; the run re-couples at step 0
-        return bed, out
+        return make_coupled_bed(wl, U, P, bed_kw, dev)
 
     def run(bed, out, steps, start):
-        s = start
-        end = start + steps
-        while s < end:
-            if s % COUPLING_EVERY == 0:
-                bed.couple(U, P, out=out)
-            chunk = min(COUPLING_EVERY - s % COUPLING_EVERY, end - s)
-            bed.step(chunk)
-            s += chunk
-        return s
+        return run_coupled(bed, out, U, P, steps, start)
 
     # throughput: W warmup steps, then exactly K timed steps without per-kernel
     # instrumentation
@@ -371,6 +512,7 @@ def main():
     alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
     achieved = alg_bytes / force_avg_s / 1e9
     traffic = traffic_entry(bed_kw)
+    qpts = wl.fluid["n_el"][0] * wl.fluid["n_el"][1] * wl.fluid["n_el"][2] * (wl.fluid["order"] + 1) ** 3
 
     result = {
         "metric": METRIC,
@@ -396,6 +538,12 @@ def main():
             "tuned": dict(bed_kw, trials=tune_report["trials"],
                           default_ms_per_step=tune_report["default_ms_per_step"]),
             "parallelism": "1 GPU",
+        },
+        "rates": {
+            "particle_steps_per_s": value,
+            "contacts_per_s": contacts * args.steps / elapsed,
+            "quadrature_points_per_s": qpts * couplings_in(args.warmup, args.steps) / elapsed,
+            "contacts": contacts, "quadrature_points": qpts,
         },
         "roofline": {
             "bound": "hbm",
@@ -426,9 +574,15 @@ def main():
         progress("settling: starting")
         result["settling"] = settling_run(dev)
         progress(f"settling: {result['settling']['steps_to_rest']} steps to rest")
+    if not args.no_spouted:
+        progress("spouted bed: starting")
+        result["spouted"] = spouted_run(dev)
+        progress(f"spouted: {result['spouted']['ms_per_step']:.4f} ms per step")
     if not args.no_cpu:
         progress("oracle sample: starting")
-        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        result["cpu_baseline"], ref = cpu_baseline(wl, args.cpu_steps)
+        progress("GPU paths against the oracle sample")
+        result["error_vs_fp64_oracle"] = errors_vs_oracle(wl, U, P, bed_kw, dev, ref, args.cpu_steps)
     print(json.dumps(result), flush=True)
 
 

@@ -7,13 +7,16 @@
 //
 // couple_classify: one wavefront per kClassElems consecutive elements reads
 // their cell counts (coalesced), writes the outputs of the empty ones as
-// contiguous runs and appends the occupied ones to a list.
+// contiguous runs and appends the occupied ones to a list (one atomic per
+// block).
 //
 // couple_occupied: one block of kCplThreads threads per listed element:
 //   1. gathers the element's particles from its nested DEM cells (the grid
-//      built at the current positions); each thread orders the particles of
-//      its own cells by index, so that every sum below has an order fixed by
-//      the set of particles alone,
+//      built at the current positions), cell by cell, each cell's particles
+//      ordered by index, so that every sum below has an order fixed by the
+//      set of particles alone; a cell holding more particles than were
+//      loaded with its count (large elements of few cells) is copied by the
+//      whole block and ordered by a rank sort,
 //   2. particle-centroid void fraction eps_e = 1 - sum V_p / V_e
 //      (Eq. "void_fraction"),
 //   3. per particle (one per thread): Q_n interpolation of the fluid
@@ -34,7 +37,7 @@ constexpr int kWave = 64;
 constexpr int kCplThreads = 128;    // threads per occupied element
 constexpr int kCplWaves = kCplThreads / kWave;
 constexpr int kClassElems = 8;      // elements per wavefront of the classify pass
-constexpr int kClassBlock = 256;
+constexpr int kClassBlock = 1024;  // 16 wavefronts: one list append per 128 elements
 constexpr int kMaxCoupleBlocks = 4096;  // grid of the occupied-element pass
 constexpr int kSlotPre = 4;         // slot entries per cell loaded with the counts
 
@@ -433,14 +436,31 @@ __device__ inline void insert_rest(int *ids, int w, const int *sl, int from, int
   }
 }
 
+// Cell of entry j of the gathered list: the last cell whose run starts at or
+// before j (runs of empty cells have no entries, so that cell's run holds j).
+__device__ inline int cell_of_entry(const int *coff, int kk, int j) {
+  int lo = 0, hi = kk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (coff[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 struct CplShared {
   int ids[kElemMaxParticles];
+  int raw[kElemMaxParticles];  // slot entries in slot order (cooperative gather)
+  int coff[kCplThreads];       // offset of each cell's run in ids (cooperative gather)
   double sU[3][27];
   double sP[8];
   double sE[27];     // smoothed void fraction at the element's velocity nodes
   double sLq[3][3];  // 1D velocity basis at the Gauss points (kernel constants)
   double red[kCplWaves][11];
   int scan[kCplWaves];
+  int longc[kCplWaves];
 };
 
 // One occupied element, computed by the whole block.  The latency is a short
@@ -503,7 +523,12 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   }
   // block exclusive scan of the per-thread counts
   const int incl = wave_incl_scan(mine, lane);
-  if (lane == kWave - 1) sh.scan[wave] = incl;
+  // does any cell hold more entries than were prefetched with the counts?
+  const bool long_cell = __ballot(m0 > kSlotPre) != 0ull;
+  if (lane == kWave - 1) {
+    sh.scan[wave] = incl;
+    sh.longc[wave] = long_cell ? 1 : 0;
+  }
   if (tid < nnode) {
     sh.sU[0][tid] = un[0];
     sh.sU[1][tid] = un[1];
@@ -511,16 +536,43 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   }
   if (pc >= 0 && pc < 8) sh.sP[pc] = pk;
   __syncthreads();
-  int off = incl - mine, total = 0;
+  int off = incl - mine, total = 0, any_long = 0;
 #pragma unroll
   for (int w = 0; w < kCplWaves; ++w) {
     if (w < wave) off += sh.scan[w];
     total += sh.scan[w];
+    any_long |= sh.longc[w];
   }
   const bool over = total > kElemMaxParticles;
   if (over && tid == 0) atomicOr(D.err, kErrCapacity);
   if (over) total = 0;
-  if (total > 0) {
+  if (total > 0 && any_long && G.kk <= kCplThreads) {
+    // one cell per thread: the slot entries are copied by the whole block
+    // (entries past the prefetched ones in one round trip, whatever the
+    // number of particles per cell), then each cell's run is ordered by
+    // index by a rank sort (particle indices are distinct)
+    if (tid < G.kk) {
+      sh.coff[tid] = off;
+#pragma unroll
+      for (int s = 0; s < kSlotPre; ++s)
+        if (s < m0) sh.raw[off + s] = v0[s];
+    }
+    __syncthreads();
+    for (int j = tid; j < total; j += kCplThreads) {
+      const int c = cell_of_entry(sh.coff, G.kk, j);
+      const int s = j - sh.coff[c];
+      if (s >= kSlotPre) sh.raw[j] = slot[(size_t)(base + c) * D.cap + s];
+    }
+    __syncthreads();
+    for (int j = tid; j < total; j += kCplThreads) {
+      const int c = cell_of_entry(sh.coff, G.kk, j);
+      const int lo = sh.coff[c], hi = c + 1 < G.kk ? sh.coff[c + 1] : total;
+      const int v = sh.raw[j];
+      int r = 0;
+      for (int k = lo; k < hi; ++k) r += sh.raw[k] < v ? 1 : 0;
+      sh.ids[lo + r] = v;
+    }
+  } else if (total > 0) {
     // each thread writes its cells' particles ordered by index, so the order
     // of ids depends on the set of particles alone
     int w = off;
@@ -649,48 +701,63 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
 // Classification of kClassElems consecutive elements starting at e0 by one
 // wavefront: empty ones get their outputs, occupied ones are appended to
-// list (entries tag | element) through the counter at cnt_word.
+// list (entries tag | element) through the counter at cnt_word, with one
+// atomic per block (a device-wide counter is a single address that every
+// XCD contends for: one atomic per wavefront serializes a large mesh).
+// Called by every thread of the block; s_cnt is LDS of kClassBlock / kWave + 1
+// ints.  The order of the list does not matter: each listed element is
+// computed on its own.
 __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C, int e0, int p3,
                                                      int *cnt_word, unsigned *list, unsigned tag,
                                                      double *__restrict__ eps_q,
                                                      double *__restrict__ beta_q,
                                                      double *__restrict__ fpf_q,
-                                                     double *__restrict__ esums) {
+                                                     double *__restrict__ esums, int *s_cnt) {
+  constexpr int kWaves = kClassBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
   const Grid &G = D.grid;
-  if (e0 >= G.n_elem) return;  // whole wavefront
-  const int ne = G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems;
-  const int *cnt = sel(D.cnt, p3);
+  const int ne = e0 >= G.n_elem ? 0 : (G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems);
   unsigned occupied = 0;
-  for (int c = lane; c - lane < G.kk; c += kWave) {
-    int m[kClassElems];
+  if (ne > 0) {  // whole wavefront
+    const int *cnt = sel(D.cnt, p3);
+    for (int c = lane; c - lane < G.kk; c += kWave) {
+      int m[kClassElems];
 #pragma unroll
-    for (int j = 0; j < kClassElems; ++j)
-      m[j] = (j < ne && c < G.kk) ? cnt[(size_t)(e0 + j) * G.kk + c] : 0;
+      for (int j = 0; j < kClassElems; ++j)
+        m[j] = (j < ne && c < G.kk) ? cnt[(size_t)(e0 + j) * G.kk + c] : 0;
 #pragma unroll
-    for (int j = 0; j < kClassElems; ++j)
-      if (__ballot(m[j] != 0)) occupied |= 1u << j;
+      for (int j = 0; j < kClassElems; ++j)
+        if (__ballot(m[j] != 0)) occupied |= 1u << j;
+    }
+    // empty elements: eps = 1, no drag, nothing handed to the fluid; their
+    // quadrature points form contiguous runs
+    const int nq = C.nq;
+    const long nqtot = (long)G.n_elem * nq;
+    const long q0 = (long)e0 * nq;
+    for (int t = lane; t < ne * nq; t += kWave) {
+      if ((occupied >> (t / nq)) & 1u) continue;
+      const long qg = q0 + t;
+      eps_q[qg] = 1.0;
+      beta_q[qg] = 0.0;
+      fpf_q[qg] = 0.0;
+      fpf_q[nqtot + qg] = 0.0;
+      fpf_q[2 * nqtot + qg] = 0.0;
+    }
+    if (esums && lane < ne && !((occupied >> lane) & 1u))
+      for (int k = 0; k < 12; ++k) esums[(long)k * G.n_elem + e0 + lane] = 0.0;
   }
-  // empty elements: eps = 1, no drag, nothing handed to the fluid; their
-  // quadrature points form contiguous runs
-  const int nq = C.nq;
-  const long nqtot = (long)G.n_elem * nq;
-  const long q0 = (long)e0 * nq;
-  for (int t = lane; t < ne * nq; t += kWave) {
-    if ((occupied >> (t / nq)) & 1u) continue;
-    const long qg = q0 + t;
-    eps_q[qg] = 1.0;
-    beta_q[qg] = 0.0;
-    fpf_q[qg] = 0.0;
-    fpf_q[nqtot + qg] = 0.0;
-    fpf_q[2 * nqtot + qg] = 0.0;
+  if (lane == 0) s_cnt[wave] = __popc(occupied);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < kWaves; ++w) tot += s_cnt[w];
+    s_cnt[kWaves] = tot > 0 ? atomicAdd(cnt_word, tot) : 0;
   }
-  if (esums && lane < ne && !((occupied >> lane) & 1u))
-    for (int k = 0; k < 12; ++k) esums[(long)k * G.n_elem + e0 + lane] = 0.0;
+  __syncthreads();
   if (occupied) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(cnt_word, __popc(occupied));
-    base = __shfl(base, 0, kWave);
+    int base = s_cnt[kWaves];
+    for (int w = 0; w < wave; ++w) base += s_cnt[w];
     if (lane < ne && ((occupied >> lane) & 1u))
       list[base + __popc(occupied & ((1u << lane) - 1u))] = tag | (unsigned)(e0 + lane);
   }
@@ -704,10 +771,11 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
                                                                double *__restrict__ beta_q,
                                                                double *__restrict__ fpf_q,
                                                                double *__restrict__ esums) {
+  __shared__ int s_cnt[kClassBlock / kWave + 1];
   const int gw = (blockIdx.x * kClassBlock + threadIdx.x) / kWave;
   if (gw == 0 && threadIdx.x == 0) D.err[kOccWord + (parity ^ 1)] = 0;
   couple_classify_body(D, C, gw * kClassElems, p3, D.err + kOccWord + parity, (unsigned *)D.occ, 0u,
-                       eps_q, beta_q, fpf_q, esums);
+                       eps_q, beta_q, fpf_q, esums, s_cnt);
 }
 
 // One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
@@ -744,6 +812,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const unsigned *__restrict__ map, int *cnt_words, unsigned *list,
     ModeLists ml) {
+  __shared__ int s_cnt[kClassBlock / kWave + 1];
   const unsigned mb = map[blockIdx.x];
   const int b = (int)(mb >> kBedShift), blk = (int)(mb & kBlockMask);
   const Dev &D = tab[b];
@@ -754,7 +823,7 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
   // occupied elements go to the list of the bed's element-kernel variant
   const int m = cpl_mode_of(C.drag, C.shear || C.smooth);
   couple_classify_body(D, C, gw * kClassElems, p3, cnt_words + m, list + ml.off[m], (unsigned)b << kBedShift,
-                       io.eps_q, io.beta_q, io.fpf_q, io.esums);
+                       io.eps_q, io.beta_q, io.fpf_q, io.esums, s_cnt);
 }
 
 template <typename R, int ORD, int MODE>

@@ -122,7 +122,9 @@ def rsa_polydisperse(rng, radius, lo, hi):
     rmax = float(radius.max())
     pts = np.zeros((n, 3))
     placed = 0
-    tree = None
+    # accepted centres in two trees: an old one, rebuilt only when the recent
+    # one has grown to a fifth of it, and a recent one rebuilt every batch
+    old_n, old_tree, trees = 0, None, []
     while placed < n:
         left = n - placed
         batch = min(left, 50000)
@@ -136,10 +138,10 @@ def rsa_polydisperse(rng, radius, lo, hi):
         cand = lo + rb[:, None] + (hi - lo - 2 * rb[:, None]) * rng.random((sid.shape[0], 3))
         ok = np.ones(sid.shape[0], dtype=bool)
         ctree = cKDTree(cand)
-        if tree is not None:
+        for first_id, tree in trees:
             m = tree.sparse_distance_matrix(ctree, 2 * rmax, output_type="ndarray")
             if m.shape[0]:
-                clash = m["v"] <= radius[m["i"]] + rb[m["j"]]
+                clash = m["v"] <= radius[first_id + m["i"]] + rb[m["j"]]
                 ok[m["j"][clash]] = False
         # inside the batch, in order: a candidate is dropped if it overlaps an
         # earlier candidate of the batch that is still accepted
@@ -163,7 +165,12 @@ def rsa_polydisperse(rng, radius, lo, hi):
         radius[placed:placed + batch] = np.concatenate([r_here[acc], r_here[rej]])
         pts[placed:placed + acc.shape[0]] = cand[first[acc]]
         placed += acc.shape[0]
-        tree = cKDTree(pts[:placed])
+        if placed - old_n > max(old_n // 5, 50000):
+            old_n = placed
+            old_tree = cKDTree(pts[:old_n])
+        trees = [(0, old_tree)] if old_n else []
+        if placed > old_n:
+            trees.append((old_n, cKDTree(pts[old_n:placed])))
     return pts.T.copy()
 
 

@@ -295,6 +295,44 @@ def _noisy_field(wl, order, seed=11, amplitude=0.05):
     return wl
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coupling_step_many_particles_per_cell(order, precision):
+    """Polydisperse spheres (d 1-4 mm, the spouted-bed recipe) on 5 mm
+    elements: one DEM cell per element, holding up to tens of particles, so
+    the element's gather copies the slot entries past the ones loaded with
+    the counts with the whole block and orders them there."""
+    wl = synth.spouted(n=3500, box=(0.03, 0.03, 0.1), fill_height=0.1, n_el=(6, 6, 20))
+    if order == 1:
+        wl = _noisy_field(wl, 1)
+    gb = gpu_bed(wl, precision)
+    _, cell, k = gb.read_cells()
+    assert k == [1, 1, 1]
+    assert np.bincount(cell.cpu().numpy()).max() > 6  # well past the prefetched entries
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    out = gb.couple(U, P, elem_sums=True)
+    ref = ob.couple(fl, wl.U, wl.P)
+    tol = TOL[precision]
+    assert np.array_equal(out["elem_sums"][0].cpu().numpy(), ref["elem_sums"][0])
+    assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-12)
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    assert_close("elem_sums", out["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+    assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
+    # the element sums do not depend on the order the slots were filled in:
+    # a re-sort permutes the slots, the outputs stay bit-identical
+    gb2 = gpu_bed(wl, precision, resort_every=1)
+    gb2.step(1)
+    gb3 = gpu_bed(wl, precision, resort_every=0)
+    gb3.step(1)
+    o2 = gb2.couple(U, P, elem_sums=True)
+    o3 = gb3.couple(U, P, elem_sums=True)
+    for key in ("eps_q", "beta_q", "fpf_q", "elem_sums"):
+        assert torch.equal(o2[key], o3[key]), key
+    assert gb.poll()[0] == 0 and gb2.poll()[0] == 0 and gb3.poll()[0] == 0
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_rolling_friction(lanes, precision):
