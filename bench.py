@@ -76,7 +76,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--bed-config", default=None,
-                    help="JSON of the main bed's skin, resort_every and lanes, used instead of tuning "
+                    help="JSON of the main bed's skin, resort_every, lanes and elem_threads, used instead "
+                         "of tuning "
                          "(to repeat a tuned run under a counter profiler)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-served", action="store_true", help="skip the served stream")
@@ -448,7 +449,9 @@ def main():
     # rate of list rebuilds grows as the bed fluidizes); results do not depend
     # on them
     if args.bed_config:
-        bed_kw = {k: json.loads(args.bed_config)[k] for k in ("skin", "resort_every", "lanes")}
+        given = json.loads(args.bed_config)
+        bed_kw = {k: given[k] for k in ("skin", "resort_every", "lanes")}
+        bed_kw["elem_threads"] = int(given.get("elem_threads", 128))
         tune_report = {"trials": 0, "default_ms_per_step": None}
     else:
         tuned, tune_report = autotune.tune([wl], "fp32", steps=args.warmup + args.steps, device=dev,

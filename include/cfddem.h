@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CFDDEM_ABI_VERSION 3
+#define CFDDEM_ABI_VERSION 4
 
 typedef struct dem_ctx dem_ctx;
 typedef int32_t dem_status;
@@ -159,6 +159,13 @@ typedef struct {
                       0: element PCM values (eps_q constant per element) */
   double smooth_L2; /* smoothing length squared (m^2), >= 0 (0: the plain
                        projection) */
+  int32_t elem_threads; /* threads computing one occupied element in the
+                       coupling step: 64 (one wavefront: twice the elements
+                       in flight, for elements of few particles) or 128 (up
+                       to 128 particles in one pass); 0 = 128.  A tuning
+                       choice: outputs depend on it only in the rounding of
+                       the element sums.  Every bed of a batch must have the
+                       same value */
 } cfd_params;
 
 /* Bytes of device workspace dem_create needs for these parameters.  Pure host

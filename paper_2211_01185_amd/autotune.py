@@ -1,6 +1,6 @@
 """Autotuner of the launch and grid choices that do not change the results.
 
-Knobs (each a dem_params field):
+Knobs (dem_params and cfd_params fields):
   * skin          neighbour-list skin, as a multiple of the smallest diameter.
                   It also sets the DEM cell size (cells are at least
                   d_max + skin wide, nested in the mesh elements), so it
@@ -8,11 +8,14 @@ Knobs (each a dem_params field):
                   needed and how long the lists are;
   * resort_every  DEM steps between re-sorts of the particle arrays by cell;
   * lanes         lanes of a wavefront sharing one particle in the
-                  contact-force kernel (the tile of list entries per lane).
+                  contact-force kernel (the tile of list entries per lane);
+  * elem_threads  threads per occupied element in the coupling step: 64 (more
+                  elements in flight, for elements of few particles) or 128.
 
 None of them changes a contact set, and forces only at the rounding level
-(the order of a particle's contact sums depends on its list layout), which the
-invariance tests check.  The tuner times coupled runs (a coupling step every
+(the order of a particle's contact sums depends on its list layout, that of
+an element's sums on the threads computing it), which the invariance tests
+check.  The tuner times coupled runs (a coupling step every
 10 DEM steps, as the workloads run) from the beds' initial state on the device
 for candidate values, one knob at a time starting from the defaults
 (coordinate descent), and keeps the fastest.  Runs should be as long as the
@@ -32,8 +35,9 @@ CANDIDATES = {
     "skin_factor": (0.05, 0.1, 0.2, 0.35),
     "resort_every": (25, 50, 100, 200),
     "lanes": (1, 2, 4),
+    "elem_threads": (64, 128),
 }
-DEFAULT = {"skin_factor": 0.1, "resort_every": 100, "lanes": 2}
+DEFAULT = {"skin_factor": 0.1, "resort_every": 100, "lanes": 2, "elem_threads": 128}
 COUPLING_EVERY = 10
 
 
@@ -66,7 +70,8 @@ def _store_cache(key: str, value: dict):
 def bed_kwargs(wl, cfg: dict) -> dict:
     """Keyword arguments of cfddem.Bed for a tuned configuration."""
     d_min = 2.0 * float(wl.radius.min())
-    return dict(skin=cfg["skin_factor"] * d_min, resort_every=int(cfg["resort_every"]), lanes=int(cfg["lanes"]))
+    return dict(skin=cfg["skin_factor"] * d_min, resort_every=int(cfg["resort_every"]), lanes=int(cfg["lanes"]),
+                elem_threads=int(cfg.get("elem_threads", DEFAULT["elem_threads"])))
 
 
 def signature(wls, precision) -> str:

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libcfddem.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 DEM_OK = 0
 DEM_E_ARG = -1
@@ -58,6 +58,7 @@ class CfdParams(C.Structure):
         ("order", C.c_int32), ("n_el", C.c_int32 * 3), ("rho_f", C.c_double), ("mu_f", C.c_double),
         ("drag", C.c_int32), ("model", C.c_int32), ("eps_min", C.c_double),
         ("shear", C.c_int32), ("smooth", C.c_int32), ("smooth_L2", C.c_double),
+        ("elem_threads", C.c_int32),
     ]
 
 
@@ -135,7 +136,7 @@ def _check(status: int, where: str):
 
 
 def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, precision="fp64",
-                max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0):
+                max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0, elem_threads=0):
     """Fill the two C parameter structs from plain dicts (see synth.Workload)."""
     dp = DemParams()
     dp.abi_version = ABI_VERSION
@@ -170,6 +171,7 @@ def make_params(dem: dict, fluid: dict, n: int, d_max: float, d_min: float, prec
     L2 = fluid.get("smooth_L2")
     cp.smooth = 0 if L2 is None else 1
     cp.smooth_L2 = 0.0 if L2 is None else float(L2)
+    cp.elem_threads = int(elem_threads)
     return dp, cp
 
 
@@ -185,8 +187,8 @@ class Bed:
     """One bed on the GPU: a dem_ctx plus the torch-owned workspace."""
 
     def __init__(self, dem: dict, fluid: dict, x, v, w, radius, density, precision="fp64",
-                 max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0, device="cuda",
-                 stream=None):
+                 max_neighbors=0, cell_capacity=0, resort_every=0, skin=0.0, lanes=0, elem_threads=0,
+                 device="cuda", stream=None):
         import torch
 
         self._torch = torch
@@ -206,7 +208,8 @@ class Bed:
             raise ValueError("radius and density must be (n,)")
         rr = r.detach().cpu().numpy()
         self.dp, self.cp = make_params(dem, fluid, self.n, 2.0 * float(rr.max()), 2.0 * float(rr.min()),
-                                       precision, max_neighbors, cell_capacity, resort_every, skin, lanes)
+                                       precision, max_neighbors, cell_capacity, resort_every, skin, lanes,
+                                       elem_threads)
         nbytes = workspace_bytes(self.dp, self.cp)
         if nbytes == 0:
             raise CfddemError(DEM_E_ARG, "dem_workspace_bytes")

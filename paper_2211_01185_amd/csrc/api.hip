@@ -37,7 +37,7 @@ hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long
                                 hipStream_t st);
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
                                const unsigned *map_class, int blocks_class, int *cnt_words,
-                               unsigned *list, const long long mode_elems[3], int order, bool fp32,
+                               unsigned *list, const long long mode_elems[3], int order, bool fp32, int nt,
                                hipStream_t st);
 int couple_class_elems_per_block();
 }  // namespace cfddem
@@ -184,6 +184,7 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
   if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
   if (cp->shear != 0 && cp->shear != 1) return DEM_E_ARG;
+  if (cp->elem_threads != 0 && cp->elem_threads != 64 && cp->elem_threads != 128) return DEM_E_ARG;
   if ((cp->smooth != 0 && cp->smooth != 1) || !(cp->smooth_L2 >= 0.0) || !isfinite(cp->smooth_L2))
     return DEM_E_ARG;
   if ((cp->drag & ~(0xff | DEM_DRAG_BETA_OVER_EPS)) != 0 || (cp->drag & 0xff) > DEM_DRAG_GIDASPOW)
@@ -809,6 +810,7 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   C.beta_over_eps = (cp->drag & DEM_DRAG_BETA_OVER_EPS) ? 1 : 0;
   C.shear = cp->shear;
   C.smooth = cp->smooth;
+  C.elem_threads = cp->elem_threads ? cp->elem_threads : 128;
   C.eps_nodes = cp->smooth ? ctx->B.sx : nullptr;
   C.Ve = S.grid.he[0] * S.grid.he[1] * S.grid.he[2];
   {
@@ -1124,6 +1126,7 @@ struct dem_batch {
   int order = 2;
   int maxn = 1;
   int lanes = kForceLanes;
+  int elem_threads = 128;  // threads per occupied element of the coupling step
   // beds are grouped by kernel variant, each group with its own launches, so
   // that a bed's arithmetic never depends on the other beds: the force map
   // holds the blocks of the beds without rolling friction first
@@ -1167,7 +1170,9 @@ dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, Batc
     if (!x) return DEM_E_ARG;
     for (int j = 0; j < b; ++j)
       if (beds[j] == x) return DEM_E_ARG;
-    if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes) return DEM_E_UNSUPPORTED;
+    if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes ||
+        x->C.elem_threads != beds[0]->C.elem_threads)
+      return DEM_E_UNSUPPORTED;
     if (x->C.smooth) return DEM_E_UNSUPPORTED;  // the smoothing solve runs per bed
     const long long n = x->S.n;
     const int bd = ceil_div(n, 256), bf = ceil_div(n * x->S.lanes, kForceBlock);
@@ -1251,7 +1256,7 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
 
 dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
   HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
-                              B->list, B->mode_elems, B->order, B->fp32, st));
+                              B->list, B->mode_elems, B->order, B->fp32, B->elem_threads, st));
   return DEM_OK;
 }
 
@@ -1307,6 +1312,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
   B->beds.assign(beds, beds + n_beds);
   B->fp32 = beds[0]->fp32;
   B->lanes = beds[0]->S.lanes;
+  B->elem_threads = beds[0]->C.elem_threads;
   B->couples = couples;
   B->order = beds[0]->cp.order;
   B->nb_drift = L.nb_drift;

@@ -10,7 +10,8 @@
 // contiguous runs and appends the occupied ones to a list (one atomic per
 // block).
 //
-// couple_occupied: one block of kCplThreads threads per listed element:
+// couple_occupied: one wavefront per listed element (so that a CU holds as
+// many elements in flight as its registers and LDS allow):
 //   1. gathers the element's particles from its nested DEM cells (the grid
 //      built at the current positions), cell by cell, each cell's particles
 //      ordered by index, so that every sum below has an order fixed by the
@@ -34,8 +35,7 @@
 namespace cfddem {
 
 constexpr int kWave = 64;
-constexpr int kCplThreads = 128;    // threads per occupied element
-constexpr int kCplWaves = kCplThreads / kWave;
+constexpr int kPressLane = 32;      // first lane loading the element's pressure corners
 constexpr int kClassElems = 8;      // elements per wavefront of the classify pass
 constexpr int kClassBlock = 1024;  // 16 wavefronts: one list append per 128 elements
 constexpr int kMaxCoupleBlocks = 4096;  // grid of the occupied-element pass
@@ -450,30 +450,48 @@ __device__ inline int cell_of_entry(const int *coff, int kk, int j) {
   return lo;
 }
 
+// LDS of one element computed by NT threads.
+template <int NT>
 struct CplShared {
   int ids[kElemMaxParticles];
   int raw[kElemMaxParticles];  // slot entries in slot order (cooperative gather)
-  int coff[kCplThreads];       // offset of each cell's run in ids (cooperative gather)
+  int coff[NT];                // offset of each cell's run in ids (cooperative gather)
   double sU[3][27];
   double sP[8];
   double sE[27];     // smoothed void fraction at the element's velocity nodes
-  double sLq[3][3];  // 1D velocity basis at the Gauss points (kernel constants)
-  double red[kCplWaves][11];
-  int scan[kCplWaves];
-  int longc[kCplWaves];
+  double red[NT / kWave][11];
+  int scan[NT / kWave];
+  int longc[NT / kWave];
 };
 
-// One occupied element, computed by the whole block.  The latency is a short
-// chain of memory round trips: counts, slot entries and nodal values are
-// loaded together, then the particles' state, then the outputs are stored.
-template <typename R, int ORD, int MODE>
+// Barrier of the NT threads (one block) computing an element: a wavefront
+// barrier when the block is one wavefront.
+template <int NT>
+__device__ inline void cpl_sync() {
+  if constexpr (NT == kWave)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// One occupied element, computed by a block of NT threads (64 or 128, a
+// tuning choice: a 64-thread block per element lets a CU hold twice the
+// elements in flight, a 128-thread one takes up to 128 particles in one
+// pass).  Particle t of the element's ordered list is handled by thread
+// t mod NT.  The latency is a short chain of memory round trips: counts,
+// slot entries and nodal values are loaded together, then the particles'
+// state, then the outputs are stored.
+template <typename R, int ORD, int MODE, int NT>
 __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
                                const double *__restrict__ P, double *__restrict__ eps_q,
                                double *__restrict__ beta_q, double *__restrict__ fpf_q,
-                               double *__restrict__ esums, int p2, int p3, CplShared &sh) {
+                               double *__restrict__ esums, int p2, int p3, CplShared<NT> &sh,
+                               const double (&sLq)[3][3]) {
+  constexpr int kCplThreads = NT;
+  constexpr int kCplWaves = NT / kWave;
   const Grid &G = D.grid;
   const int n = D.n;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & (NT - 1);
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
@@ -495,7 +513,8 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     un[2] = U[2 * nv + node];
     if (MODE == 2 && C.smooth) sh.sE[tid] = C.eps_nodes[node];  // read after the barrier below
   }
-  const int pc = tid - kWave;  // pressure corner of this thread
+  static_assert(nnode <= kPressLane && kPressLane + 8 <= kCplThreads, "nodal loads by lane");
+  const int pc = tid - kPressLane;  // pressure corner of this thread
   if (pc >= 0 && pc < 8) {
     const int ia = pc & 1, ib = (pc >> 1) & 1, ic = pc >> 2;
     pk = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
@@ -535,7 +554,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     sh.sU[2][tid] = un[2];
   }
   if (pc >= 0 && pc < 8) sh.sP[pc] = pk;
-  __syncthreads();
+  cpl_sync<NT>();
   int off = incl - mine, total = 0, any_long = 0;
 #pragma unroll
   for (int w = 0; w < kCplWaves; ++w) {
@@ -557,13 +576,13 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       for (int s = 0; s < kSlotPre; ++s)
         if (s < m0) sh.raw[off + s] = v0[s];
     }
-    __syncthreads();
+    cpl_sync<NT>();
     for (int j = tid; j < total; j += kCplThreads) {
       const int c = cell_of_entry(sh.coff, G.kk, j);
       const int s = j - sh.coff[c];
       if (s >= kSlotPre) sh.raw[j] = slot[(size_t)(base + c) * D.cap + s];
     }
-    __syncthreads();
+    cpl_sync<NT>();
     for (int j = tid; j < total; j += kCplThreads) {
       const int c = cell_of_entry(sh.coff, G.kk, j);
       const int lo = sh.coff[c], hi = c + 1 < G.kk ? sh.coff[c + 1] : total;
@@ -594,7 +613,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       w += m;
     }
   }
-  __syncthreads();
+  cpl_sync<NT>();
 
   // ---- 2. void fraction; the state of the thread's first particle is
   // loaded in the same round trip as its radius
@@ -616,7 +635,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   }
   vsum = wave_sum(vsum);
   if (lane == 0) sh.red[wave][10] = vsum;
-  __syncthreads();
+  cpl_sync<NT>();
   vsum = 0.0;
 #pragma unroll
   for (int w = 0; w < kCplWaves; ++w) vsum += sh.red[w][10];
@@ -640,7 +659,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   if (lane == 0)
 #pragma unroll
     for (int j = 0; j < 10; ++j) sh.red[wave][j] = sums[j];
-  __syncthreads();
+  cpl_sync<NT>();
 #pragma unroll
   for (int j = 0; j < 10; ++j) {
     double v = 0.0;
@@ -649,12 +668,18 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     sums[j] = v;
   }
 
-  // ---- 4. quadrature-point outputs: thread t < 3 nq computes component
-  // t / nq of F at point t % nq; the next nq threads write eps and beta
+  // ---- 4. quadrature-point outputs.  With 4 nq + 1 threads or more, thread
+  // t < 3 nq computes component t / nq of F at point t % nq; otherwise
+  // thread q < nq computes the three components at point q (same arithmetic
+  // per component).  The next nq threads write eps and beta, the one after
+  // them the element sums.
+  constexpr bool kPerComp = 4 * nq + 1 <= NT;
+  constexpr int kFThreads = kPerComp ? 3 * nq : nq;
+  static_assert(kFThreads + nq + 1 <= NT, "outputs in one pass");
   const double s_beta = sums[0];
   const double bq = s_beta / C.Ve;
-  if (tid < 3 * nq) {
-    const int c = tid / nq, q = tid % nq;
+  if (tid < kFThreads) {
+    const int q = kPerComp ? tid % nq : tid;
     const int qi[3] = {q % p1, (q / p1) % p1, q / (p1 * p1)};
     // basis values at this thread's Gauss point (staged in LDS: a
     // per-thread index into the kernel arguments would turn every use into a
@@ -663,40 +688,43 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < p1; ++b) Lg[a][b] = sh.sLq[b][qi[a]];
-    double F = 0.0;
-    if (total > 0) {
-      double uq = 0.0;
+      for (int b = 0; b < p1; ++b) Lg[a][b] = sLq[b][qi[a]];
+    const int c0 = kPerComp ? tid / nq : 0, c1 = kPerComp ? c0 + 1 : 3;
+    for (int c = c0; c < c1; ++c) {
+      double F = 0.0;
+      if (total > 0) {
+        double uq = 0.0;
 #pragma unroll
-      for (int ic = 0; ic < p1; ++ic) {
-        double acc_c = 0.0;
+        for (int ic = 0; ic < p1; ++ic) {
+          double acc_c = 0.0;
 #pragma unroll
-        for (int ib = 0; ib < p1; ++ib) {
-          double acc_b = 0.0;
+          for (int ib = 0; ib < p1; ++ib) {
+            double acc_b = 0.0;
 #pragma unroll
-          for (int ia = 0; ia < p1; ++ia) acc_b += Lg[0][ia] * sh.sU[c][(ic * p1 + ib) * p1 + ia];
-          acc_c += Lg[1][ib] * acc_b;
+            for (int ia = 0; ia < p1; ++ia) acc_b += Lg[0][ia] * sh.sU[c][(ic * p1 + ib) * p1 + ia];
+            acc_c += Lg[1][ib] * acc_b;
+          }
+          uq += Lg[2][ic] * acc_c;
+          __asm__ volatile("" ::: "memory");
         }
-        uq += Lg[2][ic] * acc_c;
-        __asm__ volatile("" ::: "memory");
+        const double ubar = s_beta > 0.0 ? sums[1 + c] / s_beta : 0.0;
+        F = -bq * (uq - ubar);
+        if (C.model == 1) F -= sums[7 + c] / C.Ve;
       }
-      const double ubar = s_beta > 0.0 ? sums[1 + c] / s_beta : 0.0;
-      F = -bq * (uq - ubar);
-      if (C.model == 1) F -= sums[7 + c] / C.Ve;
+      fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
     }
-    fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
-  } else if (tid < 4 * nq) {
-    const long qg = (long)e * nq + (tid - 3 * nq);
+  } else if (tid < kFThreads + nq) {
+    const long qg = (long)e * nq + (tid - kFThreads);
     eps_q[qg] = eps;
     beta_q[qg] = bq;
-  } else if (esums && tid == 4 * nq) {
+  } else if (esums && tid == kFThreads + nq) {
     const int ne = G.n_elem;
     esums[0 * ne + e] = (double)total;
     esums[1 * ne + e] = vsum;
 #pragma unroll
     for (int j = 0; j < 10; ++j) esums[(2 + j) * ne + e] = sums[j];
   }
-  __syncthreads();  // the block's LDS is reused for its next element
+  cpl_sync<NT>();  // the LDS is reused for the next element
 }
 
 // Classification of kClassElems consecutive elements starting at e0 by one
@@ -778,11 +806,11 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
                        eps_q, beta_q, fpf_q, esums, s_cnt);
 }
 
-// One block per listed element, up to kMaxCoupleBlocks blocks (blocks past the
-// list exit at once; dispatching one block per mesh element would cost more
-// than the work).  Longer lists are strided over the grid.
-template <typename R, int ORD, int MODE>
-__global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
+// One block of NT threads per listed element, up to kMaxCoupleBlocks blocks
+// (blocks past the list exit at once; dispatching one block per mesh element
+// would cost more than the work).  Longer lists are strided over the grid.
+template <typename R, int ORD, int MODE, int NT>
+__global__ __launch_bounds__(NT, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
                                                                     int parity,
                                                                     const double *__restrict__ U,
                                                                     const double *__restrict__ P,
@@ -790,7 +818,8 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
                                                                     double *__restrict__ beta_q,
                                                                     double *__restrict__ fpf_q,
                                                                     double *__restrict__ esums) {
-  __shared__ CplShared sh;
+  __shared__ CplShared<NT> sh;
+  __shared__ double sLq[3][3];  // 1D velocity basis at the Gauss points
   // the list entry is read in the same round trip as the list length (every
   // entry below n_elem is in bounds)
   const int nocc = D.err[kOccWord + parity];
@@ -798,11 +827,11 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied(Dev D, Cpl C, 
   __asm__ volatile("" ::: "memory");
   if ((int)blockIdx.x >= nocc) return;  // whole block
   const int tid = threadIdx.x;
-  if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD, MODE>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+  if (tid < 9) sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the element's first barrier
+  couple_element<R, ORD, MODE, NT>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh, sLq);
   // more occupied elements than blocks: the rest, strided over the grid
   for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
-    couple_element<R, ORD, MODE>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh);
+    couple_element<R, ORD, MODE, NT>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh, sLq);
 }
 
 // ---------------------------------------------------------------------------
@@ -826,27 +855,28 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
                        io.eps_q, io.beta_q, io.fpf_q, io.esums, s_cnt);
 }
 
-template <typename R, int ORD, int MODE>
+template <typename R, int ORD, int MODE, int NT>
 __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const Cpl *__restrict__ ctab,
                                               const CplIO *__restrict__ iot,
                                               const BedRun *__restrict__ run, unsigned ent,
-                                              CplShared &sh) {
+                                              CplShared<NT> &sh, double (&sLq)[3][3]) {
   const int b = (int)(ent >> kBedShift), e = (int)(ent & kBlockMask);
   const Dev &D = tab[b];
   const Cpl &C = ctab[b];
   const CplIO &io = iot[b];
   const long long s = run[b].s;
   const int tid = threadIdx.x;
-  if (tid < 9) sh.sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the first barrier
-  couple_element<R, ORD, MODE>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
-                         (int)(s % 3), sh);
+  if (tid < 9) sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the element's first barrier
+  couple_element<R, ORD, MODE, NT>(D, C, e, io.U, io.P, io.eps_q, io.beta_q, io.fpf_q, io.esums, (int)(s & 1),
+                                   (int)(s % 3), sh, sLq);
 }
 
-template <typename R, int ORD, int MODE>
-__global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
+template <typename R, int ORD, int MODE, int NT>
+__global__ __launch_bounds__(NT, 3) void couple_occupied_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list) {
-  __shared__ CplShared sh;
+  __shared__ CplShared<NT> sh;
+  __shared__ double sLq[3][3];
   const int nocc = *cnt_word;
   unsigned ent = list[blockIdx.x];
   __asm__ volatile("" ::: "memory");
@@ -854,7 +884,7 @@ __global__ __launch_bounds__(kCplThreads, 3) void couple_occupied_batch(
   // is read in the same round trip as the list length
   for (int i = blockIdx.x; i < nocc; i += gridDim.x) {
     if (i != (int)blockIdx.x) ent = list[i];
-    couple_listed<R, ORD, MODE>(tab, ctab, iot, run, ent, sh);
+    couple_listed<R, ORD, MODE, NT>(tab, ctab, iot, run, ent, sh, sLq);
   }
 }
 
@@ -862,15 +892,61 @@ __global__ void reset_count(int *cnt_words) {
   if (blockIdx.x == 0 && threadIdx.x < 3) cnt_words[threadIdx.x] = 0;
 }
 
-// Every bed of a batch (all of velocity order `order`).  Occupied elements
-// are listed per element-kernel variant (mode_elems[m] elements of beds in
-// mode m, region m of the list at ml.off[m], counted in cnt_words[m]), and
-// each variant present runs its own launch, so that every bed computes the
-// arithmetic of its own variant whatever the other beds are.  The counters
-// are zero on entry and on return.
+// Launch of an occupied-element kernel variant: precision, velocity order,
+// element-kernel mode (run time values) and threads per element.
+#define CFDDEM_DISPATCH(KERNEL_CALL, fp32, order, mode, nt)                                   \
+  do {                                                                                         \
+    if (nt == 64) {                                                                            \
+      constexpr int NT_ = 64;                                                                  \
+      CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode);                                      \
+    } else {                                                                                   \
+      constexpr int NT_ = 128;                                                                 \
+      CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode);                                      \
+    }                                                                                          \
+  } while (0)
+#define CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode)                                     \
+  do {                                                                                         \
+    if (fp32) {                                                                                \
+      using RT_ = float;                                                                       \
+      CFDDEM_DISPATCH_O(KERNEL_CALL, order, mode);                                             \
+    } else {                                                                                   \
+      using RT_ = double;                                                                      \
+      CFDDEM_DISPATCH_O(KERNEL_CALL, order, mode);                                             \
+    }                                                                                          \
+  } while (0)
+#define CFDDEM_DISPATCH_O(KERNEL_CALL, order, mode)                                            \
+  do {                                                                                         \
+    if (order == 2) {                                                                          \
+      constexpr int O_ = 2;                                                                    \
+      CFDDEM_DISPATCH_M(KERNEL_CALL, mode);                                                    \
+    } else {                                                                                   \
+      constexpr int O_ = 1;                                                                    \
+      CFDDEM_DISPATCH_M(KERNEL_CALL, mode);                                                    \
+    }                                                                                          \
+  } while (0)
+#define CFDDEM_DISPATCH_M(KERNEL_CALL, mode)                                                   \
+  do {                                                                                         \
+    if (mode == 2) {                                                                           \
+      constexpr int M_ = 2;                                                                    \
+      KERNEL_CALL;                                                                             \
+    } else if (mode == 1) {                                                                    \
+      constexpr int M_ = 1;                                                                    \
+      KERNEL_CALL;                                                                             \
+    } else {                                                                                   \
+      constexpr int M_ = 0;                                                                    \
+      KERNEL_CALL;                                                                             \
+    }                                                                                          \
+  } while (0)
+
+// Every bed of a batch (all of velocity order `order`, all with `nt` threads
+// per element).  Occupied elements are listed per element-kernel variant
+// (mode_elems[m] elements of beds in mode m, region m of the list at
+// ml.off[m], counted in cnt_words[m]), and each variant present runs its own
+// launch, so that every bed computes the arithmetic of its own variant
+// whatever the other beds are.  The counters are zero on entry and on return.
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
                                const unsigned *map_class, int blocks_class, int *cnt_words,
-                               unsigned *list, const long long mode_elems[3], int order, bool fp32,
+                               unsigned *list, const long long mode_elems[3], int order, bool fp32, int nt,
                                hipStream_t st) {
   if (blocks_class <= 0) return hipGetLastError();
   ModeLists ml;
@@ -879,22 +955,13 @@ hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot
   ml.off[2] = mode_elems[0] + mode_elems[1];
   couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_words,
                                                               list, ml);
-  const dim3 b(kCplThreads);
-#define CFDDEM_OCCB(RT, O, M)                                                                   \
-  couple_occupied_batch<RT, O, M><<<g, b, 0, st>>>(tab, ctab, iot, run, cnt_words + M, list + ml.off[M])
-#define CFDDEM_OCCB_MODE(RT, O) \
-  do { if (m == 2) CFDDEM_OCCB(RT, O, 2); else if (m == 1) CFDDEM_OCCB(RT, O, 1); else CFDDEM_OCCB(RT, O, 0); } while (0)
   for (int m = 0; m < 3; ++m) {
     if (mode_elems[m] <= 0) continue;
     const dim3 g(mode_elems[m] < kMaxCoupleBlocks ? (int)mode_elems[m] : kMaxCoupleBlocks);
-    if (fp32) {
-      if (order == 2) CFDDEM_OCCB_MODE(float, 2); else CFDDEM_OCCB_MODE(float, 1);
-    } else {
-      if (order == 2) CFDDEM_OCCB_MODE(double, 2); else CFDDEM_OCCB_MODE(double, 1);
-    }
+    CFDDEM_DISPATCH((couple_occupied_batch<RT_, O_, M_, NT_><<<g, NT_, 0, st>>>(tab, ctab, iot, run, cnt_words + M_,
+                                                                               list + ml.off[M_])),
+                    fp32, order, m, nt);
   }
-#undef CFDDEM_OCCB_MODE
-#undef CFDDEM_OCCB
   reset_count<<<1, 64, 0, st>>>(cnt_words);
   return hipGetLastError();
 }
@@ -910,19 +977,17 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
   const int waves_c = (ne + kClassElems - 1) / kClassElems;
   const int grid_c = (waves_c + kClassBlock / kWave - 1) / (kClassBlock / kWave);
   couple_classify<<<grid_c, kClassBlock, 0, st>>>(D, C, p3, parity, eps_q, beta_q, fpf_q, esums);
-  const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks), b(kCplThreads);
-#define CFDDEM_OCC(RT, O, M) couple_occupied<RT, O, M><<<g, b, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)
-#define CFDDEM_OCC_MODE(RT, O) \
-  do { if (mode == 2) CFDDEM_OCC(RT, O, 2); else if (mode == 1) CFDDEM_OCC(RT, O, 1); else CFDDEM_OCC(RT, O, 0); } while (0)
+  const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks);
   const int mode = cpl_mode_of(C.drag, C.shear || C.smooth);
-  if (fp32) {
-    if (C.order == 2) CFDDEM_OCC_MODE(float, 2); else CFDDEM_OCC_MODE(float, 1);
-  } else {
-    if (C.order == 2) CFDDEM_OCC_MODE(double, 2); else CFDDEM_OCC_MODE(double, 1);
-  }
-#undef CFDDEM_OCC_MODE
-#undef CFDDEM_OCC
+  CFDDEM_DISPATCH((couple_occupied<RT_, O_, M_, NT_><<<g, NT_, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q,
+                                                                       fpf_q, esums)),
+                  fp32, C.order, mode, C.elem_threads);
   return hipGetLastError();
 }
+
+#undef CFDDEM_DISPATCH_M
+#undef CFDDEM_DISPATCH_O
+#undef CFDDEM_DISPATCH_RT
+#undef CFDDEM_DISPATCH
 
 }  // namespace cfddem

@@ -143,6 +143,7 @@ struct Cpl {
   int shear;          // 1: shear force -V_p div(tau) added to the particle force
   int smooth;         // 1: the closure sees the smoothed void-fraction field
   const double *eps_nodes;  // that field at the velocity nodes (smooth = 1)
+  int elem_threads;   // threads per occupied element in the coupling step: 64 or 128
   double Ve;        // element volume
   double Lq[3][3];  // Lq[a][i]: 1D velocity basis a at Gauss point i
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)

@@ -38,10 +38,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "cfddem.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dem_params), offsetof(dem_params, dt),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dem_params), offsetof(dem_params, dt),
          offsetof(dem_params, max_neighbors), offsetof(dem_params, skin), sizeof(cfd_params),
          offsetof(cfd_params, eps_min), offsetof(dem_params, mu_r), offsetof(dem_params, mu_r_w),
-         offsetof(cfd_params, shear));
+         offsetof(cfd_params, shear), offsetof(cfd_params, elem_threads));
   return 0;
 }
 """
@@ -53,7 +53,8 @@ int main(void) {
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
     want = [C.sizeof(cfddem.DemParams), cfddem.DemParams.dt.offset, cfddem.DemParams.max_neighbors.offset,
             cfddem.DemParams.skin.offset, C.sizeof(cfddem.CfdParams), cfddem.CfdParams.eps_min.offset,
-            cfddem.DemParams.mu_r.offset, cfddem.DemParams.mu_r_w.offset, cfddem.CfdParams.shear.offset]
+            cfddem.DemParams.mu_r.offset, cfddem.DemParams.mu_r_w.offset, cfddem.CfdParams.shear.offset,
+            cfddem.CfdParams.elem_threads.offset]
     assert [int(v) for v in out] == want
 
 
@@ -75,7 +76,8 @@ def test_workspace_query_validates_parameters():
     _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
     cpb.order = 3
     assert cfddem.workspace_bytes(dp, cpb) == 0
-    for field, value in (("shear", 2), ("smooth", 2), ("smooth_L2", -1.0)):
+    for field, value in (("shear", 2), ("smooth", 2), ("smooth_L2", -1.0), ("elem_threads", 32),
+                         ("elem_threads", 256)):
         _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
         setattr(cpb, field, value)
         assert cfddem.workspace_bytes(dp, cpb) == 0, field

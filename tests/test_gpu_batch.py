@@ -46,8 +46,9 @@ def _q2_beds():
     return [a, b, c]
 
 
-def _make(wls, precision, resort=(0, 0, 0)):
-    beds = [cfddem.bed_from_workload(w, precision=precision, resort_every=r) for w, r in zip(wls, resort)]
+def _make(wls, precision, resort=(0, 0, 0), elem_threads=0):
+    beds = [cfddem.bed_from_workload(w, precision=precision, resort_every=r, elem_threads=elem_threads)
+            for w, r in zip(wls, resort)]
     fields = [_fields(w) for w in wls]
     return beds, fields
 
@@ -65,9 +66,10 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_mixed_batch_matches_oracle(precision):
+@pytest.mark.parametrize("elem_threads", [64, 128])
+def test_mixed_batch_matches_oracle(precision, elem_threads):
     wls = _q2_beds()
-    beds, fields = _make(wls, precision, resort=(0, 3, 7))
+    beds, fields = _make(wls, precision, resort=(0, 3, 7), elem_threads=elem_threads)
     batch = cfddem.Batch(beds, fields, elem_sums=True)
     refs = [oracle_bed(w) for w in wls]
     tol = TOL[precision]
@@ -203,6 +205,15 @@ def test_batch_rejects_mixed_precision():
     wls = _q1_beds()[:2]
     beds = [cfddem.bed_from_workload(wls[0], precision="fp64"),
             cfddem.bed_from_workload(wls[1], precision="fp32")]
+    with pytest.raises(cfddem.CfddemError) as ei:
+        cfddem.Batch(beds)
+    assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)
+
+
+def test_batch_rejects_mixed_elem_threads():
+    wls = _q1_beds()[:2]
+    beds = [cfddem.bed_from_workload(wls[0], precision="fp32", elem_threads=64),
+            cfddem.bed_from_workload(wls[1], precision="fp32", elem_threads=128)]
     with pytest.raises(cfddem.CfddemError) as ei:
         cfddem.Batch(beds)
     assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)

@@ -70,10 +70,11 @@ def test_single_step(name, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("model", [0, 1])
-def test_coupling_step(precision, model):
+@pytest.mark.parametrize("elem_threads", [64, 128])
+def test_coupling_step(precision, model, elem_threads):
     wl = _workload("lattice")
     wl.fluid["model"] = model
-    gb = gpu_bed(wl, precision)
+    gb = gpu_bed(wl, precision, elem_threads=elem_threads)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     out = gb.couple(U, P, elem_sums=True)
@@ -297,7 +298,8 @@ def _noisy_field(wl, order, seed=11, amplitude=0.05):
 
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_coupling_step_many_particles_per_cell(order, precision):
+@pytest.mark.parametrize("elem_threads", [64, 128])
+def test_coupling_step_many_particles_per_cell(order, precision, elem_threads):
     """Polydisperse spheres (d 1-4 mm, the spouted-bed recipe) on 5 mm
     elements: one DEM cell per element, holding up to tens of particles, so
     the element's gather copies the slot entries past the ones loaded with
@@ -305,7 +307,7 @@ def test_coupling_step_many_particles_per_cell(order, precision):
     wl = synth.spouted(n=3500, box=(0.03, 0.03, 0.1), fill_height=0.1, n_el=(6, 6, 20))
     if order == 1:
         wl = _noisy_field(wl, 1)
-    gb = gpu_bed(wl, precision)
+    gb = gpu_bed(wl, precision, elem_threads=elem_threads)
     _, cell, k = gb.read_cells()
     assert k == [1, 1, 1]
     assert np.bincount(cell.cpu().numpy()).max() > 6  # well past the prefetched entries
@@ -322,9 +324,9 @@ def test_coupling_step_many_particles_per_cell(order, precision):
     assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
     # the element sums do not depend on the order the slots were filled in:
     # a re-sort permutes the slots, the outputs stay bit-identical
-    gb2 = gpu_bed(wl, precision, resort_every=1)
+    gb2 = gpu_bed(wl, precision, resort_every=1, elem_threads=elem_threads)
     gb2.step(1)
-    gb3 = gpu_bed(wl, precision, resort_every=0)
+    gb3 = gpu_bed(wl, precision, resort_every=0, elem_threads=elem_threads)
     gb3.step(1)
     o2 = gb2.couple(U, P, elem_sums=True)
     o3 = gb3.couple(U, P, elem_sums=True)
