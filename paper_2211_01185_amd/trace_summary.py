@@ -6,7 +6,10 @@
 Prints the kernel statistics of the whole command and the contact-force
 kernel's launch durations over the main measurement's two regions: the timed
 steps of the first bed and the same steps replayed on a second bed (where the
-benchmark reads its per-launch HIP events).  A bed of the main measurement is
+benchmark reads its per-launch HIP events).  With --bed spouted: the kernels
+of the spouted-bed measurement's timed bed instead (the last two beds created
+at that bed's grid are the timed one and its replay; the tuner's trial beds
+come before them).  A bed of the main measurement is
 recognised by its creation-time evaluation (force_kick<float, false, false,
 L, false>: no rolling friction) at the main bed's grid size followed by step
 launches of the single-bed kernel: the measurement's two beds run exactly
@@ -40,9 +43,12 @@ def main(argv=None):
     ap.add_argument("--trace", required=True)
     ap.add_argument("--bench-json", required=True)
     ap.add_argument("--top", type=int, default=12)
+    ap.add_argument("--bed", choices=("main", "spouted"), default="main")
     args = ap.parse_args(argv)
     with open(args.bench_json) as fh:
         bench = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    if args.bed == "spouted":
+        return spouted(args, bench)
     lanes = int(bench["config"]["tuned"]["lanes"])
     n = int(bench["config"]["particles"])
     warmup, steps = int(bench["warmup"]), int(bench["steps"])
@@ -85,6 +91,43 @@ def main(argv=None):
               f"(steps that run a broad search)")
     print(f"- bench.py's HIP events over the replayed region (same run, under the profiler): "
           f"{bench['roofline']['avg_launch_us']:.2f} us per launch")
+
+
+def spouted(args, bench):
+    sp = bench["spouted"]
+    lanes = int(sp["tuned"]["lanes"])
+    n = int(sp["particles"])
+    warmup, steps = int(sp["warmup"]), int(sp["steps"])
+    grid = -(-n * lanes // FORCE_BLOCK) * FORCE_BLOCK
+    rows = _one(args.trace, "kernel_trace.csv")
+    key = "Kernel_Name" if "Kernel_Name" in rows[0] else "Name"
+    gkey = "Grid_Size" if "Grid_Size" in rows[0] else "Grid_Size_X"
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    prime_re = re.compile(rf"cfddem::force_kick<float, false, false, {lanes}, false>")
+    starts = [i for i, r in enumerate(rows) if int(r[gkey] or 0) == grid and prime_re.search(r[key])]
+    if len(starts) < 2:
+        raise SystemExit(f"found {len(starts)} beds at grid {grid}")
+    region = rows[starts[-2]:starts[-1]]
+    tot = {}
+    for r in region:
+        name = r[key]
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        c, t = tot.get(name, (0, 0.0))
+        tot[name] = (c + 1, t + d)
+    busy = sum(t for _, t in tot.values())
+    span = (int(region[-1]["End_Timestamp"]) - int(region[0]["Start_Timestamp"])) / 1e3
+    print(f"Spouted bed ({n} spheres, tuned {sp['tuned']}): kernels of the timed bed, from its creation "
+          f"through {warmup} warm-up and {steps} timed steps; {busy / 1e3:.2f} ms of kernel time in a "
+          f"{span / 1e3:.2f} ms span")
+    print()
+    print("| kernel | calls | avg us | total ms | share % |")
+    print("|---|---|---|---|---|")
+    for name, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:args.top]:
+        short = name if len(name) <= 72 else name[:69] + "..."
+        print(f"| `{short}` | {c} | {t / c:.2f} | {t / 1e3:.3f} | {100.0 * t / busy:.2f} |")
+    print()
+    print(f"- bench.py in the same run (under the profiler): {sp['ms_per_step']:.4f} ms per step, "
+          f"force kernel {sp['force_kernel']['avg_launch_us']:.2f} us per launch (HIP events, replay)")
 
 
 if __name__ == "__main__":
