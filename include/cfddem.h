@@ -160,12 +160,14 @@ typedef struct {
   double smooth_L2; /* smoothing length squared (m^2), >= 0 (0: the plain
                        projection) */
   int32_t elem_threads; /* threads computing one occupied element in the
-                       coupling step: 64 (one wavefront: twice the elements
-                       in flight, for elements of few particles) or 128 (up
-                       to 128 particles in one pass); 0 = 128.  A tuning
-                       choice: outputs depend on it only in the rounding of
-                       the element sums.  Every bed of a batch must have the
-                       same value */
+                       coupling step: 16 or 32 (a group of a wavefront: 4 or
+                       2 elements per wavefront instruction, for elements of
+                       few particles; an element may then hold at most 256
+                       or 512 particles, more raise DEM_E_CAPACITY), 64
+                       (one wavefront) or 128 (up to 128 particles in one
+                       pass); 0 = 128.  A tuning choice: outputs depend on it
+                       only in the rounding of the element sums.  Every bed
+                       of a batch must have the same value */
 } cfd_params;
 
 /* Bytes of device workspace dem_create needs for these parameters.  Pure host

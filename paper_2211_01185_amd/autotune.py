@@ -9,8 +9,10 @@ Knobs (dem_params and cfd_params fields):
   * resort_every  DEM steps between re-sorts of the particle arrays by cell;
   * lanes         lanes of a wavefront sharing one particle in the
                   contact-force kernel (the tile of list entries per lane);
-  * elem_threads  threads per occupied element in the coupling step: 64 (more
-                  elements in flight, for elements of few particles) or 128.
+  * elem_threads  threads per occupied element in the coupling step: 16 or 32
+                  (several elements of few particles per wavefront), 64 or
+                  128.  A candidate whose trial raises a device error (an
+                  element past the capacity of its group) is never kept.
 
 None of them changes a contact set, and forces only at the rounding level
 (the order of a particle's contact sums depends on its list layout, that of
@@ -35,7 +37,7 @@ CANDIDATES = {
     "skin_factor": (0.05, 0.1, 0.2, 0.35),
     "resort_every": (25, 50, 100, 200),
     "lanes": (1, 2, 4),
-    "elem_threads": (64, 128),
+    "elem_threads": (16, 32, 64, 128),
 }
 DEFAULT = {"skin_factor": 0.1, "resort_every": 100, "lanes": 2, "elem_threads": 128}
 COUPLING_EVERY = 10

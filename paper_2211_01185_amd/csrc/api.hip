@@ -184,7 +184,9 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   if (!(cp->eps_min > 0.0 && cp->eps_min <= 1.0)) return DEM_E_ARG;
   if (cp->model != DEM_MODEL_A && cp->model != DEM_MODEL_B) return DEM_E_ARG;
   if (cp->shear != 0 && cp->shear != 1) return DEM_E_ARG;
-  if (cp->elem_threads != 0 && cp->elem_threads != 64 && cp->elem_threads != 128) return DEM_E_ARG;
+  if (cp->elem_threads != 0 && cp->elem_threads != 16 && cp->elem_threads != 32 && cp->elem_threads != 64 &&
+      cp->elem_threads != 128)
+    return DEM_E_ARG;
   if ((cp->smooth != 0 && cp->smooth != 1) || !(cp->smooth_L2 >= 0.0) || !isfinite(cp->smooth_L2))
     return DEM_E_ARG;
   if ((cp->drag & ~(0xff | DEM_DRAG_BETA_OVER_EPS)) != 0 || (cp->drag & 0xff) > DEM_DRAG_GIDASPOW)

@@ -10,21 +10,22 @@
 // contiguous runs and appends the occupied ones to a list (one atomic per
 // block).
 //
-// couple_occupied: one wavefront per listed element (so that a CU holds as
-// many elements in flight as its registers and LDS allow):
+// couple_occupied: one group of 16, 32, 64 or 128 threads per listed element
+// (a tuning choice: groups smaller than a wavefront let one wavefront
+// instruction serve several elements of few particles):
 //   1. gathers the element's particles from its nested DEM cells (the grid
 //      built at the current positions), cell by cell, each cell's particles
 //      ordered by index, so that every sum below has an order fixed by the
 //      set of particles alone; a cell holding more particles than were
 //      loaded with its count (large elements of few cells) is copied by the
-//      whole block and ordered by a rank sort,
+//      whole group and ordered by a rank sort,
 //   2. particle-centroid void fraction eps_e = 1 - sum V_p / V_e
 //      (Eq. "void_fraction"),
 //   3. per particle (one per thread): Q_n interpolation of the fluid
 //      velocity and the Q1 pressure gradient from the element's nodal values
 //      staged in LDS, drag closure, f_fp = f_D + f_B + f_gradp (held by
 //      the DEM steps),
-//   4. element sums reduced across the block (fixed order), then the
+//   4. element sums reduced across the group (fixed order), then the
 //      quadrature-point outputs eps_q, beta_q and the force density on the
 //      fluid F_pf,q = -beta_q (u_q - u_bar) [- sum f_gradp / V_e for model B]
 //      (Eqs. "fa", "fb"), one (point, component) per thread.
@@ -161,17 +162,16 @@ __device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
   }
 }
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-// N butterfly sums at once, level by level, so that the lane exchanges of a
-// level are in flight together rather than N dependent chains.
-template <int N>
-__device__ inline void wave_sum_n(double (&v)[N]) {
+// Butterfly sums over aligned groups of W lanes (W a power of two <= 64),
+// level by level so that the lane exchanges of a level are in flight
+// together.  Only the first `active` lanes of the group may hold nonzero
+// values: the levels whose partners all lie past them only add zeros to the
+// first lanes and are skipped, so lane 0 of the group gets the same sum.
+template <int W, int N>
+__device__ inline void group_sum_n(double (&v)[N], int active) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+  for (int off = W / 2; off >= 1; off >>= 1) {
+    if (off >= active) continue;
     double t[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) t[j] = __shfl_xor(v[j], off, kWave);
@@ -180,9 +180,12 @@ __device__ inline void wave_sum_n(double (&v)[N]) {
   }
 }
 
-__device__ inline int wave_incl_scan(int v, int lane) {
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int t = __shfl_up(v, off, kWave);
+// Inclusive scan over aligned groups of W lanes; lane is the index in the group.
+template <int W>
+__device__ inline int group_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int off = 1; off < W; off <<= 1) {
+    const int t = __shfl_up(v, off, W);
     if (lane >= off) v += t;
   }
   return v;
@@ -450,37 +453,54 @@ __device__ inline int cell_of_entry(const int *coff, int kk, int j) {
   return lo;
 }
 
+// Particles one element may hold when computed by NT threads (more raise the
+// capacity error): groups smaller than a wavefront share its LDS.
+template <int NT>
+constexpr int elem_capacity() {
+  return NT >= kWave ? kElemMaxParticles : 16 * NT;
+}
+
+// Wavefronts of the NT threads computing one element (1 for a group of a
+// wavefront).
+template <int NT>
+constexpr int elem_waves() {
+  return NT > kWave ? NT / kWave : 1;
+}
+
 // LDS of one element computed by NT threads.
 template <int NT>
 struct CplShared {
-  int ids[kElemMaxParticles];
-  int raw[kElemMaxParticles];  // slot entries in slot order (cooperative gather)
-  int coff[NT];                // offset of each cell's run in ids (cooperative gather)
+  int ids[elem_capacity<NT>()];
+  int raw[elem_capacity<NT>()];  // slot entries in slot order (cooperative gather)
+  int coff[NT];                  // offset of each cell's run in ids (cooperative gather)
   double sU[3][27];
   double sP[8];
   double sE[27];     // smoothed void fraction at the element's velocity nodes
-  double red[NT / kWave][11];
-  int scan[NT / kWave];
-  int longc[NT / kWave];
+  double red[elem_waves<NT>()][11];
+  int scan[elem_waves<NT>()];
+  int longc[elem_waves<NT>()];
 };
 
-// Barrier of the NT threads (one block) computing an element: a wavefront
-// barrier when the block is one wavefront.
+// Barrier of the NT threads computing an element: the block for 128, else a
+// wavefront barrier (the group is a wavefront or a part of one; the groups of
+// a wavefront may be on different branches, which a wavefront executes one
+// after the other).
 template <int NT>
 __device__ inline void cpl_sync() {
-  if constexpr (NT == kWave)
+  if constexpr (NT <= kWave)
     wave_sync();
   else
     __syncthreads();
 }
 
-// One occupied element, computed by a block of NT threads (64 or 128, a
-// tuning choice: a 64-thread block per element lets a CU hold twice the
-// elements in flight, a 128-thread one takes up to 128 particles in one
-// pass).  Particle t of the element's ordered list is handled by thread
-// t mod NT.  The latency is a short chain of memory round trips: counts,
-// slot entries and nodal values are loaded together, then the particles'
-// state, then the outputs are stored.
+// One occupied element, computed by NT threads (16, 32, 64 or 128, a tuning
+// choice): a group of 16 or 32 lanes, so that a wavefront computes 4 or 2
+// elements of few particles at once (every wavefront instruction serves all
+// of them), a whole wavefront, or a 128-thread block taking up to 128
+// particles in one pass.  Particle t of the element's ordered list is
+// handled by thread t mod NT.  The latency is a short chain of memory round
+// trips: counts, slot entries and nodal values are loaded together, then the
+// particles' state, then the outputs are stored.
 template <typename R, int ORD, int MODE, int NT>
 __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e, const double *__restrict__ U,
                                const double *__restrict__ P, double *__restrict__ eps_q,
@@ -488,12 +508,14 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
                                double *__restrict__ esums, int p2, int p3, CplShared<NT> &sh,
                                const double (&sLq)[3][3]) {
   constexpr int kCplThreads = NT;
-  constexpr int kCplWaves = NT / kWave;
+  constexpr int kCplWaves = elem_waves<NT>();
+  constexpr int GW = NT < kWave ? NT : kWave;  // lanes of this element in one wavefront
   const Grid &G = D.grid;
   const int n = D.n;
   const int tid = threadIdx.x & (NT - 1);
-  const int lane = tid & (kWave - 1);
+  const int lane = tid & (GW - 1);
   const int wave = tid / kWave;
+  const int gbase = (int)threadIdx.x & (kWave - 1) & ~(GW - 1);  // first lane of the group
   const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
   const int ee[3] = {ex, ey, ez};
   constexpr int p1 = ORD + 1;
@@ -501,20 +523,28 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   constexpr int nq = p1 * p1 * p1;  // Gauss points: order + 1 per axis
   const long nqtot = (long)G.n_elem * nq;
 
-  // ---- nodal values of the element (at most 27): velocity on wave 0,
-  // pressure corners on wave 1
-  double un[3] = {0.0, 0.0, 0.0}, pk = 0.0;
-  if (tid < nnode) {
-    const long nv = (long)C.nvx * C.nvy * ((long)ORD * G.n_el[2] + 1);
-    const int ia = tid % p1, ib = (tid / p1) % p1, ic = tid / (p1 * p1);
-    const long node = (((long)ORD * ez + ic) * C.nvy + (long)ORD * ey + ib) * C.nvx + (long)ORD * ex + ia;
-    un[0] = U[node];
-    un[1] = U[nv + node];
-    un[2] = U[2 * nv + node];
-    if (MODE == 2 && C.smooth) sh.sE[tid] = C.eps_nodes[node];  // read after the barrier below
+  // ---- nodal values of the element (at most 27): velocity on the first
+  // threads (twice round for 16), pressure corners on threads 32..39 when
+  // there are that many, else on the first 8
+  constexpr int kNodeIter = (nnode + NT - 1) / NT;
+  double un[kNodeIter][3], pk = 0.0;
+#pragma unroll
+  for (int k = 0; k < kNodeIter; ++k) {
+    const int t = tid + k * NT;
+    un[k][0] = un[k][1] = un[k][2] = 0.0;
+    if (t < nnode) {
+      const long nv = (long)C.nvx * C.nvy * ((long)ORD * G.n_el[2] + 1);
+      const int ia = t % p1, ib = (t / p1) % p1, ic = t / (p1 * p1);
+      const long node = (((long)ORD * ez + ic) * C.nvy + (long)ORD * ey + ib) * C.nvx + (long)ORD * ex + ia;
+      un[k][0] = U[node];
+      un[k][1] = U[nv + node];
+      un[k][2] = U[2 * nv + node];
+      if (MODE == 2 && C.smooth) sh.sE[t] = C.eps_nodes[node];  // read after the barrier below
+    }
   }
-  static_assert(nnode <= kPressLane && kPressLane + 8 <= kCplThreads, "nodal loads by lane");
-  const int pc = tid - kPressLane;  // pressure corner of this thread
+  constexpr int kPL = NT >= kPressLane + 8 ? kPressLane : 0;
+  static_assert(nnode <= kPressLane && NT >= 8, "nodal loads by lane");
+  const int pc = tid - kPL;  // pressure corner of this thread
   if (pc >= 0 && pc < 8) {
     const int ia = pc & 1, ib = (pc >> 1) & 1, ic = pc >> 2;
     pk = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
@@ -540,18 +570,23 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     const int m = cnt[base + c];
     mine += m < D.cap ? m : D.cap;
   }
-  // block exclusive scan of the per-thread counts
-  const int incl = wave_incl_scan(mine, lane);
+  // exclusive scan of the per-thread counts over the element's threads
+  const int incl = group_incl_scan<GW>(mine, lane);
   // does any cell hold more entries than were prefetched with the counts?
-  const bool long_cell = __ballot(m0 > kSlotPre) != 0ull;
-  if (lane == kWave - 1) {
+  const unsigned long long lmask = GW == kWave ? ~0ull : (((1ull << GW) - 1ull) << gbase);
+  const bool long_cell = (__ballot(m0 > kSlotPre) & lmask) != 0ull;
+  if (lane == GW - 1) {
     sh.scan[wave] = incl;
     sh.longc[wave] = long_cell ? 1 : 0;
   }
-  if (tid < nnode) {
-    sh.sU[0][tid] = un[0];
-    sh.sU[1][tid] = un[1];
-    sh.sU[2][tid] = un[2];
+#pragma unroll
+  for (int k = 0; k < kNodeIter; ++k) {
+    const int t = tid + k * NT;
+    if (t < nnode) {
+      sh.sU[0][t] = un[k][0];
+      sh.sU[1][t] = un[k][1];
+      sh.sU[2][t] = un[k][2];
+    }
   }
   if (pc >= 0 && pc < 8) sh.sP[pc] = pk;
   cpl_sync<NT>();
@@ -562,7 +597,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     total += sh.scan[w];
     any_long |= sh.longc[w];
   }
-  const bool over = total > kElemMaxParticles;
+  const bool over = total > elem_capacity<NT>();
   if (over && tid == 0) atomicOr(D.err, kErrCapacity);
   if (over) total = 0;
   if (total > 0 && any_long && G.kk <= kCplThreads) {
@@ -633,7 +668,13 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     const double r = D.rad[sh.ids[t]];
     vsum += 4.0 / 3.0 * kPi * r * r * r;
   }
-  vsum = wave_sum(vsum);
+  // lanes of this wavefront holding particles (the others hold zeros)
+  const int active = min(GW, max(0, total - wave * kWave));
+  {
+    double vs[1] = {vsum};
+    group_sum_n<GW>(vs, active);
+    vsum = vs[0];
+  }
   if (lane == 0) sh.red[wave][10] = vsum;
   cpl_sync<NT>();
   vsum = 0.0;
@@ -655,7 +696,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     }
     particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sh.sE, sums);
   }
-  wave_sum_n(sums);
+  group_sum_n<GW>(sums, active);
   if (lane == 0)
 #pragma unroll
     for (int j = 0; j < 10; ++j) sh.red[wave][j] = sums[j];
@@ -668,61 +709,65 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     sums[j] = v;
   }
 
-  // ---- 4. quadrature-point outputs.  With 4 nq + 1 threads or more, thread
-  // t < 3 nq computes component t / nq of F at point t % nq; otherwise
-  // thread q < nq computes the three components at point q (same arithmetic
-  // per component).  The next nq threads write eps and beta, the one after
-  // them the element sums.
+  // ---- 4. quadrature-point outputs.  With 4 nq + 1 threads or more, item
+  // t < 3 nq is component t / nq of F at point t % nq; otherwise item q < nq
+  // is the three components at point q (same arithmetic per component).  The
+  // next nq items write eps and beta, the one after them the element sums.
+  // Items go round the element's threads (more than one pass only for groups
+  // of 16 or 32).
   constexpr bool kPerComp = 4 * nq + 1 <= NT;
   constexpr int kFThreads = kPerComp ? 3 * nq : nq;
-  static_assert(kFThreads + nq + 1 <= NT, "outputs in one pass");
+  constexpr int kItems = kFThreads + nq + 1;
   const double s_beta = sums[0];
   const double bq = s_beta / C.Ve;
-  if (tid < kFThreads) {
-    const int q = kPerComp ? tid % nq : tid;
-    const int qi[3] = {q % p1, (q / p1) % p1, q / (p1 * p1)};
-    // basis values at this thread's Gauss point (staged in LDS: a
-    // per-thread index into the kernel arguments would turn every use into a
-    // memory round trip)
-    double Lg[3][p1];
+#pragma unroll 1
+  for (int t = tid; t < kItems; t += NT) {
+    if (t < kFThreads) {
+      const int q = kPerComp ? t % nq : t;
+      const int qi[3] = {q % p1, (q / p1) % p1, q / (p1 * p1)};
+      // basis values at this item's Gauss point (staged in LDS: a per-thread
+      // index into the kernel arguments would turn every use into a memory
+      // round trip)
+      double Lg[3][p1];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < p1; ++b) Lg[a][b] = sLq[b][qi[a]];
-    const int c0 = kPerComp ? tid / nq : 0, c1 = kPerComp ? c0 + 1 : 3;
-    for (int c = c0; c < c1; ++c) {
-      double F = 0.0;
-      if (total > 0) {
-        double uq = 0.0;
+        for (int b = 0; b < p1; ++b) Lg[a][b] = sLq[b][qi[a]];
+      const int c0 = kPerComp ? t / nq : 0, c1 = kPerComp ? c0 + 1 : 3;
+      for (int c = c0; c < c1; ++c) {
+        double F = 0.0;
+        if (total > 0) {
+          double uq = 0.0;
 #pragma unroll
-        for (int ic = 0; ic < p1; ++ic) {
-          double acc_c = 0.0;
+          for (int ic = 0; ic < p1; ++ic) {
+            double acc_c = 0.0;
 #pragma unroll
-          for (int ib = 0; ib < p1; ++ib) {
-            double acc_b = 0.0;
+            for (int ib = 0; ib < p1; ++ib) {
+              double acc_b = 0.0;
 #pragma unroll
-            for (int ia = 0; ia < p1; ++ia) acc_b += Lg[0][ia] * sh.sU[c][(ic * p1 + ib) * p1 + ia];
-            acc_c += Lg[1][ib] * acc_b;
+              for (int ia = 0; ia < p1; ++ia) acc_b += Lg[0][ia] * sh.sU[c][(ic * p1 + ib) * p1 + ia];
+              acc_c += Lg[1][ib] * acc_b;
+            }
+            uq += Lg[2][ic] * acc_c;
+            __asm__ volatile("" ::: "memory");
           }
-          uq += Lg[2][ic] * acc_c;
-          __asm__ volatile("" ::: "memory");
+          const double ubar = s_beta > 0.0 ? sums[1 + c] / s_beta : 0.0;
+          F = -bq * (uq - ubar);
+          if (C.model == 1) F -= sums[7 + c] / C.Ve;
         }
-        const double ubar = s_beta > 0.0 ? sums[1 + c] / s_beta : 0.0;
-        F = -bq * (uq - ubar);
-        if (C.model == 1) F -= sums[7 + c] / C.Ve;
+        fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
       }
-      fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
-    }
-  } else if (tid < kFThreads + nq) {
-    const long qg = (long)e * nq + (tid - kFThreads);
-    eps_q[qg] = eps;
-    beta_q[qg] = bq;
-  } else if (esums && tid == kFThreads + nq) {
-    const int ne = G.n_elem;
-    esums[0 * ne + e] = (double)total;
-    esums[1 * ne + e] = vsum;
+    } else if (t < kFThreads + nq) {
+      const long qg = (long)e * nq + (t - kFThreads);
+      eps_q[qg] = eps;
+      beta_q[qg] = bq;
+    } else if (esums) {
+      const int ne = G.n_elem;
+      esums[0 * ne + e] = (double)total;
+      esums[1 * ne + e] = vsum;
 #pragma unroll
-    for (int j = 0; j < 10; ++j) esums[(2 + j) * ne + e] = sums[j];
+      for (int j = 0; j < 10; ++j) esums[(2 + j) * ne + e] = sums[j];
+    }
   }
   cpl_sync<NT>();  // the LDS is reused for the next element
 }
@@ -806,32 +851,54 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
                        eps_q, beta_q, fpf_q, esums, s_cnt);
 }
 
-// One block of NT threads per listed element, up to kMaxCoupleBlocks blocks
-// (blocks past the list exit at once; dispatching one block per mesh element
-// would cost more than the work).  Longer lists are strided over the grid.
+// Elements a block computes at once (the groups of a wavefront for 16 or 32
+// threads per element) and its threads.
+template <int NT>
+constexpr int elems_per_block() {
+  return NT < kWave ? kWave / NT : 1;
+}
+template <int NT>
+constexpr int block_threads() {
+  return NT < kWave ? kWave : NT;
+}
+template <int NT>
+int occ_grid(long long elems) {
+  const long long b = (elems + elems_per_block<NT>() - 1) / elems_per_block<NT>();
+  return (int)(b < kMaxCoupleBlocks ? b : kMaxCoupleBlocks);
+}
+
+// Each group of NT threads takes one listed element at a time, up to
+// kMaxCoupleBlocks blocks (blocks past the list exit at once; dispatching one
+// block per mesh element would cost more than the work).  Longer lists are
+// strided over the grid.
 template <typename R, int ORD, int MODE, int NT>
-__global__ __launch_bounds__(NT, 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
-                                                                    int parity,
-                                                                    const double *__restrict__ U,
-                                                                    const double *__restrict__ P,
-                                                                    double *__restrict__ eps_q,
-                                                                    double *__restrict__ beta_q,
-                                                                    double *__restrict__ fpf_q,
-                                                                    double *__restrict__ esums) {
-  __shared__ CplShared<NT> sh;
+__global__ __launch_bounds__(block_threads<NT>(), 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
+                                                                            int parity,
+                                                                            const double *__restrict__ U,
+                                                                            const double *__restrict__ P,
+                                                                            double *__restrict__ eps_q,
+                                                                            double *__restrict__ beta_q,
+                                                                            double *__restrict__ fpf_q,
+                                                                            double *__restrict__ esums) {
+  constexpr int kG = elems_per_block<NT>();
+  __shared__ CplShared<NT> sh[kG];
   __shared__ double sLq[3][3];  // 1D velocity basis at the Gauss points
-  // the list entry is read in the same round trip as the list length (every
-  // entry below n_elem is in bounds)
+  const int g = (int)threadIdx.x / NT;
+  const int first = (int)blockIdx.x * kG + g;
+  const int last = D.grid.n_elem - 1;
+  // the list entry is read in the same round trip as the list length (the
+  // list has n_elem entries)
   const int nocc = D.err[kOccWord + parity];
-  const int e = D.occ[blockIdx.x];
+  const int e = D.occ[first < last ? first : last];
   __asm__ volatile("" ::: "memory");
-  if ((int)blockIdx.x >= nocc) return;  // whole block
+  if ((int)blockIdx.x * kG >= nocc) return;  // whole block
   const int tid = threadIdx.x;
   if (tid < 9) sLq[tid / 3][tid % 3] = C.Lq[tid / 3][tid % 3];  // read after the element's first barrier
-  couple_element<R, ORD, MODE, NT>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh, sLq);
-  // more occupied elements than blocks: the rest, strided over the grid
-  for (int i = blockIdx.x + gridDim.x; i < nocc; i += gridDim.x)
-    couple_element<R, ORD, MODE, NT>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh, sLq);
+  if (first >= nocc) return;  // whole group (a group of a wavefront: no block barrier follows)
+  couple_element<R, ORD, MODE, NT>(D, C, e, U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh[g], sLq);
+  // more occupied elements than groups: the rest, strided over the grid
+  for (int i = first + (int)gridDim.x * kG; i < nocc; i += (int)gridDim.x * kG)
+    couple_element<R, ORD, MODE, NT>(D, C, D.occ[i], U, P, eps_q, beta_q, fpf_q, esums, p2, p3, sh[g], sLq);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,19 +939,24 @@ __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const
 }
 
 template <typename R, int ORD, int MODE, int NT>
-__global__ __launch_bounds__(NT, 3) void couple_occupied_batch(
+__global__ __launch_bounds__(block_threads<NT>(), 3) void couple_occupied_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
-    const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list) {
-  __shared__ CplShared<NT> sh;
+    const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list, long long cap) {
+  constexpr int kG = elems_per_block<NT>();
+  __shared__ CplShared<NT> sh[kG];
   __shared__ double sLq[3][3];
+  const int g = (int)threadIdx.x / NT;
+  const long long first = (long long)blockIdx.x * kG + g;
   const int nocc = *cnt_word;
-  unsigned ent = list[blockIdx.x];
+  unsigned ent = list[first < cap ? first : cap - 1];  // the list region has cap entries
   __asm__ volatile("" ::: "memory");
   // one call site (the element computation is inlined once); the first entry
-  // is read in the same round trip as the list length
-  for (int i = blockIdx.x; i < nocc; i += gridDim.x) {
-    if (i != (int)blockIdx.x) ent = list[i];
-    couple_listed<R, ORD, MODE, NT>(tab, ctab, iot, run, ent, sh, sLq);
+  // is read in the same round trip as the list length.  The groups of a block
+  // hold consecutive entries, so the first group has an element whenever
+  // another has (it stages the basis values).
+  for (long long i = first; i < nocc; i += (long long)gridDim.x * kG) {
+    if (i != first) ent = list[i];
+    couple_listed<R, ORD, MODE, NT>(tab, ctab, iot, run, ent, sh[g], sLq);
   }
 }
 
@@ -896,7 +968,13 @@ __global__ void reset_count(int *cnt_words) {
 // element-kernel mode (run time values) and threads per element.
 #define CFDDEM_DISPATCH(KERNEL_CALL, fp32, order, mode, nt)                                   \
   do {                                                                                         \
-    if (nt == 64) {                                                                            \
+    if (nt == 16) {                                                                            \
+      constexpr int NT_ = 16;                                                                  \
+      CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode);                                      \
+    } else if (nt == 32) {                                                                     \
+      constexpr int NT_ = 32;                                                                  \
+      CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode);                                      \
+    } else if (nt == 64) {                                                                     \
       constexpr int NT_ = 64;                                                                  \
       CFDDEM_DISPATCH_RT(KERNEL_CALL, fp32, order, mode);                                      \
     } else {                                                                                   \
@@ -957,9 +1035,9 @@ hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot
                                                               list, ml);
   for (int m = 0; m < 3; ++m) {
     if (mode_elems[m] <= 0) continue;
-    const dim3 g(mode_elems[m] < kMaxCoupleBlocks ? (int)mode_elems[m] : kMaxCoupleBlocks);
-    CFDDEM_DISPATCH((couple_occupied_batch<RT_, O_, M_, NT_><<<g, NT_, 0, st>>>(tab, ctab, iot, run, cnt_words + M_,
-                                                                               list + ml.off[M_])),
+    CFDDEM_DISPATCH((couple_occupied_batch<RT_, O_, M_, NT_><<<occ_grid<NT_>(mode_elems[m]), block_threads<NT_>(), 0,
+                                                               st>>>(tab, ctab, iot, run, cnt_words + M_,
+                                                                     list + ml.off[M_], mode_elems[M_])),
                     fp32, order, m, nt);
   }
   reset_count<<<1, 64, 0, st>>>(cnt_words);
@@ -977,10 +1055,9 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
   const int waves_c = (ne + kClassElems - 1) / kClassElems;
   const int grid_c = (waves_c + kClassBlock / kWave - 1) / (kClassBlock / kWave);
   couple_classify<<<grid_c, kClassBlock, 0, st>>>(D, C, p3, parity, eps_q, beta_q, fpf_q, esums);
-  const dim3 g(ne < kMaxCoupleBlocks ? ne : kMaxCoupleBlocks);
   const int mode = cpl_mode_of(C.drag, C.shear || C.smooth);
-  CFDDEM_DISPATCH((couple_occupied<RT_, O_, M_, NT_><<<g, NT_, 0, st>>>(D, C, p2, p3, parity, U, P, eps_q, beta_q,
-                                                                       fpf_q, esums)),
+  CFDDEM_DISPATCH((couple_occupied<RT_, O_, M_, NT_><<<occ_grid<NT_>(ne), block_threads<NT_>(), 0, st>>>(
+                      D, C, p2, p3, parity, U, P, eps_q, beta_q, fpf_q, esums)),
                   fp32, C.order, mode, C.elem_threads);
   return hipGetLastError();
 }

@@ -76,7 +76,7 @@ def test_workspace_query_validates_parameters():
     _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
     cpb.order = 3
     assert cfddem.workspace_bytes(dp, cpb) == 0
-    for field, value in (("shear", 2), ("smooth", 2), ("smooth_L2", -1.0), ("elem_threads", 32),
+    for field, value in (("shear", 2), ("smooth", 2), ("smooth_L2", -1.0), ("elem_threads", 8),
                          ("elem_threads", 256)):
         _, cpb = cfddem.make_params(wl.dem, wl.fluid, wl.n, 3e-3, 3e-3)
         setattr(cpb, field, value)

@@ -66,7 +66,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("elem_threads", [64, 128])
+@pytest.mark.parametrize("elem_threads", [16, 32, 64, 128])
 def test_mixed_batch_matches_oracle(precision, elem_threads):
     wls = _q2_beds()
     beds, fields = _make(wls, precision, resort=(0, 3, 7), elem_threads=elem_threads)

@@ -70,7 +70,7 @@ def test_single_step(name, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("model", [0, 1])
-@pytest.mark.parametrize("elem_threads", [64, 128])
+@pytest.mark.parametrize("elem_threads", [16, 32, 64, 128])
 def test_coupling_step(precision, model, elem_threads):
     wl = _workload("lattice")
     wl.fluid["model"] = model
@@ -298,7 +298,7 @@ def _noisy_field(wl, order, seed=11, amplitude=0.05):
 
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("elem_threads", [64, 128])
+@pytest.mark.parametrize("elem_threads", [16, 32, 64, 128])
 def test_coupling_step_many_particles_per_cell(order, precision, elem_threads):
     """Polydisperse spheres (d 1-4 mm, the spouted-bed recipe) on 5 mm
     elements: one DEM cell per element, holding up to tens of particles, so
