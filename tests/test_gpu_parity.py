@@ -264,13 +264,14 @@ def test_lanes_per_particle(lanes, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("drag", ["dallavalle", "rong", "koch_hill", "beetstra", "gidaspow"])
 @pytest.mark.parametrize("beta_over_eps", [0, 1])
-def test_coupling_step_other_closures(drag, beta_over_eps, precision):
+@pytest.mark.parametrize("elem_threads", [16, 128])
+def test_coupling_step_other_closures(drag, beta_over_eps, precision, elem_threads):
     """Every drag closure of Section 2.3.2 (and beta_B = beta_A / eps)
     against the oracle on one coupling step; the lattice spans fluid fractions
     on both sides of the Gidaspow (0.8) and Koch-Hill (eps_p = 0.4) joins."""
     wl = _workload("lattice")
     wl.fluid.update(drag=drag, beta_over_eps=beta_over_eps, model=1)
-    gb = gpu_bed(wl, precision)
+    gb = gpu_bed(wl, precision, elem_threads=elem_threads)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     out = gb.couple(U, P, elem_sums=True)
@@ -365,7 +366,8 @@ def test_rolling_friction(lanes, precision):
 @pytest.mark.parametrize("model", [0, 1])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("drag", ["difelice", "gidaspow"])
-def test_coupling_step_with_shear_force(drag, order, model, precision):
+@pytest.mark.parametrize("elem_threads", [16, 32, 128])
+def test_coupling_step_with_shear_force(drag, order, model, precision, elem_threads):
     """The shear force -V_p div(tau_f) (Eqs. "fa", "fb", "stress") on one
     coupling step: particle forces, element sums and (model B) the force on
     the fluid against the oracle, Q1 and Q2 fields.  A water-like fluid
@@ -373,7 +375,7 @@ def test_coupling_step_with_shear_force(drag, order, model, precision):
     above the FP32 tolerance."""
     wl = _noisy_field(_workload("lattice"), order, amplitude=0.3)
     wl.fluid.update(shear=1, model=model, drag=drag, mu_f=1.0e-3, rho_f=1000.0)
-    gb = gpu_bed(wl, precision)
+    gb = gpu_bed(wl, precision, elem_threads=elem_threads)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     out = gb.couple(U, P, elem_sums=True)
@@ -405,14 +407,15 @@ def test_coupling_step_with_shear_force(drag, order, model, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("L2", [0.0, 4 * 3e-3 ** 2, 5 * 3e-3 ** 2])  # 4 d^2, 5 d^2 of Tables 2, 4
-def test_coupling_step_with_smoothed_void_fraction(L2, order, precision):
+@pytest.mark.parametrize("elem_threads", [16, 128])
+def test_coupling_step_with_smoothed_void_fraction(L2, order, precision, elem_threads):
     """The smoothed void fraction (fast diagonalization on the GPU, a direct
     sparse solve of the assembled system in the oracle): eps_q at every
     quadrature point, the closure fed by the field at each particle, over two
     coupling steps, against the oracle."""
     wl = _noisy_field(_workload("lattice"), order)
     wl.fluid.update(smooth_L2=L2, model=1)
-    gb = gpu_bed(wl, precision)
+    gb = gpu_bed(wl, precision, elem_threads=elem_threads)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     tol = TOL[precision]
