@@ -141,7 +141,8 @@ def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample
     """Best configuration for running these beds, tuned on up to `sample` of
     them: one bed is timed through the single-bed entry points, several as a
     batch.  A candidate replaces the current best only when it is faster by
-    more than `min_gain` (relative), so that timing noise does not move the
+    more than `min_gain` (relative), and still so when both are timed once
+    more (each keeps its fastest run), so that timing noise does not move the
     choice.  Returns (config, report)."""
     import torch
 
@@ -156,11 +157,11 @@ def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample
     best = dict(DEFAULT)
     trials = {}
 
-    def timed(cfg):
+    def timed(cfg, again=False):
         k = json.dumps(cfg, sort_keys=True)
-        if k not in trials:
-            trials[k] = _time_batch(sub, fields, cfg, precision, steps, device)
-        return trials[k]
+        if k not in trials or again:
+            trials.setdefault(k, []).append(_time_batch(sub, fields, cfg, precision, steps, device))
+        return min(trials[k])
 
     t_best = timed(best)
     for knob, values in CANDIDATES.items():
@@ -168,9 +169,15 @@ def tune(wls, precision="fp32", steps=100, device="cuda", use_cache=True, sample
             cfg = dict(best, **{knob: v})
             t = timed(cfg)
             if t < t_best * (1.0 - min_gain):
-                best, t_best = cfg, t
-    report = {"config": best, "ms_per_step": t_best * 1e3, "default_ms_per_step": trials[json.dumps(DEFAULT, sort_keys=True)] * 1e3,
-              "trials": len(trials), "tuned_on_beds": len(sub), "signature": key, "cached": False}
+                t, t_b = timed(cfg, again=True), timed(best, again=True)
+                if t < t_b * (1.0 - min_gain):
+                    best, t_best = cfg, t
+                else:
+                    t_best = t_b
+    report = {"config": best, "ms_per_step": t_best * 1e3,
+              "default_ms_per_step": min(trials[json.dumps(DEFAULT, sort_keys=True)]) * 1e3,
+              "trials": sum(len(v) for v in trials.values()), "configs": len(trials), "tuned_on_beds": len(sub),
+              "signature": key, "cached": False}
     if use_cache:
         _store_cache(key, {k: v for k, v in report.items() if k != "cached"})
     return best, report
