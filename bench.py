@@ -24,6 +24,9 @@ sample of the same workload; and the two other parts of the metric:
            aggregate particle-steps/s over the jobs after the warm-up ones;
   smoothing: the benchmark bed with the smoothed void fraction (L^2 = 5 d^2):
            200 coupled steps, and the first coupling step timed alone;
+  packed:  the main measurement on a physically packed bed: the settling run's
+           bed at rest, then the fluidized bed's fluid from that state
+           (far more contacts than the lattice), tuned on that bed;
   spouted: the 500,000-sphere polydisperse spouted bed (Q2 30x30x120, Gaussian
            jet), tuned, 500 coupled steps after 20 warm-up ones, with the
            contact-force kernel's launches timed on a replay;
@@ -41,7 +44,7 @@ step, and the end of the oracle's sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--no-batched] [--no-served] [--no-smoothing] [--no-spouted]
-                       [--no-settling] [--served-jobs J]
+                       [--no-packed] [--no-settling] [--served-jobs J]
 """
 import argparse
 import hashlib
@@ -84,6 +87,7 @@ def parse():
     ap.add_argument("--no-settling", action="store_true", help="skip the DEM-only settling run")
     ap.add_argument("--no-smoothing", action="store_true", help="skip the smoothed void-fraction run")
     ap.add_argument("--no-spouted", action="store_true", help="skip the spouted-bed run")
+    ap.add_argument("--no-packed", action="store_true", help="skip the packed-bed run")
     ap.add_argument("--batched-beds", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--served-jobs", type=int, default=650)
@@ -406,6 +410,70 @@ def settling_run(dev, max_steps=100_000):
             "dtype": "f32 forces / f64 state", "check_every_steps": 500}
 
 
+def packed_run(dev, steps=1000, warmup=20):
+    """The fluidized-bed measurement on a physically packed bed: the 100,000
+    spheres of the filling workload settled to rest (as the settling run),
+    then the fluidized bed's fluid (Q2 20x20x80, U = (0,0,1.2) + N(0, 0.05),
+    linear pressure) from that state, FP32 forces; tuned on this bed, then
+    coupled steps timed as the main measurement, and the contact-force
+    kernel's launches timed on a replay of the same steps."""
+    import torch
+
+    from paper_2211_01185_amd import autotune, cfddem, settle, synth
+
+    fw = synth.filling()
+    bed = cfddem.bed_from_workload(fw, precision="fp32", device=dev, resort_every=200)
+    res = settle.settle(bed, settle.energy_scale(fw), rest=1e-4, every=500, max_steps=100_000)
+    st = {k: t.cpu().numpy() for k, t in bed.read_state().items()}
+    bed.close()
+    base = synth.fluidized()
+    wl = synth.Workload("packed", st["x"], st["v"], st["w"], fw.radius, fw.density, base.dem, base.fluid,
+                        base.run, base.U, base.P)
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    tuned, tune_report = autotune.tune([wl], "fp32", steps=warmup + steps, device=dev, use_cache=False)
+    bed_kw = autotune.bed_kwargs(wl, tuned)
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    s = run_coupled(bed, out, U, P, warmup, 0)
+    torch.cuda.synchronize()
+    pairs0, walls0 = contact_counts(bed)
+    t0 = time.perf_counter()
+    run_coupled(bed, out, U, P, steps, s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    err, _ = bed.poll()
+    pairs1, walls1 = contact_counts(bed)
+    nq_total = bed.n_elem * bed.nq
+    bed.close()
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    s = run_coupled(bed, out, U, P, warmup, 0)
+    bed.kernel_timing(True)
+    run_coupled(bed, out, U, P, steps, s)
+    torch.cuda.synchronize()
+    bed.kernel_timing(False)
+    launches, force_ms = bed.kernel_timing_read()
+    err2, _ = bed.poll()
+    bed.close()
+    contacts = 0.5 * (pairs0 + walls0 + pairs1 + walls1)
+    force_avg_s = force_ms / 1e3 / max(launches, 1)
+    alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
+    achieved = alg_bytes / force_avg_s / 1e9
+    return {"workload": "packed fluidized bed: the 100,000-sphere filling (d = 1 mm) settled to rest in the "
+                        "0.1 x 0.1 x 0.4 m column, then the fluidized bed's fluid (Q2 20x20x80, 1.2 m/s "
+                        f"upflow) from that state, coupling every {COUPLING_EVERY} steps",
+            "particles": wl.n, "steps": steps, "warmup": warmup, "settle_steps": res.steps,
+            "value": wl.n * steps / wall, "unit": "particle-steps/s", "ms_per_step": wall * 1e3 / steps,
+            "contacts_per_s": contacts * steps / wall,
+            "quadrature_points_per_s": nq_total * couplings_in(warmup, steps) / wall,
+            "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
+            "tuned": dict(bed_kw, trials=tune_report["trials"],
+                          default_ms_per_step=tune_report["default_ms_per_step"]),
+            "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
+                             "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
+                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
+            "errors": int(err or err2), "dtype": "f32 forces / f64 state"}
+
+
 def served_stream(n_jobs, warmup, dev):
     """The served stream: Poisson arrivals, continuous batching; statistics
     over the jobs after the first `warmup` ones."""
@@ -577,6 +645,10 @@ def main():
         progress("settling: starting")
         result["settling"] = settling_run(dev)
         progress(f"settling: {result['settling']['steps_to_rest']} steps to rest")
+    if not args.no_packed:
+        progress("packed bed: starting")
+        result["packed"] = packed_run(dev)
+        progress(f"packed: {result['packed']['ms_per_step']:.4f} ms per step")
     if not args.no_spouted:
         progress("spouted bed: starting")
         result["spouted"] = spouted_run(dev)
