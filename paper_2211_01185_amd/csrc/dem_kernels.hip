@@ -387,6 +387,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const double va0 = vhs[a], va1 = vhs[n + a], va2 = vhs[2 * n + a];
   const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
   const double ma = D.mass[a];
+  // the held fluid force, loaded with the rest of this particle's state (the
+  // kick after the list walk would otherwise wait for it)
+  const double fa[3] = {D.ffp[a], D.ffp[n + a], D.ffp[2 * n + a]};
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   // rolling torques, summed apart and added to T only for a bed with rolling
   // friction, so that a bed without it gets the same arithmetic in either
@@ -502,10 +505,10 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     double vb[3], wb[3], acc[3], alpha[3];
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + a;
-      acc[c] = (F[c] + D.ffp[i]) / ma + D.g[c];
+      acc[c] = (F[c] + fa[c]) / ma + D.g[c];
       alpha[c] = T[c] / inertia;
-      vb[c] = vhs[i] + 0.5 * D.dt * acc[c];
-      wb[c] = whs[i] + 0.5 * D.dt * alpha[c];
+      vb[c] = (c == 0 ? va0 : (c == 1 ? va1 : va2)) + 0.5 * D.dt * acc[c];
+      wb[c] = (c == 0 ? wa0 : (c == 1 ? wa1 : wa2)) + 0.5 * D.dt * alpha[c];
       if (!CONT) {
         D.v[i] = vb[c];
         D.w[i] = wb[c];
