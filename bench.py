@@ -474,13 +474,15 @@ def packed_run(dev, steps=1000, warmup=20):
             "errors": int(err or err2), "dtype": "f32 forces / f64 state"}
 
 
-def served_stream(n_jobs, warmup, dev):
+def served_stream(n_jobs, warmup, dev, config=None):
     """The served stream: Poisson arrivals, continuous batching; statistics
-    over the jobs after the first `warmup` ones."""
+    over the jobs after the first `warmup` ones.  config: the launch
+    choices of every job's bed (the batched ensemble's tuned configuration:
+    the jobs are beds of the same recipe), or None for the defaults."""
     from paper_2211_01185_amd import serve, synth
 
     jobs = synth.job_stream(n_jobs)
-    server = serve.Server(device=dev)
+    server = serve.Server(device=dev, config=config)
     results, wall = server.run(jobs)
     measured = [r for r in results if r.index >= warmup]
     t_first = min(r.arrival for r in measured)
@@ -635,7 +637,9 @@ def main():
         progress(f"batched: {result['batched']['value']:.4g} particle-steps/s")
     if not args.no_served:
         progress("served stream: starting")
-        result["served"] = served_stream(args.served_jobs, args.served_warmup, dev)
+        cfg = result["batched"]["autotune"]["config"] if "batched" in result else None
+        result["served"] = served_stream(args.served_jobs, args.served_warmup, dev, cfg)
+        result["served"]["config"] = cfg
         progress(f"served: p99 {result['served']['latency_p99_s']:.4f} s")
     if not args.no_smoothing:
         progress("smoothing: starting")

@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import cfddem
+from . import autotune, cfddem
 
 CHUNK_STEPS = 10  # DEM steps per coupling step
 
@@ -59,12 +59,13 @@ class _Active:
         self.admitted = admitted
 
 
-def footprint(wl, precision="fp32", resort_every=100) -> int:
+def footprint(wl, precision="fp32", resort_every=100, **bed_kw) -> int:
     """Device bytes a job holds while active: its workspace, fluid field and
-    coupling outputs (batch tables are small and not counted)."""
+    coupling outputs (batch tables are small and not counted).  bed_kw: the
+    launch choices of its bed (skin, lanes, elem_threads)."""
     d = 2.0 * float(wl.radius.max())
     dp, cp = cfddem.make_params(wl.dem, wl.fluid, wl.n, d, 2.0 * float(wl.radius.min()), precision,
-                                resort_every=resort_every)
+                                resort_every=resort_every, **bed_kw)
     ws = cfddem.workspace_bytes(dp, cp)
     n_el = int(np.prod(wl.fluid["n_el"]))
     nq = (int(wl.fluid["order"]) + 1) ** 3
@@ -75,13 +76,18 @@ class Server:
     """Runs a job stream in real time (arrival times in seconds from start)."""
 
     def __init__(self, budget_bytes=64 << 30, precision="fp32", resort_every=100, device="cuda",
-                 clock=time.perf_counter, speed=1.0):
+                 clock=time.perf_counter, speed=1.0, config=None):
         import torch
 
         self.torch = torch
         self.budget = int(budget_bytes)
         self.precision = precision
         self.resort_every = resort_every
+        # an autotuner configuration (skin factor, re-sort interval, lanes,
+        # threads per element) for every job's bed, or None for the defaults
+        # with resort_every; one configuration for all jobs, since the beds
+        # of a batch must share their lanes and threads per element
+        self.config = config
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         self.clock = clock
@@ -93,10 +99,15 @@ class Server:
         self.chunks = 0
         self.rebuilds = 0
 
+    def _bed_kw(self, wl) -> dict:
+        if self.config is None:
+            return dict(resort_every=self.resort_every)
+        return autotune.bed_kwargs(wl, self.config)
+
     def _admit(self, job, wl, now):
         torch = self.torch
-        bed = cfddem.bed_from_workload(wl, precision=self.precision, device=self.device,
-                                       resort_every=self.resort_every, stream=self.stream)
+        bed = cfddem.bed_from_workload(wl, precision=self.precision, device=self.device, stream=self.stream,
+                                       **self._bed_kw(wl))
         U = torch.as_tensor(wl.U, dtype=torch.float64, device=self.device).contiguous()
         P = torch.as_tensor(wl.P, dtype=torch.float64, device=self.device).contiguous()
         self.active.append(_Active(job, wl, bed, U, P, now))
@@ -139,7 +150,7 @@ class Server:
                 j = pending[0]
                 if j.index not in sizes:
                     wls[j.index] = j.workload()
-                    sizes[j.index] = footprint(wls[j.index], self.precision, self.resort_every)
+                    sizes[j.index] = footprint(wls[j.index], self.precision, **self._bed_kw(wls[j.index]))
                 if self.active and self.used + sizes[j.index] > self.budget:
                     break
                 pending.popleft()

@@ -19,9 +19,11 @@ def _small_stream(n_jobs=8):
     return synth.job_stream(n_jobs, rate=400.0, n_min=1_000, n_max=6_000)
 
 
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("config", [None, {"skin_factor": 0.05, "resort_every": 200, "lanes": 2,
+                                             "elem_threads": 16}])
+def test_results_alone_equal_results_in_the_mix(config):
     jobs = _small_stream()
-    server = serve.Server()
+    server = serve.Server(config=config)
     mixed, _ = server.run(jobs)
     assert len(mixed) == len(jobs)
     assert server.rebuilds > 1  # the set of active jobs changed while others ran
@@ -29,7 +31,7 @@ def test_results_alone_equal_results_in_the_mix():
                for m in mixed) > 1  # some jobs were on the device together
     by_index = {r.index: r for r in mixed}
     for job in jobs:
-        (alone,), _ = serve.Server().run([job])
+        (alone,), _ = serve.Server(config=config).run([job])
         r = by_index[job.index]
         assert r.error == 0 and alone.error == 0
         for k in ("x", "v", "w"):
