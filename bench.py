@@ -40,7 +40,8 @@ Beside particle-steps/s the main line gives contacts/s (contact pairs and
 wall contacts resolved per second) and quadrature-points/s (points of the
 coupling steps per second).  The CPU leg also compares both GPU paths (FP32
 forces, all FP64) with the oracle on the main bed: the first coupling and DEM
-step, and the end of the oracle's sample.
+step, and the end of the oracle's sample; and on the first coupling and DEM
+step, the spouted bed's path and a batched bed's path (FP32 forces).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--no-batched] [--no-served] [--no-smoothing] [--no-spouted]
@@ -194,6 +195,64 @@ def rel_max_err(got, want):
     return diff / scale if scale > 0.0 else diff
 
 
+def first_step_errors(c, st, F, T, ref):
+    """The parity tests' measure on the first coupling step (c: eps_q, beta_q,
+    fpf_q) and the first DEM step (st: state, F, T: contact force and torque)."""
+    o1 = ref["step1"]
+    return {"eps_q": rel_max_err(c["eps_q"], ref["couple"]["eps_q"]),
+            "beta_q": rel_max_err(c["beta_q"], ref["couple"]["beta_q"]),
+            "fpf_q": rel_max_err(c["fpf_q"], ref["couple"]["fpf_q"]),
+            "f_fp": rel_max_err(st["ffp"], o1["ffp"]),
+            "contact_force": rel_max_err(F, o1["Fc"]), "contact_torque": rel_max_err(T, o1["Tc"]),
+            "x": rel_max_err(st["x"], o1["x"]), "v": rel_max_err(st["v"], o1["v"]),
+            "w": rel_max_err(st["w"], o1["w"])}
+
+
+def oracle_first_step(wl):
+    """The FP64 oracle's first coupling step and first DEM step on a workload."""
+    from oracle import oracle as O
+
+    d, f = wl.dem, wl.fluid
+    p = O.make_params(d["box_lo"], d["box_hi"], d["gravity"], d["dt"], d["E"], d["nu"], d["e"], d["mu"],
+                      d["E_w"], d["nu_w"], d["e_w"], d["mu_w"])
+    fl = O.make_fluid(f["order"], f["n_el"], f["rho_f"], f["mu_f"], f["model"], f["eps_min"])
+    bed = O.OracleBed(p, wl.x, wl.v, wl.w, wl.radius, wl.density)
+    r = bed.couple(fl, wl.U, wl.P)
+    bed.step(1)
+    return {"couple": r, "step1": bed.state()}
+
+
+def gpu_first_step_errors(wl, ref, dev, bed_kw, batch=False):
+    """A GPU bed (FP32 forces) from the same inputs as the oracle: its first
+    coupling step and first DEM step, through the single-bed entry points or
+    as a batch of one (the batched kernels and graph replay)."""
+    import torch
+
+    from paper_2211_01185_amd import cfddem
+
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    bed = cfddem.bed_from_workload(wl, precision="fp32", device=dev, **bed_kw)
+    if batch:
+        b = cfddem.Batch([bed], [(U, P)])
+        out = b.couple()[0]
+        c = {k: out[k].cpu().numpy() for k in ("eps_q", "beta_q", "fpf_q")}
+        b.step(1)
+        torch.cuda.synchronize()
+        b.close()
+    else:
+        out = bed.couple(U, P)
+        c = {k: out[k].cpu().numpy() for k in ("eps_q", "beta_q", "fpf_q")}
+        bed.step(1)
+    st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
+    F, T = (t.cpu().numpy() for t in bed.read_forces())
+    err, _ = bed.poll()
+    bed.close()
+    e = first_step_errors(c, st, F, T, ref)
+    e["errors"] = int(err)
+    return e
+
+
 def errors_vs_oracle(wl, U, P, bed_kw, dev, ref, dem_steps):
     """The GPU paths (FP32 forces / FP64 state, and all FP64) against the FP64
     oracle on the main bed: the first coupling step and the first DEM step
@@ -208,14 +267,7 @@ def errors_vs_oracle(wl, U, P, bed_kw, dev, ref, dem_steps):
         bed.step(1)
         st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
         F, T = (t.cpu().numpy() for t in bed.read_forces())
-        o1 = ref["step1"]
-        e = {"eps_q": rel_max_err(c["eps_q"], ref["couple"]["eps_q"]),
-             "beta_q": rel_max_err(c["beta_q"], ref["couple"]["beta_q"]),
-             "fpf_q": rel_max_err(c["fpf_q"], ref["couple"]["fpf_q"]),
-             "f_fp": rel_max_err(st["ffp"], o1["ffp"]),
-             "contact_force": rel_max_err(F, o1["Fc"]), "contact_torque": rel_max_err(T, o1["Tc"]),
-             "x": rel_max_err(st["x"], o1["x"]), "v": rel_max_err(st["v"], o1["v"]),
-             "w": rel_max_err(st["w"], o1["w"])}
+        e = first_step_errors(c, st, F, T, ref)
         run_coupled(bed, out, U, P, dem_steps - 1, 1)
         st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
         err, _ = bed.poll()
@@ -234,7 +286,8 @@ def spouted_run(dev, steps=500, warmup=20):
     """The spouted bed (500,000 polydisperse spheres, Q2 30x30x120, Gaussian
     jet), FP32 forces: tuned as the main bed, then `warmup` + `steps` coupled
     steps timed as the main measurement, and the same steps replayed on a
-    fresh bed with the contact-force kernel's launches timed."""
+    fresh bed with the contact-force kernel's launches timed.  Returns the
+    result, the workload and the tuned bed keyword arguments."""
     import torch
 
     from paper_2211_01185_amd import autotune, synth
@@ -284,7 +337,7 @@ def spouted_run(dev, steps=500, warmup=20):
             "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
                              "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
                              "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
-            "generation_s": gen_s, "errors": int(err or err2), "dtype": "f32 forces / f64 state"}
+            "generation_s": gen_s, "errors": int(err or err2), "dtype": "f32 forces / f64 state"}, wl, bed_kw
 
 
 def batched_ensemble(n_beds, steps, dev):
@@ -655,13 +708,27 @@ def main():
         progress(f"packed: {result['packed']['ms_per_step']:.4f} ms per step")
     if not args.no_spouted:
         progress("spouted bed: starting")
-        result["spouted"] = spouted_run(dev)
+        result["spouted"], sp_wl, sp_kw = spouted_run(dev)
         progress(f"spouted: {result['spouted']['ms_per_step']:.4f} ms per step")
     if not args.no_cpu:
         progress("oracle sample: starting")
         result["cpu_baseline"], ref = cpu_baseline(wl, args.cpu_steps)
         progress("GPU paths against the oracle sample")
         result["error_vs_fp64_oracle"] = errors_vs_oracle(wl, U, P, bed_kw, dev, ref, args.cpu_steps)
+        # the other results' paths on the first coupling and DEM step: the
+        # spouted bed (tuned as measured), the first bed of the batched
+        # ensemble run as a batch of one with the ensemble's tuned choices
+        if not args.no_spouted:
+            progress("spouted bed against the oracle")
+            result["error_vs_fp64_oracle"]["spouted_fp32"] = gpu_first_step_errors(
+                sp_wl, oracle_first_step(sp_wl), dev, sp_kw)
+        if not args.no_batched:
+            from paper_2211_01185_amd import autotune, synth
+
+            bw = synth.batched_bed(0)
+            bkw = autotune.bed_kwargs(bw, result["batched"]["autotune"]["config"])
+            result["error_vs_fp64_oracle"]["batched_bed0_fp32"] = gpu_first_step_errors(
+                bw, oracle_first_step(bw), dev, bkw, batch=True)
     print(json.dumps(result), flush=True)
 
 
