@@ -165,6 +165,40 @@ def test_contact_capacity_error():
     assert err == cfddem.DEM_E_CAPACITY
 
 
+@pytest.mark.parametrize("elem_threads", [16, 32, 128])
+def test_element_capacity_of_small_groups(elem_threads):
+    """Elements of about 340 particles (a lattice on a 2 x 2 x 2 mesh, 343
+    DEM cells per element, more than a group's threads): a group of 16
+    threads holds at most 256 particles and raises the capacity error; 32
+    and 128 threads compute the step, against the oracle."""
+    from paper_2211_01185_amd import cfddem
+    wl = synth.lattice(n_side=(14, 14, 14))
+    lo, hi = wl.dem["box_lo"], wl.dem["box_hi"]
+    wl.fluid["n_el"] = [2, 2, 2]
+    wl.U = np.zeros((3, synth.node_grid(lo, hi, [2, 2, 2], 2).shape[1]))
+    wl.U[2] = 0.5
+    wl.P = 100.0 * (1.0 - synth.node_grid(lo, hi, [2, 2, 2], 1)[2] / hi[2])
+    h = (np.array(hi) - np.array(lo)) / 2
+    e3 = np.clip(np.floor((wl.x.T - lo) / h).astype(int), 0, 1)
+    per_el = np.bincount((e3[:, 2] * 2 + e3[:, 1]) * 2 + e3[:, 0], minlength=8)
+    assert 256 < per_el.max() <= 512
+    gb = gpu_bed(wl, "fp64", elem_threads=elem_threads)
+    U, P = _fields(wl)
+    out = gb.couple(U, P)
+    err, _ = gb.poll()
+    if elem_threads == 16:
+        assert err == cfddem.DEM_E_CAPACITY
+        return
+    assert err == 0
+    ob, fl = oracle_bed(wl)
+    ref = ob.couple(fl, wl.U, wl.P)
+    tol = TOL["fp64"]
+    assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-12)
+    assert_close("beta_q", out["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+    assert_close("fpf_q", out["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+    assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], tol)
+
+
 def test_nan_error():
     from paper_2211_01185_amd import cfddem
     wl = synth.plain(n=50)
