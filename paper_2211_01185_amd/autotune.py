@@ -12,7 +12,11 @@ Knobs (dem_params and cfd_params fields):
   * elem_threads  threads per occupied element in the coupling step: 16 or 32
                   (several elements of few particles per wavefront), 64 or
                   128.  A candidate whose trial raises a device error (an
-                  element past the capacity of its group) is never kept.
+                  element past the capacity of its group) is never kept; a
+                  bed that packs its elements denser later than the tuned
+                  run reaches may still meet that capacity (256 or 512
+                  particles per element for 16 or 32 threads), which the
+                  sticky capacity error reports.
 
 None of them changes a contact set, and forces only at the rounding level
 (the order of a particle's contact sums depends on its list layout, that of
