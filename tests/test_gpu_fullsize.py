@@ -4,11 +4,13 @@ second per coupling step at these sizes).
 
 * The 100,000-sphere fluidized bed in the launch configuration that bench.py
   times (FP32 force and drag arithmetic, a coupling step every 10 DEM steps;
-  skin, re-sort interval and lanes at the defaults and at tuned values):
+  skin, re-sort interval, lanes and threads per element at the defaults, at
+  the values the tuner picks on the MI355X and at another tuned set):
   110 steps, crossing re-sorts and neighbour-list rebuilds; also with the
   FP64 path.
-* The 500,000-sphere polydisperse spouted bed: priming, one coupling step and
-  ten DEM steps.
+* The 500,000-sphere polydisperse spouted bed, at the defaults and at the
+  tuned values (16 threads per element): priming, one coupling step and ten
+  DEM steps.
 
 Contact sets must match bit for bit at every check.  Coupling outputs, which
 depend on the current state only, are held to the single-step bar (1e-5 FP32,
@@ -45,7 +47,14 @@ def _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums):
     assert_close("f_fp", gb.read_state()["ffp"].cpu().numpy(), ob.state()["ffp"], tol)
 
 
+# the configuration the tuner picks for this bed in bench.py on the MI355X
+TUNED_FLUIDIZED = {"skin_factor": 0.05, "resort_every": 200, "lanes": 2, "elem_threads": 128}
+# and for the spouted bed (16 threads per element: four elements per wavefront)
+TUNED_SPOUTED = {"skin_factor": 0.2, "resort_every": 200, "lanes": 2, "elem_threads": 16}
+
+
 @pytest.mark.parametrize("precision,cfg", [("fp32", autotune.DEFAULT),
+                                           ("fp32", TUNED_FLUIDIZED),
                                            ("fp32", {"skin_factor": 0.2, "resort_every": 200, "lanes": 4}),
                                            ("fp64", autotune.DEFAULT)])
 def test_fluidized_bed_bench_configuration(precision, cfg):
@@ -78,10 +87,11 @@ def spouted():
     return synth.spouted()
 
 
-def test_spouted_bed_full_size(spouted):
+@pytest.mark.parametrize("cfg", [None, TUNED_SPOUTED])
+def test_spouted_bed_full_size(spouted, cfg):
     wl = spouted
-    gb = cfddem.bed_from_workload(wl, precision="fp32", device=torch.device("cuda:0"),
-                                  resort_every=bench.RESORT_EVERY)
+    kw = dict(resort_every=bench.RESORT_EVERY) if cfg is None else autotune.bed_kwargs(wl, cfg)
+    gb = cfddem.bed_from_workload(wl, precision="fp32", device=torch.device("cuda:0"), **kw)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
     tol = TOL["fp32"]
