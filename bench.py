@@ -178,7 +178,14 @@ def cpu_baseline(wl, dem_steps):
             ref["couple"] = r
             ref["step1"] = bed.state()
     ref["end"] = bed.state()
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     out = {"value": wl.n * dem_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "cpu_model": cpu_model,
            "sample": f"{dem_steps} DEM steps + {dem_steps // COUPLING_EVERY} coupling steps of the same "
                      f"{wl.n}-sphere bed, single-threaded FP64 C oracle, {dt:.1f} s"}
     return out, ref
