@@ -289,23 +289,13 @@ def errors_vs_oracle(wl, U, P, bed_kw, dev, ref, dem_steps):
             "bound_single_step": {"fp32": 1e-5, "fp64": 1e-10}, **res}
 
 
-def spouted_run(dev, steps=500, warmup=20):
-    """The spouted bed (500,000 polydisperse spheres, Q2 30x30x120, Gaussian
-    jet), FP32 forces: tuned as the main bed, then `warmup` + `steps` coupled
-    steps timed as the main measurement, and the same steps replayed on a
-    fresh bed with the contact-force kernel's launches timed.  Returns the
-    result, the workload and the tuned bed keyword arguments."""
+def measure_coupled(wl, U, P, bed_kw, dev, steps, warmup):
+    """`warmup` + `steps` coupled steps of a fresh bed (FP32 forces) with the
+    `steps` timed, then the same steps replayed on another fresh bed with the
+    contact-force kernel's launches timed by HIP events (the runs are
+    deterministic)."""
     import torch
 
-    from paper_2211_01185_amd import autotune, synth
-
-    t0 = time.perf_counter()
-    wl = synth.spouted()
-    gen_s = time.perf_counter() - t0
-    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
-    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
-    tuned, tune_report = autotune.tune([wl], "fp32", steps=warmup + steps, device=dev, use_cache=False)
-    bed_kw = autotune.bed_kwargs(wl, tuned)
     bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
     s = run_coupled(bed, out, U, P, warmup, 0)
     torch.cuda.synchronize()
@@ -331,20 +321,44 @@ def spouted_run(dev, steps=500, warmup=20):
     force_avg_s = force_ms / 1e3 / max(launches, 1)
     alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
     achieved = alg_bytes / force_avg_s / 1e9
+    return {"wall": wall, "errors": int(err or err2), "nq_total": nq_total, "contacts": contacts,
+            "pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
+            "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
+                             "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
+                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}}
+
+
+def spouted_run(dev, steps=500, warmup=20):
+    """The spouted bed (500,000 polydisperse spheres, Q2 30x30x120, Gaussian
+    jet), FP32 forces: tuned as the main bed, then `warmup` + `steps` coupled
+    steps timed as the main measurement, and the same steps replayed on a
+    fresh bed with the contact-force kernel's launches timed.  Returns the
+    result, the workload and the tuned bed keyword arguments."""
+    import torch
+
+    from paper_2211_01185_amd import autotune, synth
+
+    t0 = time.perf_counter()
+    wl = synth.spouted()
+    gen_s = time.perf_counter() - t0
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    tuned, tune_report = autotune.tune([wl], "fp32", steps=warmup + steps, device=dev, use_cache=False)
+    bed_kw = autotune.bed_kwargs(wl, tuned)
+    m = measure_coupled(wl, U, P, bed_kw, dev, steps, warmup)
+    wall, contacts = m["wall"], m["contacts"]
     return {"workload": "spouted bed: 500,000 spheres, d lognormal (median 2 mm, sigma 0.2, clipped 1-4 mm), "
                         "0.15 x 0.15 x 0.6 m, Q2 30x30x120 mesh (2,916,000 qpts), Gaussian inlet jet 20 m/s, "
                         f"coupling every {COUPLING_EVERY} steps",
             "particles": wl.n, "steps": steps, "warmup": warmup,
             "value": wl.n * steps / wall, "unit": "particle-steps/s", "ms_per_step": wall * 1e3 / steps,
             "contacts_per_s": contacts * steps / wall,
-            "quadrature_points_per_s": nq_total * couplings_in(warmup, steps) / wall,
-            "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
+            "quadrature_points_per_s": m["nq_total"] * couplings_in(warmup, steps) / wall,
+            "contacts_pairs_walls": m["pairs_walls"],
             "tuned": dict(bed_kw, trials=tune_report["trials"],
                           default_ms_per_step=tune_report["default_ms_per_step"]),
-            "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
-                             "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
-                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
-            "generation_s": gen_s, "errors": int(err or err2), "dtype": "f32 forces / f64 state"}, wl, bed_kw
+            "force_kernel": m["force_kernel"],
+            "generation_s": gen_s, "errors": m["errors"], "dtype": "f32 forces / f64 state"}, wl, bed_kw
 
 
 def batched_ensemble(n_beds, steps, dev):
@@ -493,45 +507,20 @@ def packed_run(dev, steps=1000, warmup=20):
     P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
     tuned, tune_report = autotune.tune([wl], "fp32", steps=warmup + steps, device=dev, use_cache=False)
     bed_kw = autotune.bed_kwargs(wl, tuned)
-    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
-    s = run_coupled(bed, out, U, P, warmup, 0)
-    torch.cuda.synchronize()
-    pairs0, walls0 = contact_counts(bed)
-    t0 = time.perf_counter()
-    run_coupled(bed, out, U, P, steps, s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    err, _ = bed.poll()
-    pairs1, walls1 = contact_counts(bed)
-    nq_total = bed.n_elem * bed.nq
-    bed.close()
-    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
-    s = run_coupled(bed, out, U, P, warmup, 0)
-    bed.kernel_timing(True)
-    run_coupled(bed, out, U, P, steps, s)
-    torch.cuda.synchronize()
-    bed.kernel_timing(False)
-    launches, force_ms = bed.kernel_timing_read()
-    err2, _ = bed.poll()
-    bed.close()
-    contacts = 0.5 * (pairs0 + walls0 + pairs1 + walls1)
-    force_avg_s = force_ms / 1e3 / max(launches, 1)
-    alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
-    achieved = alg_bytes / force_avg_s / 1e9
+    m = measure_coupled(wl, U, P, bed_kw, dev, steps, warmup)
+    wall, contacts = m["wall"], m["contacts"]
     return {"workload": "packed fluidized bed: the 100,000-sphere filling (d = 1 mm) settled to rest in the "
                         "0.1 x 0.1 x 0.4 m column, then the fluidized bed's fluid (Q2 20x20x80, 1.2 m/s "
                         f"upflow) from that state, coupling every {COUPLING_EVERY} steps",
             "particles": wl.n, "steps": steps, "warmup": warmup, "settle_steps": res.steps,
             "value": wl.n * steps / wall, "unit": "particle-steps/s", "ms_per_step": wall * 1e3 / steps,
             "contacts_per_s": contacts * steps / wall,
-            "quadrature_points_per_s": nq_total * couplings_in(warmup, steps) / wall,
-            "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
+            "quadrature_points_per_s": m["nq_total"] * couplings_in(warmup, steps) / wall,
+            "contacts_pairs_walls": m["pairs_walls"],
             "tuned": dict(bed_kw, trials=tune_report["trials"],
                           default_ms_per_step=tune_report["default_ms_per_step"]),
-            "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
-                             "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
-                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
-            "errors": int(err or err2), "dtype": "f32 forces / f64 state"}
+            "force_kernel": m["force_kernel"],
+            "errors": m["errors"], "dtype": "f32 forces / f64 state"}
 
 
 def served_stream(n_jobs, warmup, dev, config=None):
