@@ -9,8 +9,8 @@ second per coupling step at these sizes).
   110 steps, crossing re-sorts and neighbour-list rebuilds; also with the
   FP64 path.
 * The 500,000-sphere polydisperse spouted bed, at the defaults and at the
-  tuned values (16 threads per element): priming, one coupling step and ten
-  DEM steps.
+  tuned values (16 threads per element), FP32 and FP64: priming, one
+  coupling step and ten DEM steps.
 
 Contact sets must match bit for bit at every check.  Coupling outputs, which
 depend on the current state only, are held to the single-step bar (1e-5 FP32,
@@ -87,14 +87,14 @@ def spouted():
     return synth.spouted()
 
 
-@pytest.mark.parametrize("cfg", [None, TUNED_SPOUTED])
-def test_spouted_bed_full_size(spouted, cfg):
+@pytest.mark.parametrize("precision,cfg", [("fp32", None), ("fp32", TUNED_SPOUTED), ("fp64", TUNED_SPOUTED)])
+def test_spouted_bed_full_size(spouted, precision, cfg):
     wl = spouted
     kw = dict(resort_every=bench.RESORT_EVERY) if cfg is None else autotune.bed_kwargs(wl, cfg)
-    gb = cfddem.bed_from_workload(wl, precision="fp32", device=torch.device("cuda:0"), **kw)
+    gb = cfddem.bed_from_workload(wl, precision=precision, device=torch.device("cuda:0"), **kw)
     ob, fl = oracle_bed(wl)
     U, P = _fields(wl)
-    tol = TOL["fp32"]
+    tol = TOL[precision]
     compare_contacts(gb, ob, tol)
     _check_coupling(gb, ob, fl, wl, U, P, tol, elem_sums=True)
     gb.step(1)
