@@ -279,9 +279,12 @@ dem_status dem_destroy(dem_ctx *ctx);
  * kernel: each block of a batched kernel finds its bed and its block within
  * the bed in a block map, and the bed's arrays and constants in device
  * tables.  The arithmetic of a bed does not depend on the other beds of the
- * batch.  Requirements: 1..4096 beds, all of the same precision; for
- * coupling, all of the same velocity order and each with fewer than 2^20
- * elements.  While a bed belongs to a batch it must be advanced only through
+ * batch.  Requirements: 1..4096 beds, all of the same precision, lanes and
+ * elem_threads; for coupling, all of the same velocity order and each with
+ * fewer than 2^20 elements.  A bed with the smoothed void fraction has its
+ * field solved on its own mesh within the batch's coupling step (launches
+ * per such bed, before the shared ones, and its quadrature-point values
+ * after them).  While a bed belongs to a batch it must be advanced only through
  * the batch (dem_read_*, dem_poll and dem_kernel_timing stay valid; errors
  * are reported per bed by dem_poll).  Destroying the batch leaves every bed
  * usable on its own.  The same algorithm as dem_step / cfd_dem_couple

@@ -23,6 +23,8 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
 int smooth_blocks(long nv);
 hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *acc,
                           double *b, hipStream_t st);
+hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, const BedRun *run, int bed,
+                              double *acc, double *b, hipStream_t st);
 hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
                                hipStream_t st);
 hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
@@ -1141,6 +1143,7 @@ struct dem_batch {
   Dev *tab = nullptr;
   Cpl *ctab = nullptr;
   CplIO *iot = nullptr;
+  std::vector<CplIO> io_host;  // the same on the host (per-bed smoothing launches)
   BedRun *run = nullptr;
   unsigned *map_drift = nullptr, *map_force = nullptr, *map_class = nullptr, *list = nullptr;
   int *cnt = nullptr;
@@ -1175,7 +1178,6 @@ dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, Batc
     if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes ||
         x->C.elem_threads != beds[0]->C.elem_threads)
       return DEM_E_UNSUPPORTED;
-    if (x->C.smooth) return DEM_E_UNSUPPORTED;  // the smoothing solve runs per bed
     const long long n = x->S.n;
     const int bd = ceil_div(n, 256), bf = ceil_div(n * x->S.lanes, kForceBlock);
     const int ne = x->S.grid.n_elem;
@@ -1257,8 +1259,21 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
 }
 
 dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
+  // beds with the smoothed void fraction: their field first (per bed: each
+  // has its own mesh and transforms), their quadrature-point values after the
+  // shared launches, as a single bed's coupling step orders them
+  for (size_t b = 0; b < B->beds.size(); ++b) {
+    dem_ctx *ctx = B->beds[b];
+    if (!ctx->C.smooth) continue;
+    HIP_TRY(launch_pcm_rhs_run(ctx->B.D, ctx->C, ctx->SO, B->run, (int)b, ctx->B.eps_e, ctx->B.sb, st));
+    HIP_TRY(launch_smooth_solve(ctx->SO, ctx->B.sb, ctx->B.sx, ctx->B.st1, ctx->B.st2, st));
+  }
   HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
                               B->list, B->mode_elems, B->order, B->fp32, B->elem_threads, st));
+  for (size_t b = 0; b < B->beds.size(); ++b) {
+    dem_ctx *ctx = B->beds[b];
+    if (ctx->C.smooth) HIP_TRY(launch_eps_q_field(ctx->SO, ctx->C, ctx->B.sx, B->io_host[b].eps_q, st));
+  }
   return DEM_OK;
 }
 
@@ -1336,7 +1351,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
     iot.push_back(io);
     run.push_back(BedRun{ctx->s, ctx->pending_src});
     if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
-    if (couples) B->mode_elems[cpl_mode_of(ctx->C.drag, ctx->C.shear)] += ctx->S.grid.n_elem;
+    if (couples) B->mode_elems[cpl_mode_of(ctx->C.drag, ctx->C.shear || ctx->C.smooth)] += ctx->S.grid.n_elem;
     const bool roll = ctx->B.D.pp.mu_r > 0.0 || ctx->B.D.pw.mu_r > 0.0;
     fill_map(md, b, ceil_div(ctx->S.n, 256));
     fill_map(roll ? mf_roll : mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
@@ -1360,6 +1375,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
             hipStreamSynchronize(st) == hipSuccess;
   if (!ok) return fail(DEM_E_HIP);
   if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) return fail(DEM_E_HIP);
+  B->io_host = iot;
   *out = B;
   return DEM_OK;
 }

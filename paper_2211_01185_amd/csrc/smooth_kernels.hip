@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void pcm_clear(int n_elem, unsigned long long 
 // One thread per cell: the volumes of its particles in fixed point (2^-50 of
 // the element volume), added to its element's accumulator.  Integer sums do
 // not depend on the order of the additions.
-__global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
+__device__ __forceinline__ void pcm_cells_body(const Dev &D, double Ve, int p2, int p3, unsigned long long *acc) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   const Grid &G = D.grid;
   if (c >= G.ncells) return;
@@ -60,6 +60,18 @@ __global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p
     sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
   }
   atomicAdd(acc + c / G.kk, sum);
+}
+
+__global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
+  pcm_cells_body(D, Ve, p2, p3, acc);
+}
+
+// The same, with the step index read on the device from run[b]: a batch
+// replays its coupling step from a graph while its steps advance there.
+__global__ __launch_bounds__(256) void pcm_cells_run(Dev D, double Ve, const BedRun *__restrict__ run, int b,
+                                                     unsigned long long *acc) {
+  const long long s = run[b].s;
+  pcm_cells_body(D, Ve, (int)(s & 1), (int)(s % 3), acc);
 }
 
 __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned long long *__restrict__ acc,
@@ -169,6 +181,16 @@ hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long lo
 
 // x = A^-1 b: transforms with V^T along x, y, z (the last one scaled by the
 // inverse diagonal), then with V along z, y, x; t1, t2 are scratch vectors.
+// As launch_pcm_rhs for bed b of a batch (step index from run[b]).
+hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, const BedRun *run, int bed,
+                              double *acc, double *b, hipStream_t st) {
+  unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
+  pcm_clear<<<(D.grid.n_elem + 255) / 256, 256, 0, st>>>(D.grid.n_elem, a);
+  pcm_cells_run<<<(D.grid.ncells + 255) / 256, 256, 0, st>>>(D, C.Ve, run, bed, a);
+  smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, a, b);
+  return hipGetLastError();
+}
+
 hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
                                hipStream_t st) {
   const int nb = smooth_blocks(S.nv);

@@ -217,3 +217,64 @@ def test_batch_rejects_mixed_elem_threads():
     with pytest.raises(cfddem.CfddemError) as ei:
         cfddem.Batch(beds)
     assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)
+
+
+def _smoothing_beds():
+    """The Q2 lattices, the first with the smoothed void fraction at
+    L^2 = 5 d^2 (Tables "tab:setup2", "tab:setup4"), the second with the plain
+    projection (L^2 = 0), the third without smoothing (element PCM values)."""
+    a, b, c = _q2_beds()
+    d = 2.0 * float(a.radius[0])
+    a.fluid.update(smooth_L2=5.0 * d * d, model=1)
+    b.fluid.update(smooth_L2=0.0)
+    return [a, b, c]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_smoothed_void_fraction_in_a_batch(precision):
+    """Beds with and without the smoothed void fraction in one batch: two
+    coupling steps with ten DEM steps between, each bed against its oracle
+    (the smoothing solved per bed, its quadrature-point values written after
+    the shared launches)."""
+    wls = _smoothing_beds()
+    beds, fields = _make(wls, precision, resort=(0, 3, 7), elem_threads=16)
+    batch = cfddem.Batch(beds, fields, elem_sums=True)
+    refs = [oracle_bed(w) for w in wls]
+    tol = TOL[precision]
+    for _ in range(2):
+        outs = batch.couple()
+        for w, (ob, fl), o in zip(wls, refs, outs):
+            ref = ob.couple(fl, w.U, w.P, smooth_L2=w.fluid.get("smooth_L2"))
+            assert_close("eps_q", o["eps_q"].cpu().numpy(), ref["eps_q"], 1e-10)
+            assert_close("beta_q", o["beta_q"].cpu().numpy(), ref["beta_q"], tol)
+            assert_close("fpf_q", o["fpf_q"].cpu().numpy(), ref["fpf_q"], tol)
+            assert_close("elem_sums", o["elem_sums"].cpu().numpy()[1:], ref["elem_sums"][1:], tol)
+        for bed, (ob, _) in zip(beds, refs):
+            assert_close("f_fp", gpu_state(bed)["ffp"], ob.state()["ffp"], tol)
+        batch.step(10)
+        for ob, _ in refs:
+            ob.step(10)
+    for bed in beds:
+        assert bed.poll()[0] == 0
+    batch.close()
+
+
+def test_smoothed_void_fraction_alone_equals_mixed_under_graph_replay():
+    """The graph-replayed chunks (coupling step + 10 steps, the step index
+    advancing on the device) give every bed the bits it gets alone."""
+    wls = _smoothing_beds()
+    beds, fields = _make(wls, "fp32", resort=(5, 0, 20))
+    mixed = cfddem.Batch(beds, fields)
+    mixed.run(3, 10, couple=True)
+    mixed_out = [{k: v.cpu().numpy() for k, v in o.items()} for o in mixed.couple()]
+    mixed_state = [_snapshot(b) for b in beds]
+    mixed.close()
+    for j, w in enumerate(wls):
+        bed, fld = _make([w], "fp32", resort=((5, 0, 20)[j],))
+        alone = cfddem.Batch(bed, fld)
+        alone.run(3, 10, couple=True)
+        out = {k: v.cpu().numpy() for k, v in alone.couple()[0].items()}
+        _same(out, mixed_out[j])
+        _same(_snapshot(bed[0]), mixed_state[j])
+        alone.close()
+

@@ -467,14 +467,3 @@ def test_coupling_step_with_smoothed_void_fraction(L2, order, precision, elem_th
         gb.step(10)
         ob.step(10)
     assert gb.poll()[0] == 0
-
-
-def test_batches_reject_the_smoothed_void_fraction():
-    from paper_2211_01185_amd import cfddem
-    wl = _workload("lattice")
-    wl.fluid["smooth_L2"] = 5 * 3e-3 ** 2
-    gb = gpu_bed(wl, "fp64")
-    with pytest.raises(cfddem.CfddemError) as ei:
-        cfddem.Batch([gb], [_fields(wl)])
-    # refused by the workspace query (no size for such a batch) or by creation
-    assert ei.value.status in (cfddem.DEM_E_UNSUPPORTED, cfddem.DEM_E_ARG)
