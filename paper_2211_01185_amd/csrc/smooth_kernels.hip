@@ -16,7 +16,7 @@
 //                  fixed point (2^-50 of the element volume), so the sum does
 //                  not depend on the order of the cell slots or of the cells
 //   smooth_rhs     b_i = sum over the elements around node i of eps_e int phi_i
-//   fd_transform   the 1D transforms of the solve
+//   fd_transform   the 1D transforms of the solve (FP64 MFMA products)
 //   eps_q_field    eps_h at every quadrature point
 #include "device.h"
 
@@ -44,22 +44,33 @@ __global__ __launch_bounds__(256) void pcm_clear(int n_elem, unsigned long long 
 
 // One thread per cell: the volumes of its particles in fixed point (2^-50 of
 // the element volume), added to its element's accumulator.  Integer sums do
-// not depend on the order of the additions.
+// not depend on the order of the additions.  The cells of an element are
+// consecutive, so the lanes of a wavefront first sum their values per element
+// (a segmented scan over the shuffles) and one lane per element adds.
 __device__ __forceinline__ void pcm_cells_body(const Dev &D, double Ve, int p2, int p3, unsigned long long *acc) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   const Grid &G = D.grid;
-  if (c >= G.ncells) return;
-  int m = sel(D.cnt, p3)[c];
-  if (m > D.cap) m = D.cap;
-  if (m == 0) return;
-  const int *sl = sel(D.slot, p2) + (size_t)c * D.cap;
-  const double scale = 0x1p50 / Ve;
   unsigned long long sum = 0;
-  for (int s = 0; s < m; ++s) {
-    const double r = D.rad[sl[s]];
-    sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
+  if (c < G.ncells) {
+    int m = sel(D.cnt, p3)[c];
+    if (m > D.cap) m = D.cap;
+    const int *sl = sel(D.slot, p2) + (size_t)c * D.cap;
+    const double scale = 0x1p50 / Ve;
+    for (int s = 0; s < m; ++s) {
+      const double r = D.rad[sl[s]];
+      sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
+    }
   }
-  atomicAdd(acc + c / G.kk, sum);
+  const int key = c / G.kk;  // past the last cell: keys no cell has, with sum 0
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long v = __shfl_up(sum, off, 64);
+    const int k = __shfl_up(key, off, 64);
+    if (lane >= off && k == key) sum += v;
+  }
+  const int next = __shfl_down(key, 1, 64);
+  if ((lane == 63 || next != key) && sum != 0 && c < G.ncells) atomicAdd(acc + key, sum);
 }
 
 __global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
@@ -117,51 +128,190 @@ __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned lon
 // (K_a, M_a) (V^T M V = I, V^T K V = diag(lam_a)), so
 //     A^-1 = (Vx Vy Vz) diag(1 / (1 + L^2 (lam_x + lam_y + lam_z))) (Vx Vy Vz)^T
 // and the solve is three 1D transforms with V^T, the diagonal scaling, and
-// three with V.  One pass: out[.., i, ..] = sum_j T[i][j] in[.., j, ..] along
-// axis a (T = V^T or V, n_a x n_a row-major), optionally scaled by the
-// diagonal.
-__global__ __launch_bounds__(kSB) void fd_transform(SmoothOp S, int axis, const double *__restrict__ T,
-                                                    const double *__restrict__ in, double *__restrict__ out,
-                                                    int scale) {
-  const long i = (long)blockIdx.x * kSB + threadIdx.x;
-  if (i >= S.nv) return;
-  int g[3];
-  node_xyz(S, i, g[0], g[1], g[2]);
-  const int n = S.nn[axis];
-  const long stride = axis == 0 ? 1L : (axis == 1 ? (long)S.nn[0] : (long)S.nn[0] * S.nn[1]);
-  const int gi = axis == 0 ? g[0] : (axis == 1 ? g[1] : g[2]);
-  const double *line = in + (i - gi * stride);
-  const double *row = T + (size_t)gi * n;
-  double v = 0.0;
-  for (int j = 0; j < n; ++j) v += row[j] * line[j * stride];
-  if (scale) v /= 1.0 + S.L2 * (S.lam[0][g[0]] + S.lam[1][g[1]] + S.lam[2][g[2]]);
-  out[i] = v;
+// three with V.  One pass applies T (V^T or V, n x n row-major, n = nodes
+// along the axis) to every line of the lattice along that axis:
+// out[line c, i] = sum_j T[i][j] in[line c, j], optionally scaled by the
+// diagonal: a (n x n) x (n x lines) product on the FP64 matrix cores.  A block
+// of four wavefronts computes kTI outputs along the axis for kTC lines; each
+// wavefront a 16 x 32 part of it as two 16 x 16 tiles of
+// v_mfma_f64_16x16x4f64 (zero padding past n adds exact zeros).  The next
+// kTK-wide chunk of T and of the lines is loaded into registers while the
+// current one is summed, and the result tile is staged through LDS, so that
+// loads and stores follow the order of memory on every axis (along the line
+// for x, across lines otherwise).
+namespace {
+constexpr int kTI = 32, kTC = 64, kTK = 64, kTT = 256;
+constexpr int kAL = kTI * kTK / kTT, kBL = kTK * kTC / kTT, kOL = kTI * kTC / kTT;  // per thread
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int AX>
+__device__ inline long line_base(const SmoothOp &S, int c) {
+  if (AX == 0) return (long)c * S.nn[0];
+  if (AX == 1) return (long)(c % S.nn[0]) + (long)(c / S.nn[0]) * S.nn[0] * S.nn[1];
+  return (long)c;
 }
 
-// eps_h at every quadrature point: thread per point, element-major numbering.
-__global__ __launch_bounds__(256) void eps_q_field(SmoothOp S, Cpl C, const double *__restrict__ eps_nodes,
-                                                   double *__restrict__ eps_q) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  const long ne = (long)S.n_el[0] * S.n_el[1] * S.n_el[2];
-  if (t >= ne * C.nq) return;
-  const long e = t / C.nq;
-  const int q = (int)(t % C.nq);
-  const int p = S.order, p1 = p + 1;
-  const int qx = q % p1, qy = (q / p1) % p1, qz = q / (p1 * p1);
-  const int ex = (int)(e % S.n_el[0]), ey = (int)((e / S.n_el[0]) % S.n_el[1]),
-            ez = (int)(e / ((long)S.n_el[0] * S.n_el[1]));
-  double v = 0.0;
-  for (int ic = 0; ic < p1; ++ic) {
-    double acc_c = 0.0;
-    for (int ib = 0; ib < p1; ++ib) {
-      double acc_b = 0.0;
-      const double *row = eps_nodes + ((long)(p * ez + ic) * S.nn[1] + (p * ey + ib)) * S.nn[0] + p * ex;
-      for (int ia = 0; ia < p1; ++ia) acc_b += C.Lq[ia][qx] * row[ia];
-      acc_c += C.Lq[ib][qy] * acc_b;
-    }
-    v += C.Lq[ic][qz] * acc_c;
+template <int AX>
+__device__ inline long axis_stride(const SmoothOp &S) {
+  return AX == 0 ? 1L : (AX == 1 ? (long)S.nn[0] : (long)S.nn[0] * S.nn[1]);
+}
+
+// Position of element e of a K x Q tile (k along the axis, q across lines)
+// in the order of memory.
+template <int AX, int K, int Q>
+__device__ inline void tile_pos(int e, int &k, int &q) {
+  if (AX == 0) {
+    k = e % K;
+    q = e / K;
+  } else {
+    k = e / Q;
+    q = e % Q;
   }
-  eps_q[t] = v;
+}
+}  // namespace
+
+template <int AX>
+__global__ __launch_bounds__(kTT) void fd_transform(SmoothOp S, const double *__restrict__ T,
+                                                    const double *__restrict__ in, double *__restrict__ out,
+                                                    int scale) {
+  __shared__ double As[kTI][kTK + 1];
+  __shared__ double Bs[kTK][kTC + 1];
+  __shared__ double Os[kTI][kTC + 1];
+  const int n = S.nn[AX];
+  const int lines = (int)(S.nv / n);
+  const int i0 = blockIdx.y * kTI, c0 = blockIdx.x * kTC;
+  const int t = threadIdx.x;
+  const long stride = axis_stride<AX>(S);
+  // the lines this thread loads, fixed over the chunks
+  long bb[kBL];
+#pragma unroll
+  for (int m = 0; m < kBL; ++m) {
+    int k, q;
+    tile_pos<AX, kTK, kTC>(t + kTT * m, k, q);
+    bb[m] = c0 + q < lines ? line_base<AX>(S, c0 + q) : -1;
+  }
+  double ar[kAL], br[kBL];
+  auto load = [&](int j0) {
+#pragma unroll
+    for (int m = 0; m < kAL; ++m) {
+      const int e = t + kTT * m, r = e / kTK, j = j0 + e % kTK;
+      ar[m] = (i0 + r < n && j < n) ? T[(size_t)(i0 + r) * n + j] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kBL; ++m) {
+      int k, q;
+      tile_pos<AX, kTK, kTC>(t + kTT * m, k, q);
+      const int j = j0 + k;
+      br[m] = (bb[m] >= 0 && j < n) ? in[bb[m] + (long)j * stride] : 0.0;
+    }
+  };
+  // this wavefront's part: rows wr .. wr+15, lines wc .. wc+31; the lane's
+  // operand row / line lr and k offset lk (A: T[row][k], B: line tile[k][line])
+  const int lane = t & 63, w = t >> 6;
+  const int wr = 16 * (w & 1), wc = 32 * (w >> 1);
+  const int lr = lane & 15, lk = lane >> 4;
+  dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int j0 = 0; j0 < n; j0 += kTK) {
+#pragma unroll
+    for (int m = 0; m < kAL; ++m) {
+      const int e = t + kTT * m;
+      As[e / kTK][e % kTK] = ar[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kBL; ++m) {
+      int k, q;
+      tile_pos<AX, kTK, kTC>(t + kTT * m, k, q);
+      Bs[k][q] = br[m];
+    }
+    __syncthreads();
+    if (j0 + kTK < n) load(j0 + kTK);
+    const int kmax = min(kTK, n - j0);
+    for (int kk = 0; kk < kmax; kk += 4) {
+      const double av = As[wr + lr][kk + lk];
+      const double b0 = Bs[kk + lk][wc + lr], b1 = Bs[kk + lk][wc + 16 + lr];
+      d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, d1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // result r of a lane: row wr + 4 r + lane / 16, line wc + lane % 16 (+ 16 for d1)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Os[wr + 4 * r + lk][wc + lr] = d0[r];
+    Os[wr + 4 * r + lk][wc + 16 + lr] = d1[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kOL; ++m) {
+    int k, q;
+    tile_pos<AX, kTI, kTC>(t + kTT * m, k, q);
+    const int i = i0 + k, c = c0 + q;
+    if (i >= n || c >= lines) continue;
+    double v = Os[k][q];
+    if (scale) {
+      const int nx = S.nn[0], ny = S.nn[1];
+      int g[3];
+      if (AX == 0) {
+        g[0] = i; g[1] = c % ny; g[2] = c / ny;
+      } else if (AX == 1) {
+        g[0] = c % nx; g[1] = i; g[2] = c / nx;
+      } else {
+        g[0] = c % nx; g[1] = c / nx; g[2] = i;
+      }
+      v /= 1.0 + S.L2 * (S.lam[0][g[0]] + S.lam[1][g[1]] + S.lam[2][g[2]]);
+    }
+    out[line_base<AX>(S, c) + (long)i * stride] = v;
+  }
+}
+
+// eps_h at every quadrature point, element-major numbering: one thread per
+// element evaluates the tensor-product interpolation of its (ORD+1)^3 nodal
+// values at its (ORD+1)^3 Gauss points (sums over x, then y, then z), staged
+// through LDS so that the block writes its points contiguously.
+template <int ORD>
+__global__ __launch_bounds__(64) void eps_q_field(SmoothOp S, Cpl C, const double *__restrict__ eps_nodes,
+                                                  double *__restrict__ eps_q, int ne) {
+  constexpr int P1 = ORD + 1, NQ = P1 * P1 * P1;
+  __shared__ double out_s[64 * NQ];
+  const int e0 = blockIdx.x * 64, e = e0 + threadIdx.x;
+  if (e < ne) {
+    const int ex = e % S.n_el[0], ey = (e / S.n_el[0]) % S.n_el[1], ez = e / (S.n_el[0] * S.n_el[1]);
+    double nod[P1][P1][P1], L[P1][P1];
+#pragma unroll
+    for (int ic = 0; ic < P1; ++ic)
+#pragma unroll
+      for (int ib = 0; ib < P1; ++ib) {
+        const double *row = eps_nodes + ((long)(ORD * ez + ic) * S.nn[1] + (ORD * ey + ib)) * S.nn[0] + ORD * ex;
+#pragma unroll
+        for (int ia = 0; ia < P1; ++ia) nod[ic][ib][ia] = row[ia];
+      }
+#pragma unroll
+    for (int a = 0; a < P1; ++a)
+#pragma unroll
+      for (int i = 0; i < P1; ++i) L[a][i] = C.Lq[a][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
+      double v = 0.0;
+#pragma unroll
+      for (int ic = 0; ic < P1; ++ic) {
+        double acc_c = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < P1; ++ib) {
+          double acc_b = 0.0;
+#pragma unroll
+          for (int ia = 0; ia < P1; ++ia) acc_b += L[ia][qx] * nod[ic][ib][ia];
+          acc_c += L[ib][qy] * acc_b;
+        }
+        v += L[ic][qz] * acc_c;
+      }
+      out_s[threadIdx.x * NQ + q] = v;
+    }
+  }
+  __syncthreads();
+  const int cnt = min(64, ne - e0) * NQ;
+  for (int k = threadIdx.x; k < cnt; k += 64) eps_q[(long)e0 * NQ + k] = out_s[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -191,22 +341,29 @@ hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, con
   return hipGetLastError();
 }
 
+static dim3 fd_grid(const SmoothOp &S, int axis) {
+  const long n = S.nn[axis], lines = S.nv / n;
+  return dim3((unsigned)((lines + kTC - 1) / kTC), (unsigned)((n + kTI - 1) / kTI));
+}
+
 hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
                                hipStream_t st) {
-  const int nb = smooth_blocks(S.nv);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 0, S.Vt[0], b, t1, 0);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 1, S.Vt[1], t1, t2, 0);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 2, S.Vt[2], t2, t1, 1);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 2, S.V[2], t1, t2, 0);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 1, S.V[1], t2, t1, 0);
-  fd_transform<<<nb, kSB, 0, st>>>(S, 0, S.V[0], t1, x, 0);
+  fd_transform<0><<<fd_grid(S, 0), kTT, 0, st>>>(S, S.Vt[0], b, t1, 0);
+  fd_transform<1><<<fd_grid(S, 1), kTT, 0, st>>>(S, S.Vt[1], t1, t2, 0);
+  fd_transform<2><<<fd_grid(S, 2), kTT, 0, st>>>(S, S.Vt[2], t2, t1, 1);
+  fd_transform<2><<<fd_grid(S, 2), kTT, 0, st>>>(S, S.V[2], t1, t2, 0);
+  fd_transform<1><<<fd_grid(S, 1), kTT, 0, st>>>(S, S.V[1], t2, t1, 0);
+  fd_transform<0><<<fd_grid(S, 0), kTT, 0, st>>>(S, S.V[0], t1, x, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
                               hipStream_t st) {
-  const long nq = (long)S.n_el[0] * S.n_el[1] * S.n_el[2] * C.nq;
-  eps_q_field<<<(int)((nq + 255) / 256), 256, 0, st>>>(S, C, eps_nodes, eps_q);
+  const int ne = S.n_el[0] * S.n_el[1] * S.n_el[2];
+  if (S.order == 1)
+    eps_q_field<1><<<(ne + 63) / 64, 64, 0, st>>>(S, C, eps_nodes, eps_q, ne);
+  else
+    eps_q_field<2><<<(ne + 63) / 64, 64, 0, st>>>(S, C, eps_nodes, eps_q, ne);
   return hipGetLastError();
 }
 
