@@ -861,6 +861,13 @@ template <int NT>
 constexpr int block_threads() {
   return NT < kWave ? kWave : NT;
 }
+// Wavefronts per SIMD the element kernels are compiled for: 3 (168 VGPRs) for
+// Di Felice alone; 2 (256 VGPRs) for the general closures, the shear force and
+// the smoothed void fraction, whose extra state would otherwise spill.
+template <int MODE>
+constexpr int occ_waves() {
+  return MODE == 0 ? 3 : 2;
+}
 template <int NT>
 int occ_grid(long long elems) {
   const long long b = (elems + elems_per_block<NT>() - 1) / elems_per_block<NT>();
@@ -872,7 +879,7 @@ int occ_grid(long long elems) {
 // block per mesh element would cost more than the work).  Longer lists are
 // strided over the grid.
 template <typename R, int ORD, int MODE, int NT>
-__global__ __launch_bounds__(block_threads<NT>(), 3) void couple_occupied(Dev D, Cpl C, int p2, int p3,
+__global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple_occupied(Dev D, Cpl C, int p2, int p3,
                                                                             int parity,
                                                                             const double *__restrict__ U,
                                                                             const double *__restrict__ P,
@@ -939,7 +946,7 @@ __device__ __forceinline__ void couple_listed(const Dev *__restrict__ tab, const
 }
 
 template <typename R, int ORD, int MODE, int NT>
-__global__ __launch_bounds__(block_threads<NT>(), 3) void couple_occupied_batch(
+__global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple_occupied_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const int *cnt_word, const unsigned *list, long long cap) {
   constexpr int kG = elems_per_block<NT>();
