@@ -12,7 +12,7 @@
 // so it is diagonalized by the generalized eigenvectors of the 1D pairs
 // (K_a, M_a) (fast diagonalization): the solve is exact up to rounding, six
 // 1D transforms and a diagonal scaling, with no iteration and no history.
-//   pcm_cells      the particle volumes of each element summed exactly in
+//   pcm_elems      the particle volumes of each element summed exactly in
 //                  fixed point (2^-50 of the element volume), so the sum does
 //                  not depend on the order of the cell slots or of the cells
 //   smooth_rhs     b_i = sum over the elements around node i of eps_e int phi_i
@@ -36,53 +36,41 @@ __device__ inline void node_xyz(const SmoothOp &S, long i, int &gx, int &gy, int
 
 }  // namespace
 
-// Zeroes the fixed-point solid-volume accumulators of the elements.
-__global__ __launch_bounds__(256) void pcm_clear(int n_elem, unsigned long long *acc) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e < n_elem) acc[e] = 0ull;
-}
-
-// One thread per cell: the volumes of its particles in fixed point (2^-50 of
-// the element volume), added to its element's accumulator.  Integer sums do
-// not depend on the order of the additions.  The cells of an element are
-// consecutive, so the lanes of a wavefront first sum their values per element
-// (a segmented scan over the shuffles) and one lane per element adds.
-__device__ __forceinline__ void pcm_cells_body(const Dev &D, double Ve, int p2, int p3, unsigned long long *acc) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
+// One wavefront per element: the volumes of the particles in its cells (kk
+// consecutive cells) in fixed point, 2^-50 of the element volume, summed over
+// the lanes and written once.  Integer sums do not depend on the order of the
+// additions, and nothing needs clearing first.
+__device__ __forceinline__ void pcm_elems_body(const Dev &D, double Ve, int p2, int p3, unsigned long long *acc) {
   const Grid &G = D.grid;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (e >= G.n_elem) return;  // whole wavefronts
+  const double scale = 0x1p50 / Ve;
   unsigned long long sum = 0;
-  if (c < G.ncells) {
+  for (int i = lane; i < G.kk; i += 64) {
+    const int c = e * G.kk + i;
     int m = sel(D.cnt, p3)[c];
     if (m > D.cap) m = D.cap;
     const int *sl = sel(D.slot, p2) + (size_t)c * D.cap;
-    const double scale = 0x1p50 / Ve;
     for (int s = 0; s < m; ++s) {
       const double r = D.rad[sl[s]];
       sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
     }
   }
-  const int key = c / G.kk;  // past the last cell: keys no cell has, with sum 0
-  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long v = __shfl_up(sum, off, 64);
-    const int k = __shfl_up(key, off, 64);
-    if (lane >= off && k == key) sum += v;
-  }
-  const int next = __shfl_down(key, 1, 64);
-  if ((lane == 63 || next != key) && sum != 0 && c < G.ncells) atomicAdd(acc + key, sum);
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if (lane == 0) acc[e] = sum;
 }
 
-__global__ __launch_bounds__(256) void pcm_cells(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
-  pcm_cells_body(D, Ve, p2, p3, acc);
+__global__ __launch_bounds__(256) void pcm_elems(Dev D, double Ve, int p2, int p3, unsigned long long *acc) {
+  pcm_elems_body(D, Ve, p2, p3, acc);
 }
 
 // The same, with the step index read on the device from run[b]: a batch
 // replays its coupling step from a graph while its steps advance there.
-__global__ __launch_bounds__(256) void pcm_cells_run(Dev D, double Ve, const BedRun *__restrict__ run, int b,
+__global__ __launch_bounds__(256) void pcm_elems_run(Dev D, double Ve, const BedRun *__restrict__ run, int b,
                                                      unsigned long long *acc) {
   const long long s = run[b].s;
-  pcm_cells_body(D, Ve, (int)(s & 1), (int)(s % 3), acc);
+  pcm_elems_body(D, Ve, (int)(s & 1), (int)(s % 3), acc);
 }
 
 __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned long long *__restrict__ acc,
@@ -323,8 +311,7 @@ hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long lo
                           double *b, hipStream_t st) {
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
-  pcm_clear<<<(D.grid.n_elem + 255) / 256, 256, 0, st>>>(D.grid.n_elem, a);
-  pcm_cells<<<(D.grid.ncells + 255) / 256, 256, 0, st>>>(D, C.Ve, p2, p3, a);
+  pcm_elems<<<(D.grid.n_elem + 3) / 4, 256, 0, st>>>(D, C.Ve, p2, p3, a);
   smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, a, b);
   return hipGetLastError();
 }
@@ -335,8 +322,7 @@ hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long lo
 hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, const BedRun *run, int bed,
                               double *acc, double *b, hipStream_t st) {
   unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
-  pcm_clear<<<(D.grid.n_elem + 255) / 256, 256, 0, st>>>(D.grid.n_elem, a);
-  pcm_cells_run<<<(D.grid.ncells + 255) / 256, 256, 0, st>>>(D, C.Ve, run, bed, a);
+  pcm_elems_run<<<(D.grid.n_elem + 3) / 4, 256, 0, st>>>(D, C.Ve, run, bed, a);
   smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, a, b);
   return hipGetLastError();
 }

@@ -438,6 +438,26 @@ def test_coupling_step_with_shear_force(drag, order, model, precision, elem_thre
     compare_states(gb, ob, 10 * tol)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_smoothed_void_fraction_on_a_long_axis(axis):
+    """The smoothed void fraction where one axis has 125 velocity nodes (Q2, 62
+    elements): its 1D transforms span two 64-wide chunks, four row tiles and
+    ragged line tiles.  eps_q and f_fp against the oracle, FP64."""
+    n_side = [6, 6, 6]
+    n_side[axis] = 250
+    wl = _noisy_field(synth.lattice(n_side=tuple(n_side), seed_index=5), 2)
+    assert wl.fluid["n_el"][axis] * 2 + 1 > 2 * 64 - 8
+    wl.fluid.update(smooth_L2=5 * 3e-3 ** 2, model=1)
+    gb = gpu_bed(wl, "fp64")
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    out = gb.couple(U, P)
+    ref = ob.couple(fl, wl.U, wl.P, smooth_L2=wl.fluid["smooth_L2"])
+    assert_close("eps_q", out["eps_q"].cpu().numpy(), ref["eps_q"], 1e-10)
+    assert_close("f_fp", gpu_state(gb)["ffp"], ob.state()["ffp"], TOL["fp64"])
+    assert gb.poll()[0] == 0
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("L2", [0.0, 4 * 3e-3 ** 2, 5 * 3e-3 ** 2])  # 4 d^2, 5 d^2 of Tables 2, 4
