@@ -155,7 +155,10 @@ typedef struct {
                       particle.  Solved directly at every coupling step (the
                       matrix is a Kronecker sum of 1D mass and stiffness
                       matrices, diagonalized at creation by their generalized
-                      eigenvectors).  Not supported in batches.
+                      eigenvectors).  In a batch, each bed with it runs
+                      its own solve inside the batch's coupling step.  A
+                      velocity lattice of more than 2^31 - 1 nodes is
+                      rejected (DEM_E_ARG).
                       0: element PCM values (eps_q constant per element) */
   double smooth_L2; /* smoothing length squared (m^2), >= 0 (0: the plain
                        projection) */

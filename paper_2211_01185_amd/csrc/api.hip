@@ -235,6 +235,7 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
   for (int a = 0; a < 3; ++a)
     if (G.he[a] < dp->d_max) return DEM_E_UNSUPPORTED;
   if (ncells > 0x7fffffffLL || n_elem > 0x7fffffffLL) return DEM_E_ARG;
+  if (S.smooth && S.nv > 0x7fffffffL) return DEM_E_ARG;  // the transforms index lattice lines with int
   G.kk = G.k[0] * G.k[1] * G.k[2];
   G.n_elem = (int)n_elem;
   G.ncells = (int)ncells;
