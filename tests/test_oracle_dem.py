@@ -1,6 +1,8 @@
 """Pins of the oracle's DEM step against facts that do not come from its code:
-brute-force contact search, Hertz contact theory, rigid-body kinematics,
-Newton's third law and exact free fall."""
+brute-force contact search, Hertz contact theory, rigid-body kinematics
+(including the spin terms of a pair's contact-point velocity and the
+tangential overlap kept in the turning tangent plane), Newton's third law,
+the pair's angular momentum and exact free fall."""
 import math
 
 import numpy as np
@@ -277,3 +279,156 @@ def test_domain_and_nan_errors(oracle_mod):
     bed = O.OracleBed(p, np.array([[0.5], [0.5], [0.5]]), v, np.zeros((3, 1)), np.full(1, 1e-3),
                       np.full(1, 2500.0))
     assert bed.error & O.ERR_NAN
+
+
+# ---------------------------------------------------------------- spin of both partners
+# The relative velocity of the contact point of a pair, v_ij = v_i - v_j +
+# (R_i w_i + R_j w_j) x n (contact-force equation), is rigid-body kinematics:
+# the contact point of i moves with v_i + w_i x (R_i n), that of j with
+# v_j + w_j x (-R_j n).  Pins that do not use the force law's constants:
+#  * a spin of i alone is equivalent to a translation v_i = R_i w_i x n, a spin
+#    of j alone to v_i = R_j w_j x n (same contact-point velocity, so the same
+#    force and torques at creation, where the tangential force is the dashpot
+#    of that velocity);
+#  * meshing spins R_i w_i + R_j w_j = 0 slide nothing: no tangential force;
+#  * equal co-rotating spins of equal spheres are braked on both.
+def _pair(O, x, v, w, r, dt=1e-6, mu=0.3, e=0.9):
+    p = O.make_params([0, 0, 0], [0.05, 0.05, 0.05], [0, 0, 0], dt, 1e6, 0.3, e, mu)
+    return O.OracleBed(p, np.asarray(x, float), np.asarray(v, float), np.asarray(w, float),
+                       np.asarray(r, float), np.full(len(r), 2500.0))
+
+
+def _oblique_pair(ri=1.5e-3, rj=1.0e-3, overlap=2e-5):
+    n = np.array([1.0, 0.3, -0.2])
+    n /= np.linalg.norm(n)
+    xi = np.array([0.02, 0.025, 0.025])
+    xj = xi + (ri + rj - overlap) * n
+    return np.stack([xi, xj], axis=1), n, np.array([ri, rj])
+
+
+@pytest.mark.parametrize("who", [0, 1])
+def test_spin_equals_equivalent_translation(oracle_mod, who):
+    O = oracle_mod
+    x, n, r = _oblique_pair()
+    spin = np.cross(n, [0.0, 0.0, 1.0])
+    spin = 40.0 * spin / np.linalg.norm(spin) + 7.0 * n  # a twist along n adds nothing
+    w = np.zeros((3, 2))
+    w[:, who] = spin
+    v_eq = np.zeros((3, 2))
+    v_eq[:, 0] = r[who] * np.cross(spin, n)
+    a = _pair(O, x, np.zeros((3, 2)), w, r, mu=10.0)  # below the Coulomb limit
+    b = _pair(O, x, v_eq, np.zeros((3, 2)), r, mu=10.0)
+    sa, sb = a.state(), b.state()
+    tan = sa["Fc"] - np.outer(n, n @ sa["Fc"])
+    assert np.linalg.norm(tan[:, 0]) > 1e-3 * np.linalg.norm(sa["Fc"][:, 0])  # a real tangential force
+    scale = np.abs(sa["Fc"]).max()
+    assert np.allclose(sa["Fc"], sb["Fc"], rtol=0, atol=1e-12 * scale)
+    assert np.allclose(sa["Tc"], sb["Tc"], rtol=0, atol=1e-12 * np.abs(sa["Tc"]).max())
+
+
+def test_meshing_spins_slide_nothing(oracle_mod):
+    O = oracle_mod
+    x, n, r = _oblique_pair()
+    axis = np.cross(n, [0.0, 1.0, 0.0])
+    axis /= np.linalg.norm(axis)
+    w = np.stack([30.0 * axis, -30.0 * r[0] / r[1] * axis], axis=1)
+    a = _pair(O, x, np.zeros((3, 2)), w, r)
+    st = a.state()
+    tan = st["Fc"] - np.outer(n, n @ st["Fc"])
+    assert np.abs(tan).max() <= 1e-12 * np.abs(st["Fc"]).max()
+    assert np.abs(st["Tc"]).max() <= 1e-12 * r[0] * np.abs(st["Fc"]).max()
+    # and stepping keeps them meshing: no torque builds up
+    a.step(50)
+    st = a.state()
+    assert np.abs(st["Tc"]).max() <= 1e-9 * r[0] * np.abs(st["Fc"]).max()
+
+
+def test_co_rotating_spins_are_braked(oracle_mod):
+    O = oracle_mod
+    x, n, r = _oblique_pair(ri=1.5e-3, rj=1.5e-3)
+    axis = np.cross(n, [0.0, 1.0, 0.0])
+    axis /= np.linalg.norm(axis)
+    w = np.stack([30.0 * axis, 30.0 * axis], axis=1)
+    a = _pair(O, x, np.zeros((3, 2)), w, r)
+    for _ in range(5):
+        a.step(20)
+        st = a.state()
+        for k in range(2):
+            assert st["Tc"][:, k] @ w[:, k] < 0.0  # each spin is opposed
+        assert np.allclose(st["Tc"][:, 0], st["Tc"][:, 1], rtol=1e-12)  # equal lever arms, same n x f_t
+        # the tangential force on i opposes the contact point's motion w x (R n)
+        ft = st["Fc"][:, 0] - n * (n @ st["Fc"][:, 0])
+        assert ft @ np.cross(w[:, 0], n) < 0.0
+
+
+# ---------------------------------------------------------------- tangential history on a turning normal
+def _oblique_impact(O, spin=True):
+    """Two unequal spheres meeting off-centre with spins: the contact normal
+    turns while they touch, and the tangential spring sticks part of the time."""
+    ri, rj = 1.5e-3, 1.1e-3
+    c = 0.025
+    b = 0.6 * (ri + rj)  # impact parameter
+    gap = 1e-6
+    x = np.array([[c - 0.5 * math.sqrt((ri + rj + gap) ** 2 - b * b), c + 0.5 * math.sqrt((ri + rj + gap) ** 2 - b * b)],
+                  [c - 0.5 * b, c + 0.5 * b], [c, c + 1e-4]])
+    v = np.array([[0.02, -0.02], [0.0, 0.0], [0.0, 0.001]])
+    w = np.array([[0.0, 3.0], [-5.0, 0.0], [10.0, -4.0]]) if spin else np.zeros((3, 2))
+    return _pair(O, x, v, w, np.array([ri, rj]), dt=1e-6, mu=0.5, e=0.8)
+
+
+def test_tangential_overlap_stays_in_the_current_tangent_plane(oracle_mod):
+    O = oracle_mod
+    bed = _oblique_impact(O)
+    seen = 0
+    n0 = None
+    turned = 0.0
+    for _ in range(3000):
+        bed.step(1)
+        i, j, dt = bed.contacts()
+        if i.size == 0:
+            if seen:
+                break
+            continue
+        st = bed.state()
+        d = st["x"][:, j[0]] - st["x"][:, i[0]]
+        n = d / np.linalg.norm(d)
+        n0 = n if n0 is None else n0
+        turned = max(turned, math.acos(min(1.0, float(n @ n0))))
+        mag = np.linalg.norm(dt[0])
+        assert abs(dt[0] @ n) <= 1e-12 * max(mag, 1e-30)
+        seen += 1
+    assert seen > 100
+    assert turned > 0.01  # the normal really turned (radians)
+
+
+def test_pair_angular_momentum_about_the_centre_of_mass(oracle_mod):
+    # Forces are exactly opposite; the torques R_i n x f_t and R_j n x f_t and
+    # the moment of the pair force about the centre of mass, -|d| n x f_t, sum
+    # to (R_i + R_j - |d|) n x f_t: total angular momentum changes only at the
+    # order of the overlap over the radius.  A sign slip in a torque or a
+    # lever arm breaks it at order one.
+    O = oracle_mod
+    bed = _oblique_impact(O)
+    st = bed.state()
+    m = 2500.0 * 4.0 / 3.0 * math.pi * np.array([1.5e-3, 1.1e-3]) ** 3
+    inertia = 0.4 * m * np.array([1.5e-3, 1.1e-3]) ** 2
+
+    def ang(st):
+        com = (st["x"] * m).sum(axis=1) / m.sum()
+        L = np.zeros(3)
+        for k in range(2):
+            L += m[k] * np.cross(st["x"][:, k] - com, st["v"][:, k]) + inertia[k] * st["w"][:, k]
+        return L
+
+    L0, spin0 = ang(st), [inertia[k] * st["w"][:, k] for k in range(2)]
+    max_dn = 0.0
+    for _ in range(3000):
+        bed.step(1)
+        i, _, _ = bed.contacts()
+        s = bed.state()
+        dist = np.linalg.norm(s["x"][:, 1] - s["x"][:, 0])
+        max_dn = max(max_dn, 2.6e-3 - dist)
+    st = bed.state()
+    dspin = sum(np.linalg.norm(inertia[k] * st["w"][:, k] - spin0[k]) for k in range(2))
+    assert dspin > 1e-3 * np.linalg.norm(L0)  # the contact exchanged real spin
+    assert np.linalg.norm(ang(st) - L0) <= 2.0 * (max_dn / 1.1e-3) * dspin + 1e-12 * np.linalg.norm(L0)

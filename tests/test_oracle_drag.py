@@ -17,9 +17,16 @@ and of the beta_B = beta_A / eps option (Eq. "beta").
   the drag handed to the fluid equals minus the particles' drag), and
   beta_B = beta_A / eps scales every particle's drag by 1/eps of its element.
 
-Parity unpinned: the eps-dependence of Rong's exponent and of Beetstra's
-Reynolds term away from these limits (the printed Beetstra bracket is
-unbalanced; the reading is stated in cfddem_oracle.c)."""
+* Voidage exponents measured at a fixed particle Reynolds number (where the
+  Re factor cancels): Di Felice's chi(Re) at its minimum 10^1.5 (3.05), at
+  10^(1.5 +- sqrt 2) and 10^2.5 (the Gaussian's width), its symmetry in
+  log10 Re and its 3.7 limits, for several eps; Rong's exponent at full,
+  1/e and vanishing bump, for several eps.
+* Beetstra: the lone-sphere correlation at eps = 1, the dense Stokes limit
+  10 eps_p/eps^2 + eps^2 (1 + 1.5 sqrt(eps_p)), the Reynolds term at the
+  Re where its denominator is exactly 2, and its large-Re asymptote (the
+  printed bracket is unbalanced; the reading is stated in
+  cfddem_oracle.c)."""
 import math
 
 import numpy as np
@@ -126,3 +133,95 @@ def test_beta_over_eps_scales_the_drag(drag):
     assert np.allclose(rb["elem_sums"][2][occ], ra["elem_sums"][2][occ] / eps[occ], rtol=1e-12)
     # the pressure-gradient and buoyancy parts are untouched
     assert np.array_equal(rb["elem_sums"][9:12], ra["elem_sums"][9:12])
+
+
+# ---------------------------------------------------------------- voidage exponents
+# At a fixed particle Reynolds number the (0.63 + 4.8/sqrt(Re))^2 factor is
+# the same for every eps, and the slip that gives that Re is mu Re/(rho eps d),
+# so beta(eps)/beta(1) = eps^(x - 1) with x the voidage exponent of C_D.  The
+# exponent measured that way isolates the exponent alone; its expected values
+# at the points below follow from the printed constants only:
+#  * Di Felice, x = 2 - chi(Re), chi = 3.7 - 0.65 exp(-(1.5 - log10 Re)^2 / 2):
+#    chi(10^1.5) = 3.05 (the minimum), chi symmetric in log10 Re about 1.5,
+#    chi(10^(1.5 +- sqrt 2)) = 3.7 - 0.65/e, chi(10^2.5) = 3.7 - 0.65 e^(-1/2),
+#    chi -> 3.7 far from 10^1.5 (whichever eps);
+#  * Rong, x = 2 - [2.65 (eps + 1) - (5.3 - 3.5 eps) eps^2 B(Re)], with the
+#    same Gaussian bump B: B = 1 at Re = 10^1.5, 1/e at 10^(1.5 +- sqrt 2),
+#    0 far away.
+def _slip_at(Re, eps):
+    return Re * MU / (RHO * eps * D)
+
+
+def _measured_exponent(drag, Re, eps):
+    b = O.drag_beta(drag, RHO, MU, eps, D, _slip_at(Re, eps))
+    b1 = O.drag_beta(drag, RHO, MU, 1.0, D, _slip_at(Re, 1.0))
+    return math.log(b / b1) / math.log(eps) + 1.0
+
+
+@pytest.mark.parametrize("eps", [0.42, 0.6, 0.85])
+def test_difelice_exponent_minimum_and_width(eps):
+    chi = lambda Re: 2.0 - _measured_exponent("difelice", Re, eps)
+    assert chi(10 ** 1.5) == pytest.approx(3.05, abs=1e-11)
+    for a in (math.sqrt(2.0), -math.sqrt(2.0)):
+        assert chi(10 ** (1.5 + a)) == pytest.approx(3.7 - 0.65 / math.e, abs=1e-11)
+    assert chi(10 ** 2.5) == pytest.approx(3.7 - 0.65 * math.exp(-0.5), abs=1e-11)
+    # far from the bump in both directions
+    assert chi(10 ** (1.5 + 12)) == pytest.approx(3.7, abs=1e-11)
+    assert chi(10 ** (1.5 - 12)) == pytest.approx(3.7, abs=1e-11)
+
+
+@pytest.mark.parametrize("a", [0.3, 0.77, 1.9])
+def test_difelice_exponent_symmetric_in_log_re(a):
+    up = _measured_exponent("difelice", 10 ** (1.5 + a), 0.55)
+    down = _measured_exponent("difelice", 10 ** (1.5 - a), 0.55)
+    assert up == pytest.approx(down, abs=1e-11)
+    # and the bump lowers chi below its limit, i.e. raises the exponent
+    assert up > 2.0 - 3.7
+
+
+@pytest.mark.parametrize("eps", [0.42, 0.6, 0.85])
+def test_rong_exponent_at_full_and_vanishing_bump(eps):
+    bracket0 = 2.65 * (eps + 1.0)
+    bump_coef = (5.3 - 3.5 * eps) * eps * eps
+    assert _measured_exponent("rong", 10 ** 1.5, eps) == pytest.approx(2.0 - bracket0 + bump_coef, abs=1e-11)
+    assert _measured_exponent("rong", 10 ** (1.5 + math.sqrt(2.0)), eps) == pytest.approx(
+        2.0 - bracket0 + bump_coef / math.e, abs=1e-11)
+    for far in (12, -12):
+        assert _measured_exponent("rong", 10 ** (1.5 + far), eps) == pytest.approx(2.0 - bracket0, abs=1e-11)
+
+
+# ---------------------------------------------------------------- Beetstra
+# beta = 3 pi mu d eps F (the slip read as the velocity), so F = beta/(3 pi mu d eps).
+def _beetstra_F(eps, Re):
+    slip = _slip_at(Re, eps) if Re > 0 else 0.0
+    return O.drag_beta("beetstra", RHO, MU, eps, D, slip) / (STOKES * eps)
+
+
+@pytest.mark.parametrize("Re", [0.01, 1.0, 20.0, 300.0, 1000.0])
+def test_beetstra_lone_sphere(Re):
+    # eps = 1 (eps_p = 0): F = 1 + 0.413 Re/24 (1 + 8.4 Re^-0.343)/(1 + Re^-1/2)
+    want = 1.0 + 0.413 * Re / 24.0 * (1.0 + 8.4 * Re ** -0.343) / (1.0 + Re ** -0.5)
+    assert _beetstra_F(1.0, Re) == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("eps", [0.35, 0.5, 0.7, 0.9])
+def test_beetstra_dense_stokes_limit(eps):
+    ep = 1.0 - eps
+    # creeping flow through an array: only the Reynolds-free part remains
+    want = 10.0 * ep / eps ** 2 + eps ** 2 * (1.0 + 1.5 * math.sqrt(ep))
+    assert _beetstra_F(eps, 0.0) == pytest.approx(want, rel=1e-12)
+    assert _beetstra_F(eps, 1e-9) == pytest.approx(want, rel=1e-6)
+
+
+@pytest.mark.parametrize("eps", [0.35, 0.5, 0.7, 0.9])
+def test_beetstra_reynolds_term(eps):
+    ep = 1.0 - eps
+    low = 10.0 * ep / eps ** 2 + eps ** 2 * (1.0 + 1.5 * math.sqrt(ep))
+    # at Re* = 10^(6 eps_p / (1 + 4 eps_p)) the denominator's second term is
+    # 10^(3 eps_p) Re*^(-(1 + 4 eps_p)/2) = 1, so the denominator is exactly 2
+    Re = 10 ** (6.0 * ep / (1.0 + 4.0 * ep))
+    want = low + 0.413 * Re / (24 * eps ** 2) * (1 / eps + 3 * ep * eps + 8.4 * Re ** -0.343) / 2.0
+    assert _beetstra_F(eps, Re) == pytest.approx(want, rel=1e-12)
+    # very large Re: F / Re -> 0.413 / (24 eps^2) (1/eps + 3 eps_p eps)
+    Re = 1e20
+    assert _beetstra_F(eps, Re) / Re == pytest.approx(0.413 / (24 * eps ** 2) * (1 / eps + 3 * ep * eps), rel=1e-6)
