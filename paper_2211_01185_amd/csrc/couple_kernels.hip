@@ -93,8 +93,33 @@ struct Tr<float> {
 //                 fluid velocity)
 //   5 Gidaspow    Ergun (eps < 0.8) or Wen-Yu (eps >= 0.8) per unit mixture
 //                 volume, times V_p / (1 - eps)
+//
+// The piecewise closures choose a branch by comparing eps, eps_p or Re with a
+// threshold, and the branches do not meet there (Gidaspow's two laws differ
+// by O(1) at eps = 0.8).  The choice is made once in FP64 by closure_branches
+// and passed in as bits, so that the FP32 path takes the branch the FP64
+// definition takes; only the arithmetic inside a branch runs in R.
+enum : unsigned {
+  kBrMoving = 1,     // slip > 0 (else every Re-dependent factor takes its limit)
+  kBrKochHillLo = 2, // Koch-Hill: eps_p < 0.4 (the rational F0)
+  kBrErgun = 4,      // Gidaspow: eps < 0.8 (Ergun; else Wen-Yu)
+  kBrReLo = 8        // Gidaspow, Wen-Yu: Re < 1000 (else C_D = 0.44)
+};
+__device__ inline unsigned closure_branches(double rho_f, double mu_f, double eps, double d,
+                                            double slip) {
+#pragma clang fp contract(off)
+  unsigned b = 0;
+  // R = float: a slip that vanishes in single precision takes the zero-slip
+  // limit, which the moving form approaches continuously
+  if (slip > 0.0 && (float)slip > 0.0f && (float)(rho_f * eps * slip * d / mu_f) > 0.0f) b |= kBrMoving;
+  if (1.0 - eps < 0.4) b |= kBrKochHillLo;
+  if (eps < 0.8) b |= kBrErgun;
+  if (rho_f * eps * slip * d / mu_f < 1000.0) b |= kBrReLo;
+  return b;
+}
+
 template <typename R>
-__device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
+__device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip, unsigned br) {
   using T = Tr<R>;
   const R r = R(0.5) * d;
   const R area = R(kPi) * r * r;
@@ -102,7 +127,7 @@ __device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
   const R ep = R(1) - eps;
   const R inv_mu = T::rcp_(mu_f);
   const R Re = rho_f * eps * slip * d * inv_mu;
-  const bool moving = slip > R(0);
+  const bool moving = (br & kBrMoving) != 0;
   switch (drag) {
     case 0:
     case 1:
@@ -129,7 +154,7 @@ __device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
     }
     case 3: {
       R F0;
-      if (ep < R(0.4)) {
+      if (br & kBrKochHillLo) {
         const R lnterm = ep > R(0) ? R(135.0 / 64.0) * ep * T::log_(ep) : R(0);
         F0 = (R(1) + R(3) * sqrt(ep * R(0.5)) + lnterm + R(16.14) * ep) /
              (R(1) + R(0.681) * ep - R(8.48) * ep * ep + R(8.14) * ep * ep * ep);
@@ -151,10 +176,10 @@ __device__ inline R drag_beta(int drag, R rho_f, R mu_f, R eps, R d, R slip) {
       return R(3.0 * kPi) * mu_f * d * eps * F;
     }
     default: {  // 5
-      if (eps < R(0.8)) return vp * (R(150) * ep * mu_f / (eps * d * d) + R(1.75) * rho_f * slip / d);
+      if (br & kBrErgun) return vp * (R(150) * ep * mu_f / (eps * d * d) + R(1.75) * rho_f * slip / d);
       R cds;  // C_D |slip|; zero slip: 24 mu_f / (rho_f eps d)
       if (moving)
-        cds = (Re < R(1000) ? R(24) * T::rcp_(Re) * (R(1) + R(0.15) * T::pow_(Re, R(0.687))) : R(0.44)) * slip;
+        cds = ((br & kBrReLo) ? R(24) * T::rcp_(Re) * (R(1) + R(0.15) * T::pow_(Re, R(0.687))) : R(0.44)) * slip;
       else
         cds = R(24) * mu_f * T::rcp_(rho_f * eps * d);
       return vp * R(0.75) * cds * eps * rho_f / d * T::pow_(eps, R(-2.65));
@@ -291,12 +316,12 @@ __device__ inline void div_tau(const double xi[3], const double (*sU)[27], const
 // any closure, 2 for any closure with the shear force, so that each path
 // keeps only the code and registers it needs.
 template <typename R>
-__device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip) {
+__device__ inline R difelice_beta(R rho_f, R mu_f, R eps, R d, R slip, unsigned br) {
   using T = Tr<R>;
   const R r = R(0.5) * d;
   const R area = R(kPi) * r * r;
   R cds, expo;
-  if (slip > R(0)) {
+  if (br & kBrMoving) {
     const R Re = rho_f * eps * slip * d * T::rcp_(mu_f);
     const R root = R(0.63) + R(4.8) * T::rsqrt_(Re);
     const R lg = R(1.5) - T::log10_(Re);
@@ -384,8 +409,9 @@ __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const i
     }
     eps_c = fmin(1.0, fmax(ev, C.eps_min));
   }
-  double beta = GEN ? (double)drag_beta<R>(C.drag, R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip))
-                    : (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip));
+  const unsigned br = closure_branches(C.rho_f, C.mu_f, eps_c, 2.0 * r, slip);
+  double beta = GEN ? (double)drag_beta<R>(C.drag, R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip), br)
+                    : (double)difelice_beta<R>(R(C.rho_f), R(C.mu_f), R(eps_c), R(2.0 * r), R(slip), br);
   if (C.beta_over_eps) beta /= eps_c;  // beta_B = beta_A / eps (Eq. "beta")
   // shear force -V_p div tau (Eqs. "fa", "fb"), when enabled; added as a
   // separate term, so that a bed without it computes the same arithmetic in

@@ -487,3 +487,98 @@ def test_coupling_step_with_smoothed_void_fraction(L2, order, precision, elem_th
         gb.step(10)
         ob.step(10)
     assert gb.poll()[0] == 0
+
+
+# ---------------------------------------------------------------- closure branches at their thresholds
+ULP = 2.0 ** -24  # spacing of single-precision values in [0.5, 1)
+
+
+def _threshold_workload(eps_targets, slips, smooth_L2=None, drag="gidaspow"):
+    """One sphere at the centre of each element of a 4 x 4 x 2 mesh of 4 mm
+    elements (no contacts, no wall contacts, no gravity), its radius chosen so
+    that its element's fluid fraction is the given target, its velocity so
+    that its slip in still water is the given one.  Elements past the targets
+    stay empty.  In water (rho 1000, mu 1e-3) a slip of Re mu/(rho eps d)
+    gives particle Reynolds number Re."""
+    n_el = [4, 4, 2]
+    h = 4e-3
+    lo, hi = [0.0, 0.0, 0.0], [n_el[0] * h, n_el[1] * h, n_el[2] * h]
+    Ve = h ** 3
+    n = len(eps_targets)
+    assert n <= n_el[0] * n_el[1] * n_el[2] and len(slips) == n
+    k = np.arange(n)
+    x = np.stack([((k % 4) + 0.5) * h, (((k // 4) % 4) + 0.5) * h, ((k // 16) + 0.5) * h])
+    r = np.cbrt(3.0 * Ve * (1.0 - np.asarray(eps_targets)) / (4.0 * np.pi))
+    v = np.zeros((3, n))
+    v[2] = -np.asarray(slips)
+    fluid = dict(order=2, n_el=n_el, rho_f=1000.0, mu_f=1e-3, model=0, eps_min=0.1, drag=drag)
+    if smooth_L2 is not None:
+        fluid["smooth_L2"] = smooth_L2
+    U = np.zeros((3, synth.node_grid(lo, hi, n_el, 2).shape[1]))
+    P = np.zeros(synth.node_grid(lo, hi, n_el, 1).shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, 0.0], dt=1e-5, E=1e6, nu=0.3, e=0.9, mu=0.3,
+               E_w=1e6, nu_w=0.3, e_w=0.9, mu_w=0.3)
+    return synth.Workload("thresholds", x, v, np.zeros((3, n)), r, np.full(n, 2500.0), dem, fluid,
+                          dict(steps=1, coupling_every=1, precision="fp32"), U, P)
+
+
+def _slip_for_re(Re, eps, d):
+    return Re * 1e-3 / (1000.0 * eps * d)
+
+
+def _per_particle_drag_check(wl, precision, smooth_L2=None):
+    gb = gpu_bed(wl, precision)
+    ob, fl = oracle_bed(wl)
+    U, P = _fields(wl)
+    gb.couple(U, P)
+    ref = ob.couple(fl, wl.U, wl.P, smooth_L2=smooth_L2)
+    assert gb.poll()[0] == 0 and ref["err"] == 0
+    g, o = gpu_state(gb)["ffp"], ob.state()["ffp"]
+    # particle by particle: a branch taken differently is off by >= 0.5 %
+    rel = np.abs(g - o).max(axis=0) / np.abs(o).max(axis=0)
+    assert rel.max() <= TOL[precision], f"worst particle {rel.argmax()}: {rel.max():.3e}"
+    return ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("drag,threshold", [("gidaspow", 0.8), ("koch_hill", 0.6)])
+def test_closure_branch_at_the_void_fraction_threshold(drag, threshold, precision):
+    """Gidaspow switches law at eps = 0.8 and Koch-Hill at eps_p = 0.4
+    (Section 2.3.2); fluid fractions within a single-precision ulp of the
+    switch (some round onto it in FP32) take the FP64 definition's branch."""
+    offs = [-3, -2, -1, -0.5, -0.25, 0, 0.25, 0.5, 1, 2, 3]
+    eps = [threshold + j * ULP for j in offs]
+    wl = _threshold_workload(eps, [0.05] * len(eps), drag=drag)
+    ref = _per_particle_drag_check(wl, precision)
+    got = 1.0 - ref["elem_sums"][1][:len(eps)] / 64e-9
+    assert np.allclose(got, eps, rtol=0, atol=1e-15)  # the fractions are where they were put
+    assert (got < threshold).any() and (got > threshold).any()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gidaspow_branch_at_reynolds_1000(precision):
+    """Gidaspow's Wen-Yu C_D switches to 0.44 at Re = 1000: slips putting Re
+    within single-precision rounding of 1000 take the FP64 definition's
+    branch."""
+    offs = [-4, -2, -1, -0.5, -0.25, 0.25, 0.5, 1, 2, 4]
+    eps = 0.9
+    d = 2.0 * np.cbrt(3.0 * 64e-9 * (1.0 - eps) / (4.0 * np.pi))
+    slips = [_slip_for_re(1000.0 * (1.0 + 2 * j * ULP), eps, d) for j in offs]
+    wl = _threshold_workload([eps] * len(offs), slips)
+    _per_particle_drag_check(wl, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("L2", [0.0, 5 * 3e-3 ** 2])
+@pytest.mark.parametrize("drag,threshold,j", [("gidaspow", 0.8, -0.5), ("gidaspow", 0.8, -0.25),
+                                              ("gidaspow", 0.8, 0.25), ("koch_hill", 0.6, -0.25),
+                                              ("koch_hill", 0.6, 0.25), ("koch_hill", 0.6, 0.5)])
+def test_closure_branch_at_the_threshold_with_smoothing(drag, threshold, j, L2, precision):
+    """With the smoothed void fraction the closure sees the continuous field at
+    the particle; a uniform element field is reproduced by the projection
+    (natural boundary conditions), so every particle sits within a fraction
+    of a single-precision ulp of the switch."""
+    eps = threshold + j * ULP
+    wl = _threshold_workload([eps] * 32, [0.05] * 32, smooth_L2=L2, drag=drag)
+    ref = _per_particle_drag_check(wl, precision, smooth_L2=L2)
+    assert np.abs(ref["eps_nodes"] - eps).max() < 0.1 * ULP
