@@ -23,8 +23,8 @@ hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call
 int smooth_blocks(long nv);
 hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long long s, double *acc,
                           double *b, hipStream_t st);
-hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, const BedRun *run, int bed,
-                              double *acc, double *b, hipStream_t st);
+hipError_t launch_pcm_rhs_run(const Dev *tab, int n_elem, const Cpl &C, const SmoothOp &S, const BedRun *run,
+                              int bed, double *acc, double *b, hipStream_t st);
 hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, double *t1, double *t2,
                                hipStream_t st);
 hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
@@ -1266,7 +1266,8 @@ dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
   for (size_t b = 0; b < B->beds.size(); ++b) {
     dem_ctx *ctx = B->beds[b];
     if (!ctx->C.smooth) continue;
-    HIP_TRY(launch_pcm_rhs_run(ctx->B.D, ctx->C, ctx->SO, B->run, (int)b, ctx->B.eps_e, ctx->B.sb, st));
+    HIP_TRY(launch_pcm_rhs_run(B->tab, ctx->S.grid.n_elem, ctx->C, ctx->SO, B->run, (int)b, ctx->B.eps_e,
+                               ctx->B.sb, st));
     HIP_TRY(launch_smooth_solve(ctx->SO, ctx->B.sb, ctx->B.sx, ctx->B.st1, ctx->B.st2, st));
   }
   HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,

@@ -65,12 +65,14 @@ __global__ __launch_bounds__(256) void pcm_elems(Dev D, double Ve, int p2, int p
   pcm_elems_body(D, Ve, p2, p3, acc);
 }
 
-// The same, with the step index read on the device from run[b]: a batch
-// replays its coupling step from a graph while its steps advance there.
-__global__ __launch_bounds__(256) void pcm_elems_run(Dev D, double Ve, const BedRun *__restrict__ run, int b,
+// The same for bed b of a batch, with the bed's arrays and step index read on
+// the device (tab[b], run[b]): a batch replays its coupling step from a graph
+// while its steps advance and its re-sorts swap its per-particle arrays.
+__global__ __launch_bounds__(256) void pcm_elems_run(const Dev *__restrict__ tab, double Ve,
+                                                     const BedRun *__restrict__ run, int b,
                                                      unsigned long long *acc) {
   const long long s = run[b].s;
-  pcm_elems_body(D, Ve, (int)(s & 1), (int)(s % 3), acc);
+  pcm_elems_body(tab[b], Ve, (int)(s & 1), (int)(s % 3), acc);
 }
 
 __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned long long *__restrict__ acc,
@@ -319,10 +321,10 @@ hipError_t launch_pcm_rhs(const Dev &D, const Cpl &C, const SmoothOp &S, long lo
 // x = A^-1 b: transforms with V^T along x, y, z (the last one scaled by the
 // inverse diagonal), then with V along z, y, x; t1, t2 are scratch vectors.
 // As launch_pcm_rhs for bed b of a batch (step index from run[b]).
-hipError_t launch_pcm_rhs_run(const Dev &D, const Cpl &C, const SmoothOp &S, const BedRun *run, int bed,
-                              double *acc, double *b, hipStream_t st) {
+hipError_t launch_pcm_rhs_run(const Dev *tab, int n_elem, const Cpl &C, const SmoothOp &S, const BedRun *run,
+                              int bed, double *acc, double *b, hipStream_t st) {
   unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
-  pcm_elems_run<<<(D.grid.n_elem + 3) / 4, 256, 0, st>>>(D, C.Ve, run, bed, a);
+  pcm_elems_run<<<(n_elem + 3) / 4, 256, 0, st>>>(tab, C.Ve, run, bed, a);
   smooth_rhs<<<smooth_blocks(S.nv), kSB, 0, st>>>(S, a, b);
   return hipGetLastError();
 }

@@ -278,3 +278,45 @@ def test_smoothed_void_fraction_alone_equals_mixed_under_graph_replay():
         _same(_snapshot(bed[0]), mixed_state[j])
         alone.close()
 
+
+
+def _polydisperse_smoothed_bed(seed_index=11):
+    """A contact-heavy lattice whose radii vary by up to 10 % (so that element
+    volumes depend on which particle is where), with the smoothed void
+    fraction at L^2 = 5 d^2."""
+    w = synth.lattice(n_side=(8, 8, 9), seed_index=seed_index)
+    rng = np.random.default_rng(1234 + seed_index)
+    w.radius = w.radius * rng.uniform(0.9, 1.0, size=w.radius.shape)
+    d = 2.0 * float(w.radius.max())
+    w.fluid.update(smooth_L2=5.0 * d * d, model=1)
+    return w
+
+
+def test_polydisperse_smoothed_bed_under_graph_replay_across_resorts():
+    """Re-sorts swap a bed's per-particle arrays; the replayed coupling graph
+    must read the bed's current arrays (radii in the new order), so graph
+    replay equals the same launches issued one by one, bit for bit, across
+    several re-sorts, and the void fraction stays the oracle's."""
+    w = _polydisperse_smoothed_bed()
+    beds_a, fields_a = _make([w], "fp64", resort=(5,))
+    beds_b, fields_b = _make([w], "fp64", resort=(5,))
+    a = cfddem.Batch(beds_a, fields_a, elem_sums=True)
+    b = cfddem.Batch(beds_b, fields_b, elem_sums=True)
+    ob, fl = oracle_bed(w)
+    a.run(3, 10, couple=True)
+    for _ in range(3):
+        b.couple()
+        b.step(10)
+        ob.couple(fl, w.U, w.P, smooth_L2=w.fluid["smooth_L2"])
+        ob.step(10)
+    _same(_snapshot(beds_a[0]), _snapshot(beds_b[0]))
+    oa = {k: v.cpu().numpy() for k, v in a.couple()[0].items()}
+    obb = {k: v.cpu().numpy() for k, v in b.couple()[0].items()}
+    _same(oa, obb)
+    ref = ob.couple(fl, w.U, w.P, smooth_L2=w.fluid["smooth_L2"])
+    assert_close("eps_q", oa["eps_q"], ref["eps_q"], 1e-10)
+    assert_close("elem_sums", oa["elem_sums"][1:], ref["elem_sums"][1:], 1e-10)
+    assert_close("f_fp", gpu_state(beds_a[0])["ffp"], ob.state()["ffp"], 1e-10)
+    assert beds_a[0].poll()[0] == 0
+    a.close()
+    b.close()
