@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define CFDDEM_ABI_VERSION 4
+#define CFDDEM_ABI_VERSION 5
 
 typedef struct dem_ctx dem_ctx;
 typedef int32_t dem_status;
@@ -254,6 +254,39 @@ dem_status dem_read_cells(dem_ctx *ctx, int32_t *elem, int32_t *cell, int32_t *k
  * the total count, which may exceed cap (then only cap are written). */
 dem_status dem_read_contacts(dem_ctx *ctx, int64_t *pairs, double *delta_t, int64_t cap,
                              int64_t *n_out, void *stream);
+
+/* ---- Checkpoint / resume ----
+ *
+ * A checkpoint is the complete state that a DEM step and a coupling step
+ * read (Sections 2.2 and 2.3): positions, velocities and angular velocities
+ * of the last completed step, the stored contact force and torque, the held
+ * fluid force, radii and masses, every contact's tangential overlap
+ * (particle pairs and walls) with the neighbour lists that carry it, the
+ * positions of the last broad search, the step and coupling-call counters
+ * and the internal particle order.  Restoring it into a context created with
+ * the same structural parameters (n, max_neighbors, cell_capacity,
+ * precision, skin and the mesh/box) and then running the same calls gives
+ * the same results bit for bit as the run that wrote it.  The blob is plain
+ * bytes (no pointers): it may be copied to the host, stored and brought back.
+ *
+ * Bytes of a checkpoint of this context (host function; 0 for NULL). */
+size_t dem_checkpoint_bytes(dem_ctx *ctx);
+
+/* Write the checkpoint into dst: device memory of >= dem_checkpoint_bytes
+ * bytes, 256-byte aligned, owned by the caller.  Synchronizes the stream.
+ * Returns the sticky error (and writes nothing) for a poisoned context,
+ * DEM_E_WORKSPACE when bytes is too small. */
+dem_status dem_read_checkpoint(dem_ctx *ctx, void *dst, size_t bytes, void *stream);
+
+/* Restore a checkpoint (device memory, 256-byte aligned, as written by
+ * dem_read_checkpoint) into ctx, replacing its whole state.  ctx must have
+ * been created with the same structural parameters as the context that wrote
+ * it (else DEM_E_ARG; DEM_E_ABI for a blob of another library version) and
+ * must not belong to a batch.  Material constants, the time step, gravity,
+ * the fluid parameters and the tuning choices (lanes, threads per element,
+ * re-sort interval) are the context's own.  Synchronizes the stream; src may
+ * be reused once the call returns. */
+dem_status dem_write_state(dem_ctx *ctx, const void *src, size_t bytes, void *stream);
 
 /* Synchronizes the stream; reports the sticky device error (0 or a negative
  * DEM_E_* code, host out) and the number of contacts of the last evaluation

@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libcfddem.so")
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 DEM_OK = 0
 DEM_E_ARG = -1
@@ -33,6 +33,7 @@ DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
+           "dem_checkpoint_bytes", "dem_read_checkpoint", "dem_write_state",
 
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
@@ -102,6 +103,12 @@ def load():
     lib.dem_read_contacts.argtypes = [vp, vp, vp, i64, C.POINTER(i64), vp]
     lib.dem_poll.restype = i32
     lib.dem_poll.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), vp]
+    lib.dem_checkpoint_bytes.restype = C.c_size_t
+    lib.dem_checkpoint_bytes.argtypes = [vp]
+    lib.dem_read_checkpoint.restype = i32
+    lib.dem_read_checkpoint.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.dem_write_state.restype = i32
+    lib.dem_write_state.argtypes = [vp, vp, C.c_size_t, vp]
     lib.dem_kernel_timing.restype = i32
     lib.dem_kernel_timing.argtypes = [vp, i32]
     lib.dem_kernel_timing_read.restype = i32
@@ -310,6 +317,31 @@ class Bed:
         pairs = pairs[:, :m].cpu().numpy()
         dt = dt[:, :m].cpu().numpy()
         return pairs[0], pairs[1], dt.T.copy()
+
+    def checkpoint(self):
+        """The bed's full state as a uint8 device tensor (dem_read_checkpoint)."""
+        torch = self._torch
+        nbytes = int(self._lib.dem_checkpoint_bytes(self._h))
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        blob = buf[off:off + nbytes]
+        _check(self._lib.dem_read_checkpoint(self._h, C.c_void_p(blob.data_ptr()), C.c_size_t(nbytes), self._st),
+               "dem_read_checkpoint")
+        return blob
+
+    def restore(self, blob):
+        """Replace the bed's state by a checkpoint (a uint8 tensor on any
+        device, as returned by checkpoint(); copied to a 256-byte aligned
+        device buffer first when needed)."""
+        torch = self._torch
+        nbytes = int(blob.numel())
+        if blob.device != self.device or blob.data_ptr() % 256:
+            buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-buf.data_ptr()) % 256
+            buf[off:off + nbytes].copy_(blob)
+            blob = buf[off:off + nbytes]
+        _check(self._lib.dem_write_state(self._h, C.c_void_p(blob.data_ptr()), C.c_size_t(nbytes), self._st),
+               "dem_write_state")
 
     def poll(self):
         """(sticky_error, n_contacts); synchronizes the stream."""

@@ -652,6 +652,38 @@ __global__ void k_contact_write(Dev D, int lb, const long long *off, long long c
 
 inline int blocks(int n, int b) { return (n + b - 1) / b; }
 
+// Device words of a context restored from a checkpoint: the list buffer the
+// next step reads, the sticky error bits; broad-search flags and the
+// occupied-element counters start cleared.
+__global__ void k_restore_words(int *err, int lb_word, int cur, int bits) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int i = 0; i < 3; ++i) err[kFlagWord + i] = 0;
+  err[kOccWord] = 0;
+  err[kOccWord + 1] = 0;
+  err[kLbufWord + lb_word] = cur;
+  err[0] = bits;
+}
+
+// Checkpoint blob: a 256-byte header, then the state arrays in the context's
+// internal (cell-sorted) order, each at a 256-byte aligned offset.
+constexpr uint64_t kCkptMagic = 0x4b43424d45444643ULL;  // "CFDEMBCK"
+constexpr int kCkptVersion = 1;
+struct CkptHeader {
+  uint64_t magic;
+  int32_t abi, version;
+  int64_t n;
+  int32_t maxn, lbuf;       // neighbour-list capacity; list buffer of the next step
+  int32_t since_sort, err;  // steps since the last re-sort; sticky error bits
+  int64_t s, n_couple;      // completed steps; coupling calls issued
+  uint64_t shape;           // hash of the structural parameters
+};
+static_assert(sizeof(CkptHeader) <= 256, "checkpoint header");
+
+struct Span {
+  void *p;
+  size_t bytes;
+};
+
 dem_status err_to_status(int bits) {
   if (bits & kErrNan) return DEM_E_NAN;
   if (bits & kErrDomain) return DEM_E_DOMAIN;
@@ -675,6 +707,7 @@ struct dem_ctx {
   dem_status poisoned = DEM_OK;
   bool timing = false;
   SmoothOp SO{};           // smoothed void fraction operator (smooth = 1)
+  int in_batch = 0;        // batches holding this bed
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   size_t ev_used = 0;
 };
@@ -737,7 +770,153 @@ static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool con
   return DEM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// checkpoints
+// ---------------------------------------------------------------------------
+// The structural parameters a checkpoint depends on (array sizes, the meaning
+// of the neighbour lists and of the cell indices), hashed (FNV-1a) over their
+// values.
+static uint64_t ckpt_shape(const dem_ctx *ctx) {
+  uint64_t h = 1469598103934665603ULL;
+  auto mix = [&h](const void *p, size_t b) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < b; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ULL;
+    }
+  };
+  const Sizes &S = ctx->S;
+  const int32_t ints[4] = {S.n, S.maxn, S.cap, ctx->fp32 ? 1 : 0};
+  mix(ints, sizeof ints);
+  mix(&S.skin, sizeof S.skin);
+  mix(S.grid.lo, sizeof S.grid.lo);
+  mix(S.grid.hi, sizeof S.grid.hi);
+  mix(S.grid.n_el, sizeof S.grid.n_el);
+  mix(S.grid.k, sizeof S.grid.k);
+  return h;
+}
+
+// The arrays of a checkpoint, in the context's internal order: positions of
+// the last completed step, boundary velocities, stored contact force and
+// torque, held fluid force, radii, masses, positions at the last broad
+// search, original IDs, wall contacts and their history, and the neighbour
+// list (buffer cur) with its touching masks and tangential history.
+static int ckpt_spans(dem_ctx *ctx, int cur, Span *sp) {
+  Dev &D = ctx->B.D;
+  const size_t n = (size_t)D.n, mn = (size_t)D.maxn * n;
+  int k = 0;
+  sp[k++] = {D.xs[ctx->s & 1], 24 * n};
+  sp[k++] = {D.v, 24 * n};
+  sp[k++] = {D.w, 24 * n};
+  sp[k++] = {D.Fc, 24 * n};
+  sp[k++] = {D.Tc, 24 * n};
+  sp[k++] = {D.ffp, 24 * n};
+  sp[k++] = {D.rad, 8 * n};
+  sp[k++] = {D.mass, 8 * n};
+  sp[k++] = {D.xb, 24 * n};
+  sp[k++] = {D.oid, 4 * n};
+  sp[k++] = {D.wmask, n};
+  sp[k++] = {D.whdt, 8 * 3 * kWalls * n};
+  sp[k++] = {D.ln[cur], 4 * n};
+  sp[k++] = {D.nbr[cur], 8 * mn};
+  sp[k++] = {D.hmask[cur], 8 * n};
+  sp[k++] = {D.hdt[cur], 24 * mn};
+  return k;
+}
+
+static size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+static size_t ckpt_size(dem_ctx *ctx) {
+  Span sp[24];
+  const int k = ckpt_spans(ctx, 0, sp);
+  size_t off = kAlign;  // header
+  for (int i = 0; i < k; ++i) off = align_up(off) + sp[i].bytes;
+  return align_up(off);
+}
+
 extern "C" {
+
+size_t dem_checkpoint_bytes(dem_ctx *ctx) { return ctx ? ckpt_size(ctx) : 0; }
+
+dem_status dem_read_checkpoint(dem_ctx *ctx, void *dst, size_t bytes, void *stream) {
+  if (!ctx || !dst || ((uintptr_t)dst % kAlign) != 0) return DEM_E_ARG;
+  if (bytes < ckpt_size(ctx)) return DEM_E_WORKSPACE;
+  if (ctx->poisoned) return ctx->poisoned;
+  hipStream_t st = (hipStream_t)stream;
+  Dev &D = ctx->B.D;
+  int words[2] = {0, 0};  // list buffer of the next step, sticky error bits
+  HIP_TRY(hipMemcpyAsync(&words[0], D.lbuf + (ctx->s + 1) % 3, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&words[1], D.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (err_to_status(words[1]) != DEM_OK) {
+    ctx->poisoned = err_to_status(words[1]);
+    return ctx->poisoned;
+  }
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.abi = CFDDEM_ABI_VERSION;
+  h.version = kCkptVersion;
+  h.n = ctx->S.n;
+  h.maxn = ctx->S.maxn;
+  h.lbuf = words[0];
+  h.since_sort = ctx->since_sort;
+  h.err = words[1];
+  h.s = ctx->s;
+  h.n_couple = ctx->n_couple;
+  h.shape = ckpt_shape(ctx);
+  char *out = static_cast<char *>(dst);
+  HIP_TRY(hipMemcpyAsync(out, &h, sizeof h, hipMemcpyHostToDevice, st));
+  Span sp[24];
+  const int k = ckpt_spans(ctx, h.lbuf, sp);
+  size_t off = kAlign;
+  for (int i = 0; i < k; ++i) {
+    off = align_up(off);
+    HIP_TRY(hipMemcpyAsync(out + off, sp[i].p, sp[i].bytes, hipMemcpyDeviceToDevice, st));
+    off += sp[i].bytes;
+  }
+  HIP_TRY(hipStreamSynchronize(st));  // the header lives on this call's stack
+  return DEM_OK;
+}
+
+dem_status dem_write_state(dem_ctx *ctx, const void *src, size_t bytes, void *stream) {
+  if (!ctx || !src || ((uintptr_t)src % kAlign) != 0 || bytes < kAlign) return DEM_E_ARG;
+  if (ctx->in_batch) return DEM_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  CkptHeader h{};
+  HIP_TRY(hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.magic != kCkptMagic || h.abi != CFDDEM_ABI_VERSION || h.version != kCkptVersion) return DEM_E_ABI;
+  if (h.n != ctx->S.n || h.maxn != ctx->S.maxn || h.shape != ckpt_shape(ctx) || h.lbuf < 0 || h.lbuf > 1 ||
+      h.s < 0 || h.n_couple < 0 || h.since_sort < 0)
+    return DEM_E_ARG;
+  if (bytes < ckpt_size(ctx)) return DEM_E_WORKSPACE;
+  Dev &D = ctx->B.D;
+  // empty every cell grid (at the cells the context's particles were binned
+  // into), then take the checkpoint's arrays, then bin its positions into
+  // the grid of its step: the grid of a completed step is the only one that
+  // holds particles between calls, and the order of the particles in a cell's
+  // slots is not part of the result
+  for (int b = 0; b < 3; ++b) HIP_TRY(launch_clear_grid(D, b, st));
+  ctx->s = h.s;
+  Span sp[24];
+  const int k = ckpt_spans(ctx, h.lbuf, sp);
+  const char *in = static_cast<const char *>(src);
+  size_t off = kAlign;
+  for (int i = 0; i < k; ++i) {
+    off = align_up(off);
+    HIP_TRY(hipMemcpyAsync(sp[i].p, in + off, sp[i].bytes, hipMemcpyDeviceToDevice, st));
+    off += sp[i].bytes;
+  }
+  k_restore_words<<<1, 64, 0, st>>>(D.err, (int)((h.s + 1) % 3), h.lbuf, h.err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_drift_bin(D, h.s, false, false, st));
+  ctx->since_sort = h.since_sort;
+  ctx->n_couple = h.n_couple;
+  ctx->pending_src = nullptr;
+  ctx->poisoned = err_to_status(h.err);
+  HIP_TRY(hipStreamSynchronize(st));
+  return DEM_OK;
+}
 
 size_t dem_workspace_bytes(const dem_params *dp, const cfd_params *cp) {
   Sizes S;
@@ -1378,6 +1557,7 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
   if (!ok) return fail(DEM_E_HIP);
   if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) return fail(DEM_E_HIP);
   B->io_host = iot;
+  for (int b = 0; b < n_beds; ++b) ++beds[b]->in_batch;
   *out = B;
   return DEM_OK;
 }
@@ -1458,6 +1638,7 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
 
 dem_status dem_batch_destroy(dem_batch *B) {
   if (!B) return DEM_E_ARG;
+  for (dem_ctx *ctx : B->beds) --ctx->in_batch;
   if (B->g_cpl) (void)hipGraphExecDestroy(B->g_cpl);
   if (B->g_step) (void)hipGraphExecDestroy(B->g_step);
   if (B->cap) (void)hipStreamDestroy(B->cap);
