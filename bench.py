@@ -544,7 +544,7 @@ def served_stream(n_jobs, warmup, dev, config=None):
         "jobs": s["jobs"], "latency_p50_s": s["latency_p50_s"], "latency_p99_s": s["latency_p99_s"],
         "value": s["particle_steps_per_s"], "unit": "particle-steps/s", "jobs_per_s": s["jobs_per_s"],
         "offered_particle_steps_per_s": offered, "errors": s["errors"], "chunks": server.chunks,
-        "batch_rebuilds": server.rebuilds, "wall_s": wall, "dtype": "f32 forces / f64 state",
+        "batches_created": server.batches, "slot_changes": server.layout_changes, "wall_s": wall, "dtype": "f32 forces / f64 state",
     }
 
 

@@ -304,7 +304,8 @@ dem_status dem_kernel_timing_read(dem_ctx *ctx, int64_t *launches, double *total
 
 /* Release the context (host memory and HIP events).  The workspace stays the
  * caller's.  Work already enqueued must have completed or be on the stream
- * that the caller synchronizes before freeing the workspace. */
+ * that the caller synchronizes before freeing the workspace.  DEM_E_ARG (and
+ * nothing released) while the bed belongs to a batch. */
 dem_status dem_destroy(dem_ctx *ctx);
 
 /* ---- Batches: many independent beds advanced by the same launches ----
@@ -320,10 +321,12 @@ dem_status dem_destroy(dem_ctx *ctx);
  * fewer than 2^20 elements.  A bed with the smoothed void fraction has its
  * field solved on its own mesh within the batch's coupling step (launches
  * per such bed, before the shared ones, and its quadrature-point values
- * after them).  While a bed belongs to a batch it must be advanced only through
- * the batch (dem_read_*, dem_poll and dem_kernel_timing stay valid; errors
- * are reported per bed by dem_poll).  Destroying the batch leaves every bed
- * usable on its own.  The same algorithm as dem_step / cfd_dem_couple
+ * after them).  A bed belongs to at most one batch at a time; while it does
+ * it must be advanced only through the batch (dem_read_*, dem_poll,
+ * dem_kernel_timing and dem_read_checkpoint stay valid; dem_step,
+ * dem_write_state and dem_destroy do not; errors are reported per bed by
+ * dem_poll).  Destroying the batch, or retiring the bed from its slot,
+ * leaves the bed usable on its own.  The same algorithm as dem_step / cfd_dem_couple
  * (Sections 2.2 and 2.3) runs on every bed. */
 typedef struct dem_batch dem_batch;
 
@@ -331,7 +334,8 @@ typedef struct dem_batch dem_batch;
  * arguments).  beds: host array of n_beds contexts. */
 size_t dem_batch_workspace_bytes(int32_t n_beds, dem_ctx *const *beds);
 
-/* Build the batch.  The coupling buffers are host arrays of n_beds device
+/* Build the batch (slots 0..n_beds-1 of a batch of exactly these beds' size,
+ * see dem_batch_create_slots).  The coupling buffers are host arrays of n_beds device
  * pointers with the meaning and layout of cfd_dem_couple's arguments, bed by
  * bed; u_nodes == NULL builds a batch without coupling (the other five
  * arrays are then ignored), elem_sums may be NULL or hold NULL entries.
@@ -364,9 +368,58 @@ dem_status dem_batch_couple(dem_batch *batch, void *stream);
 dem_status dem_batch_run(dem_batch *batch, int32_t n_chunks, int32_t steps_per_chunk,
                          int32_t couple, void *stream);
 
-/* Release the batch (host memory, its graph and capture stream); the beds
- * and the workspace stay the caller's. */
+/* Release the batch (host memory, its graphs, capture stream and pinned map
+ * staging); the beds and the workspace stay the caller's, and every bed it
+ * held is usable on its own again. */
 dem_status dem_batch_destroy(dem_batch *batch);
+
+/* ---- Batch slots: beds join and leave a running batch ----
+ *
+ * For serving a stream of jobs (continuous batching): a batch with a fixed
+ * number of slots and limits on the particles and mesh elements it holds at
+ * once; beds are admitted into free slots and retired from them between
+ * calls, while the other beds keep their state on the device.  Each bed
+ * computes exactly what it computes alone (the arithmetic of a bed does not
+ * depend on the others).  The launch layout (block maps, coupling lists) is
+ * rebuilt at the next dem_batch_step / dem_batch_couple / dem_batch_run after
+ * a change, uploaded stream-ordered from pinned host staging that the batch
+ * allocates (launches already enqueued keep the maps they were enqueued
+ * with), and the captured graphs are re-captured then (graphs of the old
+ * layout are destroyed once their last replay has run). */
+typedef struct {
+  int32_t slots;          /* beds held at once, 1..4096 */
+  int32_t couples;        /* 1: beds are admitted with coupling buffers */
+  int64_t max_particles;  /* sum of the held beds' particle counts, >= 1 */
+  int64_t max_elements;   /* sum of the held beds' mesh elements (coupling) */
+} dem_batch_limits;
+
+/* Device workspace of an empty batch with these limits (host function; 0 on
+ * invalid limits). */
+size_t dem_batch_slots_workspace_bytes(const dem_batch_limits *limits);
+
+/* An empty batch.  workspace: >= dem_batch_slots_workspace_bytes bytes,
+ * 256-byte aligned, caller-owned until dem_batch_destroy.  *out (host)
+ * receives the batch. */
+dem_status dem_batch_create_slots(const dem_batch_limits *limits, void *workspace, size_t ws_bytes,
+                                  void *stream, dem_batch **out);
+
+/* Put bed into free slot `slot`, with its coupling buffers (meaning and
+ * layout of cfd_dem_couple's arguments; required when the batch couples,
+ * elem_sums may be NULL; ignored otherwise).  The bed continues from its
+ * current state and step counter.  Errors: DEM_E_ARG (slot out of range or
+ * taken, bed already in a batch, missing buffers), DEM_E_UNSUPPORTED (another
+ * precision, lanes, threads per element or velocity order than the beds
+ * held), DEM_E_CAPACITY (the limits would be exceeded), or the bed's sticky
+ * error.  Enqueues the slot's table entries on the stream. */
+dem_status dem_batch_admit(dem_batch *batch, int32_t slot, dem_ctx *bed, const double *u_nodes,
+                           const double *p_nodes, double *eps_q, double *beta_q, double *fpf_q,
+                           double *elem_sums, void *stream);
+
+/* Free slot `slot`; its bed is usable on its own again (dem_read_*,
+ * dem_step, dem_destroy).  Work already enqueued on the batch's stream still
+ * reads the bed's workspace: the caller keeps it until the stream has passed
+ * that point.  Host-only call. */
+dem_status dem_batch_retire(dem_batch *batch, int32_t slot);
 
 /* Static description of a status code. */
 const char *dem_status_string(dem_status s);

@@ -38,6 +38,7 @@ SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "d
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
            "dem_batch_step", "dem_batch_couple", "dem_batch_run", "dem_batch_destroy",
+           "dem_batch_slots_workspace_bytes", "dem_batch_create_slots", "dem_batch_admit", "dem_batch_retire",
            "dem_status_string")
 
 
@@ -61,6 +62,11 @@ class CfdParams(C.Structure):
         ("shear", C.c_int32), ("smooth", C.c_int32), ("smooth_L2", C.c_double),
         ("elem_threads", C.c_int32),
     ]
+
+
+class BatchLimits(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("couples", C.c_int32), ("max_particles", C.c_int64),
+                ("max_elements", C.c_int64)]
 
 
 class CfddemError(RuntimeError):
@@ -127,6 +133,14 @@ def load():
     lib.dem_batch_run.argtypes = [vp, i32, i32, i32, vp]
     lib.dem_batch_destroy.restype = i32
     lib.dem_batch_destroy.argtypes = [vp]
+    lib.dem_batch_slots_workspace_bytes.restype = C.c_size_t
+    lib.dem_batch_slots_workspace_bytes.argtypes = [C.POINTER(BatchLimits)]
+    lib.dem_batch_create_slots.restype = i32
+    lib.dem_batch_create_slots.argtypes = [C.POINTER(BatchLimits), vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.dem_batch_admit.restype = i32
+    lib.dem_batch_admit.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dem_batch_retire.restype = i32
+    lib.dem_batch_retire.argtypes = [vp, i32]
     lib.dem_status_string.restype = C.c_char_p
     lib.dem_status_string.argtypes = [i32]
     _lib = lib
@@ -434,6 +448,83 @@ class Batch:
             self.stream.synchronize()
             self._lib.dem_batch_destroy(self._h)
             self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SlotBatch:
+    """A batch with fixed slots that beds join and leave while it runs
+    (dem_batch_create_slots / dem_batch_admit / dem_batch_retire): the
+    continuous-batching form used by the server.  admit() returns the bed's
+    coupling outputs (a dict of device tensors rewritten by every coupling
+    step of the batch)."""
+
+    def __init__(self, slots, max_particles, max_elements=0, couples=True, device="cuda", stream=None):
+        import torch
+
+        self._torch = torch
+        lib = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.limits = BatchLimits(int(slots), 1 if couples else 0, int(max_particles), int(max_elements))
+        nbytes = int(lib.dem_batch_slots_workspace_bytes(C.byref(self.limits)))
+        if nbytes == 0:
+            raise CfddemError(DEM_E_ARG, "dem_batch_slots_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._h = C.c_void_p()
+        self._lib = lib
+        _check(lib.dem_batch_create_slots(C.byref(self.limits), C.c_void_p(self.workspace.data_ptr() + off),
+                                          C.c_size_t(nbytes), self._st, C.byref(self._h)), "dem_batch_create_slots")
+        self.held = {}  # slot -> (bed, fields, outputs)
+
+    @property
+    def _st(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def admit(self, slot, bed, fields=None, elem_sums=False):
+        torch = self._torch
+        out = None
+        args = [None] * 6
+        if self.limits.couples:
+            U, P = (t.contiguous() for t in fields)
+            m = bed.n_elem * bed.nq
+            out = dict(eps_q=torch.empty(m, dtype=torch.float64, device=self.device),
+                       beta_q=torch.empty(m, dtype=torch.float64, device=self.device),
+                       fpf_q=torch.empty((3, m), dtype=torch.float64, device=self.device))
+            if elem_sums:
+                out["elem_sums"] = torch.empty((12, bed.n_elem), dtype=torch.float64, device=self.device)
+            fields = (U, P)
+            args = [_ptr(U), _ptr(P), _ptr(out["eps_q"]), _ptr(out["beta_q"]), _ptr(out["fpf_q"]),
+                    _ptr(out.get("elem_sums"))]
+        _check(self._lib.dem_batch_admit(self._h, int(slot), bed._h, *args, self._st), "dem_batch_admit")
+        self.held[int(slot)] = (bed, fields, out)
+        return out
+
+    def retire(self, slot):
+        _check(self._lib.dem_batch_retire(self._h, int(slot)), "dem_batch_retire")
+        return self.held.pop(int(slot))
+
+    def step(self, n_steps: int = 1):
+        _check(self._lib.dem_batch_step(self._h, int(n_steps), self._st), "dem_batch_step")
+
+    def couple(self):
+        _check(self._lib.dem_batch_couple(self._h, self._st), "dem_batch_couple")
+
+    def run(self, n_chunks: int, steps_per_chunk: int, couple: bool = True):
+        _check(self._lib.dem_batch_run(self._h, int(n_chunks), int(steps_per_chunk), 1 if couple else 0,
+                                       self._st), "dem_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.stream.synchronize()
+            self._lib.dem_batch_destroy(self._h)
+            self._h = C.c_void_p()
+            self.held = {}
 
     def __del__(self):
         try:

@@ -37,6 +37,7 @@ hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsi
 hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
 hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
                                 hipStream_t st);
+hipError_t launch_batch_set_cpl(Cpl *ctab, CplIO *iot, int b, const Cpl &C, const CplIO &io, hipStream_t st);
 hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot, const BedRun *run,
                                const unsigned *map_class, int blocks_class, int *cnt_words,
                                unsigned *list, const long long mode_elems[3], int order, bool fp32, int nt,
@@ -1292,7 +1293,7 @@ dem_status dem_kernel_timing_read(dem_ctx *ctx, int64_t *launches, double *total
 }
 
 dem_status dem_destroy(dem_ctx *ctx) {
-  if (!ctx) return DEM_E_ARG;
+  if (!ctx || ctx->in_batch) return DEM_E_ARG;
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
   return DEM_OK;
@@ -1304,92 +1305,86 @@ dem_status dem_destroy(dem_ctx *ctx) {
 }  // extern "C"
 
 struct dem_batch {
-  std::vector<dem_ctx *> beds;
-  bool fp32 = false;
+  // slots: the beds held (nullptr = free), their coupling buffers
+  int n_slots = 0;
+  long long max_particles = 0, max_elements = 0;
   bool couples = false;
+  std::vector<dem_ctx *> slot;
+  std::vector<CplIO> io_host;
+  int held = 0;  // occupied slots
+  long long held_particles = 0, held_elements = 0;
+  // shared by every bed held (fixed while the batch is not empty)
+  bool fp32 = false;
   int order = 2;
-  int maxn = 1;
   int lanes = kForceLanes;
   int elem_threads = 128;  // threads per occupied element of the coupling step
-  // beds are grouped by kernel variant, each group with its own launches, so
-  // that a bed's arithmetic never depends on the other beds: the force map
-  // holds the blocks of the beds without rolling friction first
-  // (nb_force_plain of them), then those of the beds with it; the coupling
-  // lists occupied elements per element-kernel variant (mode_elems[m]
-  // elements of the beds in mode m)
+  int maxn = 1;
+  // launch layout, rebuilt when the slots change.  Beds are grouped by kernel
+  // variant, each group with its own launches, so that a bed's arithmetic
+  // never depends on the other beds: the force map holds the blocks of the
+  // beds without rolling friction first (nb_force_plain of them), then those
+  // of the beds with it; the coupling lists occupied elements per
+  // element-kernel variant (mode_elems[m] elements of the beds in mode m)
+  bool dirty = true;
   int nb_force_plain = 0;
   long long mode_elems[3] = {0, 0, 0};
+  int nb_drift = 0, nb_force = 0, nb_class = 0;
   // device tables and maps (carved from the caller's workspace)
   Dev *tab = nullptr;
   Cpl *ctab = nullptr;
   CplIO *iot = nullptr;
-  std::vector<CplIO> io_host;  // the same on the host (per-bed smoothing launches)
   BedRun *run = nullptr;
   unsigned *map_drift = nullptr, *map_force = nullptr, *map_class = nullptr, *list = nullptr;
+  long long cap_drift = 0, cap_force = 0, cap_class = 0;
   int *cnt = nullptr;
-  int nb_drift = 0, nb_force = 0, nb_class = 0;
-  long long total_elems = 0;
-  // graphs of a chunk: the coupling step, and g_steps DEM steps
+  // pinned host staging of the maps, reused once its last upload is done
+  unsigned *stage = nullptr;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
+  // graphs of a chunk: the coupling step, and g_steps DEM steps; graphs of
+  // an older layout wait for their last replay before they are destroyed
   hipStream_t cap = nullptr;
   hipGraphExec_t g_cpl = nullptr;
   hipGraphExec_t g_step = nullptr;
   int g_steps = -1;
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> stale;
 };
 
 namespace {
 
-struct BatchLayout {
-  int nb_drift = 0, nb_force = 0, nb_class = 0;
-  long long total_elems = 0;
-};
-
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-// Validates the beds and counts the blocks of each batched launch.
-dem_status batch_layout(int32_t n_beds, dem_ctx *const *beds, bool couples, BatchLayout &L) {
-  if (n_beds < 1 || n_beds > kMaxBeds || !beds) return DEM_E_ARG;
-  const long long max_blocks = 0x7fffffffLL;
-  long long d = 0, f = 0, c = 0, e = 0;
-  for (int b = 0; b < n_beds; ++b) {
-    const dem_ctx *x = beds[b];
-    if (!x) return DEM_E_ARG;
-    for (int j = 0; j < b; ++j)
-      if (beds[j] == x) return DEM_E_ARG;
-    if (x->fp32 != beds[0]->fp32 || x->S.lanes != beds[0]->S.lanes ||
-        x->C.elem_threads != beds[0]->C.elem_threads)
-      return DEM_E_UNSUPPORTED;
-    const long long n = x->S.n;
-    const int bd = ceil_div(n, 256), bf = ceil_div(n * x->S.lanes, kForceBlock);
-    const int ne = x->S.grid.n_elem;
-    const int bc = ceil_div(ne, couple_class_elems_per_block());
-    if (bd > (int)kBlockMask || bf > (int)kBlockMask || bc > (int)kBlockMask) return DEM_E_UNSUPPORTED;
-    if (couples) {
-      if (x->cp.order != beds[0]->cp.order) return DEM_E_UNSUPPORTED;
-      if (ne > (int)kBlockMask) return DEM_E_UNSUPPORTED;
-    }
-    d += bd;
-    f += bf;
-    c += bc;
-    e += ne;
-  }
-  if (d > max_blocks || f > max_blocks || c > max_blocks) return DEM_E_UNSUPPORTED;
-  L.nb_drift = (int)d;
-  L.nb_force = (int)f;
-  L.nb_class = couples ? (int)c : 0;
-  L.total_elems = couples ? e : 0;
-  return DEM_OK;
+// Capacity of the maps and lists of a batch of these limits (force blocks
+// sized for four lanes per particle, the most a bed may use).
+struct SlotCaps {
+  long long drift, force, cls, elems;
+};
+SlotCaps slot_caps(const dem_batch_limits &L) {
+  SlotCaps c;
+  c.drift = L.max_particles / 256 + L.slots;
+  c.force = L.max_particles * 4 / kForceBlock + L.slots;
+  c.cls = L.couples ? L.max_elements / couple_class_elems_per_block() + L.slots : 0;
+  c.elems = L.couples ? L.max_elements : 0;
+  return c;
 }
 
-size_t batch_carve(int32_t n_beds, const BatchLayout &L, char *base, dem_batch *B) {
+bool limits_ok(const dem_batch_limits *L) {
+  return L && L->slots >= 1 && L->slots <= kMaxBeds && L->max_particles >= 1 &&
+         L->max_particles <= 0x7ffffff0LL && L->max_elements >= 0 && L->max_elements <= 0x7ffffff0LL &&
+         (L->couples == 0 || L->couples == 1);
+}
+
+size_t batch_carve(const dem_batch_limits &L, char *base, dem_batch *B) {
+  const SlotCaps k = slot_caps(L);
   Carver c{base};
-  Dev *tab = c.take<Dev>((size_t)n_beds);
-  Cpl *ctab = c.take<Cpl>((size_t)n_beds);
-  CplIO *iot = c.take<CplIO>((size_t)n_beds);
-  BedRun *run = c.take<BedRun>((size_t)n_beds);
-  unsigned *md = c.take<unsigned>((size_t)L.nb_drift);
-  unsigned *mf = c.take<unsigned>((size_t)L.nb_force);
-  unsigned *mc = c.take<unsigned>((size_t)(L.nb_class > 0 ? L.nb_class : 1));
-  unsigned *list = c.take<unsigned>((size_t)(L.total_elems > 0 ? L.total_elems : 1));
+  Dev *tab = c.take<Dev>((size_t)L.slots);
+  Cpl *ctab = c.take<Cpl>((size_t)L.slots);
+  CplIO *iot = c.take<CplIO>((size_t)L.slots);
+  BedRun *run = c.take<BedRun>((size_t)L.slots);
+  unsigned *md = c.take<unsigned>((size_t)k.drift);
+  unsigned *mf = c.take<unsigned>((size_t)k.force);
+  unsigned *mc = c.take<unsigned>((size_t)(k.cls > 0 ? k.cls : 1));
+  unsigned *list = c.take<unsigned>((size_t)(k.elems > 0 ? k.elems : 1));
   int *cnt = c.take<int>(64);
   if (B) {
     B->tab = tab;
@@ -1401,22 +1396,101 @@ size_t batch_carve(int32_t n_beds, const BatchLayout &L, char *base, dem_batch *
     B->map_class = mc;
     B->list = list;
     B->cnt = cnt;
+    B->cap_drift = k.drift;
+    B->cap_force = k.force;
+    B->cap_class = k.cls;
   }
   return c.off + kAlign;
 }
 
-void fill_map(std::vector<unsigned> &m, int bed, int blocks) {
-  for (int k = 0; k < blocks; ++k) m.push_back(((unsigned)bed << kBedShift) | (unsigned)k);
+void fill_map(unsigned *m, long long &at, int bed, int blocks) {
+  for (int k = 0; k < blocks; ++k) m[at++] = ((unsigned)bed << kBedShift) | (unsigned)k;
+}
+
+// Graphs of the old layout are destroyed once their last replay has run.
+void retire_graphs(dem_batch *B, hipStream_t st) {
+  for (hipGraphExec_t *g : {&B->g_cpl, &B->g_step}) {
+    if (!*g) continue;
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess && hipEventRecord(e, st) == hipSuccess) {
+      B->stale.emplace_back(*g, e);
+    } else {
+      if (e) (void)hipEventDestroy(e);
+      (void)hipStreamSynchronize(st);
+      (void)hipGraphExecDestroy(*g);
+    }
+    *g = nullptr;
+  }
+  B->g_steps = -1;
+  for (size_t i = 0; i < B->stale.size();) {
+    if (hipEventQuery(B->stale[i].second) == hipSuccess) {
+      (void)hipGraphExecDestroy(B->stale[i].first);
+      (void)hipEventDestroy(B->stale[i].second);
+      B->stale[i] = B->stale.back();
+      B->stale.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+// Rebuilds the launch layout from the held beds and uploads the maps (from
+// pinned staging, stream-ordered: launches already enqueued keep reading the
+// maps they were enqueued with).
+dem_status batch_layout(dem_batch *B, hipStream_t st) {
+  if (!B->dirty) return DEM_OK;
+  if (B->stage_pending) {
+    HIP_TRY(hipEventSynchronize(B->stage_ev));  // the last upload has left the staging
+    B->stage_pending = false;
+  }
+  unsigned *md = B->stage;
+  unsigned *mf = md + B->cap_drift;
+  unsigned *mc = mf + B->cap_force;
+  long long nd = 0, nf = 0, nc = 0;
+  B->mode_elems[0] = B->mode_elems[1] = B->mode_elems[2] = 0;
+  B->maxn = 1;
+  for (int pass = 0; pass < 2; ++pass)  // force blocks: beds without rolling friction first
+    for (int b = 0; b < B->n_slots; ++b) {
+      const dem_ctx *ctx = B->slot[b];
+      if (!ctx) continue;
+      const bool roll = ctx->B.D.pp.mu_r > 0.0 || ctx->B.D.pw.mu_r > 0.0;
+      if (roll != (pass == 1)) continue;
+      fill_map(mf, nf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
+    }
+  B->nb_force_plain = 0;
+  for (int b = 0; b < B->n_slots; ++b) {
+    const dem_ctx *ctx = B->slot[b];
+    if (!ctx) continue;
+    if (!(ctx->B.D.pp.mu_r > 0.0 || ctx->B.D.pw.mu_r > 0.0))
+      B->nb_force_plain += ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock);
+    fill_map(md, nd, b, ceil_div(ctx->S.n, 256));
+    if (B->couples) {
+      fill_map(mc, nc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));
+      B->mode_elems[cpl_mode_of(ctx->C.drag, ctx->C.shear || ctx->C.smooth)] += ctx->S.grid.n_elem;
+    }
+    if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
+  }
+  B->nb_drift = (int)nd;
+  B->nb_force = (int)nf;
+  B->nb_class = (int)nc;
+  if (nd) HIP_TRY(hipMemcpyAsync(B->map_drift, md, sizeof(unsigned) * nd, hipMemcpyHostToDevice, st));
+  if (nf) HIP_TRY(hipMemcpyAsync(B->map_force, mf, sizeof(unsigned) * nf, hipMemcpyHostToDevice, st));
+  if (nc) HIP_TRY(hipMemcpyAsync(B->map_class, mc, sizeof(unsigned) * nc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(B->stage_ev, st));
+  B->stage_pending = true;
+  retire_graphs(B, st);
+  B->dirty = false;
+  return DEM_OK;
 }
 
 // Re-sorts the beds whose re-sort is due and refreshes their table entries.
 dem_status batch_resorts(dem_batch *B, hipStream_t st) {
-  for (size_t b = 0; b < B->beds.size(); ++b) {
-    dem_ctx *ctx = B->beds[b];
-    if (ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
+  for (int b = 0; b < B->n_slots; ++b) {
+    dem_ctx *ctx = B->slot[b];
+    if (ctx && ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) {
       dem_status r = resort(ctx, st);
       if (r != DEM_OK) return r;
-      HIP_TRY(launch_batch_set_bed(B->tab, B->run, (int)b, ctx->B.D, ctx->s, ctx->pending_src, st));
+      HIP_TRY(launch_batch_set_bed(B->tab, B->run, b, ctx->B.D, ctx->s, ctx->pending_src, st));
     }
   }
   return DEM_OK;
@@ -1434,7 +1508,7 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
       HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force + B->nb_force_plain, nb_roll, i, i < n,
                                       B->fp32, B->maxn, B->lanes, true, st));
   }
-  HIP_TRY(launch_batch_advance(B->run, (int)B->beds.size(), n, st));
+  HIP_TRY(launch_batch_advance(B->run, B->n_slots, n, st));
   return DEM_OK;
 }
 
@@ -1442,24 +1516,25 @@ dem_status batch_enqueue_couple(dem_batch *B, hipStream_t st) {
   // beds with the smoothed void fraction: their field first (per bed: each
   // has its own mesh and transforms), their quadrature-point values after the
   // shared launches, as a single bed's coupling step orders them
-  for (size_t b = 0; b < B->beds.size(); ++b) {
-    dem_ctx *ctx = B->beds[b];
-    if (!ctx->C.smooth) continue;
-    HIP_TRY(launch_pcm_rhs_run(B->tab, ctx->S.grid.n_elem, ctx->C, ctx->SO, B->run, (int)b, ctx->B.eps_e,
+  for (int b = 0; b < B->n_slots; ++b) {
+    dem_ctx *ctx = B->slot[b];
+    if (!ctx || !ctx->C.smooth) continue;
+    HIP_TRY(launch_pcm_rhs_run(B->tab, ctx->S.grid.n_elem, ctx->C, ctx->SO, B->run, b, ctx->B.eps_e,
                                ctx->B.sb, st));
     HIP_TRY(launch_smooth_solve(ctx->SO, ctx->B.sb, ctx->B.sx, ctx->B.st1, ctx->B.st2, st));
   }
-  HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt,
-                              B->list, B->mode_elems, B->order, B->fp32, B->elem_threads, st));
-  for (size_t b = 0; b < B->beds.size(); ++b) {
-    dem_ctx *ctx = B->beds[b];
-    if (ctx->C.smooth) HIP_TRY(launch_eps_q_field(ctx->SO, ctx->C, ctx->B.sx, B->io_host[b].eps_q, st));
+  HIP_TRY(launch_couple_batch(B->tab, B->ctab, B->iot, B->run, B->map_class, B->nb_class, B->cnt, B->list,
+                              B->mode_elems, B->order, B->fp32, B->elem_threads, st));
+  for (int b = 0; b < B->n_slots; ++b) {
+    dem_ctx *ctx = B->slot[b];
+    if (ctx && ctx->C.smooth) HIP_TRY(launch_eps_q_field(ctx->SO, ctx->C, ctx->B.sx, B->io_host[b].eps_q, st));
   }
   return DEM_OK;
 }
 
 void batch_mirror_steps(dem_batch *B, int n) {
-  for (dem_ctx *ctx : B->beds) {
+  for (dem_ctx *ctx : B->slot) {
+    if (!ctx) continue;
     ctx->s += n;
     ctx->since_sort += n;
     ctx->pending_src = nullptr;
@@ -1467,8 +1542,28 @@ void batch_mirror_steps(dem_batch *B, int n) {
 }
 
 dem_status batch_poisoned(const dem_batch *B) {
-  for (const dem_ctx *ctx : B->beds)
-    if (ctx->poisoned) return ctx->poisoned;
+  for (const dem_ctx *ctx : B->slot)
+    if (ctx && ctx->poisoned) return ctx->poisoned;
+  return DEM_OK;
+}
+
+// Whether bed ctx may join the beds the batch holds (same precision, lanes
+// and threads per element; for coupling, the same velocity order), and fits
+// the block-map encoding.
+dem_status bed_fits(const dem_batch *B, const dem_ctx *ctx) {
+  const long long n = ctx->S.n;
+  const int bd = ceil_div(n, 256), bf = ceil_div(n * ctx->S.lanes, kForceBlock);
+  const int ne = ctx->S.grid.n_elem;
+  if (bd > (int)kBlockMask || bf > (int)kBlockMask) return DEM_E_UNSUPPORTED;
+  if (B->couples && (ne > (int)kBlockMask || ceil_div(ne, couple_class_elems_per_block()) > (int)kBlockMask))
+    return DEM_E_UNSUPPORTED;
+  if (B->held > 0) {
+    if (ctx->fp32 != B->fp32 || ctx->S.lanes != B->lanes || ctx->C.elem_threads != B->elem_threads)
+      return DEM_E_UNSUPPORTED;
+    if (B->couples && ctx->cp.order != B->order) return DEM_E_UNSUPPORTED;
+  }
+  if (B->held_particles + n > B->max_particles) return DEM_E_CAPACITY;
+  if (B->couples && B->held_elements + ne > B->max_elements) return DEM_E_CAPACITY;
   return DEM_OK;
 }
 
@@ -1476,12 +1571,90 @@ dem_status batch_poisoned(const dem_batch *B) {
 
 extern "C" {
 
+size_t dem_batch_slots_workspace_bytes(const dem_batch_limits *limits) {
+  if (!limits_ok(limits)) return 0;
+  return batch_carve(*limits, nullptr, nullptr);
+}
+
+dem_status dem_batch_create_slots(const dem_batch_limits *limits, void *workspace, size_t ws_bytes, void *stream,
+                                  dem_batch **out) {
+  if (!out) return DEM_E_ARG;
+  *out = nullptr;
+  if (!limits_ok(limits)) return DEM_E_ARG;
+  const size_t need = batch_carve(*limits, nullptr, nullptr);
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need) return DEM_E_WORKSPACE;
+  dem_batch *B = new (std::nothrow) dem_batch();
+  if (!B) return DEM_E_ARG;
+  batch_carve(*limits, (char *)workspace, B);
+  B->n_slots = limits->slots;
+  B->max_particles = limits->max_particles;
+  B->max_elements = limits->max_elements;
+  B->couples = limits->couples != 0;
+  B->slot.assign((size_t)B->n_slots, nullptr);
+  B->io_host.assign((size_t)B->n_slots, CplIO{});
+  hipStream_t st = (hipStream_t)stream;
+  const size_t stage_words = (size_t)(B->cap_drift + B->cap_force + B->cap_class);
+  bool ok = hipHostMalloc((void **)&B->stage, sizeof(unsigned) * stage_words, hipHostMallocDefault) == hipSuccess &&
+            hipEventCreateWithFlags(&B->stage_ev, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipMemsetAsync(B->cnt, 0, sizeof(int) * 64, st) == hipSuccess;
+  if (!ok) {
+    dem_batch_destroy(B);
+    return DEM_E_HIP;
+  }
+  *out = B;
+  return DEM_OK;
+}
+
+dem_status dem_batch_admit(dem_batch *B, int32_t slot, dem_ctx *bed, const double *u_nodes, const double *p_nodes,
+                           double *eps_q, double *beta_q, double *fpf_q, double *elem_sums, void *stream) {
+  if (!B || !bed || slot < 0 || slot >= B->n_slots || B->slot[slot] || bed->in_batch) return DEM_E_ARG;
+  if (B->couples && (!u_nodes || !p_nodes || !eps_q || !beta_q || !fpf_q)) return DEM_E_ARG;
+  if (bed->poisoned) return bed->poisoned;
+  const dem_status f = bed_fits(B, bed);
+  if (f != DEM_OK) return f;
+  hipStream_t st = (hipStream_t)stream;
+  const CplIO io = B->couples ? CplIO{u_nodes, p_nodes, eps_q, beta_q, fpf_q, elem_sums} : CplIO{};
+  HIP_TRY(launch_batch_set_bed(B->tab, B->run, slot, bed->B.D, bed->s, bed->pending_src, st));
+  HIP_TRY(launch_batch_set_cpl(B->ctab, B->iot, slot, bed->C, io, st));
+  if (B->held == 0) {
+    B->fp32 = bed->fp32;
+    B->lanes = bed->S.lanes;
+    B->elem_threads = bed->C.elem_threads;
+    B->order = bed->cp.order;
+  }
+  B->slot[slot] = bed;
+  B->io_host[slot] = io;
+  ++B->held;
+  B->held_particles += bed->S.n;
+  B->held_elements += bed->S.grid.n_elem;
+  ++bed->in_batch;
+  B->dirty = true;
+  return DEM_OK;
+}
+
+dem_status dem_batch_retire(dem_batch *B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->n_slots || !B->slot[slot]) return DEM_E_ARG;
+  dem_ctx *bed = B->slot[slot];
+  B->slot[slot] = nullptr;
+  B->io_host[slot] = CplIO{};
+  --B->held;
+  B->held_particles -= bed->S.n;
+  B->held_elements -= bed->S.grid.n_elem;
+  --bed->in_batch;
+  B->dirty = true;
+  return DEM_OK;
+}
+
 size_t dem_batch_workspace_bytes(int32_t n_beds, dem_ctx *const *beds) {
-  // sized for coupling when the beds allow it, else for stepping only
-  BatchLayout L;
-  if (batch_layout(n_beds, beds, true, L) != DEM_OK && batch_layout(n_beds, beds, false, L) != DEM_OK)
-    return 0;
-  return batch_carve(n_beds, L, nullptr, nullptr);
+  if (n_beds < 1 || n_beds > kMaxBeds || !beds) return 0;
+  dem_batch_limits L{n_beds, 1, 0, 0};
+  for (int b = 0; b < n_beds; ++b) {
+    if (!beds[b]) return 0;
+    L.max_particles += beds[b]->S.n;
+    L.max_elements += beds[b]->S.grid.n_elem;
+  }
+  return limits_ok(&L) ? batch_carve(L, nullptr, nullptr) : 0;
 }
 
 dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *const *u_nodes,
@@ -1491,73 +1664,33 @@ dem_status dem_batch_create(int32_t n_beds, dem_ctx *const *beds, const double *
                             void *stream, dem_batch **out) {
   if (!out) return DEM_E_ARG;
   *out = nullptr;
+  if (n_beds < 1 || n_beds > kMaxBeds || !beds) return DEM_E_ARG;
   const bool couples = u_nodes != nullptr;
-  BatchLayout L;
-  dem_status r = batch_layout(n_beds, beds, couples, L);
-  if (r != DEM_OK) return r;
-  if (couples) {
-    if (!p_nodes || !eps_q || !beta_q || !fpf_q) return DEM_E_ARG;
-    for (int b = 0; b < n_beds; ++b)
-      if (!u_nodes[b] || !p_nodes[b] || !eps_q[b] || !beta_q[b] || !fpf_q[b]) return DEM_E_ARG;
-  }
-  for (int b = 0; b < n_beds; ++b)
-    if (beds[b]->poisoned) return beds[b]->poisoned;
-  const size_t need = batch_carve(n_beds, L, nullptr, nullptr);
-  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || ws_bytes < need) return DEM_E_WORKSPACE;
-  dem_batch *B = new (std::nothrow) dem_batch();
-  if (!B) return DEM_E_ARG;
-  batch_carve(n_beds, L, (char *)workspace, B);
-  B->beds.assign(beds, beds + n_beds);
-  B->fp32 = beds[0]->fp32;
-  B->lanes = beds[0]->S.lanes;
-  B->elem_threads = beds[0]->C.elem_threads;
-  B->couples = couples;
-  B->order = beds[0]->cp.order;
-  B->nb_drift = L.nb_drift;
-  B->nb_force = L.nb_force;
-  B->nb_class = L.nb_class;
-  B->total_elems = L.total_elems;
-  std::vector<Dev> tab;
-  std::vector<Cpl> ctab;
-  std::vector<CplIO> iot;
-  std::vector<BedRun> run;
-  std::vector<unsigned> md, mf, mf_roll, mc;
+  if (couples && (!p_nodes || !eps_q || !beta_q || !fpf_q)) return DEM_E_ARG;
+  dem_batch_limits L{n_beds, couples ? 1 : 0, 0, 0};
   for (int b = 0; b < n_beds; ++b) {
-    const dem_ctx *ctx = beds[b];
-    tab.push_back(ctx->B.D);
-    ctab.push_back(ctx->C);
-    CplIO io{};
-    if (couples)
-      io = CplIO{u_nodes[b], p_nodes[b], eps_q[b], beta_q[b], fpf_q[b], elem_sums ? elem_sums[b] : nullptr};
-    iot.push_back(io);
-    run.push_back(BedRun{ctx->s, ctx->pending_src});
-    if (ctx->S.maxn > B->maxn) B->maxn = ctx->S.maxn;
-    if (couples) B->mode_elems[cpl_mode_of(ctx->C.drag, ctx->C.shear || ctx->C.smooth)] += ctx->S.grid.n_elem;
-    const bool roll = ctx->B.D.pp.mu_r > 0.0 || ctx->B.D.pw.mu_r > 0.0;
-    fill_map(md, b, ceil_div(ctx->S.n, 256));
-    fill_map(roll ? mf_roll : mf, b, ceil_div((long long)ctx->S.n * ctx->S.lanes, kForceBlock));
-    if (couples) fill_map(mc, b, ceil_div(ctx->S.grid.n_elem, couple_class_elems_per_block()));
+    if (!beds[b]) return DEM_E_ARG;
+    for (int j = 0; j < b; ++j)
+      if (beds[j] == beds[b]) return DEM_E_ARG;
+    if (beds[b]->poisoned) return beds[b]->poisoned;
+    L.max_particles += beds[b]->S.n;
+    L.max_elements += beds[b]->S.grid.n_elem;
   }
-  B->nb_force_plain = (int)mf.size();
-  mf.insert(mf.end(), mf_roll.begin(), mf_roll.end());
-  hipStream_t st = (hipStream_t)stream;
-  auto fail = [&](dem_status code) {
-    delete B;
-    return code;
-  };
-  bool ok = hipMemcpyAsync(B->tab, tab.data(), sizeof(Dev) * tab.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(B->ctab, ctab.data(), sizeof(Cpl) * ctab.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(B->iot, iot.data(), sizeof(CplIO) * iot.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(B->run, run.data(), sizeof(BedRun) * run.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(B->map_drift, md.data(), sizeof(unsigned) * md.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            hipMemcpyAsync(B->map_force, mf.data(), sizeof(unsigned) * mf.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-            (mc.empty() || hipMemcpyAsync(B->map_class, mc.data(), sizeof(unsigned) * mc.size(), hipMemcpyHostToDevice, st) == hipSuccess) &&
-            hipMemsetAsync(B->cnt, 0, sizeof(int) * 64, st) == hipSuccess &&
-            hipStreamSynchronize(st) == hipSuccess;
-  if (!ok) return fail(DEM_E_HIP);
-  if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) return fail(DEM_E_HIP);
-  B->io_host = iot;
-  for (int b = 0; b < n_beds; ++b) ++beds[b]->in_batch;
+  if (!limits_ok(&L)) return DEM_E_UNSUPPORTED;
+  dem_batch *B = nullptr;
+  dem_status r = dem_batch_create_slots(&L, workspace, ws_bytes, stream, &B);
+  if (r != DEM_OK) return r;
+  for (int b = 0; b < n_beds && r == DEM_OK; ++b)
+    r = couples ? dem_batch_admit(B, b, beds[b], u_nodes[b], p_nodes[b], eps_q[b], beta_q[b], fpf_q[b],
+                                  elem_sums ? elem_sums[b] : nullptr, stream)
+                : dem_batch_admit(B, b, beds[b], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, stream);
+  if (r == DEM_OK) r = batch_layout(B, (hipStream_t)stream);
+  if (r == DEM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) r = DEM_E_HIP;
+  if (r != DEM_OK) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    dem_batch_destroy(B);
+    return r;
+  }
   *out = B;
   return DEM_OK;
 }
@@ -1566,8 +1699,10 @@ dem_status dem_batch_step(dem_batch *B, int32_t n_steps, void *stream) {
   if (!B || n_steps < 0) return DEM_E_ARG;
   dem_status r = batch_poisoned(B);
   if (r != DEM_OK) return r;
-  if (n_steps == 0) return DEM_OK;
+  if (n_steps == 0 || B->held == 0) return DEM_OK;
   hipStream_t st = (hipStream_t)stream;
+  r = batch_layout(B, st);
+  if (r != DEM_OK) return r;
   r = batch_resorts(B, st);
   if (r != DEM_OK) return r;
   r = batch_enqueue_steps(B, n_steps, st);
@@ -1581,7 +1716,11 @@ dem_status dem_batch_couple(dem_batch *B, void *stream) {
   if (!B->couples) return DEM_E_ARG;
   dem_status r = batch_poisoned(B);
   if (r != DEM_OK) return r;
-  return batch_enqueue_couple(B, (hipStream_t)stream);
+  if (B->held == 0) return DEM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  r = batch_layout(B, st);
+  if (r != DEM_OK) return r;
+  return batch_enqueue_couple(B, st);
 }
 
 dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk, int32_t couple,
@@ -1589,8 +1728,10 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
   if (!B || n_chunks < 0 || steps_per_chunk < 0 || (couple && !B->couples)) return DEM_E_ARG;
   dem_status r = batch_poisoned(B);
   if (r != DEM_OK) return r;
-  if (n_chunks == 0 || (steps_per_chunk == 0 && !couple)) return DEM_OK;
+  if (n_chunks == 0 || (steps_per_chunk == 0 && !couple) || B->held == 0) return DEM_OK;
   hipStream_t st = (hipStream_t)stream;
+  r = batch_layout(B, st);
+  if (r != DEM_OK) return r;
   // capture what this call needs and is not captured yet
   auto capture = [&](bool cpl, int steps, hipGraphExec_t *exec) -> dem_status {
     HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
@@ -1615,6 +1756,7 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
   }
   if (steps_per_chunk > 0 && (!B->g_step || B->g_steps != steps_per_chunk)) {
     if (B->g_step) {
+      HIP_TRY(hipStreamSynchronize(st));  // its replays are done
       HIP_TRY(hipGraphExecDestroy(B->g_step));
       B->g_step = nullptr;
     }
@@ -1638,10 +1780,21 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
 
 dem_status dem_batch_destroy(dem_batch *B) {
   if (!B) return DEM_E_ARG;
-  for (dem_ctx *ctx : B->beds) --ctx->in_batch;
+  for (dem_ctx *ctx : B->slot)
+    if (ctx) --ctx->in_batch;
+  for (auto &g : B->stale) {
+    (void)hipEventSynchronize(g.second);
+    (void)hipGraphExecDestroy(g.first);
+    (void)hipEventDestroy(g.second);
+  }
   if (B->g_cpl) (void)hipGraphExecDestroy(B->g_cpl);
   if (B->g_step) (void)hipGraphExecDestroy(B->g_step);
   if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->stage_ev) {
+    (void)hipEventSynchronize(B->stage_ev);
+    (void)hipEventDestroy(B->stage_ev);
+  }
+  if (B->stage) (void)hipHostFree(B->stage);
   delete B;
   return DEM_OK;
 }

@@ -660,6 +660,18 @@ hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long
   return hipGetLastError();
 }
 
+// Writes one bed's coupling constants and buffers into the batch tables.
+__global__ void batch_set_cpl(Cpl *ctab, CplIO *iot, int b, Cpl C, CplIO io) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  ctab[b] = C;
+  iot[b] = io;
+}
+
+hipError_t launch_batch_set_cpl(Cpl *ctab, CplIO *iot, int b, const Cpl &C, const CplIO &io, hipStream_t st) {
+  batch_set_cpl<<<1, 64, 0, st>>>(ctab, iot, b, C, io);
+  return hipGetLastError();
+}
+
 hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st) {
   const int grid = (D.n + 255) / 256;
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);

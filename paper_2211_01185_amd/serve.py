@@ -3,16 +3,22 @@
 Jobs (independent beds, each with its own particle count, materials, mesh
 and fluid field, a number of DEM steps and a coupling step every 10 steps)
 arrive over time.  The server keeps every admitted job's state on the device
-and advances all of them together: each chunk is one coupling step plus ten
-DEM steps for every active job, replayed from one captured HIP graph
-(dem_batch_run).  Between chunks it
+in one slot batch (dem_batch_create_slots) and advances all of them
+together: each chunk is one coupling step plus ten DEM steps for every job
+held, replayed from captured HIP graphs (dem_batch_run).  Around the chunks:
 
-  * retires jobs that have run all their steps (final state copied to the
-    host; the latency of a job is the time from its arrival to that point),
-  * admits jobs that have arrived, oldest first, while their device
-    footprint fits the memory budget (a job that does not fit waits; later
-    jobs do not overtake it),
-  * rebuilds the batch tables when the set of jobs changed.
+  * a job that has arrived is admitted into a free slot (dem_batch_admit),
+    oldest first, while its device footprint fits the memory budget (a job
+    that does not fit waits; later jobs do not overtake it); its bed is
+    created on a side stream, so that creating it does not wait for the
+    chunks in flight;
+  * a job that has run all its steps leaves its slot (dem_batch_retire) as
+    soon as its last chunk is enqueued; its final state is copied to pinned
+    host memory on the stream, and the job is finished (its latency is the
+    time from its arrival to that point) when that copy has completed;
+  * at most `depth` chunks are in flight; the host waits on the oldest
+    chunk's event, not on the whole stream, and generates the beds of jobs
+    about to arrive on a worker thread meanwhile.
 
 A job's arithmetic does not depend on the other jobs in the batch, so its
 result is the same alone and in the mix.
@@ -21,6 +27,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -49,14 +56,23 @@ class JobResult:
 
 
 class _Active:
-    def __init__(self, job, wl, bed, U, P, admitted):
+    def __init__(self, job, bed, U, P, slot, admitted):
         self.job = job
-        self.wl = wl
         self.bed = bed
         self.U = U
         self.P = P
+        self.slot = slot
         self.left = job.steps
         self.admitted = admitted
+
+
+class _Finishing:
+    """A retired job whose final state is being copied to the host."""
+
+    def __init__(self, a, host, event):
+        self.a = a
+        self.host = host
+        self.event = event
 
 
 def footprint(wl, precision="fp32", resort_every=100, **bed_kw) -> int:
@@ -76,7 +92,7 @@ class Server:
     """Runs a job stream in real time (arrival times in seconds from start)."""
 
     def __init__(self, budget_bytes=64 << 30, precision="fp32", resort_every=100, device="cuda",
-                 clock=time.perf_counter, speed=1.0, config=None):
+                 clock=time.perf_counter, speed=1.0, config=None, slots=256, depth=2, prefetch=4):
         import torch
 
         self.torch = torch
@@ -90,98 +106,165 @@ class Server:
         self.config = config
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
+        self.side = torch.cuda.Stream(self.device)  # bed creation
         self.clock = clock
         self.speed = float(speed)  # arrival times are divided by speed
+        self.slots = int(slots)
+        self.depth = max(1, int(depth))
+        self.prefetch = int(prefetch)
         self.active: list[_Active] = []
         self.used = 0
-        self.batch = None
-        self.dirty = False
         self.chunks = 0
-        self.rebuilds = 0
+        self.batches = 0         # slot batches created (one per run)
+        self.layout_changes = 0  # admissions and retirements between chunks
 
     def _bed_kw(self, wl) -> dict:
         if self.config is None:
             return dict(resort_every=self.resort_every)
         return autotune.bed_kwargs(wl, self.config)
 
-    def _admit(self, job, wl, now):
+    def _prepare(self, job):
+        """Host work of a job before it can be admitted (worker thread): its
+        bed's arrays and its device footprint."""
+        wl = job.workload()
+        return wl, footprint(wl, self.precision, **self._bed_kw(wl))
+
+    def _admit(self, sb, job, wl, now):
         torch = self.torch
-        bed = cfddem.bed_from_workload(wl, precision=self.precision, device=self.device, stream=self.stream,
-                                       **self._bed_kw(wl))
-        U = torch.as_tensor(wl.U, dtype=torch.float64, device=self.device).contiguous()
-        P = torch.as_tensor(wl.P, dtype=torch.float64, device=self.device).contiguous()
-        self.active.append(_Active(job, wl, bed, U, P, now))
-        self.dirty = True
+        with torch.cuda.stream(self.side):
+            bed = cfddem.bed_from_workload(wl, precision=self.precision, device=self.device, stream=self.side,
+                                           **self._bed_kw(wl))
+            U = torch.as_tensor(wl.U, dtype=torch.float64, device=self.device).contiguous()
+            P = torch.as_tensor(wl.P, dtype=torch.float64, device=self.device).contiguous()
+            self.side.synchronize()  # created (only the side stream's own work)
+        # from now on the bed lives on the batch's stream
+        for t in (bed.workspace, U, P):
+            t.record_stream(self.stream)
+        bed.stream = self.stream
+        slot = self._free_slots.pop()
+        sb.admit(slot, bed, (U, P))
+        self.active.append(_Active(job, bed, U, P, slot, now))
+        self.layout_changes += 1
 
-    def _retire(self, a, now_fn) -> JobResult:
-        err, _ = a.bed.poll()  # synchronizes the stream
+    def _retire(self, sb, a) -> _Finishing:
+        """Leaves the slot now; the final state is read behind the chunks
+        already enqueued."""
+        torch = self.torch
+        sb.retire(a.slot)
+        self._free_slots.append(a.slot)
+        self.layout_changes += 1
         st = a.bed.read_state()
-        x, v, w = (st[k].cpu().numpy() for k in ("x", "v", "w"))
-        res = JobResult(a.job.index, a.job.n, a.job.steps, a.job.arrival, a.admitted, now_fn(), x, v, w, err)
-        a.bed.close()
-        self.dirty = True
-        return res
+        host = {}
+        for k in ("x", "v", "w"):
+            h = torch.empty(st[k].shape, dtype=st[k].dtype, pin_memory=True)
+            h.copy_(st[k], non_blocking=True)
+            host[k] = h
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return _Finishing(a, host, ev)
 
-    def _rebuild(self):
-        if self.batch is not None:
-            self.batch.close()
-            self.batch = None
-        if self.active:
-            self.batch = cfddem.Batch([a.bed for a in self.active], [(a.U, a.P) for a in self.active],
-                                      stream=self.stream)
-        self.dirty = False
-        self.rebuilds += 1
+    def _finish(self, f, now, sizes) -> JobResult:
+        a = f.a
+        # the batch's stream is past this job's last work: its error flag is
+        # read on the side stream, without waiting for the chunks after it
+        a.bed.stream = self.side
+        err, _ = a.bed.poll()
+        x, v, w = (f.host[k].numpy().copy() for k in ("x", "v", "w"))
+        res = JobResult(a.job.index, a.job.n, a.job.steps, a.job.arrival, a.admitted, now, x, v, w, err)
+        a.bed.close()
+        self.used -= sizes.pop(a.job.index)
+        return res
 
     def run(self, jobs):
         """Serve `jobs` (objects with index, arrival, steps and workload()).
         Returns (results, wall seconds)."""
+        torch = self.torch
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
         sizes = {}
-        wls = {}
+        prepared = {}   # job index -> future of (workload, footprint)
         results = []
+        finishing: list[_Finishing] = []
+        inflight = deque()  # events of enqueued chunks
+        self._free_slots = list(range(self.slots - 1, -1, -1))
+        held_n = 0
+        # limits of what the batch may hold at once: the memory budget bounds
+        # both (a bed's workspace takes more than 500 bytes per particle and
+        # its coupling outputs more than 300 per element)
+        sb = cfddem.SlotBatch(self.slots, max_particles=max(1, self.budget // 500),
+                              max_elements=max(1, self.budget // 300), couples=True, device=self.device,
+                              stream=self.stream)
+        self.batches += 1
+        pool = ThreadPoolExecutor(max_workers=2)
         t0 = self.clock()
 
         def now():
             return (self.clock() - t0) * self.speed
 
-        while pending or self.active:
-            # admissions: arrived jobs, oldest first, while the budget allows
-            while pending and pending[0].arrival <= now():
-                j = pending[0]
-                if j.index not in sizes:
-                    wls[j.index] = j.workload()
-                    sizes[j.index] = footprint(wls[j.index], self.precision, **self._bed_kw(wls[j.index]))
-                if self.active and self.used + sizes[j.index] > self.budget:
-                    break
-                pending.popleft()
-                self.used += sizes[j.index]
-                self._admit(j, wls.pop(j.index), now())
-            if not self.active:
-                # idle until the next arrival
-                wait = (pending[0].arrival - now()) / self.speed
-                if wait > 0:
-                    time.sleep(wait)
-                continue
-            if self.dirty:
-                self._rebuild()
-            self.batch.run(1, CHUNK_STEPS, couple=True)
-            self.chunks += 1
-            for a in self.active:
-                a.left -= CHUNK_STEPS
-            done = [a for a in self.active if a.left <= 0]
-            if done:
-                self.active = [a for a in self.active if a.left > 0]
-                if self.batch is not None:
-                    self.batch.close()  # the retiring beds leave the batch first
-                    self.batch = None
-                for a in done:
-                    results.append(self._retire(a, now))
-                    self.used -= sizes[a.job.index]
-            else:
-                self.stream.synchronize()
-        if self.batch is not None:
-            self.batch.close()
-            self.batch = None
+        def prefetch():
+            for j in list(pending)[:self.prefetch]:
+                if j.index not in prepared:
+                    prepared[j.index] = pool.submit(self._prepare, j)
+
+        def finish_ready(block=False):
+            for f in list(finishing):
+                if block:
+                    f.event.synchronize()
+                if f.event.query():
+                    finishing.remove(f)
+                    results.append(self._finish(f, now(), sizes))
+
+        try:
+            while pending or self.active or finishing:
+                prefetch()
+                # admissions: arrived jobs, oldest first, while the budget allows
+                while pending and pending[0].arrival <= now() and self._free_slots:
+                    j = pending[0]
+                    wl, size = prepared.setdefault(j.index, pool.submit(self._prepare, j)).result()
+                    # over the budget only when nothing else holds device memory
+                    # (a retired job holds its memory until its result is read)
+                    if (self.active or finishing) and (self.used + size > self.budget
+                                                       or held_n + j.n > sb.limits.max_particles):
+                        break
+                    pending.popleft()
+                    prepared.pop(j.index)
+                    sizes[j.index] = size
+                    self.used += size
+                    held_n += j.n
+                    self._admit(sb, j, wl, now())
+                finish_ready()
+                if not self.active:
+                    if finishing:
+                        finish_ready(block=True)  # releases memory a waiting job may need
+                        continue
+                    # idle until the next arrival
+                    wait = (pending[0].arrival - now()) / self.speed
+                    if wait > 0:
+                        time.sleep(wait)
+                    continue
+                # at most `depth` chunks in flight: wait for the oldest
+                while len(inflight) >= self.depth:
+                    ev = inflight.popleft()
+                    while not ev.query():
+                        finish_ready()
+                        time.sleep(0)
+                sb.run(1, CHUNK_STEPS, couple=True)
+                ev = torch.cuda.Event()
+                ev.record(self.stream)
+                inflight.append(ev)
+                self.chunks += 1
+                for a in self.active:
+                    a.left -= CHUNK_STEPS
+                done = [a for a in self.active if a.left <= 0]
+                if done:
+                    self.active = [a for a in self.active if a.left > 0]
+                    for a in done:
+                        finishing.append(self._retire(sb, a))
+                        held_n -= a.job.n
+            finish_ready(block=True)
+        finally:
+            pool.shutdown(wait=True)
+            self.stream.synchronize()
+            sb.close()
         return results, (self.clock() - t0)
 
 

@@ -320,3 +320,94 @@ def test_polydisperse_smoothed_bed_under_graph_replay_across_resorts():
     assert beds_a[0].poll()[0] == 0
     a.close()
     b.close()
+
+
+# ---------------------------------------------------------------- slots: beds join and leave a running batch
+def _alone(w, chunks, final_couple, steps=5, resort=4):
+    (bed,), fields = _make([w], "fp32", resort=(resort,))
+    b = cfddem.Batch([bed], fields)
+    b.run(chunks, steps, couple=True)
+    out = None
+    if final_couple:
+        out = {k: v.cpu().numpy() for k, v in b.couple()[0].items()}
+    snap = _snapshot(bed)
+    b.close()
+    return snap, out
+
+
+def test_slots_admit_and_retire_match_each_bed_alone():
+    """Beds admitted at different times into a running batch, others retired
+    and their slots reused: every bed ends with the bits it gets alone over
+    the same number of chunks (state, contacts, coupling outputs), and a
+    retired bed keeps stepping on its own."""
+    wls = _q1_beds() + [synth.column_bed(synth.rng_for(4, 530), 2500, 1.7e-3, 0.8, 0.7, name="t3",
+                                         precision="fp64")]
+    beds, fields = _make(wls, "fp32", resort=(4, 4, 4, 4))
+    total_n = sum(w.n for w in wls)
+    total_el = sum(int(np.prod(w.fluid["n_el"])) for w in wls)
+    sb = cfddem.SlotBatch(slots=3, max_particles=total_n, max_elements=total_el)
+    chunks = {0: 0, 1: 0, 2: 0, 3: 0}
+    slot_of, outs = {}, {}
+
+    def admit(j, slot):
+        slot_of[j] = slot
+        outs[j] = sb.admit(slot, beds[j], fields[j])
+
+    def run(n):
+        sb.run(n, 5, couple=True)
+        for j in slot_of:
+            chunks[j] += n
+
+    admit(0, 0)
+    admit(1, 1)
+    run(2)
+    admit(2, 2)
+    run(1)
+    sb.retire(slot_of.pop(0))
+    run(2)
+    admit(3, 0)  # the freed slot is reused
+    run(2)
+    sb.couple()  # a last coupling step for the beds held now (1, 2, 3)
+    coupled = set(slot_of)
+    got_out = {j: {k: v.cpu().numpy() for k, v in outs[j].items()} for j in coupled}
+    for j in list(slot_of):
+        sb.retire(slot_of.pop(j))
+    got = {j: _snapshot(beds[j]) for j in range(4)}
+    sb.close()
+    assert chunks == {0: 3, 1: 7, 2: 5, 3: 2} and coupled == {1, 2, 3}
+    for j, w in enumerate(wls):
+        want, want_out = _alone(w, chunks[j], j in coupled)
+        _same(got[j], want)
+        if j in coupled:
+            _same(got_out[j], want_out)
+    # a retired bed is usable on its own
+    beds[0].step(3)
+    assert beds[0].poll()[0] == 0
+
+
+def test_slots_refuse_what_does_not_fit():
+    wls = _q1_beds()
+    beds, fields = _make(wls, "fp32")
+    sb = cfddem.SlotBatch(slots=2, max_particles=wls[0].n + wls[1].n,
+                          max_elements=sum(int(np.prod(w.fluid["n_el"])) for w in wls))
+    sb.admit(0, beds[0], fields[0])
+    with pytest.raises(cfddem.CfddemError) as ei:
+        sb.admit(0, beds[1], fields[1])  # slot taken
+    assert ei.value.status == cfddem.DEM_E_ARG
+    with pytest.raises(cfddem.CfddemError) as ei:
+        sb.admit(1, beds[0], fields[0])  # already held
+    assert ei.value.status == cfddem.DEM_E_ARG
+    with pytest.raises(cfddem.CfddemError) as ei:
+        sb.admit(1, beds[2], fields[2])  # more particles than the limit
+    assert ei.value.status == cfddem.DEM_E_CAPACITY
+    other = cfddem.bed_from_workload(wls[1], precision="fp64")
+    with pytest.raises(cfddem.CfddemError) as ei:
+        sb.admit(1, other, fields[1])  # another precision than the beds held
+    assert ei.value.status == cfddem.DEM_E_UNSUPPORTED
+    # a held bed can be neither destroyed nor restored
+    assert cfddem.load().dem_destroy(beds[0]._h) == cfddem.DEM_E_ARG
+    sb.retire(0)
+    sb.admit(1, other, fields[1])  # empty again: any precision
+    sb.run(1, 3, couple=True)
+    sb.close()
+    assert other.poll()[0] == 0
