@@ -240,6 +240,18 @@ dem_status dem_read_forces(dem_ctx *ctx, double *F_c, double *T_c, void *stream)
  * context without computing. */
 dem_status dem_kinetic_energy(dem_ctx *ctx, double *out, void *stream);
 
+/* For callers that cannot allocate or synchronize: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * sums as dem_kinetic_energy, bit for bit, with its per-block partial sums in
+ * a fixed device array of the library (1 MiB per GPU, held until the process
+ * ends) instead of the bed's workspace; calls no allocating routine and does
+ * not synchronize.  out: DEVICE array of 2 doubles, written on the stream.
+ * Beds of more than 256 x 65536 = 16,777,216 particles are refused with
+ * DEM_E_CAPACITY.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams or host threads) race; calls on one
+ * stream are ordered.  Returns the sticky error of a poisoned context. */
+dem_status dem_kinetic_energy_noalloc(dem_ctx *ctx, double *out, void *stream);
+
 /* Element and DEM-cell index of every particle at its last binning, original-ID
  * order.  Element index as in cfd_params; cell index
  * element*(kx*ky*kz) + (sz*ky+sy)*kx + sx with sub-cell s_a in [0, k_a).

@@ -33,7 +33,7 @@ DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
-           "dem_checkpoint_bytes", "dem_read_checkpoint", "dem_write_state",
+           "dem_checkpoint_bytes", "dem_read_checkpoint", "dem_write_state", "dem_kinetic_energy_noalloc",
 
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
@@ -105,6 +105,8 @@ def load():
     lib.dem_read_cells.argtypes = [vp, vp, vp, C.POINTER(i32), vp]
     lib.dem_kinetic_energy.restype = i32
     lib.dem_kinetic_energy.argtypes = [vp, C.POINTER(dbl), vp]
+    lib.dem_kinetic_energy_noalloc.restype = i32
+    lib.dem_kinetic_energy_noalloc.argtypes = [vp, vp, vp]
     lib.dem_read_contacts.restype = i32
     lib.dem_read_contacts.argtypes = [vp, vp, vp, i64, C.POINTER(i64), vp]
     lib.dem_poll.restype = i32

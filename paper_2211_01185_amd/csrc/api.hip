@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -718,6 +719,37 @@ struct dem_ctx {
     if ((__VA_ARGS__) != hipSuccess) return DEM_E_HIP; \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free kinetic-energy call
+// ---------------------------------------------------------------------------
+// Per-block partial sums (2 per block of 256 particles) of
+// dem_kinetic_energy_noalloc live in this fixed array, which every GPU the
+// library runs on holds for the life of the process (1 MiB), instead of in a
+// bed's workspace.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the device current at the first call there.
+constexpr int kEnergyScratchBlocks = 65536;  // beds of up to 256 x 65536 particles
+static __device__ __align__(256) double scratch[2 * kEnergyScratchBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+dem_status scratch_of_current_device(double **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DEM_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DEM_E_HIP;
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DEM_OK;
+}
+}  // namespace
+
 static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   Buffers &B = ctx->B;
   Dev &D = B.D;
@@ -1206,6 +1238,23 @@ dem_status dem_kinetic_energy(dem_ctx *ctx, double *out, void *stream) {
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(out, part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return DEM_OK;
+}
+
+dem_status dem_kinetic_energy_noalloc(dem_ctx *ctx, double *out, void *stream) {
+  if (!ctx || !out) return DEM_E_ARG;
+  if (ctx->poisoned) return ctx->poisoned;
+  const Dev &D = ctx->B.D;
+  const int nb = blocks(D.n, 256);
+  if (nb > kEnergyScratchBlocks) return DEM_E_CAPACITY;
+  double *part = nullptr;
+  const dem_status r = scratch_of_current_device(&part);
+  if (r != DEM_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  // every block writes its partials before the total reads them: nothing to clear
+  k_energy_partials<<<nb, 256, 0, st>>>(D, part);
+  k_energy_total<<<1, 64, 0, st>>>(nb, part, out);
+  HIP_TRY(hipGetLastError());
   return DEM_OK;
 }
 
