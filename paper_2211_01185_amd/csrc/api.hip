@@ -276,7 +276,8 @@ struct Carver {
 struct Buffers {
   Dev D;
   // alternates for the re-sort (swapped with D's arrays)
-  double *x2, *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2, *whdt2;
+  double4 *x2;
+  double *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2, *whdt2;
   int *oid2, *cell2;
   unsigned char *wmask2;
   int *perm;                    // new index -> old index of the last re-sort
@@ -318,11 +319,10 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
     }
   }
   for (int b = 0; b < 2; ++b) {
-    D.xs[b] = c.take<double>(3 * n);
-    D.vhs[b] = c.take<double>(3 * n);
-    D.whs[b] = c.take<double>(3 * n);
+    D.pr[b] = c.take<double4>(n);
+    D.vm[b] = c.take<double4>(n);
+    D.ws[b] = c.take<double4>(n);
     D.slot[b] = c.take<int>((size_t)S.grid.ncells * S.cap);
-    D.srec[b] = c.take<float4>((size_t)S.grid.ncells * S.cap);
   }
   for (int b = 0; b < 3; ++b) {
     D.cell[b] = c.take<int>(n);
@@ -346,7 +346,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   D.wmask = c.take<unsigned char>(n);
   D.whdt = c.take<double>(3 * kWalls * n);
   D.occ = c.take<int>((size_t)S.grid.n_elem);
-  B.x2 = c.take<double>(3 * n);
+  B.x2 = c.take<double4>(n);
   B.v2 = c.take<double>(3 * n);
   B.w2 = c.take<double>(3 * n);
   B.Fc2 = c.take<double>(3 * n);
@@ -374,8 +374,8 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
   const int n = D.n;
+  D.pr[0][k] = make_double4(x[k], x[n + k], x[2 * n + k], r[k]);
   for (int c = 0; c < 3; ++c) {
-    D.xs[0][c * n + k] = x[c * n + k];
     D.v[c * n + k] = v[c * n + k];
     D.w[c * n + k] = w[c * n + k];
     D.Fc[c * n + k] = 0.0;
@@ -399,6 +399,16 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
                                 : 0x7ff8000000000000ULL;
   atomicMax(&rbits[0], bits);
   atomicMin(&rbits[1], bits);
+}
+
+__global__ void k_scatter_pos(int n, const int *oid, const double4 *src, double *dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int o = oid[k];
+  const double4 p = src[k];
+  dst[o] = p.x;
+  dst[n + o] = p.y;
+  dst[2 * n + o] = p.z;
 }
 
 __global__ void k_scatter3(int n, const int *oid, const double *src, double *dst) {
@@ -520,12 +530,14 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long a, unsigned
 }
 
 struct PermSrc {
-  const double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
+  const double4 *x;
+  const double *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   const int *oid, *cell;
   const unsigned char *wmask;
 };
 struct PermDst {
-  double *x, *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
+  double4 *x;
+  double *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   int *oid, *cell;
   unsigned char *wmask;
 };
@@ -537,8 +549,8 @@ __global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   if (k >= n) return;
   int o = perm[k];
   if (o < 0 || o >= n) o = k;  // only after a capacity error (already flagged)
+  d.x[k] = s.x[o];
   for (int c = 0; c < 3; ++c) {
-    d.x[c * n + k] = s.x[c * n + o];
     d.v[c * n + k] = s.v[c * n + o];
     d.w[c * n + k] = s.w[c * n + o];
     d.Fc[c * n + k] = s.Fc[c * n + o];
@@ -669,7 +681,7 @@ __global__ void k_restore_words(int *err, int lb_word, int cur, int bits) {
 // Checkpoint blob: a 256-byte header, then the state arrays in the context's
 // internal (cell-sorted) order, each at a 256-byte aligned offset.
 constexpr uint64_t kCkptMagic = 0x4b43424d45444643ULL;  // "CFDEMBCK"
-constexpr int kCkptVersion = 1;
+constexpr int kCkptVersion = 2;
 struct CkptHeader {
   uint64_t magic;
   int32_t abi, version;
@@ -759,13 +771,13 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   HIP_TRY(device_exclusive_scan<int, int>(D.grid.ncells, D.cnt[p3], D.cap, B.start, B.bsum, st));
   k_rank<<<blocks(n, 256), 256, 0, st>>>(D, p2, p3, B.start, B.perm);
   HIP_TRY(hipGetLastError());
-  PermSrc src{D.xs[p2], D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell[p3],
+  PermSrc src{D.pr[p2], D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell[p3],
               D.wmask};
   PermDst dst{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.whdt2, B.oid2, B.cell2,
               B.wmask2};
   k_permute<<<blocks(n, 256), 256, 0, st>>>(n, B.perm, src, dst);
   HIP_TRY(hipGetLastError());
-  std::swap(D.xs[p2], B.x2);
+  std::swap(D.pr[p2], B.x2);
   std::swap(D.v, B.v2);
   std::swap(D.w, B.w2);
   std::swap(D.Fc, B.Fc2);
@@ -838,7 +850,7 @@ static int ckpt_spans(dem_ctx *ctx, int cur, Span *sp) {
   Dev &D = ctx->B.D;
   const size_t n = (size_t)D.n, mn = (size_t)D.maxn * n;
   int k = 0;
-  sp[k++] = {D.xs[ctx->s & 1], 24 * n};
+  sp[k++] = {D.pr[ctx->s & 1], 32 * n};
   sp[k++] = {D.v, 24 * n};
   sp[k++] = {D.w, 24 * n};
   sp[k++] = {D.Fc, 24 * n};
@@ -984,15 +996,6 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
   D.maxn = S.maxn;
   D.skin = S.skin;
   D.trig2 = (0.499 * S.skin) * (0.499 * S.skin);
-  {
-    // single-precision coordinates are off by at most 2^-24 of the largest
-    // coordinate magnitude; the broad-search test widens its cutoff by 2^-20
-    // of it (and by 2^-18 relative), so that it keeps every pair that the
-    // exact test would
-    double xm = 0.0;
-    for (int a = 0; a < 3; ++a) xm = fmax(xm, fmax(fabs(S.grid.lo[a]), fabs(S.grid.hi[a])));
-    D.marg = (float)ldexp(xm, -20);
-  }
   D.dt = dp->dt;
   for (int a = 0; a < 3; ++a) D.g[a] = dp->gravity[a];
   D.grid = S.grid;
@@ -1206,9 +1209,13 @@ dem_status dem_read_state(dem_ctx *ctx, double *x, double *v, double *omega, dou
   if (!ctx) return DEM_E_ARG;
   hipStream_t st = (hipStream_t)stream;
   const Dev &D = ctx->B.D;
-  const double *src[4] = {D.xs[ctx->s & 1], D.v, D.w, D.ffp};
-  double *dst[4] = {x, v, omega, f_fp};
-  for (int i = 0; i < 4; ++i) {
+  if (x) {
+    k_scatter_pos<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, D.pr[ctx->s & 1], x);
+    HIP_TRY(hipGetLastError());
+  }
+  const double *src[4] = {nullptr, D.v, D.w, D.ffp};
+  double *dst[4] = {nullptr, v, omega, f_fp};
+  for (int i = 1; i < 4; ++i) {
     if (!dst[i]) continue;
     k_scatter3<<<blocks(D.n, 256), 256, 0, st>>>(D.n, D.oid, src[i], dst[i]);
     HIP_TRY(hipGetLastError());

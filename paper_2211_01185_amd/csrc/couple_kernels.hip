@@ -678,16 +678,17 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
   // ---- 2. void fraction; the state of the thread's first particle is
   // loaded in the same round trip as its radius
-  const double *X = sel(D.xs, p2);
+  const double4 *X = sel(D.pr, p2);
   const int k0 = tid < total ? sh.ids[tid] : -1;
   double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, r0 = 0.0;
   if (k0 >= 0) {
+    const double4 p = X[k0];
+    x0[0] = p.x;
+    x0[1] = p.y;
+    x0[2] = p.z;
+    r0 = p.w;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      x0[c] = X[c * n + k0];
-      u0[c] = D.v[c * n + k0];
-    }
-    r0 = D.rad[k0];
+    for (int c = 0; c < 3; ++c) u0[c] = D.v[c * n + k0];
   }
   double vsum = k0 >= 0 ? 4.0 / 3.0 * kPi * r0 * r0 * r0 : 0.0;
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
@@ -714,13 +715,11 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   if (k0 >= 0) particle_force<R, ORD, MODE>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sh.sE, sums);
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
     const int k = sh.ids[t];
-    double xp[3], up[3];
+    const double4 p = X[k];
+    double xp[3] = {p.x, p.y, p.z}, up[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      xp[c] = X[c * n + k];
-      up[c] = D.v[c * n + k];
-    }
-    particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, D.rad[k], eps_c, sh.sU, sh.sP, sh.sE, sums);
+    for (int c = 0; c < 3; ++c) up[c] = D.v[c * n + k];
+    particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, p.w, eps_c, sh.sU, sh.sP, sh.sE, sums);
   }
   group_sum_n<GW>(sums, active);
   if (lane == 0)

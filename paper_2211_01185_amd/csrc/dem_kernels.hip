@@ -2,26 +2,27 @@
 // & Blais, arXiv 2211.01185), one kernel launch per step:
 //   drift_bin   : opens a run of steps: half kick + drift from the boundary
 //                 state, binning of the new centres into the nested cell grid
-//                 (atomic slot insertion, with a single-precision record of
-//                 position and radius per slot), displacement test that requests a
+//                 (atomic slot insertion), displacement test that requests a
 //                 new broad search
 //   force_kick  : step s: broad search when requested (cell-list neighbour
 //                 list over the 27-cell stencil: every pair within
-//                 R_i + R_j + skin, found by a single-precision test against
-//                 the cells' slot records whose cutoff is widened to cover
-//                 its rounding; sorted by partner original ID, history carried
-//                 by a merge),
+//                 R_i + R_j + skin, the candidates shared out over the lanes
+//                 of the particle's group and tested on their position
+//                 records; sorted by partner original ID, history carried
+//                 over by a binary search of the new list in LDS),
 //                 fine search (exact overlap test over the list and the six
 //                 walls), Hertz-Mindlin contact law (Table "tab:viscoelastic",
 //                 contact-force equation) with tangential history and Coulomb
 //                 limit, per-particle gather of force and torque (no float
 //                 atomics), second half kick; when another step follows, also
 //                 its half kick, drift, binning and displacement test
-// Two lanes per particle over SoA FP64 arrays.  A pair is evaluated by both of
-// its particles, each from its own side; every quantity one side computes is
-// the exact negation of, or identical to, the other side's, so the forces are
-// exactly opposite and each particle keeps its own copy of the tangential
-// history in its own list slot.
+// The per-step state is kept as 32-byte records per particle (position and
+// radius; half-step velocity and mass; half-step angular velocity), so that a
+// partner costs a few 16-byte loads from three addresses.  A pair is
+// evaluated by both of its particles, each from its own side; every quantity
+// one side computes is the exact negation of, or identical to, the other
+// side's, so the forces are exactly opposite and each particle keeps its own
+// copy of the tangential history in its own list slot.
 //
 // Each kernel body takes the bed's Dev and the block index explicitly: the
 // single-bed kernels pass their argument and blockIdx.x, the batched kernels
@@ -32,12 +33,10 @@
 
 namespace cfddem {
 
-// Binning of x into the grid of a step (counts cnt, slots sl with their
-// single-precision records rec, cells cl) and the displacement test against
-// the last broad-search positions.
-__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], double r, int *cnt,
-                                    int *sl, float4 *rec, int *cl, int *flag, bool force_flag,
-                                    int &bits) {
+// Binning of x into the grid of a step (counts cnt, slots sl, cells cl) and
+// the displacement test against the last broad-search positions.
+__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], const double xbk[3], int *cnt,
+                                    int *sl, int *cl, int *flag, bool force_flag, int &bits) {
   int elem, cell;
   bool inside;
   bin_point(D.grid, xp, elem, cell, inside);
@@ -45,14 +44,12 @@ __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], dou
   if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
   cl[k] = cell;
   const int s = atomicAdd(&cnt[cell], 1);
-  if (s >= 0 && s < D.cap) {
+  if (s >= 0 && s < D.cap)
     sl[(size_t)cell * D.cap + s] = k;
-    rec[(size_t)cell * D.cap + s] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)r);
-  } else
+  else
     bits |= kErrCapacity;
   // a list built at xb stays complete while every particle is within skin/2
-  const int n = D.n;
-  const double d0 = xp[0] - D.xb[k], d1 = xp[1] - D.xb[n + k], d2 = xp[2] - D.xb[2 * n + k];
+  const double d0 = xp[0] - xbk[0], d1 = xp[1] - xbk[1], d2 = xp[2] - xbk[2];
   if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) atomicOr(flag, 1);
 }
 
@@ -60,40 +57,44 @@ __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], dou
 // drift + binning (first step of a run; also the creation-time binning)
 // ---------------------------------------------------------------------------
 // p2 = s & 1, p3 = s % 3 of the step being opened.  DRIFT = false bins the
-// positions already in xs[p2] (creation).
+// positions already in pr[p2] (creation, restore) and writes the step's
+// velocity records from the boundary velocities.
 template <bool DRIFT>
 __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int p3, int force_flag) {
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
-  const double *x0 = sel(D.xs, p2 ^ 1);
-  double *x1 = sel(D.xs, p2), *vh = sel(D.vhs, p2), *wh = sel(D.whs, p2);
+  double4 *x1 = sel(D.pr, p2), *vh = sel(D.vm, p2), *wh = sel(D.ws, p2);
+  const double m = D.mass[k];
+  const double r = D.rad[k];
   if (DRIFT) {
-    const double m = D.mass[k];
-    const double r = D.rad[k];
+    const double4 xo = sel(D.pr, p2 ^ 1)[k];
+    const double x0[3] = {xo.x, xo.y, xo.z};
     const double inertia = 0.4 * m * r * r;
+    double vhc[3], whc[3];
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + k;
       const double acc = (D.Fc[i] + D.ffp[i]) / m + D.g[c];
       const double alpha = D.Tc[i] / inertia;
-      const double vhc = D.v[i] + 0.5 * D.dt * acc;
-      const double whc = D.w[i] + 0.5 * D.dt * alpha;
-      xp[c] = x0[i] + D.dt * vhc;
-      vh[i] = vhc;
-      wh[i] = whc;
-      x1[i] = xp[c];
+      vhc[c] = D.v[i] + 0.5 * D.dt * acc;
+      whc[c] = D.w[i] + 0.5 * D.dt * alpha;
+      xp[c] = x0[c] + D.dt * vhc[c];
     }
+    x1[k] = make_double4(xp[0], xp[1], xp[2], r);
+    vh[k] = make_double4(vhc[0], vhc[1], vhc[2], m);
+    wh[k] = make_double4(whc[0], whc[1], whc[2], 0.0);
   } else {
-    for (int c = 0; c < 3; ++c) {
-      const int i = c * n + k;
-      xp[c] = x1[i];
-      vh[i] = D.v[i];
-      wh[i] = D.w[i];
-    }
+    const double4 xo = x1[k];
+    xp[0] = xo.x;
+    xp[1] = xo.y;
+    xp[2] = xo.z;
+    vh[k] = make_double4(D.v[k], D.v[n + k], D.v[2 * n + k], m);
+    wh[k] = make_double4(D.w[k], D.w[n + k], D.w[2 * n + k], 0.0);
   }
   int bits = 0;
-  bin_and_test(D, k, xp, D.rad[k], sel(D.cnt, p3), sel(D.slot, p2), sel(D.srec, p2), sel(D.cell, p3),
-               D.flag + p3, force_flag != 0, bits);
+  const double xbk[3] = {D.xb[k], D.xb[n + k], D.xb[2 * n + k]};
+  bin_and_test(D, k, xp, xbk, sel(D.cnt, p3), sel(D.slot, p2), sel(D.cell, p3), D.flag + p3, force_flag != 0,
+               bits);
   if (bits) atomicOr(D.err, bits);
 }
 
@@ -192,10 +193,10 @@ __device__ inline void lever_sum(double ra, double wa0, double wa1, double wa2, 
 // ---------------------------------------------------------------------------
 // L consecutive lanes of a wavefront share one particle: lane l walks the list
 // entries t = l, l + L, ..., lane L-1 also the walls, and the partial force
-// and torque are summed over the L lanes in a fixed butterfly order.  Lane 0
-// does a broad search, when one is due, into the group's list in LDS; every
-// lane then stores its own entries.  Lane 0 finishes the step.
-// p2 = s & 1, p3 = s % 3.  The grid p3 / slot buffer p2 hold x_s.
+// and torque are summed over the L lanes in a fixed butterfly order.  When a
+// broad search is due the group's lanes share its candidates and build the
+// list in LDS; every lane then stores its own entries.  Lane 0 finishes the
+// step.  p2 = s & 1, p3 = s % 3.  The grid p3 / slot buffer p2 hold x_s.
 // ADVANCE = false: creation-time evaluation (no history advance, no kick).
 // src: after a re-sort, the index each particle had when its list was built
 //      (NULL otherwise).
@@ -214,117 +215,104 @@ __device__ inline unsigned long long group_or(unsigned long long v) {
   return v;
 }
 
-// ROLL: some rolling friction coefficient is nonzero (a separate
-// instantiation, so that the kernels without it keep their registers).
-template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-__device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src) {
-  const int gid = blk * kForceBlock + threadIdx.x;
-  const int a = gid / L;
-  const int lane = gid % L;
-  if (a >= D.n) return;  // whole groups leave together
-  const int n = D.n;
-  const Grid &G = D.grid;
-  const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
-  const int r3 = p3 == 0 ? 2 : p3 - 1;  // (s - 1) % 3
-  const double *xs = sel(D.xs, p2);
-  const double *vhs = sel(D.vhs, p2);
-  const double *whs = sel(D.whs, p2);
-  const int lold = D.lbuf[p3];
-  const bool rebuild = !ADVANCE || src != nullptr || D.flag[p3] != 0;
-  const int cur = rebuild ? (lold ^ 1) : lold;
+// LDS writes of one lane become visible to the other lanes of its wavefront.
+__device__ inline void wave_publish() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-  const double xa0 = xs[a], xa1 = xs[n + a], xa2 = xs[2 * n + a];
-  const double ra = D.rad[a];
-  const size_t mn = (size_t)D.maxn * n;
-  int bits = 0;
-  unsigned long long mask_prev;
-  int m = 0;  // list length (kept in registers: only lane 0 stores it)
-
-  // candidate list of this group while a broad search runs (lane 0 fills it)
-  extern __shared__ unsigned long long sh_list[];
+// Broad search of particle a by the L lanes of its group over the 27-cell
+// stencil of grid p3 / slot buffer p2.  Plane by plane, the nine cell counts
+// are loaded together, and the plane's candidates are dealt out to the lanes
+// four at a time: their slot entries in one round trip, their position
+// records and original IDs in a second, then the exact test
+// |x_b - x_a| < R_a + R_b + skin; the lanes then insert their passing
+// candidates into the group's LDS list, sorted by partner original ID, one
+// lane after the other.  Returns the list length, the same on every lane of
+// the group.
+template <int L>
+__device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3, double xa0, double xa1,
+                                   double xa2, double ra, unsigned long long *my_list, int &bits) {
   constexpr int kGroups = kForceBlock / L;
-  unsigned long long *my_list = sh_list + threadIdx.x / L;  // stride kGroups
-
-  if (rebuild) {
-    // ---- broad search over the 27-cell stencil (lane 0), insertion-sorted
-    //      by partner original ID in LDS
-    if (lane == 0) {
-      const int ca = sel(D.cell, p3)[a];
-      const int el = ca / G.kk, sub = ca - el * G.kk;
-      const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
-      const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
-      const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
-      // the index of a stencil cell is a sum of one term per axis (element
-      // part plus sub-cell part); -1 marks a term outside the grid
-      int tx[3], ty[3], tz[3];
-      #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int gx = g0 + d - 1, gy = g1 + d - 1, gz = g2 + d - 1;
-        tx[d] = (gx >= 0 && gx < G.gc[0]) ? (gx / G.k[0]) * G.kk + gx % G.k[0] : -1;
-        ty[d] = (gy >= 0 && gy < G.gc[1]) ? (gy / G.k[1]) * G.n_el[0] * G.kk + (gy % G.k[1]) * G.k[0] : -1;
-        tz[d] = (gz >= 0 && gz < G.gc[2])
-                    ? (gz / G.k[2]) * G.n_el[1] * G.n_el[0] * G.kk + (gz % G.k[2]) * G.k[1] * G.k[0]
-                    : -1;
+  const Grid &G = D.grid;
+  const int ca = sel(D.cell, p3)[a];
+  const int el = ca / G.kk, sub = ca - el * G.kk;
+  const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
+  const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
+  const int g2 = (el / (G.n_el[0] * G.n_el[1])) * G.k[2] + sub / (G.k[0] * G.k[1]);
+  // the index of a stencil cell is a sum of one term per axis (element part
+  // plus sub-cell part); -1 marks a term outside the grid
+  int tx[3], ty[3], tz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int gx = g0 + d - 1, gy = g1 + d - 1, gz = g2 + d - 1;
+    tx[d] = (gx >= 0 && gx < G.gc[0]) ? (gx / G.k[0]) * G.kk + gx % G.k[0] : -1;
+    ty[d] = (gy >= 0 && gy < G.gc[1]) ? (gy / G.k[1]) * G.n_el[0] * G.kk + (gy % G.k[1]) * G.k[0] : -1;
+    tz[d] = (gz >= 0 && gz < G.gc[2])
+                ? (gz / G.k[2]) * G.n_el[1] * G.n_el[0] * G.kk + (gz % G.k[2]) * G.k[1] * G.k[0]
+                : -1;
+  }
+  const int *cnt = sel(D.cnt, p3);
+  const int *slot = sel(D.slot, p2);
+  const double4 *P = sel(D.pr, p2);
+  const double rsk = ra + D.skin;
+  constexpr int kCand = 4;
+  const int first_lane = (threadIdx.x & 63) & ~(L - 1);
+  int m = 0;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {
+    // the plane's candidates are numbered 0 .. tot-1 across its nine cells
+    int cc[9], pf[10];
+    pf[0] = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int z = tz[dz], y = ty[j / 3], x = tx[j % 3];
+      const bool in = z >= 0 && y >= 0 && x >= 0;
+      cc[j] = in ? z + y + x : 0;
+      const int cj = cnt[cc[j]];
+      pf[j + 1] = pf[j] + (in ? min(cj, D.cap) : 0);
+    }
+    const int tot = pf[9];
+#pragma unroll 1
+    for (int q0 = 0; q0 < tot; q0 += kCand * L) {
+      // round trip 1: the candidates' slot entries; round trip 2: their
+      // position records and original IDs, then the exact test
+      // |x_b - x_a| < R_a + R_b + skin
+      int bq[kCand];
+      bool ok[kCand];
+#pragma unroll
+      for (int i = 0; i < kCand; ++i) {
+        const int q = q0 + lane + L * i;
+        ok[i] = q < tot;
+        // the last cell whose first candidate is at or before q holds q
+        int c = cc[0], first = 0;
+#pragma unroll
+        for (int j = 1; j < 9; ++j)
+          if (q >= pf[j]) {
+            c = cc[j];
+            first = pf[j];
+          }
+        const size_t at = ok[i] ? (size_t)c * D.cap + (q - first) : 0;
+        bq[i] = slot[at];
+        ok[i] = ok[i] && bq[i] != a;
       }
-      const int *cnt = sel(D.cnt, p3);
-      const int *slot = sel(D.slot, p2);
-      const float4 *rec = sel(D.srec, p2);
-      // single-precision prefilter against the slot records, its cutoff
-      // widened so that it keeps every pair within ra + rb + skin exactly
-      const float xf0 = (float)xa0, xf1 = (float)xa1, xf2 = (float)xa2;
-      const float rsk = (float)ra + (float)D.skin;
-      constexpr float kCutRel = 1.0f + 0x1p-18f;
-      constexpr int kCand = 8;
-      m = 0;
-      #pragma unroll 1
-      for (int dz = 0; dz < 3; ++dz) {
-        const int z = dz == 0 ? tz[0] : (dz == 1 ? tz[1] : tz[2]);
-        if (z < 0) continue;
-        // the nine counts of this plane are loaded together; their prefix
-        // sums number the plane's candidates 0 .. tot-1 across its cells
-        int cc[9], pf[10];
-        pf[0] = 0;
-        #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-          const int y = ty[j / 3], x = tx[j % 3];
-          const bool in = y >= 0 && x >= 0;
-          cc[j] = in ? z + y + x : 0;
-          pf[j + 1] = pf[j] + (in ? min(cnt[cc[j]], D.cap) : 0);
-        }
-        const int tot = pf[9];
-        // eight candidates at a time, whatever cells they are in: slot
-        // indices and records loaded together, then the original IDs of the
-        // candidates that pass
-        #pragma unroll 1
-        for (int q0 = 0; q0 < tot; q0 += kCand) {
-          int bq[kCand];
-          float4 rq[kCand];
-          bool ok[kCand];
-          #pragma unroll
-          for (int i = 0; i < kCand; ++i) {
-            const int q = q0 + i;
-            ok[i] = q < tot;
-            // the last cell whose first candidate is at or before q holds q
-            int c = cc[0], first = 0;
-            #pragma unroll
-            for (int j = 1; j < 9; ++j)
-              if (q >= pf[j]) {
-                c = cc[j];
-                first = pf[j];
-              }
-            const size_t at = (size_t)c * D.cap + (q - first);
-            bq[i] = ok[i] ? slot[at] : a;
-            rq[i] = ok[i] ? rec[at] : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-          unsigned oq[kCand];
-          #pragma unroll
-          for (int i = 0; i < kCand; ++i) {
-            const float d0 = rq[i].x - xf0, d1 = rq[i].y - xf1, d2 = rq[i].z - xf2;
-            const float cut = (rsk + rq[i].w) * kCutRel + D.marg;
-            ok[i] = ok[i] && bq[i] != a && d0 * d0 + d1 * d1 + d2 * d2 < cut * cut;
-            oq[i] = ok[i] ? (unsigned)D.oid[bq[i]] : 0u;
-          }
-          #pragma unroll
+      unsigned oq[kCand];
+#pragma unroll
+      for (int i = 0; i < kCand; ++i) {
+        const int b = ok[i] ? bq[i] : a;
+        const double4 pb = P[b];
+        oq[i] = (unsigned)D.oid[b];
+        const double d0 = pb.x - xa0, d1 = pb.y - xa1, d2 = pb.z - xa2;
+        const double cut = rsk + pb.w;
+        ok[i] = ok[i] && d0 * d0 + d1 * d1 + d2 * d2 < cut * cut;
+      }
+      // insertion by partner original ID, one lane of the group after the
+      // other; the list length follows each lane's turn
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (lane == l) {
+#pragma unroll
           for (int i = 0; i < kCand; ++i) {
             if (!ok[i]) continue;
             const unsigned long long key = ((unsigned long long)oq[i] << 32) | (unsigned)bq[i];
@@ -341,93 +329,208 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
             }
           }
         }
+        if (L > 1) {
+          wave_publish();
+          m = __shfl(m, first_lane + l, 64);
+        }
       }
+    }
+  }
+  return m;
+}
+
+// One neighbour-list entry's data: the partner's position, velocity and
+// spin records and the entry's stored tangential overlap.
+struct Entry {
+  double4 p, v, w;
+  double h[3];
+};
+// b comes from a list entry; an index outside [0, n) (only a slot past the
+// list's length can hold one) reads the particle itself.
+__device__ __forceinline__ Entry load_entry(const double4 *P, const double4 *VM, const double4 *WS,
+                                            const double *hdt, size_t mn, int n, int a, int b, int t) {
+  b = (unsigned)b < (unsigned)n ? b : a;
+  Entry e;
+  e.p = P[b];
+  e.v = VM[b];
+  e.w = WS[b];
+  const size_t i = (size_t)t * n + a;
+  e.h[0] = hdt[i];
+  e.h[1] = hdt[mn + i];
+  e.h[2] = hdt[2 * mn + i];
+  return e;
+}
+
+// ROLL: some rolling friction coefficient is nonzero (a separate
+// instantiation, so that the kernels without it keep their registers).
+template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
+__device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src) {
+  const int gid = blk * kForceBlock + threadIdx.x;
+  const int a = gid / L;
+  const int lane = gid % L;
+  if (a >= D.n) return;  // whole groups leave together
+  const int n = D.n;
+  const Grid &G = D.grid;
+  const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
+  const int r3 = p3 == 0 ? 2 : p3 - 1;  // (s - 1) % 3
+  const double4 *P = sel(D.pr, p2);
+  const double4 *VM = sel(D.vm, p2);
+  const double4 *WS = sel(D.ws, p2);
+  const int lold = D.lbuf[p3];
+  const bool rebuild = !ADVANCE || src != nullptr || D.flag[p3] != 0;
+  const int cur = rebuild ? (lold ^ 1) : lold;
+
+  const double4 pa = P[a];
+  const double xa0 = pa.x, xa1 = pa.y, xa2 = pa.z, ra = pa.w;
+  // walls touched at the last step, and the cell of x_{s-1} whose count this
+  // particle clears at the end: loaded first, so that waiting for them later
+  // waits for nothing else
+  const unsigned wmask_a = D.wmask[a];
+  const int c_old = sel(D.cell, r3)[a];
+  const size_t mn = (size_t)D.maxn * n;
+  constexpr int kCand8 = 8;     // old list entries per lane and round trip
+  int bits = 0;
+  int m_new = 0;                // list length after a broad search
+  unsigned long long carried = 0;  // entries of this lane with carried history
+
+  // the group's list (maxn keys, stride kGroups) and, while the history is
+  // carried after a broad search, the old position each new entry takes its
+  // history from (maxn bytes, stride kGroups)
+  extern __shared__ unsigned long long sh_list[];
+  constexpr int kGroups = kForceBlock / L;
+  unsigned long long *my_list = sh_list + threadIdx.x / L;
+  unsigned char *my_from =
+      reinterpret_cast<unsigned char *>(sh_list + (size_t)D.maxn * kGroups) + threadIdx.x / L;
+
+  if (rebuild) {
+    const int m = broad_search<L>(D, a, lane, p2, p3, xa0, xa1, xa2, ra, my_list, bits);
+    m_new = m;
+    if (lane == 0) {
       sel(D.ln, cur)[a] = m;
       D.xb[a] = xa0;
       D.xb[n + a] = xa1;
       D.xb[2 * n + a] = xa2;
     }
-    // lane 0's LDS list and count become visible to the rest of the group
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    m = __shfl(m, (threadIdx.x & 63) & ~(L - 1), 64);
-    // ---- each lane stores its own entries and carries their tangential
-    //      history from the previous list (both sorted by partner oid)
+    // ---- tangential history of the pairs that touched at the last step:
+    //      each lane finds its share of the old touching entries in the new
+    //      (sorted) list by binary search in LDS and notes where each new
+    //      entry's history comes from; then every lane stores its own new
+    //      entries and copies their history
     const int s = src ? src[a] : a;
     const int mo = sel(D.ln, lold)[s];
     const unsigned long long mask_old = sel(D.hmask, lold)[s];
     const unsigned long long *olst = sel(D.nbr, lold);
-    unsigned long long *lst = sel(D.nbr, cur);
-    unsigned long long carried = 0;
-    int q = 0;
+    for (int t = lane; t < m; t += L) my_from[t * kGroups] = 0;
+    wave_publish();
+    if (ADVANCE) {
+#pragma unroll 1
+      for (int q0 = 0; q0 < mo; q0 += kCand8 * L) {
+        unsigned ok_old[kCand8];
+#pragma unroll
+        for (int i = 0; i < kCand8; ++i) {
+          const int qo = q0 + lane + L * i;
+          const bool live = qo < mo && ((mask_old >> qo) & 1ull);
+          ok_old[i] = live ? (unsigned)(olst[(size_t)qo * n + s] >> 32) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int i = 0; i < kCand8; ++i) {
+          if (ok_old[i] == 0xffffffffu) continue;
+          int lo = 0, hi = m - 1;
+          while (lo <= hi) {
+            const int mid = (lo + hi) >> 1;
+            const unsigned om = (unsigned)(my_list[mid * kGroups] >> 32);
+            if (om == ok_old[i]) {
+              my_from[mid * kGroups] = (unsigned char)(q0 + lane + L * i + 1);
+              break;
+            }
+            if (om < ok_old[i])
+              lo = mid + 1;
+            else
+              hi = mid - 1;
+          }
+        }
+      }
+      wave_publish();
+    }
+    unsigned long long *lst_new = sel(D.nbr, cur);
     for (int t = lane; t < m; t += L) {
-      const unsigned long long key = my_list[t * kGroups];
-      lst[(size_t)t * n + a] = key;
-      const unsigned ot = (unsigned)(key >> 32);
-      while (q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) < ot) ++q;
-      if (ADVANCE && q < mo && (unsigned)(olst[(size_t)q * n + s] >> 32) == ot &&
-          ((mask_old >> q) & 1ull)) {
+      lst_new[(size_t)t * n + a] = my_list[t * kGroups];
+      const int from = my_from[t * kGroups];
+      if (from) {
         for (int c = 0; c < 3; ++c)
           sel(D.hdt, cur)[(size_t)c * mn + (size_t)t * n + a] =
-              sel(D.hdt, lold)[(size_t)c * mn + (size_t)q * n + s];
+              sel(D.hdt, lold)[(size_t)c * mn + (size_t)(from - 1) * n + s];
         carried |= 1ull << t;
       }
     }
-    mask_prev = carried;  // bits of this lane's entries
-  } else {
-    mask_prev = sel(D.hmask, cur)[a];
-    m = sel(D.ln, cur)[a];
   }
   // keep the fast path's loads below the (rare) broad search, so that their
   // registers are not live across it
   __asm__ __volatile__("" ::: "memory");
 
-  // ---- fine search and forces over this lane's list entries
-  const double va0 = vhs[a], va1 = vhs[n + a], va2 = vhs[2 * n + a];
-  const double wa0 = whs[a], wa1 = whs[n + a], wa2 = whs[2 * n + a];
-  const double ma = D.mass[a];
-  // the held fluid force, loaded with the rest of this particle's state (the
-  // kick after the list walk would otherwise wait for it)
+  // ---- one round trip: the list header, this lane's first entry (after a
+  //      broad search this lane stored its own entries and their history
+  //      itself), the last broad search's position, the particle's own
+  //      half-step state and held fluid force, and, on the walls' lane, the
+  //      history of the first wall touched last step.  Every load is
+  //      unconditional (a stale value is replaced by a select), so that no
+  //      branch makes the wavefront wait for the others.
+  const unsigned long long *lst = sel(D.nbr, cur);
+  double *hdt = sel(D.hdt, cur);
+  const unsigned long long hm = sel(D.hmask, cur)[a];
+  const int lnv = sel(D.ln, cur)[a];
+  unsigned long long key = lst[(size_t)min(lane, D.maxn - 1) * n + a];
+  const double xbl[3] = {D.xb[a], D.xb[n + a], D.xb[2 * n + a]};
+  const double4 va = VM[a], wa = WS[a];
+  const double va0 = va.x, va1 = va.y, va2 = va.z, ma = va.w;
+  const double wa0 = wa.x, wa1 = wa.y, wa2 = wa.z;
   const double fa[3] = {D.ffp[a], D.ffp[n + a], D.ffp[2 * n + a]};
+  const unsigned wold = (ADVANCE && lane == L - 1) ? wmask_a : 0u;
+  const int w_first = wold ? __ffs(wold) - 1 : 0;
+  const double wdt_l[3] = {D.whdt[(size_t)w_first * n + a], D.whdt[(size_t)(kWalls + w_first) * n + a],
+                           D.whdt[(size_t)(2 * kWalls + w_first) * n + a]};
+  const int m = rebuild ? m_new : lnv;
+  unsigned long long mask_prev = rebuild ? carried : hm;
+  const double xba[3] = {rebuild ? xa0 : xbl[0], rebuild ? xa1 : xbl[1], rebuild ? xa2 : xbl[2]};
+
+  // ---- fine search and forces over this lane's list entries
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   // rolling torques, summed apart and added to T only for a bed with rolling
   // friction, so that a bed without it gets the same arithmetic in either
   // instantiation
   double Tr[3] = {0.0, 0.0, 0.0};
-  const unsigned long long *lst = sel(D.nbr, cur);
-  double *hdt = sel(D.hdt, cur);
   unsigned long long mask_new = 0;
+  const int last = D.maxn - 1;
   for (int t = lane; t < m; t += L) {
-    const unsigned long long key = lst[(size_t)t * n + a];  // this lane stored its own entries
-    const int b = (int)(unsigned)(key & 0xffffffffu);
-    const double xb0 = xs[b], xb1 = xs[n + b], xb2 = xs[2 * n + b];
-    const double rb = D.rad[b];
-    if (!touching(xa0, xa1, xa2, xb0, xb1, xb2, ra, rb)) continue;
-    double dto[3] = {0.0, 0.0, 0.0};
-    if (ADVANCE && ((mask_prev >> t) & 1ull))
-      for (int c = 0; c < 3; ++c) dto[c] = hdt[(size_t)c * mn + (size_t)t * n + a];
-    const double vb0 = vhs[b], vb1 = vhs[n + b], vb2 = vhs[2 * n + b];
-    const double wb0 = whs[b], wb1 = whs[n + b], wb2 = whs[2 * n + b];
-    const double mb = D.mass[b];
+    // one round trip per entry: the partner's records, this entry's stored
+    // tangential overlap and the next entry's key (its slot clamped to the
+    // list capacity; past the list's length its value is not used)
+    const Entry cur_e = load_entry(P, VM, WS, hdt, mn, n, a, (int)(unsigned)(key & 0xffffffffu), t);
+    key = lst[(size_t)min(t + L, last) * n + a];
+    const double4 pb = cur_e.p, vb = cur_e.v, wb = cur_e.w;
+    const double rb = pb.w;
+    if (!touching(xa0, xa1, xa2, pb.x, pb.y, pb.z, ra, rb)) continue;
+    const bool had = ADVANCE && ((mask_prev >> t) & 1ull);
+    const double dto[3] = {had ? cur_e.h[0] : 0.0, had ? cur_e.h[1] : 0.0, had ? cur_e.h[2] : 0.0};
+    const double mb = vb.w;
     // Evaluated from this particle's side.  Every quantity the partner
     // computes from its side is the exact negation (d, n, relative velocity,
     // tangential overlap, force) or identical (|d|, dn, R_e, m_e, n x f_t), so
     // the two sides stay bit-consistent: force on b = -force on a exactly.
-    const double d0 = xb0 - xa0, d1 = xb1 - xa1, d2 = xb2 - xa2;
+    const double d0 = pb.x - xa0, d1 = pb.y - xa1, d2 = pb.z - xa2;
     const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     double nrm[3], vij[3], rw[3], f[3], nxft[3], dtn[3], mr[3];
     nrm[0] = d0 / dist;
     nrm[1] = d1 / dist;
     nrm[2] = d2 / dist;
     const double dn = (ra + rb) - dist;
-    lever_sum(ra, wa0, wa1, wa2, rb, wb0, wb1, wb2, rw);
-    vij[0] = va0 - vb0 + (rw[1] * nrm[2] - rw[2] * nrm[1]);
-    vij[1] = va1 - vb1 + (rw[2] * nrm[0] - rw[0] * nrm[2]);
-    vij[2] = va2 - vb2 + (rw[0] * nrm[1] - rw[1] * nrm[0]);
+    lever_sum(ra, wa0, wa1, wa2, rb, wb.x, wb.y, wb.z, rw);
+    vij[0] = va0 - vb.x + (rw[1] * nrm[2] - rw[2] * nrm[1]);
+    vij[1] = va1 - vb.y + (rw[2] * nrm[0] - rw[0] * nrm[2]);
+    vij[2] = va2 - vb.z + (rw[0] * nrm[1] - rw[1] * nrm[0]);
     const double Re = 1.0 / (1.0 / ra + 1.0 / rb);
     const double me = 1.0 / (1.0 / ma + 1.0 / mb);
-    const double wr[3] = {wa0 - wb0, wa1 - wb1, wa2 - wb2};
+    const double wr[3] = {wa0 - wb.x, wa1 - wb.y, wa2 - wb.z};
     contact_law<R, ADVANCE, ROLL>(D.pp, nrm, dn, vij, Re, me, D.dt, dto, wr, f, nxft, dtn, mr);
     for (int c = 0; c < 3; ++c) {
       F[c] += f[c];
@@ -439,7 +542,6 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   }
   // ---- walls (last lane of the group)
   if (lane == L - 1) {
-    const unsigned wold = ADVANCE ? D.wmask[a] : 0u;
     unsigned wnew = 0;
     for (int wall = 0; wall < kWalls; ++wall) {
       // axis quantities by selection (no run-time index into the grid)
@@ -459,7 +561,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
       vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
       vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
-      if ((wold >> wall) & 1u)
+      if (wall == w_first && ((wold >> wall) & 1u))
+        for (int c = 0; c < 3; ++c) dto[c] = wdt_l[c];
+      else if ((wold >> wall) & 1u)
         for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
       const double wr[3] = {wa0, wa1, wa2};
       contact_law<R, ADVANCE, ROLL>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, wr, f, nxft, dtn, mr);
@@ -498,7 +602,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
   // the grid of step s-1 is free: clear it for step s+2
-  sel(D.cnt, r3)[sel(D.cell, r3)[a]] = 0;
+  sel(D.cnt, r3)[c_old] = 0;
 
   if (ADVANCE) {
     const double inertia = 0.4 * ma * ra * ra;
@@ -517,20 +621,17 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     if (vb[0] != vb[0] || vb[1] != vb[1] || vb[2] != vb[2]) bits |= kErrNan;
     if (CONT) {
       // open step s+1 with the same held fluid force
-      double xp[3];
-      double *x1 = sel(D.xs, p2 ^ 1), *vh1 = sel(D.vhs, p2 ^ 1), *wh1 = sel(D.whs, p2 ^ 1);
+      double xp[3], vh[3], wh[3];
       const double xa[3] = {xa0, xa1, xa2};
       for (int c = 0; c < 3; ++c) {
-        const int i = c * n + a;
-        const double vhc = vb[c] + 0.5 * D.dt * acc[c];
-        const double whc = wb[c] + 0.5 * D.dt * alpha[c];
-        xp[c] = xa[c] + D.dt * vhc;
-        vh1[i] = vhc;
-        wh1[i] = whc;
-        x1[i] = xp[c];
+        vh[c] = vb[c] + 0.5 * D.dt * acc[c];
+        wh[c] = wb[c] + 0.5 * D.dt * alpha[c];
+        xp[c] = xa[c] + D.dt * vh[c];
       }
-      bin_and_test(D, a, xp, ra, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.srec, p2 ^ 1), sel(D.cell, q3),
-                   D.flag + q3, false, bits);
+      sel(D.pr, p2 ^ 1)[a] = make_double4(xp[0], xp[1], xp[2], ra);
+      sel(D.vm, p2 ^ 1)[a] = make_double4(vh[0], vh[1], vh[2], ma);
+      sel(D.ws, p2 ^ 1)[a] = make_double4(wh[0], wh[1], wh[2], 0.0);
+      bin_and_test(D, a, xp, xba, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.cell, q3), D.flag + q3, false, bits);
     }
   }
   if (a == 0) {
@@ -542,13 +643,19 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
+__global__ __launch_bounds__(kForceBlock, 3) void force_kick(Dev D, int p2, int p3, const int *src) {
   force_kick_body<R, ADVANCE, CONT, L, ROLL>(D, blockIdx.x, p2, p3, src);
 }
 
 // ---------------------------------------------------------------------------
 // batched kernels: one launch over every bed of a batch
 // ---------------------------------------------------------------------------
+// Dynamic LDS of the contact-force kernel: per group, maxn list keys and
+// maxn history-source bytes.
+static size_t force_lds_bytes(int maxn, int L) {
+  return (sizeof(unsigned long long) + 1) * (size_t)maxn * (kForceBlock / L);
+}
+
 __device__ inline void bed_of_block(const unsigned *__restrict__ map, int &bed, int &blk) {
   const unsigned m = map[blockIdx.x];
   bed = (int)(m >> kBedShift);
@@ -569,7 +676,7 @@ __global__ __launch_bounds__(256) void drift_bin_batch(const Dev *__restrict__ t
 
 // Step run.s + i of every bed (i = 1 applies the bed's pending permutation).
 template <typename R, bool CONT, int L, bool ROLL>
-__global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__restrict__ tab,
+__global__ __launch_bounds__(kForceBlock, 3) void force_kick_batch(const Dev *__restrict__ tab,
                                                                    const BedRun *__restrict__ run,
                                                                    const unsigned *__restrict__ map,
                                                                    int i) {
@@ -611,7 +718,7 @@ hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsig
 template <int L, bool ROLL>
 static void launch_fkb(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
                        bool cont, bool fp32, int maxn, hipStream_t st) {
-  const size_t lds = sizeof(unsigned long long) * (size_t)maxn * (kForceBlock / L);
+  const size_t lds = force_lds_bytes(maxn, L);
   if (fp32) {
     if (cont)
       force_kick_batch<float, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
@@ -691,7 +798,7 @@ template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
 static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
   const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
-  const size_t lds = sizeof(unsigned long long) * (size_t)D.maxn * (kForceBlock / L);
+  const size_t lds = force_lds_bytes(D.maxn, L);
   if (e0)
     hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L, ROLL>, dim3(grid), dim3(kForceBlock), lds, st,
                           e0, e1, 0, D, p2, p3, src);

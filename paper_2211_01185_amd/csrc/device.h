@@ -43,7 +43,7 @@ struct Grid {
 
 // Everything a DEM kernel needs, passed by value.  Arrays are indexed by the
 // internal (sorted) particle index; vectors are component-major (c*n + k).
-// Step s keeps its positions and half-step velocities in buffer s&1 and its
+// Step s keeps its position and half-step velocity records in buffer s&1 and its
 // cell grid counts in buffer s%3, so that one kernel can read step s while it
 // prepares step s+1 and clears what step s-1 left behind.
 struct Dev {
@@ -54,11 +54,13 @@ struct Dev {
   double g[3];
   double skin;        // neighbour-list skin
   double trig2;       // squared displacement that triggers a new broad search
-  float marg;         // absolute margin of the single-precision broad-search test
   Material pp, pw;
   Grid grid;
-  double *xs[2];         // positions x_s, by step parity
-  double *vhs[2], *whs[2];  // half-step velocities of step s, by parity
+  // Per-step records, by step parity, one 32-byte record per particle so
+  // that a partner's state is a few 16-byte loads from one address each:
+  double4 *pr[2];        // (x, y, z, R): position x_s and radius
+  double4 *vm[2];        // (vx, vy, vz, m): half-step velocity of step s and mass
+  double4 *ws[2];        // (wx, wy, wz, 0): half-step angular velocity of step s
   double *v, *w;         // boundary velocities (end of the last step)
   double *Fc, *Tc;       // stored contact force / torque
   double *ffp;           // held fluid force
@@ -68,8 +70,6 @@ struct Dev {
   int *cell[3];          // cell of x_s, by step mod 3
   int *cnt[3];           // particles per cell, by step mod 3
   int *slot[2];          // ncells x cap particle indices, by step parity
-  float4 *srec[2];       // ncells x cap: position and radius of each slot's particle
-                         // in single precision (broad-search prefilter), by parity
   int *flag;             // [3] broad search requested, by step mod 3
   int *lbuf;             // [3] neighbour-list buffer in use, by step mod 3
   // neighbour lists (buffer lbuf): entries sorted by partner original ID
