@@ -276,7 +276,7 @@ struct Carver {
 struct Buffers {
   Dev D;
   // alternates for the re-sort (swapped with D's arrays)
-  double4 *x2;
+  dvec4 *x2;
   double *v2, *w2, *Fc2, *Tc2, *ffp2, *rad2, *mass2, *whdt2;
   int *oid2, *cell2;
   unsigned char *wmask2;
@@ -319,9 +319,9 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
     }
   }
   for (int b = 0; b < 2; ++b) {
-    D.pr[b] = c.take<double4>(n);
-    D.vm[b] = c.take<double4>(n);
-    D.ws[b] = c.take<double4>(n);
+    D.pr[b] = c.take<dvec4>(n);
+    D.vm[b] = c.take<dvec4>(n);
+    D.ws[b] = c.take<dvec4>(n);
     D.slot[b] = c.take<int>((size_t)S.grid.ncells * S.cap);
   }
   for (int b = 0; b < 3; ++b) {
@@ -346,7 +346,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   D.wmask = c.take<unsigned char>(n);
   D.whdt = c.take<double>(3 * kWalls * n);
   D.occ = c.take<int>((size_t)S.grid.n_elem);
-  B.x2 = c.take<double4>(n);
+  B.x2 = c.take<dvec4>(n);
   B.v2 = c.take<double>(3 * n);
   B.w2 = c.take<double>(3 * n);
   B.Fc2 = c.take<double>(3 * n);
@@ -374,7 +374,7 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
   const int n = D.n;
-  D.pr[0][k] = make_double4(x[k], x[n + k], x[2 * n + k], r[k]);
+  D.pr[0][k] = dvec4{x[k], x[n + k], x[2 * n + k], r[k]};
   for (int c = 0; c < 3; ++c) {
     D.v[c * n + k] = v[c * n + k];
     D.w[c * n + k] = w[c * n + k];
@@ -401,11 +401,11 @@ __global__ void k_init(Dev D, const double *x, const double *v, const double *w,
   atomicMin(&rbits[1], bits);
 }
 
-__global__ void k_scatter_pos(int n, const int *oid, const double4 *src, double *dst) {
+__global__ void k_scatter_pos(int n, const int *oid, const dvec4 *src, double *dst) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int o = oid[k];
-  const double4 p = src[k];
+  const dvec4 p = src[k];
   dst[o] = p.x;
   dst[n + o] = p.y;
   dst[2 * n + o] = p.z;
@@ -530,13 +530,13 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long a, unsigned
 }
 
 struct PermSrc {
-  const double4 *x;
+  const dvec4 *x;
   const double *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   const int *oid, *cell;
   const unsigned char *wmask;
 };
 struct PermDst {
-  double4 *x;
+  dvec4 *x;
   double *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
   int *oid, *cell;
   unsigned char *wmask;

@@ -678,11 +678,11 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
   // ---- 2. void fraction; the state of the thread's first particle is
   // loaded in the same round trip as its radius
-  const double4 *X = sel(D.pr, p2);
+  const dvec4 *X = sel(D.pr, p2);
   const int k0 = tid < total ? sh.ids[tid] : -1;
   double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, r0 = 0.0;
   if (k0 >= 0) {
-    const double4 p = X[k0];
+    const dvec4 p = X[k0];
     x0[0] = p.x;
     x0[1] = p.y;
     x0[2] = p.z;
@@ -715,7 +715,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   if (k0 >= 0) particle_force<R, ORD, MODE>(D, C, k0, ee, x0, u0, r0, eps_c, sh.sU, sh.sP, sh.sE, sums);
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
     const int k = sh.ids[t];
-    const double4 p = X[k];
+    const dvec4 p = X[k];
     double xp[3] = {p.x, p.y, p.z}, up[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) up[c] = D.v[c * n + k];

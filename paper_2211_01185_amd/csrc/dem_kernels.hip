@@ -35,22 +35,22 @@ namespace cfddem {
 
 // Binning of x into the grid of a step (counts cnt, slots sl, cells cl) and
 // the displacement test against the last broad-search positions.
-__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], const double xbk[3], int *cnt,
-                                    int *sl, int *cl, int *flag, bool force_flag, int &bits) {
+__device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], const double xbk[3], gptr<int> cnt,
+                                    gptr<int> sl, gptr<int> cl, gptr<int> flag, bool force_flag, int &bits) {
   int elem, cell;
   bool inside;
   bin_point(D.grid, xp, elem, cell, inside);
   if (!inside) bits |= kErrDomain;
   if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
   cl[k] = cell;
-  const int s = atomicAdd(&cnt[cell], 1);
+  const int s = __hip_atomic_fetch_add(&cnt[cell], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (s >= 0 && s < D.cap)
     sl[(size_t)cell * D.cap + s] = k;
   else
     bits |= kErrCapacity;
   // a list built at xb stays complete while every particle is within skin/2
   const double d0 = xp[0] - xbk[0], d1 = xp[1] - xbk[1], d2 = xp[2] - xbk[2];
-  if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) atomicOr(flag, 1);
+  if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -64,38 +64,38 @@ __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int 
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
-  double4 *x1 = sel(D.pr, p2), *vh = sel(D.vm, p2), *wh = sel(D.ws, p2);
-  const double m = D.mass[k];
-  const double r = D.rad[k];
+  const gptr<dvec4> x1 = gsel(D.pr, p2), vh = gsel(D.vm, p2), wh = gsel(D.ws, p2);
+  const double m = glb(D.mass)[k];
+  const double r = glb(D.rad)[k];
   if (DRIFT) {
-    const double4 xo = sel(D.pr, p2 ^ 1)[k];
+    const dvec4 xo = gsel(D.pr, p2 ^ 1)[k];
     const double x0[3] = {xo.x, xo.y, xo.z};
     const double inertia = 0.4 * m * r * r;
     double vhc[3], whc[3];
     for (int c = 0; c < 3; ++c) {
       const int i = c * n + k;
-      const double acc = (D.Fc[i] + D.ffp[i]) / m + D.g[c];
-      const double alpha = D.Tc[i] / inertia;
-      vhc[c] = D.v[i] + 0.5 * D.dt * acc;
-      whc[c] = D.w[i] + 0.5 * D.dt * alpha;
+      const double acc = (glb(D.Fc)[i] + glb(D.ffp)[i]) / m + D.g[c];
+      const double alpha = glb(D.Tc)[i] / inertia;
+      vhc[c] = glb(D.v)[i] + 0.5 * D.dt * acc;
+      whc[c] = glb(D.w)[i] + 0.5 * D.dt * alpha;
       xp[c] = x0[c] + D.dt * vhc[c];
     }
-    x1[k] = make_double4(xp[0], xp[1], xp[2], r);
-    vh[k] = make_double4(vhc[0], vhc[1], vhc[2], m);
-    wh[k] = make_double4(whc[0], whc[1], whc[2], 0.0);
+    x1[k] = dvec4{xp[0], xp[1], xp[2], r};
+    vh[k] = dvec4{vhc[0], vhc[1], vhc[2], m};
+    wh[k] = dvec4{whc[0], whc[1], whc[2], 0.0};
   } else {
-    const double4 xo = x1[k];
+    const dvec4 xo = x1[k];
     xp[0] = xo.x;
     xp[1] = xo.y;
     xp[2] = xo.z;
-    vh[k] = make_double4(D.v[k], D.v[n + k], D.v[2 * n + k], m);
-    wh[k] = make_double4(D.w[k], D.w[n + k], D.w[2 * n + k], 0.0);
+    vh[k] = dvec4{glb(D.v)[k], glb(D.v)[n + k], glb(D.v)[2 * n + k], m};
+    wh[k] = dvec4{glb(D.w)[k], glb(D.w)[n + k], glb(D.w)[2 * n + k], 0.0};
   }
   int bits = 0;
-  const double xbk[3] = {D.xb[k], D.xb[n + k], D.xb[2 * n + k]};
-  bin_and_test(D, k, xp, xbk, sel(D.cnt, p3), sel(D.slot, p2), sel(D.cell, p3), D.flag + p3, force_flag != 0,
+  const double xbk[3] = {glb(D.xb)[k], glb(D.xb)[n + k], glb(D.xb)[2 * n + k]};
+  bin_and_test(D, k, xp, xbk, gsel(D.cnt, p3), gsel(D.slot, p2), gsel(D.cell, p3), glb(D.flag) + p3, force_flag != 0,
                bits);
-  if (bits) atomicOr(D.err, bits);
+  if (bits) __hip_atomic_fetch_or(glb(D.err), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool DRIFT>
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int forc
 __global__ void clear_grid(Dev D, int p3) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
-  sel(D.cnt, p3)[sel(D.cell, p3)[k]] = 0;
-  if (k == 0) D.flag[p3] = 0;
+  gsel(D.cnt, p3)[gsel(D.cell, p3)[k]] = 0;
+  if (k == 0) glb(D.flag)[p3] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -236,7 +236,7 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
                                    double xa2, double ra, unsigned long long *my_list, int &bits) {
   constexpr int kGroups = kForceBlock / L;
   const Grid &G = D.grid;
-  const int ca = sel(D.cell, p3)[a];
+  const int ca = gsel(D.cell, p3)[a];
   const int el = ca / G.kk, sub = ca - el * G.kk;
   const int g0 = (el % G.n_el[0]) * G.k[0] + sub % G.k[0];
   const int g1 = ((el / G.n_el[0]) % G.n_el[1]) * G.k[1] + (sub / G.k[0]) % G.k[1];
@@ -253,9 +253,9 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
                 ? (gz / G.k[2]) * G.n_el[1] * G.n_el[0] * G.kk + (gz % G.k[2]) * G.k[1] * G.k[0]
                 : -1;
   }
-  const int *cnt = sel(D.cnt, p3);
-  const int *slot = sel(D.slot, p2);
-  const double4 *P = sel(D.pr, p2);
+  const gptr<const int> cnt = gsel(D.cnt, p3);
+  const gptr<const int> slot = gsel(D.slot, p2);
+  const gptr<const dvec4> P = gsel(D.pr, p2);
   const double rsk = ra + D.skin;
   constexpr int kCand = 4;
   const int first_lane = (threadIdx.x & 63) & ~(L - 1);
@@ -301,8 +301,8 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
 #pragma unroll
       for (int i = 0; i < kCand; ++i) {
         const int b = ok[i] ? bq[i] : a;
-        const double4 pb = P[b];
-        oq[i] = (unsigned)D.oid[b];
+        const dvec4 pb = P[b];
+        oq[i] = (unsigned)glb(D.oid)[b];
         const double d0 = pb.x - xa0, d1 = pb.y - xa1, d2 = pb.z - xa2;
         const double cut = rsk + pb.w;
         ok[i] = ok[i] && d0 * d0 + d1 * d1 + d2 * d2 < cut * cut;
@@ -342,13 +342,13 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
 // One neighbour-list entry's data: the partner's position, velocity and
 // spin records and the entry's stored tangential overlap.
 struct Entry {
-  double4 p, v, w;
+  dvec4 p, v, w;
   double h[3];
 };
 // b comes from a list entry; an index outside [0, n) (only a slot past the
 // list's length can hold one) reads the particle itself.
-__device__ __forceinline__ Entry load_entry(const double4 *P, const double4 *VM, const double4 *WS,
-                                            const double *hdt, size_t mn, int n, int a, int b, int t) {
+__device__ __forceinline__ Entry load_entry(gptr<const dvec4> P, gptr<const dvec4> VM, gptr<const dvec4> WS,
+                                            gptr<const double> hdt, size_t mn, int n, int a, int b, int t) {
   b = (unsigned)b < (unsigned)n ? b : a;
   Entry e;
   e.p = P[b];
@@ -373,20 +373,20 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const Grid &G = D.grid;
   const int q3 = p3 == 2 ? 0 : p3 + 1;  // (s + 1) % 3
   const int r3 = p3 == 0 ? 2 : p3 - 1;  // (s - 1) % 3
-  const double4 *P = sel(D.pr, p2);
-  const double4 *VM = sel(D.vm, p2);
-  const double4 *WS = sel(D.ws, p2);
-  const int lold = D.lbuf[p3];
-  const bool rebuild = !ADVANCE || src != nullptr || D.flag[p3] != 0;
+  const gptr<const dvec4> P = gsel(D.pr, p2);
+  const gptr<const dvec4> VM = gsel(D.vm, p2);
+  const gptr<const dvec4> WS = gsel(D.ws, p2);
+  const int lold = glb(D.lbuf)[p3];
+  const bool rebuild = !ADVANCE || src != nullptr || glb(D.flag)[p3] != 0;
   const int cur = rebuild ? (lold ^ 1) : lold;
 
-  const double4 pa = P[a];
+  const dvec4 pa = P[a];
   const double xa0 = pa.x, xa1 = pa.y, xa2 = pa.z, ra = pa.w;
   // walls touched at the last step, and the cell of x_{s-1} whose count this
   // particle clears at the end: loaded first, so that waiting for them later
   // waits for nothing else
-  const unsigned wmask_a = D.wmask[a];
-  const int c_old = sel(D.cell, r3)[a];
+  const unsigned wmask_a = glb(D.wmask)[a];
+  const int c_old = gsel(D.cell, r3)[a];
   const size_t mn = (size_t)D.maxn * n;
   constexpr int kCand8 = 8;     // old list entries per lane and round trip
   int bits = 0;
@@ -406,10 +406,10 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     const int m = broad_search<L>(D, a, lane, p2, p3, xa0, xa1, xa2, ra, my_list, bits);
     m_new = m;
     if (lane == 0) {
-      sel(D.ln, cur)[a] = m;
-      D.xb[a] = xa0;
-      D.xb[n + a] = xa1;
-      D.xb[2 * n + a] = xa2;
+      gsel(D.ln, cur)[a] = m;
+      glb(D.xb)[a] = xa0;
+      glb(D.xb)[n + a] = xa1;
+      glb(D.xb)[2 * n + a] = xa2;
     }
     // ---- tangential history of the pairs that touched at the last step:
     //      each lane finds its share of the old touching entries in the new
@@ -417,9 +417,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     //      entry's history comes from; then every lane stores its own new
     //      entries and copies their history
     const int s = src ? src[a] : a;
-    const int mo = sel(D.ln, lold)[s];
-    const unsigned long long mask_old = sel(D.hmask, lold)[s];
-    const unsigned long long *olst = sel(D.nbr, lold);
+    const int mo = gsel(D.ln, lold)[s];
+    const unsigned long long mask_old = gsel(D.hmask, lold)[s];
+    const gptr<const unsigned long long> olst = gsel(D.nbr, lold);
     for (int t = lane; t < m; t += L) my_from[t * kGroups] = 0;
     wave_publish();
     if (ADVANCE) {
@@ -452,14 +452,14 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       }
       wave_publish();
     }
-    unsigned long long *lst_new = sel(D.nbr, cur);
+    const gptr<unsigned long long> lst_new = gsel(D.nbr, cur);
     for (int t = lane; t < m; t += L) {
       lst_new[(size_t)t * n + a] = my_list[t * kGroups];
       const int from = my_from[t * kGroups];
       if (from) {
         for (int c = 0; c < 3; ++c)
-          sel(D.hdt, cur)[(size_t)c * mn + (size_t)t * n + a] =
-              sel(D.hdt, lold)[(size_t)c * mn + (size_t)(from - 1) * n + s];
+          gsel(D.hdt, cur)[(size_t)c * mn + (size_t)t * n + a] =
+              gsel(D.hdt, lold)[(size_t)c * mn + (size_t)(from - 1) * n + s];
         carried |= 1ull << t;
       }
     }
@@ -475,20 +475,20 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   //      history of the first wall touched last step.  Every load is
   //      unconditional (a stale value is replaced by a select), so that no
   //      branch makes the wavefront wait for the others.
-  const unsigned long long *lst = sel(D.nbr, cur);
-  double *hdt = sel(D.hdt, cur);
-  const unsigned long long hm = sel(D.hmask, cur)[a];
-  const int lnv = sel(D.ln, cur)[a];
+  const gptr<const unsigned long long> lst = gsel(D.nbr, cur);
+  const gptr<double> hdt = gsel(D.hdt, cur);
+  const unsigned long long hm = gsel(D.hmask, cur)[a];
+  const int lnv = gsel(D.ln, cur)[a];
   unsigned long long key = lst[(size_t)min(lane, D.maxn - 1) * n + a];
-  const double xbl[3] = {D.xb[a], D.xb[n + a], D.xb[2 * n + a]};
-  const double4 va = VM[a], wa = WS[a];
+  const double xbl[3] = {glb(D.xb)[a], glb(D.xb)[n + a], glb(D.xb)[2 * n + a]};
+  const dvec4 va = VM[a], wa = WS[a];
   const double va0 = va.x, va1 = va.y, va2 = va.z, ma = va.w;
   const double wa0 = wa.x, wa1 = wa.y, wa2 = wa.z;
-  const double fa[3] = {D.ffp[a], D.ffp[n + a], D.ffp[2 * n + a]};
+  const double fa[3] = {glb(D.ffp)[a], glb(D.ffp)[n + a], glb(D.ffp)[2 * n + a]};
   const unsigned wold = (ADVANCE && lane == L - 1) ? wmask_a : 0u;
   const int w_first = wold ? __ffs(wold) - 1 : 0;
-  const double wdt_l[3] = {D.whdt[(size_t)w_first * n + a], D.whdt[(size_t)(kWalls + w_first) * n + a],
-                           D.whdt[(size_t)(2 * kWalls + w_first) * n + a]};
+  const double wdt_l[3] = {glb(D.whdt)[(size_t)w_first * n + a], glb(D.whdt)[(size_t)(kWalls + w_first) * n + a],
+                           glb(D.whdt)[(size_t)(2 * kWalls + w_first) * n + a]};
   const int m = rebuild ? m_new : lnv;
   unsigned long long mask_prev = rebuild ? carried : hm;
   const double xba[3] = {rebuild ? xa0 : xbl[0], rebuild ? xa1 : xbl[1], rebuild ? xa2 : xbl[2]};
@@ -507,7 +507,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     // list capacity; past the list's length its value is not used)
     const Entry cur_e = load_entry(P, VM, WS, hdt, mn, n, a, (int)(unsigned)(key & 0xffffffffu), t);
     key = lst[(size_t)min(t + L, last) * n + a];
-    const double4 pb = cur_e.p, vb = cur_e.v, wb = cur_e.w;
+    const dvec4 pb = cur_e.p, vb = cur_e.v, wb = cur_e.w;
     const double rb = pb.w;
     if (!touching(xa0, xa1, xa2, pb.x, pb.y, pb.z, ra, rb)) continue;
     const bool had = ADVANCE && ((mask_prev >> t) & 1ull);
@@ -564,18 +564,18 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       if (wall == w_first && ((wold >> wall) & 1u))
         for (int c = 0; c < 3; ++c) dto[c] = wdt_l[c];
       else if ((wold >> wall) & 1u)
-        for (int c = 0; c < 3; ++c) dto[c] = D.whdt[(size_t)(c * kWalls + wall) * n + a];
+        for (int c = 0; c < 3; ++c) dto[c] = glb(D.whdt)[(size_t)(c * kWalls + wall) * n + a];
       const double wr[3] = {wa0, wa1, wa2};
       contact_law<R, ADVANCE, ROLL>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, wr, f, nxft, dtn, mr);
       for (int c = 0; c < 3; ++c) {
         F[c] += f[c];
         T[c] += ra * nxft[c];
         if (ROLL) Tr[c] += mr[c];
-        D.whdt[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
+        glb(D.whdt)[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
       }
       wnew |= 1u << wall;
     }
-    if (wnew != wold || !ADVANCE) D.wmask[a] = (unsigned char)wnew;
+    if (wnew != wold || !ADVANCE) glb(D.wmask)[a] = (unsigned char)wnew;
   }
   for (int c = 0; c < 3; ++c) {
     F[c] = group_sum<L>(F[c]);
@@ -586,23 +586,23 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   mask_new = group_or<L>(mask_new);
   mask_prev = group_or<L>(mask_prev);
   if (lane != 0) {
-    if (bits) atomicOr(D.err, bits);
+    if (bits) __hip_atomic_fetch_or(glb(D.err), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
 
   // ---- lane 0: store the step, open the next one.  Inside a run the
   //      boundary velocities and the stored force/torque are never read, so
   //      only the last step of a run stores them.
-  if (rebuild || mask_new != mask_prev) sel(D.hmask, cur)[a] = mask_new;
+  if (rebuild || mask_new != mask_prev) gsel(D.hmask, cur)[a] = mask_new;
   if (!CONT) {
     for (int c = 0; c < 3; ++c) {
-      D.Fc[c * n + a] = F[c];
-      D.Tc[c * n + a] = T[c];
+      glb(D.Fc)[c * n + a] = F[c];
+      glb(D.Tc)[c * n + a] = T[c];
     }
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
   // the grid of step s-1 is free: clear it for step s+2
-  sel(D.cnt, r3)[c_old] = 0;
+  gsel(D.cnt, r3)[c_old] = 0;
 
   if (ADVANCE) {
     const double inertia = 0.4 * ma * ra * ra;
@@ -614,8 +614,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       vb[c] = (c == 0 ? va0 : (c == 1 ? va1 : va2)) + 0.5 * D.dt * acc[c];
       wb[c] = (c == 0 ? wa0 : (c == 1 ? wa1 : wa2)) + 0.5 * D.dt * alpha[c];
       if (!CONT) {
-        D.v[i] = vb[c];
-        D.w[i] = wb[c];
+        glb(D.v)[i] = vb[c];
+        glb(D.w)[i] = wb[c];
       }
     }
     if (vb[0] != vb[0] || vb[1] != vb[1] || vb[2] != vb[2]) bits |= kErrNan;
@@ -628,18 +628,18 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
         wh[c] = wb[c] + 0.5 * D.dt * alpha[c];
         xp[c] = xa[c] + D.dt * vh[c];
       }
-      sel(D.pr, p2 ^ 1)[a] = make_double4(xp[0], xp[1], xp[2], ra);
-      sel(D.vm, p2 ^ 1)[a] = make_double4(vh[0], vh[1], vh[2], ma);
-      sel(D.ws, p2 ^ 1)[a] = make_double4(wh[0], wh[1], wh[2], 0.0);
-      bin_and_test(D, a, xp, xba, sel(D.cnt, q3), sel(D.slot, p2 ^ 1), sel(D.cell, q3), D.flag + q3, false, bits);
+      gsel(D.pr, p2 ^ 1)[a] = dvec4{xp[0], xp[1], xp[2], ra};
+      gsel(D.vm, p2 ^ 1)[a] = dvec4{vh[0], vh[1], vh[2], ma};
+      gsel(D.ws, p2 ^ 1)[a] = dvec4{wh[0], wh[1], wh[2], 0.0};
+      bin_and_test(D, a, xp, xba, gsel(D.cnt, q3), gsel(D.slot, p2 ^ 1), gsel(D.cell, q3), glb(D.flag) + q3, false, bits);
     }
   }
   if (a == 0) {
-    D.flag[r3] = 0;
-    if (!CONT) D.flag[q3] = 0;
-    D.lbuf[q3] = cur;
+    glb(D.flag)[r3] = 0;
+    if (!CONT) glb(D.flag)[q3] = 0;
+    glb(D.lbuf)[q3] = cur;
   }
-  if (bits) atomicOr(D.err, bits);
+  if (bits) __hip_atomic_fetch_or(glb(D.err), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>

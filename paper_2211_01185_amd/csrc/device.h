@@ -19,6 +19,10 @@ enum : int { kErrDomain = 1, kErrCapacity = 2, kErrNan = 4 };
 // flags, [32..34] list buffer, [48..49] occupied-element counts by call parity
 enum : int { kFlagWord = 16, kLbufWord = 32, kOccWord = 48 };
 
+// Four doubles as a native vector (32-byte aligned): loads and stores of a
+// record are 16-byte vector accesses through pointers of any address space.
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
 struct Material {
   double Ye;        // effective Young's modulus
   double Ge;        // effective shear modulus
@@ -58,9 +62,9 @@ struct Dev {
   Grid grid;
   // Per-step records, by step parity, one 32-byte record per particle so
   // that a partner's state is a few 16-byte loads from one address each:
-  double4 *pr[2];        // (x, y, z, R): position x_s and radius
-  double4 *vm[2];        // (vx, vy, vz, m): half-step velocity of step s and mass
-  double4 *ws[2];        // (wx, wy, wz, 0): half-step angular velocity of step s
+  dvec4 *pr[2];          // (x, y, z, R): position x_s and radius
+  dvec4 *vm[2];          // (vx, vy, vz, m): half-step velocity of step s and mass
+  dvec4 *ws[2];          // (wx, wy, wz, 0): half-step angular velocity of step s
   double *v, *w;         // boundary velocities (end of the last step)
   double *Fc, *Tc;       // stored contact force / torque
   double *ffp;           // held fluid force
@@ -149,6 +153,17 @@ struct Cpl {
   double Lq1[2][3]; // 1D Q1 basis at Gauss point i (unused for order 2)
 };
 
+// Pointers typed as global memory: loads and stores through them are global
+// instructions (with an SGPR base where the address allows), whereas a
+// generic pointer read from device memory (a batch table) would give FLAT
+// instructions, which also hold up every wait for scalar loads.
+template <typename T>
+using gptr = T __attribute__((address_space(1))) *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p) {
+  return (gptr<T>)p;
+}
+
 // Buffer i of a double- or triple-buffered array, with constant indices only
 // (so that a Dev copied into registers stays in registers).
 template <typename T>
@@ -158,6 +173,10 @@ __device__ __forceinline__ T *sel(T *const (&a)[2], int i) {
 template <typename T>
 __device__ __forceinline__ T *sel(T *const (&a)[3], int i) {
   return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+template <typename T, int K>
+__device__ __forceinline__ gptr<T> gsel(T *const (&a)[K], int i) {
+  return glb(sel(a, i));
 }
 
 __device__ inline int floor_clamp(double t, int n) {
