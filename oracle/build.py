@@ -1,7 +1,8 @@
 """Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
 
 Plain gcc, no FMA contraction, so every floating-point expression is evaluated
-exactly as written.
+exactly as written; OpenMP for the loops whose iterations are independent (the
+sums stay serial and in order, so the thread count does not change results).
 """
 import os
 import subprocess
@@ -13,7 +14,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -37,28 +37,41 @@
  *                             linear pressure exact
  *   Di Felice                 terminal velocity printed in Section 3.1
  *                             (0.2328 m/s) and its closed form; 0.96 x Stokes at
- *                             vanishing Reynolds number; voidage exponent 3.7 in
- *                             both Reynolds limits
+ *                             vanishing Reynolds number; the voidage exponent
+ *                             measured at fixed Reynolds number: 3.7 in both
+ *                             limits, minimum 3.05 at Re = 10^1.5, symmetric in
+ *                             log10 Re, 3.7 - 0.65/e at 10^(1.5 +- sqrt 2)
  *   other closures            Stokes' 3 pi mu d for a lone sphere at vanishing
  *                             Reynolds number (Koch-Hill, Beetstra, Gidaspow;
  *                             0.96 of it for Dallavalle and Rong); Di Felice and
- *                             Rong equal Dallavalle at eps = 1; Gidaspow's dense
- *                             branch equals the textbook Ergun pressure drop;
- *                             near-continuity of the Gidaspow (Re = 1000) and
- *                             Koch-Hill (eps_p = 0.4) branch joins
+ *                             Rong equal Dallavalle at eps = 1; Rong's exponent
+ *                             at full and vanishing bump; Beetstra's lone-sphere
+ *                             Reynolds term, dense Stokes limit and large-Re
+ *                             asymptote; Gidaspow's dense branch equals the
+ *                             textbook Ergun pressure drop; near-continuity of
+ *                             the Gidaspow (Re = 1000) and Koch-Hill
+ *                             (eps_p = 0.4) branch joins
+ *   pair spin terms           a spin equals the translation with the same
+ *                             contact-point velocity; meshing spins slide
+ *                             nothing; co-rotating spins are braked; the stored
+ *                             tangential overlap stays in the turning tangent
+ *                             plane; pair angular momentum about the centre of
+ *                             mass
  *   qpt reduction             momentum balance of the drag (and pressure force
  *                             for model B) over the quadrature weights, for
  *                             every closure; beta_B = beta_A / eps per element
- * Parity unpinned: the middle-Reynolds shape of the Di Felice voidage exponent
- * (no printed value exercises it), the eps-dependence of Rong's exponent and of
- * Beetstra's Reynolds term away from the limits above, and long chaotic
- * trajectories.
+ *   threads                   results bit-identical at one and several threads
+ * Parity unpinned: long chaotic trajectories, and the form of the rolling
+ * torque (named by the paper without a form).
  */
 #include "cfddem_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -85,6 +98,35 @@ static void *xcalloc(size_t count, size_t size) {
   if (!p) abort();
   return p;
 }
+
+/* Threads: loops whose iterations are independent run in parallel (OpenMP);
+ * every sum over particles or contacts is accumulated afterwards by one thread
+ * in the same order as a serial run, so results do not depend on the thread
+ * count. */
+static int orc_nthreads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+static int orc_thread_id(void) {
+#ifdef _OPENMP
+  return omp_get_thread_num();
+#else
+  return 0;
+#endif
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) { return orc_nthreads(); }
 
 /* ------------------------------------------------------------------------- */
 /* Binning (broad search)                                                     */
@@ -179,30 +221,51 @@ static long find_pairs_alloc(long n, const double *x, const double *r, const dou
     next[i] = head[c];
     head[c] = i;
   }
-  long cap = 1024, cnt = 0;
-  pair_t *list = (pair_t *)xmalloc(sizeof(pair_t) * cap);
-  for (long i = 0; i < n; ++i) {
-    double xi[3] = {x[i], x[n + i], x[2 * n + i]};
-    for (long dz = -1; dz <= 1; ++dz)
-      for (long dy = -1; dy <= 1; ++dy)
-        for (long dx = -1; dx <= 1; ++dx) {
-          long cx = cc[3 * i] + dx, cy = cc[3 * i + 1] + dy, cz = cc[3 * i + 2] + dz;
-          if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
-          for (long j = head[(cz * nc[1] + cy) * nc[0] + cx]; j >= 0; j = next[j]) {
-            if (j <= i) continue;
-            double xj[3] = {x[j], x[n + j], x[2 * n + j]};
-            if (!touching(xi, xj, r[i], r[j])) continue;
-            if (cnt == cap) {
-              cap *= 2;
-              list = (pair_t *)realloc(list, sizeof(pair_t) * cap);
-              if (!list) abort();
+  /* each thread collects the pairs of its own range of i; the lists are
+   * concatenated and sorted, so the result does not depend on the split */
+  int nt = orc_nthreads();
+  pair_t **tl = (pair_t **)xcalloc((size_t)nt, sizeof(pair_t *));
+  long *tc = (long *)xcalloc((size_t)nt, sizeof(long));
+#pragma omp parallel num_threads(nt)
+  {
+    int t = orc_thread_id();
+    long cap = 1024, cnt = 0;
+    pair_t *list = (pair_t *)xmalloc(sizeof(pair_t) * cap);
+#pragma omp for schedule(static)
+    for (long i = 0; i < n; ++i) {
+      double xi[3] = {x[i], x[n + i], x[2 * n + i]};
+      for (long dz = -1; dz <= 1; ++dz)
+        for (long dy = -1; dy <= 1; ++dy)
+          for (long dx = -1; dx <= 1; ++dx) {
+            long cx = cc[3 * i] + dx, cy = cc[3 * i + 1] + dy, cz = cc[3 * i + 2] + dz;
+            if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
+            for (long j = head[(cz * nc[1] + cy) * nc[0] + cx]; j >= 0; j = next[j]) {
+              if (j <= i) continue;
+              double xj[3] = {x[j], x[n + j], x[2 * n + j]};
+              if (!touching(xi, xj, r[i], r[j])) continue;
+              if (cnt == cap) {
+                cap *= 2;
+                list = (pair_t *)realloc(list, sizeof(pair_t) * cap);
+                if (!list) abort();
+              }
+              list[cnt].a = i;
+              list[cnt].b = j;
+              cnt++;
             }
-            list[cnt].a = i;
-            list[cnt].b = j;
-            cnt++;
           }
-        }
+    }
+    tl[t] = list;
+    tc[t] = cnt;
   }
+  long cnt = 0;
+  for (int t = 0; t < nt; ++t) cnt += tc[t];
+  pair_t *list = (pair_t *)xmalloc(sizeof(pair_t) * (cnt ? cnt : 1));
+  for (long t = 0, at = 0; t < nt; at += tc[t], ++t) {
+    memcpy(list + at, tl[t], sizeof(pair_t) * tc[t]);
+    free(tl[t]);
+  }
+  free(tl);
+  free(tc);
   qsort(list, (size_t)cnt, sizeof(pair_t), cmp_pair);
   free(head);
   free(next);
@@ -390,6 +453,12 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
   long *nb = (long *)xmalloc(sizeof(long) * (nc ? nc : 1));
   double *ndt = (double *)xmalloc(sizeof(double) * 3 * (nc ? nc : 1));
 
+  /* per-contact force and torques in parallel; F_c and T_c summed below in
+   * contact order */
+  double *cf = (double *)xmalloc(sizeof(double) * 3 * (nc ? nc : 1));
+  double *cti = (double *)xmalloc(sizeof(double) * 3 * (nc ? nc : 1));
+  double *ctj = (double *)xmalloc(sizeof(double) * 3 * (nc ? nc : 1));
+#pragma omp parallel for schedule(static)
   for (long c = 0; c < nc; ++c) {
     long i = all[c].a, j = all[c].b;
     double xi[3], vi[3], wi[3];
@@ -425,10 +494,9 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
       for (int k = 0; k < 3; ++k) {
         ti[k] = Ri * nxft[k];
         tj[k] = Rj * nxft[k];
-        s->Fc[k * n + i] += f[k];
-        s->Fc[k * n + j] -= f[k];
-        s->Tc[k * n + i] += ti[k] + Mr[k];
-        s->Tc[k * n + j] += tj[k] - Mr[k];
+        cf[3 * c + k] = f[k];
+        cti[3 * c + k] = ti[k] + Mr[k];
+        ctj[3 * c + k] = tj[k] - Mr[k];
       }
     } else {
       int wall = -1 - (int)j;
@@ -446,14 +514,29 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
       rolling_torque(s->pw.mu_r, Ri, fn_mag, wi, Mr);
       cross3(nrm, ft, nxft);
       for (int k = 0; k < 3; ++k) {
-        s->Fc[k * n + i] += f[k];
-        s->Tc[k * n + i] += Ri * nxft[k] + Mr[k];
+        cf[3 * c + k] = f[k];
+        cti[3 * c + k] = Ri * nxft[k] + Mr[k];
       }
     }
     na[c] = i;
     nb[c] = j;
     for (int k = 0; k < 3; ++k) ndt[3 * c + k] = dt_new[k];
   }
+  /* F_i = sum of f over the contacts of i, T_i likewise (contact order) */
+  for (long c = 0; c < nc; ++c) {
+    long i = na[c], j = nb[c];
+    for (int k = 0; k < 3; ++k) {
+      s->Fc[k * n + i] += cf[3 * c + k];
+      s->Tc[k * n + i] += cti[3 * c + k];
+      if (j >= 0) {
+        s->Fc[k * n + j] -= cf[3 * c + k];
+        s->Tc[k * n + j] += ctj[3 * c + k];
+      }
+    }
+  }
+  free(cf);
+  free(cti);
+  free(ctj);
   free(all);
   free(s->ha);
   free(s->hb);
@@ -470,15 +553,18 @@ static void evaluate_contacts(orc_dem *s, const double *v, const double *w, int 
 
 static void check_state(orc_dem *s) {
   long n = s->n;
+  int err = 0;
+#pragma omp parallel for schedule(static) reduction(| : err)
   for (long i = 0; i < n; ++i) {
     for (int a = 0; a < 3; ++a) {
       double xa = s->x[a * n + i];
       if (xa != xa || s->v[a * n + i] != s->v[a * n + i] || s->w[a * n + i] != s->w[a * n + i])
-        s->err |= ORC_ERR_NAN;
+        err |= ORC_ERR_NAN;
       else if (xa < s->p.box_lo[a] || xa > s->p.box_hi[a])
-        s->err |= ORC_ERR_DOMAIN;
+        err |= ORC_ERR_DOMAIN;
     }
   }
+  s->err |= err;
 }
 
 orc_dem *orc_dem_create(const orc_params *p, long n, const double *x, const double *v,
@@ -528,6 +614,7 @@ int orc_dem_step(orc_dem *s, long nsteps) {
   double *wh = (double *)xmalloc(sizeof(double) * 3 * (n ? n : 1));
   for (long step = 0; step < nsteps; ++step) {
     /* half kick and drift with the stored forces */
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
       for (int a = 0; a < 3; ++a) {
         long k = a * n + i;
@@ -541,6 +628,7 @@ int orc_dem_step(orc_dem *s, long nsteps) {
     /* contacts and forces at the new positions, half-step velocities */
     evaluate_contacts(s, vh, wh, 1);
     /* second half kick */
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
       for (int a = 0; a < 3; ++a) {
         long k = a * n + i;
@@ -918,7 +1006,12 @@ int orc_dem_couple_field(orc_dem *s, const orc_fluid *f, const double *U, const 
   long *pe = (long *)xmalloc(sizeof(long) * (n ? n : 1));
   double *pxi = (double *)xmalloc(sizeof(double) * 3 * (n ? n : 1));
 
+  /* per-particle terms of the element sums (rows 2-11), added in particle
+   * order after the parallel loops */
+  double *pt = (double *)xmalloc(sizeof(double) * 10 * (n ? n : 1));
+
   /* 1. locate and particle-centroid solid volume per element */
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < n; ++i) {
     double xp[3], xi[3];
     long e[3];
@@ -926,11 +1019,14 @@ int orc_dem_couple_field(orc_dem *s, const orc_fluid *f, const double *U, const 
     locate(f, lo, hi, xp, e, xi);
     pe[i] = (e[2] * f->n_el[1] + e[1]) * f->n_el[0] + e[0];
     for (int a = 0; a < 3; ++a) pxi[3 * i + a] = xi[a];
+  }
+  for (long i = 0; i < n; ++i) {
     double Vp = 4.0 / 3.0 * PI * s->r[i] * s->r[i] * s->r[i];
     sums[0 * nel + pe[i]] += 1.0;
     sums[1 * nel + pe[i]] += Vp;
   }
   /* 2. per-particle forces */
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < n; ++i) {
     long el = pe[i];
     long e[3] = {el % f->n_el[0], (el / f->n_el[0]) % f->n_el[1], el / ((long)f->n_el[0] * f->n_el[1])};
@@ -956,15 +1052,26 @@ int orc_dem_couple_field(orc_dem *s, const orc_fluid *f, const double *U, const 
       double fG = -Vp * gp[c];
       double fS = -Vp * dtau[c]; /* shear force (zero unless enabled) */
       s->ffp[c * n + i] = fD + fB + fG + fS;
-      sums[(3 + c) * nel + el] += beta * up[c];
-      sums[(6 + c) * nel + el] += fD;
-      sums[(9 + c) * nel + el] += fG + fS; /* undisturbed-flow forces */
+      pt[10 * i + 1 + c] = beta * up[c];
+      pt[10 * i + 4 + c] = fD;
+      pt[10 * i + 7 + c] = fG + fS; /* undisturbed-flow forces */
     }
-    sums[2 * nel + el] += beta;
+    pt[10 * i] = beta;
   }
+  for (long i = 0; i < n; ++i) {
+    long el = pe[i];
+    for (int c = 0; c < 3; ++c) {
+      sums[(3 + c) * nel + el] += pt[10 * i + 1 + c];
+      sums[(6 + c) * nel + el] += pt[10 * i + 4 + c];
+      sums[(9 + c) * nel + el] += pt[10 * i + 7 + c];
+    }
+    sums[2 * nel + el] += pt[10 * i];
+  }
+  free(pt);
   /* 3. quadrature-point outputs */
   double gpt[3], gwt[3];
   gauss_rule(nq1, gpt, gwt);
+#pragma omp parallel for schedule(static)
   for (long el = 0; el < nel; ++el) {
     long e[3] = {el % f->n_el[0], (el / f->n_el[0]) % f->n_el[1], el / ((long)f->n_el[0] * f->n_el[1])};
     double eps = 1.0 - sums[1 * nel + el] / Ve;

@@ -60,6 +60,13 @@ typedef struct {
 
 typedef struct orc_dem orc_dem;
 
+/* Threads of the parallel loops (OpenMP; 1 when built without it).  Results
+ * are bit-identical for every thread count: only independent per-particle,
+ * per-contact and per-element work runs in parallel, and every sum is then
+ * accumulated by one thread in the serial order. */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
 /* ---- stand-alone building blocks (also used by the whole-step routines) ---- */
 
 /* Hierarchical binning: element index e_a = clamp(floor((x_a-lo_a)*inv_he_a)),

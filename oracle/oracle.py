@@ -92,12 +92,25 @@ def _load():
     lib.orc_dem_error.argtypes = [C.c_void_p]
     lib.orc_dem_free.restype = None
     lib.orc_dem_free.argtypes = [C.c_void_p]
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_get_threads.restype = C.c_int
+    lib.orc_get_threads.argtypes = []
     _lib = lib
     return lib
 
 
 def _d(a):
     return a.ctypes.data_as(_dp)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
 
 
 def _f64(a, shape=None):
