@@ -9,11 +9,21 @@ falls on every tenth step is inside the timed region.  Inputs are generated
 and copied to HBM before timing.
 
 Prints ONE JSON line: metric/value (particle-steps/s) over K timed steps; the
-roofline of the dominant kernel (contact search + forces), measured with HIP
-events bound to each of its launches while the same K steps are replayed on a
-fresh bed (the runs are deterministic); the CPU oracle timed on a bounded
-sample of the same workload; and the two other parts of the metric:
+roofline of the dominant kernel (contact search + forces) over a fixed window,
+the same for every K: a fresh bed run 20 steps, then 1,000 steps measured with
+their re-sorts, broad searches and coupling steps, once without
+instrumentation (the whole step's time) and once replayed on a fresh bed with
+HIP events bound to each launch of the kernel (the runs are deterministic);
+beside the kernel's fraction of the HBM peak, the whole step's (algorithmic
+bytes of a DEM step plus a tenth of a coupling step over the time per step);
+the CPU oracle timed on a bounded sample of the same workload at one thread
+and at all the threads the process may use; and the other parts of the
+metric:
 
+  fp64:    the same bed and window with all arithmetic in FP64;
+  plain_fp64_2k: the plain FP64 configuration (2,000 spheres d = 3 mm, Q2
+           4x4x16, 100 DEM steps with a coupling step every 10), fresh beds,
+           median of 5 runs;
   batched: 64 independent column beds (5k-80k spheres each, their own
            diameter, restitution, inlet velocity and Q1 mesh) advanced 1,000
            steps by shared launches replayed from a HIP graph (FP32 forces),
@@ -40,17 +50,20 @@ Beside particle-steps/s the main line gives contacts/s (contact pairs and
 wall contacts resolved per second) and quadrature-points/s (points of the
 coupling steps per second).  The CPU leg also compares both GPU paths (FP32
 forces, all FP64) with the oracle on the main bed: the first coupling and DEM
-step, and the end of the oracle's sample; and on the first coupling and DEM
-step, the spouted bed's path and a batched bed's path (FP32 forces).
+step, and the end of the oracle's sample; on the first coupling and DEM
+step, the spouted bed's path and a batched bed's path (FP32 forces); and the
+plain FP64 configuration's whole run.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--no-batched] [--no-served] [--no-smoothing] [--no-spouted]
-                       [--no-packed] [--no-settling] [--served-jobs J]
+                       [--no-packed] [--no-settling] [--no-fp64] [--no-config1]
+                       [--served-jobs J] [--bed-config JSON]
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -68,6 +81,19 @@ RESORT_EVERY = 100
 # and read the partner index (8 B).
 FORCE_BYTES_PER_PARTICLE = 184
 BYTES_PER_CONTACT = 56
+# algorithmic bytes of one coupling step: per particle read x, v, r and its
+# element (60 B) and write f_fp (24 B); per occupied element read its share of
+# the velocity nodes (8 nodes x 24 B for Q2, 1 x 24 B for Q1) and of the
+# pressure nodes (8 B); per quadrature point write eps, beta and F_pf (40 B)
+CPL_BYTES_PER_PARTICLE = 84
+CPL_NODE_BYTES = {1: 24, 2: 192}
+CPL_PRESSURE_BYTES = 8
+CPL_BYTES_PER_QPT = 40
+# the roofline window: a fresh bed run WINDOW_WARMUP steps, then WINDOW_STEPS
+# steps (with their re-sorts, broad searches and coupling steps) measured,
+# whatever the timed region's length
+WINDOW_WARMUP = 20
+WINDOW_STEPS = 1000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kick_fluidized_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_01185_amd", "csrc", "dem_kernels.hip")
 
@@ -89,6 +115,8 @@ def parse():
     ap.add_argument("--no-smoothing", action="store_true", help="skip the smoothed void-fraction run")
     ap.add_argument("--no-spouted", action="store_true", help="skip the spouted-bed run")
     ap.add_argument("--no-packed", action="store_true", help="skip the packed-bed run")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 line of the 100k bed")
+    ap.add_argument("--no-config1", action="store_true", help="skip the plain FP64 2,000-sphere line")
     ap.add_argument("--batched-beds", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--served-jobs", type=int, default=650)
@@ -105,20 +133,40 @@ def kernel_source_sha():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_entry(bed_kw):
+def traffic_entry(lanes, precision="fp32"):
     """HBM bytes per launch of the force kernel from the committed rocprofv3
-    counter summary, or None if it is absent, the kernel changed since, or it
-    was taken with another tuned configuration."""
+    counter summary, with the configuration they were taken at, or (None,
+    None) if it is absent or the kernel source or its launch shape (lanes per
+    particle, precision) differs."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha256") != kernel_source_sha():
-        return None
+        return None, None
     cfg = t.get("config") or {}
-    same = (cfg.get("lanes") == bed_kw["lanes"] and cfg.get("resort_every") == bed_kw["resort_every"]
-            and abs(float(cfg.get("skin", -1.0)) - bed_kw["skin"]) <= 1e-9 * bed_kw["skin"])
-    return float(t["hbm_bytes_per_launch"]) if same else None
+    if cfg.get("lanes") != lanes or cfg.get("precision", "fp32") != precision:
+        return None, None
+    return float(t["hbm_bytes_per_launch"]), cfg
+
+
+def occupied_elements(wl, x):
+    """Mesh elements holding at least one particle centre (x: 3 x n)."""
+    import numpy as np
+
+    lo = np.asarray(wl.dem["box_lo"], dtype=np.float64)[:, None]
+    hi = np.asarray(wl.dem["box_hi"], dtype=np.float64)[:, None]
+    n_el = np.asarray(wl.fluid["n_el"], dtype=np.int64)[:, None]
+    e = np.clip(np.floor((x - lo) / (hi - lo) * n_el).astype(np.int64), 0, n_el - 1)
+    return int(np.unique((e[2] * n_el[1] + e[1]) * n_el[0] + e[0]).size)
+
+
+def coupling_bytes(wl, n_occ):
+    """Algorithmic bytes of one coupling step with n_occ occupied elements."""
+    order = int(wl.fluid["order"])
+    n_el = int(wl.fluid["n_el"][0]) * int(wl.fluid["n_el"][1]) * int(wl.fluid["n_el"][2])
+    return (CPL_BYTES_PER_PARTICLE * wl.n + n_occ * (CPL_NODE_BYTES[order] + CPL_PRESSURE_BYTES)
+            + CPL_BYTES_PER_QPT * n_el * (order + 1) ** 3)
 
 
 def contact_counts(bed):
@@ -153,12 +201,43 @@ def couplings_in(start, steps):
     return sum(1 for s in range(start, start + steps) if s % COUPLING_EVERY == 0)
 
 
-def cpu_baseline(wl, dem_steps):
-    """The FP64 oracle, as it stands, on the same bed: dem_steps DEM steps with
-    a coupling step every COUPLING_EVERY steps.  Also returns what the GPU
-    paths are compared with: the first coupling step's outputs, the state
-    after the first step and the state at the end (copied outside the timed
-    steps)."""
+def cpu_info():
+    """The host CPU as lscpu reports it, and the threads this process may run
+    (its CPU affinity, capped by OMP_NUM_THREADS when set and by the physical
+    cores)."""
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+
+    def num(key):
+        try:
+            return int(info.get(key, ""))
+        except ValueError:
+            return None
+
+    sockets, per_socket, per_core = num("Socket(s)"), num("Core(s) per socket"), num("Thread(s) per core")
+    physical = sockets * per_socket if sockets and per_socket else None
+    threads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads = min(threads, int(env))
+    if physical:
+        threads = min(threads, physical)
+    return {"model": info.get("Model name"), "sockets": sockets, "physical_cores": physical,
+            "threads_per_core": per_core, "logical_cpus": num("CPU(s)"),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "threads_used": max(1, threads)}
+
+
+def oracle_sample(wl, dem_steps, keep=False):
+    """One timed run of the oracle on the bed: dem_steps DEM steps with a
+    coupling step every COUPLING_EVERY steps (creation not timed).  With
+    keep, also the first coupling step's outputs, the state after the first
+    step and the state at the end (copied outside the timed steps)."""
     from oracle import oracle as O
 
     d, f = wl.dem, wl.fluid
@@ -174,20 +253,45 @@ def cpu_baseline(wl, dem_steps):
             r = bed.couple(fl, wl.U, wl.P)
         bed.step(1)
         dt += time.perf_counter() - t0
-        if s == 0:
+        if keep and s == 0:
             ref["couple"] = r
             ref["step1"] = bed.state()
-    ref["end"] = bed.state()
-    cpu_model = None
-    try:
-        with open("/proc/cpuinfo") as fh:
-            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
-    except OSError:
-        pass
-    out = {"value": wl.n * dem_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-           "cpu_model": cpu_model,
+    if keep:
+        ref["end"] = bed.state()
+    return dt, ref
+
+
+def cpu_baseline(wl, dem_steps, repeats=3):
+    """The FP64 oracle, as it stands, on the same bed: dem_steps DEM steps with
+    a coupling step every COUPLING_EVERY steps, timed at one thread and at all
+    the threads this process may use, median of `repeats` runs each (the
+    oracle's results do not depend on its thread count).  Also returns what
+    the GPU paths are compared with (from the first run)."""
+    import statistics
+
+    from oracle import oracle as O
+
+    cpu = cpu_info()
+    times, ref = {}, None
+    for threads in (1, cpu["threads_used"]):
+        O.set_threads(threads)
+        ts = []
+        for _ in range(repeats):
+            dt, r = oracle_sample(wl, dem_steps, keep=ref is None)
+            ref = ref or r
+            ts.append(dt)
+        times[threads] = statistics.median(ts)
+    nt = cpu["threads_used"]
+    rate = {t: wl.n * dem_steps / v for t, v in times.items()}
+    out = {"value": rate[nt], "unit": "particle-steps/s", "cores": nt, "kind": "oracle",
+           "cpu_model": cpu["model"], "physical_cores": cpu["physical_cores"],
+           "threads_per_core": cpu["threads_per_core"], "affinity_cpus": cpu["affinity_cpus"],
+           "one_core": {"value": rate[1], "unit": "particle-steps/s", "cores": 1, "seconds": times[1]},
+           "all_cores": {"value": rate[nt], "unit": "particle-steps/s", "cores": nt, "seconds": times[nt]},
            "sample": f"{dem_steps} DEM steps + {dem_steps // COUPLING_EVERY} coupling steps of the same "
-                     f"{wl.n}-sphere bed, single-threaded FP64 C oracle, {dt:.1f} s"}
+                     f"{wl.n}-sphere bed, FP64 C oracle (OpenMP over independent per-particle, per-contact "
+                     f"and per-element work; sums serial), median of {repeats} runs at 1 thread "
+                     f"({times[1]:.1f} s) and at {nt} threads ({times[nt]:.1f} s)"}
     return out, ref
 
 
@@ -289,26 +393,36 @@ def errors_vs_oracle(wl, U, P, bed_kw, dev, ref, dem_steps):
             "bound_single_step": {"fp32": 1e-5, "fp64": 1e-10}, **res}
 
 
-def measure_coupled(wl, U, P, bed_kw, dev, steps, warmup):
-    """`warmup` + `steps` coupled steps of a fresh bed (FP32 forces) with the
-    `steps` timed, then the same steps replayed on another fresh bed with the
-    contact-force kernel's launches timed by HIP events (the runs are
-    deterministic)."""
+def measure_coupled(wl, U, P, bed_kw, dev, steps, warmup, precision="fp32"):
+    """`warmup` + `steps` coupled steps of a fresh bed with the `steps` timed
+    (wall clock and HIP events on the bed's stream), then the same steps
+    replayed on another fresh bed with the contact-force kernel's launches
+    timed by HIP events (the runs are deterministic).  Returns the timing,
+    the force kernel's roofline and the whole step's: algorithmic bytes of a
+    DEM step plus a tenth of a coupling step over the measured time per
+    step."""
     import torch
 
-    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev, precision)
     s = run_coupled(bed, out, U, P, warmup, 0)
     torch.cuda.synchronize()
     pairs0, walls0 = contact_counts(bed)
-    t0 = time.perf_counter()
-    run_coupled(bed, out, U, P, steps, s)
+    occ0 = occupied_elements(wl, bed.read_state()["x"].cpu().numpy())
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ev0.record(bed.stream)
+    run_coupled(bed, out, U, P, steps, s)
+    ev1.record(bed.stream)
+    torch.cuda.synchronize()
+    wall = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
     err, _ = bed.poll()
     pairs1, walls1 = contact_counts(bed)
+    occ1 = occupied_elements(wl, bed.read_state()["x"].cpu().numpy())
     nq_total = bed.n_elem * bed.nq
     bed.close()
-    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev)
+    bed, out = make_coupled_bed(wl, U, P, bed_kw, dev, precision)
     s = run_coupled(bed, out, U, P, warmup, 0)
     bed.kernel_timing(True)
     run_coupled(bed, out, U, P, steps, s)
@@ -321,11 +435,83 @@ def measure_coupled(wl, U, P, bed_kw, dev, steps, warmup):
     force_avg_s = force_ms / 1e3 / max(launches, 1)
     alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
     achieved = alg_bytes / force_avg_s / 1e9
+    n_occ = 0.5 * (occ0 + occ1)
+    step_bytes = alg_bytes + coupling_bytes(wl, n_occ) / COUPLING_EVERY
+    step_s = wall / steps
     return {"wall": wall, "errors": int(err or err2), "nq_total": nq_total, "contacts": contacts,
             "pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
             "force_kernel": {"avg_launch_us": force_avg_s * 1e6, "launches": launches,
                              "algorithmic_bytes_per_launch": alg_bytes, "achieved_GBs": achieved,
-                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS}}
+                             "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
+            "whole_step": {"us_per_step": step_s * 1e6, "algorithmic_bytes_per_step": step_bytes,
+                           "occupied_elements": n_occ, "achieved_GBs": step_bytes / step_s / 1e9,
+                           "frac_of_hbm_peak": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
+                           "bytes": "184 B/particle + 56 B/contact per DEM step, plus a tenth of "
+                                    "84 B/particle + (node share + 8 B)/occupied element + 40 B/quadrature point"}}
+
+
+def config1_run(dev, repeats=5):
+    """The plain FP64 configuration (2,000 spheres d = 3 mm in 0.05 x 0.05 x
+    0.2 m, Q2 4x4x16 with a uniform 0.5 m/s upflow): its 100 DEM steps with a
+    coupling step every 10, all FP64, from a fresh bed each time (creation not
+    timed); median of `repeats` runs."""
+    import statistics
+
+    import torch
+
+    from paper_2211_01185_amd import synth
+
+    wl = synth.plain()
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    steps = int(wl.run["steps"])
+    times, errs, contacts = [], 0, 0
+    for _ in range(repeats):
+        bed, out = make_coupled_bed(wl, U, P, dict(resort_every=RESORT_EVERY), dev, "fp64")
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(bed.stream)
+        run_coupled(bed, out, U, P, steps, 0)
+        ev1.record(bed.stream)
+        torch.cuda.synchronize()
+        times.append(max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3))
+        err, contacts = bed.poll()
+        errs += 1 if err else 0
+        bed.close()
+    t = statistics.median(times)
+    return {"workload": "plain FP64: 2,000 spheres d = 3 mm, rho 2500, random non-overlapping in "
+                        "0.05 x 0.05 x 0.2 m, Q2 4x4x16 mesh with a uniform (0, 0, 0.5) m/s field, "
+                        f"Di Felice, {steps} DEM steps with a coupling step every {COUPLING_EVERY}",
+            "particles": wl.n, "steps": steps, "value": wl.n * steps / t, "unit": "particle-steps/s",
+            "ms_per_step": t * 1e3 / steps, "ms_per_run": t * 1e3, "runs": repeats,
+            "contacts_end": int(contacts), "errors": errs, "dtype": "f64",
+            "launch": "single-bed entry points, fresh bed per run"}
+
+
+def config1_errors(dev):
+    """The plain FP64 configuration's whole run (100 steps) on the GPU against
+    the oracle: the parity tests' measure on x, v and w at the end."""
+    import numpy as np
+    import torch
+
+    from paper_2211_01185_amd import synth
+
+    wl = synth.plain()
+    steps = int(wl.run["steps"])
+    _, ref = oracle_sample(wl, steps, keep=True)
+    U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
+    P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
+    bed, out = make_coupled_bed(wl, U, P, dict(resort_every=RESORT_EVERY), dev, "fp64")
+    run_coupled(bed, out, U, P, steps, 0)
+    st = {k: v.cpu().numpy() for k, v in bed.read_state().items()}
+    err, _ = bed.poll()
+    bed.close()
+    d = 2.0 * float(wl.radius.min())
+    return {f"x_after_{steps}_steps_over_d": float(np.max(np.abs(st["x"] - ref["end"]["x"]))) / d,
+            f"v_after_{steps}_steps": rel_max_err(st["v"], ref["end"]["v"]),
+            f"w_after_{steps}_steps": rel_max_err(st["w"], ref["end"]["w"]), "errors": int(err)}
 
 
 def spouted_run(dev, steps=500, warmup=20):
@@ -357,7 +543,7 @@ def spouted_run(dev, steps=500, warmup=20):
             "contacts_pairs_walls": m["pairs_walls"],
             "tuned": dict(bed_kw, trials=tune_report["trials"],
                           default_ms_per_step=tune_report["default_ms_per_step"]),
-            "force_kernel": m["force_kernel"],
+            "force_kernel": m["force_kernel"], "whole_step": m["whole_step"],
             "generation_s": gen_s, "errors": m["errors"], "dtype": "f32 forces / f64 state"}, wl, bed_kw
 
 
@@ -519,7 +705,7 @@ def packed_run(dev, steps=1000, warmup=20):
             "contacts_pairs_walls": m["pairs_walls"],
             "tuned": dict(bed_kw, trials=tune_report["trials"],
                           default_ms_per_step=tune_report["default_ms_per_step"]),
-            "force_kernel": m["force_kernel"],
+            "force_kernel": m["force_kernel"], "whole_step": m["whole_step"],
             "errors": m["errors"], "dtype": "f32 forces / f64 state"}
 
 
@@ -564,8 +750,9 @@ def main():
     U = torch.as_tensor(wl.U, dtype=torch.float64, device=dev).contiguous()
     P = torch.as_tensor(wl.P, dtype=torch.float64, device=dev).contiguous()
     # skin (DEM cell size), re-sort interval and lanes per particle: tuned on
-    # runs of this bed from its start over as many steps as are measured (the
-    # rate of list rebuilds grows as the bed fluidizes); results do not depend
+    # runs of this bed over the roofline window (from its start, the warm-up
+    # and the measured steps: the rate of list rebuilds grows as the bed
+    # fluidizes), whatever the timed region's length; results do not depend
     # on them
     if args.bed_config:
         given = json.loads(args.bed_config)
@@ -573,7 +760,7 @@ def main():
         bed_kw["elem_threads"] = int(given.get("elem_threads", 128))
         tune_report = {"trials": 0, "default_ms_per_step": None}
     else:
-        tuned, tune_report = autotune.tune([wl], "fp32", steps=args.warmup + args.steps, device=dev,
+        tuned, tune_report = autotune.tune([wl], "fp32", steps=WINDOW_WARMUP + WINDOW_STEPS, device=dev,
                                            use_cache=False)
         bed_kw = autotune.bed_kwargs(wl, tuned)
     progress(f"tuned {bed_kw} in {tune_report['trials']} trials")
@@ -612,28 +799,22 @@ def main():
     del bed, out
     progress(f"timed region: {wall * 1e3 / args.steps:.4f} ms per step")
 
-    # roofline: the same deterministic trajectory replayed on a fresh bed, with
-    # HIP events bound to every launch of the contact-force kernel on its
-    # stream during the same K steps (the events add launch latency, so this
-    # replay is not used for the throughput)
-    bed, out = make_bed()
-    step = run(bed, out, args.warmup, 0)
-    bed.kernel_timing(True)
-    step = run(bed, out, args.steps, step)
-    torch.cuda.synchronize()
-    bed.kernel_timing(False)
-    launches, force_ms = bed.kernel_timing_read()
-    pairs2, walls2 = contact_counts(bed)
-    bed.close()
-    progress(f"replayed region: {launches} force-kernel launches, {force_ms * 1e3 / max(launches, 1):.2f} us each")
+    # roofline: the fixed window (WINDOW_WARMUP + WINDOW_STEPS steps of a
+    # fresh bed) run once without instrumentation for the whole step's time,
+    # then replayed on another fresh bed with HIP events bound to every launch
+    # of the contact-force kernel on its stream (the events add launch
+    # latency, so the timed region runs without them)
+    win = measure_coupled(wl, U, P, bed_kw, dev, WINDOW_STEPS, WINDOW_WARMUP)
+    fk = win["force_kernel"]
+    progress(f"roofline window: {fk['launches']} force-kernel launches, {fk['avg_launch_us']:.2f} us each; "
+             f"{win['whole_step']['us_per_step']:.2f} us per step")
+    if win["errors"]:
+        raise SystemExit("device error in the roofline window")
 
     elapsed = max(wall, gpu_ms / 1e3)
     value = wl.n * args.steps / elapsed
-    contacts = 0.5 * (pairs0 + walls0 + pairs2 + walls2)
-    force_avg_s = force_ms / 1e3 / max(launches, 1)
-    alg_bytes = FORCE_BYTES_PER_PARTICLE * wl.n + BYTES_PER_CONTACT * contacts
-    achieved = alg_bytes / force_avg_s / 1e9
-    traffic = traffic_entry(bed_kw)
+    contacts = 0.5 * (pairs0 + walls0 + pairs1 + walls1)
+    traffic, traffic_cfg = traffic_entry(bed_kw["lanes"], "fp32")
     qpts = wl.fluid["n_el"][0] * wl.fluid["n_el"][1] * wl.fluid["n_el"][2] * (wl.fluid["order"] + 1) ** 3
 
     result = {
@@ -658,7 +839,8 @@ def main():
             "precision": "FP32 pair-force and drag arithmetic, FP64 positions/velocities/history/sums",
             "contacts_pairs_walls": [int(round(0.5 * (pairs0 + pairs1))), int(round(0.5 * (walls0 + walls1)))],
             "tuned": dict(bed_kw, trials=tune_report["trials"],
-                          default_ms_per_step=tune_report["default_ms_per_step"]),
+                          default_ms_per_step=tune_report["default_ms_per_step"],
+                          tuned_over_steps=WINDOW_WARMUP + WINDOW_STEPS),
             "parallelism": "1 GPU",
         },
         "rates": {
@@ -671,16 +853,38 @@ def main():
             "bound": "hbm",
             "kernel": f"force_kick<float, true, *, {bed_kw['lanes']}> (contact search + Hertz-Mindlin "
                       "forces + second half kick)",
-            "achieved": achieved,
+            "achieved": fk["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": fk["frac_of_hbm_peak"],
             "traffic": traffic,
-            "avg_launch_us": force_avg_s * 1e6,
-            "launches": launches,
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "traffic_taken_with": traffic_cfg,
+            "avg_launch_us": fk["avg_launch_us"],
+            "launches": fk["launches"],
+            "algorithmic_bytes_per_launch": fk["algorithmic_bytes_per_launch"],
+            "window": {"warmup": WINDOW_WARMUP, "steps": WINDOW_STEPS,
+                       "what": "a fresh bed, WINDOW_WARMUP steps, then WINDOW_STEPS measured steps with their "
+                               "re-sorts, broad searches and coupling steps; the same for every --steps",
+                       "contacts_pairs_walls": win["pairs_walls"], "ms_per_step": win["wall"] * 1e3 / WINDOW_STEPS,
+                       "particle_steps_per_s": wl.n * WINDOW_STEPS / win["wall"]},
+            "whole_step": win["whole_step"],
         },
     }
+    if not args.no_fp64:
+        progress("FP64 100k bed: starting")
+        m = measure_coupled(wl, U, P, bed_kw, dev, WINDOW_STEPS, WINDOW_WARMUP, precision="fp64")
+        result["fp64"] = {"workload": "the same fluidized bed, all FP64 (pair forces and drag too), the roofline "
+                                      "window's steps with the FP32 bed's launch choices",
+                          "particles": wl.n, "steps": WINDOW_STEPS, "warmup": WINDOW_WARMUP,
+                          "value": wl.n * WINDOW_STEPS / m["wall"], "unit": "particle-steps/s",
+                          "ms_per_step": m["wall"] * 1e3 / WINDOW_STEPS, "contacts_pairs_walls": m["pairs_walls"],
+                          "force_kernel": m["force_kernel"], "whole_step": m["whole_step"],
+                          "errors": m["errors"], "dtype": "f64"}
+        progress(f"FP64: {result['fp64']['ms_per_step']:.4f} ms per step")
+    if not args.no_config1:
+        progress("plain FP64 configuration: starting")
+        result["plain_fp64_2k"] = config1_run(dev)
+        progress(f"plain FP64: {result['plain_fp64_2k']['ms_per_step']:.4f} ms per step")
     if not args.no_batched:
         result["batched"] = batched_ensemble(args.batched_beds, args.batched_steps, dev)
         progress(f"batched: {result['batched']['value']:.4g} particle-steps/s")
@@ -718,6 +922,9 @@ def main():
             progress("spouted bed against the oracle")
             result["error_vs_fp64_oracle"]["spouted_fp32"] = gpu_first_step_errors(
                 sp_wl, oracle_first_step(sp_wl), dev, sp_kw)
+        if not args.no_config1:
+            progress("plain FP64 configuration against the oracle")
+            result["error_vs_fp64_oracle"]["plain_fp64_2k"] = config1_errors(dev)
         if not args.no_batched:
             from paper_2211_01185_amd import autotune, synth
 

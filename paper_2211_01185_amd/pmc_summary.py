@@ -3,12 +3,14 @@
 Inputs: one `rocprofv3 --pmc FETCH_SIZE` and one `--pmc WRITE_SIZE` run of
 the benchmark's main measurement (its JSON line saved to a file), and the same
 two counters over the plain device copy of calib.py.  The force-kernel
-dispatches of the replayed region are selected (after the bed's
-creation-time evaluation, skipping the warm-up steps), each counter is scaled
+dispatches of the roofline window's replay are selected (the last FP32 bed the
+run created at the main bed's launch shape, after its creation-time
+evaluation, skipping the window's warm-up steps), each counter is scaled
 by true copy bytes / counted copy bytes, and the mean per dispatch is written
 as the JSON entry the benchmark reports as roofline.traffic.  The entry is
-keyed by the hash of the kernel source and by the tuned configuration of the
-run: a different kernel or configuration reads as no measurement.
+keyed by the hash of the kernel source and by its launch shape (lanes per
+particle, precision); it records the whole configuration it was taken at
+(skin, re-sort interval), which the benchmark reports beside it.
 
     python -m paper_2211_01185_amd.pmc_summary --fetch D1 --write D2 \\
         --cal-fetch D3 --cal-write D4 --bench-json F1 --bench-json-write F2 --out JSON
@@ -79,7 +81,9 @@ def main(argv=None):
     other = bench_line(args.bench_json_write)["config"]["tuned"]
     if {k: other[k] for k in cfg} != cfg:
         raise SystemExit("the two counter runs used different configurations")
-    warmup, steps = int(bench["warmup"]), int(bench["steps"])
+    window = bench["roofline"]["window"]
+    warmup, steps = int(window["warmup"]), int(window["steps"])
+    cfg["precision"] = "fp32"
     fs, nf = _scale(args.cal_fetch, "FETCH_SIZE")
     ws, nw = _scale(args.cal_write, "WRITE_SIZE")
     f = _region(args.fetch, "FETCH_SIZE", cfg["lanes"], warmup, steps)

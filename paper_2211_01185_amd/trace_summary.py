@@ -4,17 +4,18 @@
     python -m paper_2211_01185_amd.trace_summary --trace DIR --bench-json FILE
 
 Prints the kernel statistics of the whole command and the contact-force
-kernel's launch durations over the main measurement's two regions: the timed
-steps of the first bed and the same steps replayed on a second bed (where the
-benchmark reads its per-launch HIP events).  With --bed spouted: the kernels
+kernel's launch durations over the main bed's timed region and over the
+roofline window's two runs (the second is where the benchmark reads its
+per-launch HIP events).  With --bed spouted: the kernels
 of the spouted-bed measurement's timed bed instead (the last two beds created
 at that bed's grid are the timed one and its replay; the tuner's trial beds
 come before them).  A bed of the main measurement is
 recognised by its creation-time evaluation (force_kick<float, false, false,
 L, false>: no rolling friction) at the main bed's grid size followed by step
-launches of the single-bed kernel: the measurement's two beds run exactly
-warm-up + timed steps (the autotuner's trials run two more coupling periods,
-the settling run thousands of steps, the smoothing run fewer).
+launches of the single-bed kernel; the timed bed runs exactly warm-up + timed
+steps and the window's beds the window's steps (the autotuner's trials run two
+more coupling periods, the settling run thousands of steps, the smoothing run
+fewer).
 """
 from __future__ import annotations
 
@@ -76,20 +77,29 @@ def main(argv=None):
             beds.append(cur)
         elif cur is not None and step_re.search(r[key]):
             cur.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    full = [b for b in beds if len(b) == warmup + steps]
-    if len(full) != 2:
-        raise SystemExit(f"found {len(full)} beds with exactly {warmup + steps} step launches at grid {grid}")
+    # beds in creation order: the tuner's trials (two coupling periods longer
+    # than the window), the timed region (warmup + steps launches), then the
+    # roofline window's run and its replay (WINDOW launches each)
+    window = bench["roofline"]["window"]
+    ww, ws = int(window["warmup"]), int(window["steps"])
+    timed = [b for b in beds if len(b) == warmup + steps]
+    win = [b for b in beds if len(b) == ww + ws]
+    if warmup + steps == ww + ws:
+        win = win[1:]  # the timed region itself comes first
+    if not timed or len(win) < 2:
+        raise SystemExit(f"found {len(timed)} timed beds and {len(win)} window beds at grid {grid}")
     print()
-    print(f"Contact-force kernel `force_kick<float, true, *, {lanes}>` over the main measurement "
-          f"({steps} launches after {warmup} warm-up steps; grid {grid}):")
+    print(f"Contact-force kernel `force_kick<float, true, *, {lanes}>` of the main bed (grid {grid}):")
     print()
-    for name, b in (("timed region (first bed)", full[0]), ("replayed region (second bed)", full[1])):
-        x = np.array(b[warmup:warmup + steps])
+    for name, b, w0, k in (("timed region", timed[0], warmup, steps),
+                           ("roofline window, run", win[0], ww, ws),
+                           ("roofline window, replay with per-launch events", win[1], ww, ws)):
+        x = np.array(b[w0:w0 + k])
         med = float(np.median(x))
-        print(f"- {name}: mean {x.mean():.2f} us, median {med:.2f} us, p90 {np.percentile(x, 90):.2f} us, "
-              f"max {x.max():.2f} us; {int((x > 2 * med).sum())} launches above twice the median "
-              f"(steps that run a broad search)")
-    print(f"- bench.py's HIP events over the replayed region (same run, under the profiler): "
+        print(f"- {name} ({k} launches after {w0} warm-up steps): mean {x.mean():.2f} us, median {med:.2f} us, "
+              f"p90 {np.percentile(x, 90):.2f} us, max {x.max():.2f} us; {int((x > 2 * med).sum())} launches "
+              f"above twice the median (steps that run a broad search)")
+    print(f"- bench.py's HIP events over the window's replay (same run, under the profiler): "
           f"{bench['roofline']['avg_launch_us']:.2f} us per launch")
 
 
