@@ -480,18 +480,12 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const unsigned long long hm = gsel(D.hmask, cur)[a];
   const int lnv = gsel(D.ln, cur)[a];
   unsigned long long key = lst[(size_t)min(lane, D.maxn - 1) * n + a];
-  const double xbl[3] = {glb(D.xb)[a], glb(D.xb)[n + a], glb(D.xb)[2 * n + a]};
   const dvec4 va = VM[a], wa = WS[a];
   const double va0 = va.x, va1 = va.y, va2 = va.z, ma = va.w;
   const double wa0 = wa.x, wa1 = wa.y, wa2 = wa.z;
-  const double fa[3] = {glb(D.ffp)[a], glb(D.ffp)[n + a], glb(D.ffp)[2 * n + a]};
   const unsigned wold = (ADVANCE && lane == L - 1) ? wmask_a : 0u;
-  const int w_first = wold ? __ffs(wold) - 1 : 0;
-  const double wdt_l[3] = {glb(D.whdt)[(size_t)w_first * n + a], glb(D.whdt)[(size_t)(kWalls + w_first) * n + a],
-                           glb(D.whdt)[(size_t)(2 * kWalls + w_first) * n + a]};
   const int m = rebuild ? m_new : lnv;
   unsigned long long mask_prev = rebuild ? carried : hm;
-  const double xba[3] = {rebuild ? xa0 : xbl[0], rebuild ? xa1 : xbl[1], rebuild ? xa2 : xbl[2]};
 
   // ---- fine search and forces over this lane's list entries
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
@@ -561,9 +555,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       vij[0] = va0 + (rw1 * nrm[2] - rw2 * nrm[1]);
       vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
       vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
-      if (wall == w_first && ((wold >> wall) & 1u))
-        for (int c = 0; c < 3; ++c) dto[c] = wdt_l[c];
-      else if ((wold >> wall) & 1u)
+      if ((wold >> wall) & 1u)
         for (int c = 0; c < 3; ++c) dto[c] = glb(D.whdt)[(size_t)(c * kWalls + wall) * n + a];
       const double wr[3] = {wa0, wa1, wa2};
       contact_law<R, ADVANCE, ROLL>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, wr, f, nxft, dtn, mr);
@@ -605,6 +597,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   gsel(D.cnt, r3)[c_old] = 0;
 
   if (ADVANCE) {
+    const double fa[3] = {glb(D.ffp)[a], glb(D.ffp)[n + a], glb(D.ffp)[2 * n + a]};
+    const double xbl[3] = {glb(D.xb)[a], glb(D.xb)[n + a], glb(D.xb)[2 * n + a]};
+    const double xba[3] = {rebuild ? xa0 : xbl[0], rebuild ? xa1 : xbl[1], rebuild ? xa2 : xbl[2]};
     const double inertia = 0.4 * ma * ra * ra;
     double vb[3], wb[3], acc[3], alpha[3];
     for (int c = 0; c < 3; ++c) {
@@ -643,7 +638,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-__global__ __launch_bounds__(kForceBlock, 3) void force_kick(Dev D, int p2, int p3, const int *src) {
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
   force_kick_body<R, ADVANCE, CONT, L, ROLL>(D, blockIdx.x, p2, p3, src);
 }
 
@@ -676,7 +671,7 @@ __global__ __launch_bounds__(256) void drift_bin_batch(const Dev *__restrict__ t
 
 // Step run.s + i of every bed (i = 1 applies the bed's pending permutation).
 template <typename R, bool CONT, int L, bool ROLL>
-__global__ __launch_bounds__(kForceBlock, 3) void force_kick_batch(const Dev *__restrict__ tab,
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__restrict__ tab,
                                                                    const BedRun *__restrict__ run,
                                                                    const unsigned *__restrict__ map,
                                                                    int i) {
