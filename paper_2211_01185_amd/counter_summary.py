@@ -2,7 +2,8 @@
 
 Each run (`rocprofv3 --pmc C1 C2 ...` of the benchmark's main measurement,
 its JSON line saved to a file) is reduced to the mean of every counter over
-the step launches of the replayed region (as pmc_summary selects them), and
+the step launches of the roofline window's replay (as pmc_summary selects
+them), and
 printed as a markdown table with these ratios where their counters are
 present (the SQ cycle counters share one unit, four cycles):
 
@@ -31,14 +32,15 @@ def main(argv=None):
     with open(args.bench_json) as fh:
         bench = json.loads([ln for ln in fh if ln.startswith("{")][-1])
     lanes = int(bench["config"]["tuned"]["lanes"])
-    warmup, steps = int(bench["warmup"]), int(bench["steps"])
+    window = bench["roofline"]["window"]
+    warmup, steps = int(window["warmup"]), int(window["steps"])
     means = {}
     for d in args.run:
         for c in sorted({r["Counter_Name"] for r in _rows(d)}):
             v = _region(d, c, lanes, warmup, steps)
             means[c] = sum(v) / len(v)
     print(f"Contact-force kernel `force_kick<float, true, *, {lanes}>`, mean per launch over the "
-          f"{steps} step launches of the replayed region:")
+          f"{steps} step launches of the roofline window's replay:")
     print()
     print("| counter | mean per launch |")
     print("|---|---|")

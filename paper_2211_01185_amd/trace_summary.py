@@ -114,10 +114,17 @@ def spouted(args, bench):
     gkey = "Grid_Size" if "Grid_Size" in rows[0] else "Grid_Size_X"
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     prime_re = re.compile(rf"cfddem::force_kick<float, false, false, {lanes}, false>")
+    step_re = re.compile(rf"cfddem::force_kick<float, true, (true|false), {lanes}, false>")
     starts = [i for i, r in enumerate(rows) if int(r[gkey] or 0) == grid and prime_re.search(r[key])]
-    if len(starts) < 2:
-        raise SystemExit(f"found {len(starts)} beds at grid {grid}")
-    region = rows[starts[-2]:starts[-1]]
+    starts.append(len(rows))
+    # the timed bed: the first bed at this grid that runs exactly warm-up +
+    # timed step launches (the tuner's trials run two coupling periods more,
+    # the replay comes after it and the oracle comparison's bed one step)
+    timed = [(b, e) for b, e in zip(starts, starts[1:])
+             if sum(1 for r in rows[b:e] if int(r[gkey] or 0) == grid and step_re.search(r[key])) == warmup + steps]
+    if not timed:
+        raise SystemExit(f"no bed at grid {grid} with {warmup + steps} step launches")
+    region = rows[timed[0][0]:timed[0][1]]
     tot = {}
     for r in region:
         name = r[key]
