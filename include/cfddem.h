@@ -252,6 +252,29 @@ dem_status dem_kinetic_energy(dem_ctx *ctx, double *out, void *stream);
  * stream are ordered.  Returns the sticky error of a poisoned context. */
 dem_status dem_kinetic_energy_noalloc(dem_ctx *ctx, double *out, void *stream);
 
+/* Monitoring metrics of the current state, for checking a run against the
+ * conservation properties of the method: Newton's third law makes the
+ * contact forces conserve total momentum (Section 2.2, Eq. "newton_law");
+ * the contact-force equation needs normal overlaps small against the radii;
+ * the particle-centroid void fraction (Eq. "void_fraction") conserves the
+ * solid volume, sum over elements of (1 - eps_e) V_e = sum of V_p.
+ * out (host, 7 doubles):
+ *   [0..2] total linear momentum, sum of m v over the particles (boundary
+ *          velocities of the last completed step);
+ *   [3]    largest normal overlap of the last evaluation's contacts over the
+ *          smaller radius of the pair (the particle's radius for a wall);
+ *          0 without contacts;
+ *   [4]    total solid volume, sum of 4/3 pi R^3;
+ *   [5]    the same volume seen by the fluid: sum over the quadrature points
+ *          of w_q (1 - eps_q), with eps_q as cfd_dem_couple wrote it (device,
+ *          n_elem x (order+1)^3, may be NULL: then NaN) and w_q the Gauss
+ *          weights times the element volume;
+ *   [6]    largest particle speed |v|.
+ * Sums are reduced in a fixed order (the same bits on every call).  Uses the
+ * workspace and synchronizes the stream.  Errors: DEM_E_ARG (ctx or out
+ * NULL), the sticky error of a poisoned context. */
+dem_status dem_metrics(dem_ctx *ctx, const double *eps_q, double *out, void *stream);
+
 /* Element and DEM-cell index of every particle at its last binning, original-ID
  * order.  Element index as in cfd_params; cell index
  * element*(kx*ky*kz) + (sz*ky+sy)*kx + sx with sub-cell s_a in [0, k_a).

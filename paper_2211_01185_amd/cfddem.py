@@ -33,7 +33,7 @@ DRAG = {"difelice": 0, "dallavalle": 1, "rong": 2, "koch_hill": 3, "beetstra": 4
 
 SYMBOLS = ("dem_workspace_bytes", "dem_create", "dem_step", "cfd_dem_couple", "dem_read_state",
            "dem_read_forces", "dem_read_cells", "dem_read_contacts", "dem_poll", "dem_kinetic_energy",
-           "dem_checkpoint_bytes", "dem_read_checkpoint", "dem_write_state", "dem_kinetic_energy_noalloc",
+           "dem_checkpoint_bytes", "dem_read_checkpoint", "dem_write_state", "dem_kinetic_energy_noalloc", "dem_metrics",
 
            "dem_kernel_timing",
            "dem_kernel_timing_read", "dem_destroy", "dem_batch_workspace_bytes", "dem_batch_create",
@@ -107,6 +107,8 @@ def load():
     lib.dem_kinetic_energy.argtypes = [vp, C.POINTER(dbl), vp]
     lib.dem_kinetic_energy_noalloc.restype = i32
     lib.dem_kinetic_energy_noalloc.argtypes = [vp, vp, vp]
+    lib.dem_metrics.restype = i32
+    lib.dem_metrics.argtypes = [vp, vp, vp, vp]
     lib.dem_read_contacts.restype = i32
     lib.dem_read_contacts.argtypes = [vp, vp, vp, i64, C.POINTER(i64), vp]
     lib.dem_poll.restype = i32
@@ -309,6 +311,17 @@ class Bed:
         out = (C.c_double * 2)()
         _check(self._lib.dem_kinetic_energy(self._h, out, self._st), "dem_kinetic_energy")
         return float(out[0]), float(out[1])
+
+    def metrics(self, eps_q=None):
+        """Monitoring metrics of the current state (dem_metrics): total
+        momentum, largest overlap over the smaller radius, solid volume of the
+        particles and, given the eps_q of a coupling step, the solid volume at
+        the quadrature points; synchronizes the bed's stream."""
+        out = (C.c_double * 7)()
+        _check(self._lib.dem_metrics(self._h, _ptr(eps_q), out, self._st), "dem_metrics")
+        return {"momentum": (float(out[0]), float(out[1]), float(out[2])), "max_overlap_over_radius": float(out[3]),
+                "solid_volume": float(out[4]), "solid_volume_at_quadrature_points": float(out[5]),
+                "max_speed": float(out[6])}
 
     def read_cells(self):
         torch = self._torch

@@ -63,6 +63,7 @@ struct Sizes {
   int n, maxn, cap;
   int lanes;  // lanes per particle in the contact-force kernel
   int smooth;     // smoothed void fraction
+  int order;      // velocity element order (1 or 2)
   int nn[3];      // velocity nodes per axis
   long nv;        // velocity nodes
   double skin;
@@ -198,6 +199,7 @@ dem_status derive(const dem_params *dp, const cfd_params *cp, Sizes &S) {
 
   S.n = (int)dp->n;
   S.smooth = cp->smooth;
+  S.order = cp->order;
   S.nv = 1;
   for (int a = 0; a < 3; ++a) {
     S.nn[a] = cp->order * cp->n_el[a] + 1;
@@ -286,6 +288,7 @@ struct Buffers {
   long long *bsum;              // per-block partial sums of the device scan
   unsigned long long *scalars;  // [0] contact count, [1] radius max bits, [2] radius min bits
   double *energy;               // per-block kinetic energies, then the two totals
+  double *metrics;              // per-block metric partials, then the seven results
   // smoothed void fraction (only when enabled): fixed-point element volume
   // sums, the right-hand side, the field, two scratch vectors, and per axis
   // the generalized eigenvectors (and transpose) and eigenvalues
@@ -304,6 +307,11 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   }
   B.scalars = c.take<unsigned long long>(8);
   B.energy = c.take<double>(2 * ((n + 255) / 256) + 2);
+  {
+    const size_t nq1 = (size_t)S.order + 1;
+    const size_t nqt = (size_t)S.grid.n_elem * nq1 * nq1 * nq1;
+    B.metrics = c.take<double>(6 * ((n + 255) / 256) + (nqt + 255) / 256 + 8);
+  }
   if (S.smooth) {
     const size_t nv = (size_t)S.nv;
     B.eps_e = c.take<double>((size_t)S.grid.n_elem);
@@ -614,6 +622,118 @@ __global__ __launch_bounds__(64) void k_energy_total(int nb, const double *part,
   if (threadIdx.x == 0) {
     out[0] = et;
     out[1] = er;
+  }
+}
+
+// Metrics of the current state, per block of 256 particles: momentum (3),
+// solid volume, largest overlap ratio, largest speed.  lbw: word of the lbuf
+// array holding the list buffer of the last evaluation; p2: position buffer
+// of the last completed step.
+__global__ __launch_bounds__(256) void k_metrics_partials(Dev D, int lbw, int p2, double *part) {
+  __shared__ double sh[6][256];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k < D.n) {
+    const int n = D.n;
+    const double m = D.mass[k], r = D.rad[k];
+    double v2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double vc = D.v[c * n + k];
+      q[c] = m * vc;
+      v2 += vc * vc;
+    }
+    q[3] = 4.0 / 3.0 * kPi * r * r * r;
+    q[5] = sqrt(v2);
+    // normal overlaps of the touching list entries and walls, at the
+    // positions the last evaluation used
+    const int lb = D.lbuf[lbw];
+    const dvec4 *X = D.pr[p2];
+    const dvec4 xa = X[k];
+    const unsigned long long mask = D.hmask[lb][k];
+    const int len = D.ln[lb][k];
+    double worst = 0.0;
+    for (int t = 0; t < len; ++t) {
+      if (!((mask >> t) & 1ull)) continue;
+      const int b = (int)(D.nbr[lb][(size_t)t * n + k] & 0xffffffffull);
+      const dvec4 xb = X[b];
+      const double d0 = xb.x - xa.x, d1 = xb.y - xa.y, d2 = xb.z - xa.z;
+      const double dn = (xa.w + xb.w) - sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      worst = fmax(worst, dn / fmin(xa.w, xb.w));
+    }
+    const unsigned wm = D.wmask[k];
+    for (int w = 0; w < kWalls; ++w) {
+      if (!((wm >> w) & 1u)) continue;
+      const int ax = w >> 1;
+      const double xax = ax == 0 ? xa.x : (ax == 1 ? xa.y : xa.z);
+      const double lo = ax == 0 ? D.grid.lo[0] : (ax == 1 ? D.grid.lo[1] : D.grid.lo[2]);
+      const double hi = ax == 0 ? D.grid.hi[0] : (ax == 1 ? D.grid.hi[1] : D.grid.hi[2]);
+      const double dist = (w & 1) ? hi - xax : xax - lo;
+      worst = fmax(worst, (xa.w - dist) / xa.w);
+    }
+    q[4] = worst;
+  }
+  for (int j = 0; j < 6; ++j) sh[j][threadIdx.x] = q[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + h];
+      for (int j = 4; j < 6; ++j) sh[j][threadIdx.x] = fmax(sh[j][threadIdx.x], sh[j][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Solid volume seen at the quadrature points, per block of 256 points:
+// sum of w_q (1 - eps_q), w_q = Ve times the product of the 1D Gauss weights
+// (points ordered element-major, then z, y, x inside an element).
+__global__ __launch_bounds__(256) void k_qsolid_partials(const double *eps_q, long long nqt, int nq1, double wa,
+                                                         double wb, double Ve, double *part) {
+  __shared__ double sh[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < nqt) {
+    const int nq = nq1 * nq1 * nq1;
+    const int l = (int)(i % nq);
+    const int qx = l % nq1, qy = (l / nq1) % nq1, qz = l / (nq1 * nq1);
+    // 1D weight: wa at the end points, wb at the middle one (three points)
+    const double w = (qx == 1 && nq1 == 3 ? wb : wa) * (qy == 1 && nq1 == 3 ? wb : wa) *
+                     (qz == 1 && nq1 == 3 ? wb : wa);
+    v = Ve * w * (1.0 - eps_q[i]);
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// The seven metrics from the block partials, in a fixed order.
+__global__ __launch_bounds__(64) void k_metrics_total(int nb, const double *part, int nbq, const double *qpart,
+                                                      double *out) {
+  double q[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = (int)threadIdx.x; i < nb; i += 64) {
+    for (int j = 0; j < 4; ++j) q[j] += part[6 * i + j];
+    q[4] = fmax(q[4], part[6 * i + 4]);
+    q[6] = fmax(q[6], part[6 * i + 5]);
+  }
+  for (int i = (int)threadIdx.x; i < nbq; i += 64) q[5] += qpart[i];
+  for (int off = 1; off < 64; off <<= 1) {
+    for (int j = 0; j < 4; ++j) q[j] += __shfl_xor(q[j], off, 64);
+    q[5] += __shfl_xor(q[5], off, 64);
+    q[4] = fmax(q[4], __shfl_xor(q[4], off, 64));
+    q[6] = fmax(q[6], __shfl_xor(q[6], off, 64));
+  }
+  if (threadIdx.x == 0) {
+    out[0] = q[0];
+    out[1] = q[1];
+    out[2] = q[2];
+    out[3] = q[4];
+    out[4] = q[3];
+    out[5] = nbq > 0 ? q[5] : __builtin_nan("");
+    out[6] = q[6];
   }
 }
 
@@ -1262,6 +1382,30 @@ dem_status dem_kinetic_energy_noalloc(dem_ctx *ctx, double *out, void *stream) {
   k_energy_partials<<<nb, 256, 0, st>>>(D, part);
   k_energy_total<<<1, 64, 0, st>>>(nb, part, out);
   HIP_TRY(hipGetLastError());
+  return DEM_OK;
+}
+
+dem_status dem_metrics(dem_ctx *ctx, const double *eps_q, double *out, void *stream) {
+  if (!ctx || !out) return DEM_E_ARG;
+  if (ctx->poisoned) return ctx->poisoned;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev &D = ctx->B.D;
+  const int nb = blocks(D.n, 256);
+  const long long nqt = (long long)D.grid.n_elem * ctx->C.nq;
+  const int nbq = eps_q ? (int)((nqt + 255) / 256) : 0;
+  double *part = ctx->B.metrics;
+  double *qpart = part + 6 * (size_t)nb;
+  double *res = qpart + (nqt + 255) / 256;
+  k_metrics_partials<<<nb, 256, 0, st>>>(D, (int)((ctx->s + 1) % 3), (int)(ctx->s & 1), part);
+  if (nbq) {
+    // Gauss-Legendre weights on [0, 1]: 1/2, 1/2 (two points); 5/18, 8/18, 5/18 (three)
+    const double wa = ctx->C.nq1 == 2 ? 0.5 : 5.0 / 18.0, wb = ctx->C.nq1 == 2 ? 0.5 : 8.0 / 18.0;
+    k_qsolid_partials<<<nbq, 256, 0, st>>>(eps_q, nqt, ctx->C.nq1, wa, wb, ctx->C.Ve, qpart);
+  }
+  k_metrics_total<<<1, 64, 0, st>>>(nb, part, nbq, qpart, res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, res, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return DEM_OK;
 }
 
