@@ -95,7 +95,10 @@ typedef struct {
   double E_w, nu_w, e_w, mu_w; /* wall: Young, Poisson; particle-wall restitution, friction */
   int32_t max_neighbors; /* neighbour-list capacity per particle: partners closer
                             than R_i + R_j + skin, 1..64; 0 = 32 */
-  int32_t cell_capacity; /* particles per DEM cell, 1..1024; 0 = derived from sizes */
+  int32_t cell_capacity; /* particles per DEM cell, 1..1024; 0 = derived from sizes.
+                            Between re-sorts, inside a run of steps, only the
+                            particles away from the cell they were sorted into
+                            take a slot; the last step of every run lists all */
   int32_t resort_every;  /* DEM steps between re-sorts of the particle arrays by
                             cell; 0 = never (order of creation) */
   int32_t lanes;         /* lanes of a wavefront sharing one particle in the

@@ -14,9 +14,9 @@
 #include "device.h"
 
 namespace cfddem {
-hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st);
+hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, bool exact, hipStream_t st);
 hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st);
-hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
+hipError_t launch_force_kick(const Dev &D, long long s, const int *src, int gmode, bool advance, bool cont,
                              bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_couple(const Dev &D, const Cpl &C, long long s, long long call, const double *U,
                          const double *P, double *eps_q, double *beta_q, double *fpf_q,
@@ -30,11 +30,10 @@ hipError_t launch_smooth_solve(const SmoothOp &S, const double *b, double *x, do
                                hipStream_t st);
 hipError_t launch_eps_q_field(const SmoothOp &S, const Cpl &C, const double *eps_nodes, double *eps_q,
                               hipStream_t st);
-hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int n,
                                   hipStream_t st);
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, int lanes, bool roll,
-                                   hipStream_t st);
+                                   int i, int n, bool fp32, int maxn, int lanes, bool roll, hipStream_t st);
 hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
 hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
                                 hipStream_t st);
@@ -354,6 +353,8 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   D.wmask = c.take<unsigned char>(n);
   D.whdt = c.take<double>(3 * kWalls * n);
   D.occ = c.take<int>((size_t)S.grid.n_elem);
+  D.home = c.take<int>(n);
+  D.base = c.take<int>((size_t)S.grid.ncells);
   B.x2 = c.take<dvec4>(n);
   B.v2 = c.take<double>(3 * n);
   B.w2 = c.take<double>(3 * n);
@@ -368,6 +369,7 @@ size_t carve(const Sizes &S, char *base, Buffers &B) {
   B.whdt2 = c.take<double>(3 * kWalls * n);
   B.perm = c.take<int>(n);
   B.start = c.take<int>((size_t)S.grid.ncells);
+  D.start = B.start;
   B.cnt64 = c.take<long long>(n + 1);
   B.off64 = c.take<long long>(n + 1);
   B.bsum = c.take<long long>((size_t)S.scan_blocks + 1);
@@ -546,7 +548,7 @@ struct PermSrc {
 struct PermDst {
   dvec4 *x;
   double *v, *w, *Fc, *Tc, *ffp, *rad, *mass, *whdt;
-  int *oid, *cell;
+  int *oid, *cell, *home;
   unsigned char *wmask;
 };
 
@@ -569,6 +571,7 @@ __global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   d.mass[k] = s.mass[o];
   d.oid[k] = s.oid[o];
   d.cell[k] = s.cell[o];
+  d.home[k] = s.cell[o];
   d.wmask[k] = s.wmask[o];
   for (int j = 0; j < 3 * kWalls; ++j) d.whdt[(size_t)j * n + k] = s.whdt[(size_t)j * n + o];
 }
@@ -882,6 +885,21 @@ dem_status scratch_of_current_device(double **out) {
 }
 }  // namespace
 
+// Particles per cell of the grid just sorted (at most cap): with start and
+// home, the listing the following runs take as their cells' home ranges.
+__global__ void k_home_base(int ncells, const int *cnt, int cap, int *base) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncells) base[c] = min(cnt[c], cap);
+}
+
+// No home cells (before the first re-sort, after a restore): every grid
+// lists all of its particles in its slots.
+static hipError_t clear_epoch(const Dev &D, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(D.base, 0, sizeof(int) * (size_t)D.grid.ncells, st);
+  if (e == hipSuccess) e = hipMemsetAsync(D.home, 0xff, sizeof(int) * (size_t)D.n, st);
+  return e;
+}
+
 static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   Buffers &B = ctx->B;
   Dev &D = B.D;
@@ -894,8 +912,10 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
   PermSrc src{D.pr[p2], D.v, D.w, D.Fc, D.Tc, D.ffp, D.rad, D.mass, D.whdt, D.oid, D.cell[p3],
               D.wmask};
   PermDst dst{B.x2, B.v2, B.w2, B.Fc2, B.Tc2, B.ffp2, B.rad2, B.mass2, B.whdt2, B.oid2, B.cell2,
-              B.wmask2};
+              D.home, B.wmask2};
   k_permute<<<blocks(n, 256), 256, 0, st>>>(n, B.perm, src, dst);
+  HIP_TRY(hipGetLastError());
+  k_home_base<<<blocks(D.grid.ncells, 256), 256, 0, st>>>(D.grid.ncells, D.cnt[p3], D.cap, D.base);
   HIP_TRY(hipGetLastError());
   std::swap(D.pr[p2], B.x2);
   std::swap(D.v, B.v2);
@@ -915,7 +935,7 @@ static dem_status resort(dem_ctx *ctx, hipStream_t st) {
 }
 
 // Launch step s (or the creation-time evaluation when !advance).
-static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool cont, hipStream_t st) {
+static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool cont, int gmode, hipStream_t st) {
   const int *src = advance ? ctx->pending_src : nullptr;
   ctx->pending_src = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -931,7 +951,7 @@ static dem_status force_launch(dem_ctx *ctx, long long s, bool advance, bool con
     e1 = ctx->ev[ctx->ev_used + 1];
     ctx->ev_used += 2;
   }
-  HIP_TRY(launch_force_kick(ctx->B.D, s, src, advance, cont, ctx->fp32, ctx->S.lanes, st, e0, e1));
+  HIP_TRY(launch_force_kick(ctx->B.D, s, src, gmode, advance, cont, ctx->fp32, ctx->S.lanes, st, e0, e1));
   return DEM_OK;
 }
 
@@ -1074,7 +1094,9 @@ dem_status dem_write_state(dem_ctx *ctx, const void *src, size_t bytes, void *st
   }
   k_restore_words<<<1, 64, 0, st>>>(D.err, (int)((h.s + 1) % 3), h.lbuf, h.err);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_drift_bin(D, h.s, false, false, st));
+  // the checkpoint's particle order is not a re-sort's: no home cells
+  HIP_TRY(clear_epoch(D, st));
+  HIP_TRY(launch_drift_bin(D, h.s, false, false, true, st));
   ctx->since_sort = h.since_sort;
   ctx->n_couple = h.n_couple;
   ctx->pending_src = nullptr;
@@ -1263,14 +1285,15 @@ dem_status dem_create(const dem_params *dp, const cfd_params *cp, const double *
 
   // priming: bin the initial positions, optionally sort by cell, evaluate
   ctx->s = 0;
-  if (launch_drift_bin(D, 0, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
+  if (clear_epoch(D, st) != hipSuccess) return fail(DEM_E_HIP);
+  if (launch_drift_bin(D, 0, false, false, true, st) != hipSuccess) return fail(DEM_E_HIP);
   if (dp->resort_every > 0) {
     if (resort(ctx, st) != DEM_OK) return fail(DEM_E_HIP);
     ctx->pending_src = nullptr;  // nothing to carry at creation
     if (launch_clear_grid(ctx->B.D, 0, st) != hipSuccess) return fail(DEM_E_HIP);
-    if (launch_drift_bin(ctx->B.D, 0, false, false, st) != hipSuccess) return fail(DEM_E_HIP);
+    if (launch_drift_bin(ctx->B.D, 0, false, false, true, st) != hipSuccess) return fail(DEM_E_HIP);
   }
-  if (force_launch(ctx, 0, false, false, st) != DEM_OK) return fail(DEM_E_HIP);
+  if (force_launch(ctx, 0, false, false, kGridCurExact | kGridPrevExact, st) != DEM_OK) return fail(DEM_E_HIP);
   *out = ctx;
   return DEM_OK;
 }
@@ -1287,9 +1310,9 @@ dem_status dem_step(dem_ctx *ctx, int32_t n_steps, void *stream) {
   // the held fluid force may have changed since the last step: open the run
   // with a separate half kick + drift, then one kernel per step
   const long long s0 = ctx->s + 1;
-  HIP_TRY(launch_drift_bin(ctx->B.D, s0, true, ctx->pending_src != nullptr, st));
+  HIP_TRY(launch_drift_bin(ctx->B.D, s0, true, ctx->pending_src != nullptr, n_steps == 1, st));
   for (int i = 0; i < n_steps; ++i) {
-    dem_status r = force_launch(ctx, s0 + i, true, i + 1 < n_steps, st);
+    dem_status r = force_launch(ctx, s0 + i, true, i + 1 < n_steps, grid_mode(i + 1, n_steps), st);
     if (r != DEM_OK) return r;
   }
   ctx->s += n_steps;
@@ -1698,14 +1721,14 @@ dem_status batch_resorts(dem_batch *B, hipStream_t st) {
 
 // Enqueues n steps of every bed (no re-sorts).
 dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
-  HIP_TRY(launch_drift_bin_batch(B->tab, B->run, B->map_drift, B->nb_drift, st));
+  HIP_TRY(launch_drift_bin_batch(B->tab, B->run, B->map_drift, B->nb_drift, n, st));
   const int nb_roll = B->nb_force - B->nb_force_plain;
   for (int i = 1; i <= n; ++i) {
     if (B->nb_force_plain > 0)
-      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force_plain, i, i < n, B->fp32,
+      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force, B->nb_force_plain, i, n, B->fp32,
                                       B->maxn, B->lanes, false, st));
     if (nb_roll > 0)
-      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force + B->nb_force_plain, nb_roll, i, i < n,
+      HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force + B->nb_force_plain, nb_roll, i, n,
                                       B->fp32, B->maxn, B->lanes, true, st));
   }
   HIP_TRY(launch_batch_advance(B->run, B->n_slots, n, st));

@@ -34,20 +34,24 @@
 namespace cfddem {
 
 // Binning of x into the grid of a step (counts cnt, slots sl, cells cl) and
-// the displacement test against the last broad-search positions.
+// the displacement test against the last broad-search positions.  In a grid
+// that is not exact, a particle in its home cell (home_k) takes no slot.
 __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], const double xbk[3], gptr<int> cnt,
-                                    gptr<int> sl, gptr<int> cl, gptr<int> flag, bool force_flag, int &bits) {
+                                    gptr<int> sl, gptr<int> cl, gptr<int> flag, bool force_flag, bool exact,
+                                    int home_k, int &bits) {
   int elem, cell;
   bool inside;
   bin_point(D.grid, xp, elem, cell, inside);
   if (!inside) bits |= kErrDomain;
   if (xp[0] != xp[0] || xp[1] != xp[1] || xp[2] != xp[2]) bits |= kErrNan;
   cl[k] = cell;
-  const int s = __hip_atomic_fetch_add(&cnt[cell], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (s >= 0 && s < D.cap)
-    sl[(size_t)cell * D.cap + s] = k;
-  else
-    bits |= kErrCapacity;
+  if (exact || cell != home_k) {
+    const int s = __hip_atomic_fetch_add(&cnt[cell], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s >= 0 && s < D.cap)
+      sl[(size_t)cell * D.cap + s] = k;
+    else
+      bits |= kErrCapacity;
+  }
   // a list built at xb stays complete while every particle is within skin/2
   const double d0 = xp[0] - xbk[0], d1 = xp[1] - xbk[1], d2 = xp[2] - xbk[2];
   if (force_flag ? k == 0 : !(d0 * d0 + d1 * d1 + d2 * d2 <= D.trig2)) __hip_atomic_fetch_or(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -56,11 +60,12 @@ __device__ inline void bin_and_test(const Dev &D, int k, const double xp[3], con
 // ---------------------------------------------------------------------------
 // drift + binning (first step of a run; also the creation-time binning)
 // ---------------------------------------------------------------------------
-// p2 = s & 1, p3 = s % 3 of the step being opened.  DRIFT = false bins the
-// positions already in pr[p2] (creation, restore) and writes the step's
-// velocity records from the boundary velocities.
+// p2 = s & 1, p3 = s % 3 of the step being opened; exact: the kind of its
+// grid.  DRIFT = false bins the positions already in pr[p2] (creation,
+// restore) and writes the step's velocity records from the boundary
+// velocities.
 template <bool DRIFT>
-__device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int p3, int force_flag) {
+__device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int p3, int force_flag, bool exact) {
   if (k >= D.n) return;
   const int n = D.n;
   double xp[3];
@@ -93,17 +98,19 @@ __device__ __forceinline__ void drift_bin_body(const Dev &D, int k, int p2, int 
   }
   int bits = 0;
   const double xbk[3] = {glb(D.xb)[k], glb(D.xb)[n + k], glb(D.xb)[2 * n + k]};
+  const int home_k = exact ? -1 : glb(D.home)[k];
   bin_and_test(D, k, xp, xbk, gsel(D.cnt, p3), gsel(D.slot, p2), gsel(D.cell, p3), glb(D.flag) + p3, force_flag != 0,
-               bits);
+               exact, home_k, bits);
   if (bits) __hip_atomic_fetch_or(glb(D.err), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool DRIFT>
-__global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int force_flag) {
-  drift_bin_body<DRIFT>(D, blockIdx.x * 256 + threadIdx.x, p2, p3, force_flag);
+__global__ __launch_bounds__(256) void drift_bin(Dev D, int p2, int p3, int force_flag, int exact) {
+  drift_bin_body<DRIFT>(D, blockIdx.x * 256 + threadIdx.x, p2, p3, force_flag, exact != 0);
 }
 
-// Clear the counts of grid p3 at the cells its particles were binned into.
+// Clear the counts of grid p3 at the cells its particles were binned into
+// (every cell a grid of either kind can count).
 __global__ void clear_grid(Dev D, int p3) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.n) return;
@@ -200,6 +207,7 @@ __device__ inline void lever_sum(double ra, double wa0, double wa1, double wa2, 
 // ADVANCE = false: creation-time evaluation (no history advance, no kick).
 // src: after a re-sort, the index each particle had when its list was built
 //      (NULL otherwise).
+// gmode: kGrid* bits, the kinds of the grids of steps s, s+1 and s-1.
 template <int L>
 __device__ inline double group_sum(double v) {
   for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off, 64);
@@ -231,9 +239,15 @@ __device__ inline void wave_publish() {
 // candidates into the group's LDS list, sorted by partner original ID, one
 // lane after the other.  Returns the list length, the same on every lane of
 // the group.
+// When the grid is not exact, a cell's candidates are first its home range
+// (particles sorted into it at the last re-sort, whether or not they are
+// still there: the exact test decides) and then its slots (particles away
+// from their home cell).  A particle within the cut-off lies in the stencil,
+// so every such pair is found; one listed both in its home range and in a
+// slot is inserted once.
 template <int L>
-__device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3, double xa0, double xa1,
-                                   double xa2, double ra, unsigned long long *my_list, int &bits) {
+__device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3, bool exact, double xa0,
+                                   double xa1, double xa2, double ra, unsigned long long *my_list, int &bits) {
   constexpr int kGroups = kForceBlock / L;
   const Grid &G = D.grid;
   const int ca = gsel(D.cell, p3)[a];
@@ -255,6 +269,7 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
   }
   const gptr<const int> cnt = gsel(D.cnt, p3);
   const gptr<const int> slot = gsel(D.slot, p2);
+  const gptr<const int> hbase = glb(D.base), hstart = glb(D.start);
   const gptr<const dvec4> P = gsel(D.pr, p2);
   const double rsk = ra + D.skin;
   constexpr int kCand = 4;
@@ -262,8 +277,10 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
   int m = 0;
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz) {
-    // the plane's candidates are numbered 0 .. tot-1 across its nine cells
-    int cc[9], pf[10];
+    // the plane's candidates are numbered 0 .. tot-1 across its nine cells;
+    // those of cell j are pf[j] .. hl[j]-1 (home range: particle q + ho[j])
+    // and hl[j] .. pf[j+1]-1 (slot q - hl[j] of cell cc[j])
+    int cc[9], pf[10], hl[9], ho[9];
     pf[0] = 0;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -271,7 +288,12 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
       const bool in = z >= 0 && y >= 0 && x >= 0;
       cc[j] = in ? z + y + x : 0;
       const int cj = cnt[cc[j]];
-      pf[j + 1] = pf[j] + (in ? min(cj, D.cap) : 0);
+      const bool imp = in && !exact;
+      const int bj = imp ? hbase[cc[j]] : 0;
+      const int sj = imp ? hstart[cc[j]] : 0;
+      hl[j] = pf[j] + bj;
+      ho[j] = sj - pf[j];
+      pf[j + 1] = hl[j] + (in ? min(cj, D.cap) : 0);
     }
     const int tot = pf[9];
 #pragma unroll 1
@@ -286,15 +308,17 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
         const int q = q0 + lane + L * i;
         ok[i] = q < tot;
         // the last cell whose first candidate is at or before q holds q
-        int c = cc[0], first = 0;
+        int c = cc[0], lim = hl[0], off = ho[0];
 #pragma unroll
         for (int j = 1; j < 9; ++j)
           if (q >= pf[j]) {
             c = cc[j];
-            first = pf[j];
+            lim = hl[j];
+            off = ho[j];
           }
-        const size_t at = ok[i] ? (size_t)c * D.cap + (q - first) : 0;
-        bq[i] = slot[at];
+        const bool home = q < lim;
+        const size_t at = (ok[i] && !home) ? (size_t)c * D.cap + (q - lim) : 0;
+        bq[i] = home ? q + off : slot[at];
         ok[i] = ok[i] && bq[i] != a;
       }
       unsigned oq[kCand];
@@ -316,12 +340,11 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
           for (int i = 0; i < kCand; ++i) {
             if (!ok[i]) continue;
             const unsigned long long key = ((unsigned long long)oq[i] << 32) | (unsigned)bq[i];
+            int p = m;
+            while (p > 0 && my_list[(p - 1) * kGroups] > key) --p;
+            if (p > 0 && my_list[(p - 1) * kGroups] == key) continue;  // listed twice
             if (m < D.maxn) {
-              int p = m;
-              while (p > 0 && my_list[(p - 1) * kGroups] > key) {
-                my_list[p * kGroups] = my_list[(p - 1) * kGroups];
-                --p;
-              }
+              for (int t = m; t > p; --t) my_list[t * kGroups] = my_list[(t - 1) * kGroups];
               my_list[p * kGroups] = key;
               ++m;
             } else {
@@ -364,7 +387,7 @@ __device__ __forceinline__ Entry load_entry(gptr<const dvec4> P, gptr<const dvec
 // ROLL: some rolling friction coefficient is nonzero (a separate
 // instantiation, so that the kernels without it keep their registers).
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-__device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src) {
+__device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, int p3, const int *src, int gmode) {
   const int gid = blk * kForceBlock + threadIdx.x;
   const int a = gid / L;
   const int lane = gid % L;
@@ -382,11 +405,12 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
 
   const dvec4 pa = P[a];
   const double xa0 = pa.x, xa1 = pa.y, xa2 = pa.z, ra = pa.w;
-  // walls touched at the last step, and the cell of x_{s-1} whose count this
-  // particle clears at the end: loaded first, so that waiting for them later
-  // waits for nothing else
+  // walls touched at the last step, the cell of x_{s-1} whose count this
+  // particle clears at the end and its home cell: loaded first, so that
+  // waiting for them later waits for nothing else
   const unsigned wmask_a = glb(D.wmask)[a];
   const int c_old = gsel(D.cell, r3)[a];
+  const int home_a = glb(D.home)[a];
   const size_t mn = (size_t)D.maxn * n;
   constexpr int kCand8 = 8;     // old list entries per lane and round trip
   int bits = 0;
@@ -403,7 +427,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       reinterpret_cast<unsigned char *>(sh_list + (size_t)D.maxn * kGroups) + threadIdx.x / L;
 
   if (rebuild) {
-    const int m = broad_search<L>(D, a, lane, p2, p3, xa0, xa1, xa2, ra, my_list, bits);
+    const int m = broad_search<L>(D, a, lane, p2, p3, (gmode & kGridCurExact) != 0, xa0, xa1, xa2, ra, my_list,
+                                  bits);
     m_new = m;
     if (lane == 0) {
       gsel(D.ln, cur)[a] = m;
@@ -593,8 +618,9 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     }
   }
   if (F[0] != F[0] || F[1] != F[1] || F[2] != F[2]) bits |= kErrNan;
-  // the grid of step s-1 is free: clear it for step s+2
-  gsel(D.cnt, r3)[c_old] = 0;
+  // the grid of step s-1 is free: clear it for step s+2 (where it was not
+  // exact, only particles away from their home cell were counted)
+  if ((gmode & kGridPrevExact) || c_old != home_a) gsel(D.cnt, r3)[c_old] = 0;
 
   if (ADVANCE) {
     const double fa[3] = {glb(D.ffp)[a], glb(D.ffp)[n + a], glb(D.ffp)[2 * n + a]};
@@ -626,7 +652,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       gsel(D.pr, p2 ^ 1)[a] = dvec4{xp[0], xp[1], xp[2], ra};
       gsel(D.vm, p2 ^ 1)[a] = dvec4{vh[0], vh[1], vh[2], ma};
       gsel(D.ws, p2 ^ 1)[a] = dvec4{wh[0], wh[1], wh[2], 0.0};
-      bin_and_test(D, a, xp, xba, gsel(D.cnt, q3), gsel(D.slot, p2 ^ 1), gsel(D.cell, q3), glb(D.flag) + q3, false, bits);
+      bin_and_test(D, a, xp, xba, gsel(D.cnt, q3), gsel(D.slot, p2 ^ 1), gsel(D.cell, q3), glb(D.flag) + q3, false,
+                   (gmode & kGridNextExact) != 0, home_a, bits);
     }
   }
   if (a == 0) {
@@ -638,8 +665,8 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src) {
-  force_kick_body<R, ADVANCE, CONT, L, ROLL>(D, blockIdx.x, p2, p3, src);
+__global__ __launch_bounds__(kForceBlock, 4) void force_kick(Dev D, int p2, int p3, const int *src, int gmode) {
+  force_kick_body<R, ADVANCE, CONT, L, ROLL>(D, blockIdx.x, p2, p3, src, gmode);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,30 +684,31 @@ __device__ inline void bed_of_block(const unsigned *__restrict__ map, int &bed, 
   blk = (int)(m & kBlockMask);
 }
 
-// Opens step run.s + 1 of every bed.
+// Opens step run.s + 1 of every bed (a run of n steps).
 __global__ __launch_bounds__(256) void drift_bin_batch(const Dev *__restrict__ tab,
                                                        const BedRun *__restrict__ run,
-                                                       const unsigned *__restrict__ map) {
+                                                       const unsigned *__restrict__ map, int n) {
   int b, blk;
   bed_of_block(map, b, blk);
   const Dev &D = tab[b];
   const long long s = run[b].s + 1;
   drift_bin_body<true>(D, blk * 256 + threadIdx.x, (int)(s & 1), (int)(s % 3),
-                       run[b].src != nullptr);
+                       run[b].src != nullptr, n == 1);
 }
 
-// Step run.s + i of every bed (i = 1 applies the bed's pending permutation).
+// Step run.s + i of every bed, of a run of n steps (i = 1 applies the bed's
+// pending permutation).
 template <typename R, bool CONT, int L, bool ROLL>
 __global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__restrict__ tab,
                                                                    const BedRun *__restrict__ run,
                                                                    const unsigned *__restrict__ map,
-                                                                   int i) {
+                                                                   int i, int n) {
   int b, blk;
   bed_of_block(map, b, blk);
   const Dev &D = tab[b];
   const long long s = run[b].s + i;
   force_kick_body<R, true, CONT, L, ROLL>(D, blk, (int)(s & 1), (int)(s % 3),
-                                          i == 1 ? run[b].src : nullptr);
+                                          i == 1 ? run[b].src : nullptr, grid_mode(i, n));
 }
 
 // After a run of n steps: every bed's step index advances, pending
@@ -704,50 +732,51 @@ __global__ void batch_set_bed(Dev *tab, BedRun *run, int b, Dev D, long long s, 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
+// n: steps of the run this launch opens
+hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int n,
                                   hipStream_t st) {
-  if (blocks > 0) drift_bin_batch<<<blocks, 256, 0, st>>>(tab, run, map);
+  if (blocks > 0) drift_bin_batch<<<blocks, 256, 0, st>>>(tab, run, map, n);
   return hipGetLastError();
 }
 
 template <int L, bool ROLL>
-static void launch_fkb(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
-                       bool cont, bool fp32, int maxn, hipStream_t st) {
+static void launch_fkb(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i, int n,
+                       bool fp32, int maxn, hipStream_t st) {
   const size_t lds = force_lds_bytes(maxn, L);
+  const bool cont = i < n;
   if (fp32) {
     if (cont)
-      force_kick_batch<float, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<float, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i, n);
     else
-      force_kick_batch<float, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<float, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i, n);
   } else {
     if (cont)
-      force_kick_batch<double, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<double, true, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i, n);
     else
-      force_kick_batch<double, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i);
+      force_kick_batch<double, false, L, ROLL><<<blocks, kForceBlock, lds, st>>>(tab, run, map, i, n);
   }
 }
 
 template <bool ROLL>
-static void launch_fkb_lanes(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i,
-                             bool cont, bool fp32, int maxn, int lanes, hipStream_t st) {
+static void launch_fkb_lanes(const Dev *tab, const BedRun *run, const unsigned *map, int blocks, int i, int n,
+                             bool fp32, int maxn, int lanes, hipStream_t st) {
   if (lanes == 1)
-    launch_fkb<1, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<1, ROLL>(tab, run, map, blocks, i, n, fp32, maxn, st);
   else if (lanes == 4)
-    launch_fkb<4, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<4, ROLL>(tab, run, map, blocks, i, n, fp32, maxn, st);
   else
-    launch_fkb<2, ROLL>(tab, run, map, blocks, i, cont, fp32, maxn, st);
+    launch_fkb<2, ROLL>(tab, run, map, blocks, i, n, fp32, maxn, st);
 }
 
-// lanes: 1, 2 or 4 (the same for every bed of the batch); roll: some bed has
-// a nonzero rolling friction coefficient
+// Step i (1 .. n) of a run of n steps.  lanes: 1, 2 or 4 (the same for every
+// bed of the batch); roll: some bed has a nonzero rolling friction coefficient
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
-                                   int i, bool cont, bool fp32, int maxn, int lanes, bool roll,
-                                   hipStream_t st) {
+                                   int i, int n, bool fp32, int maxn, int lanes, bool roll, hipStream_t st) {
   if (blocks <= 0) return hipGetLastError();
   if (roll)
-    launch_fkb_lanes<true>(tab, run, map, blocks, i, cont, fp32, maxn, lanes, st);
+    launch_fkb_lanes<true>(tab, run, map, blocks, i, n, fp32, maxn, lanes, st);
   else
-    launch_fkb_lanes<false>(tab, run, map, blocks, i, cont, fp32, maxn, lanes, st);
+    launch_fkb_lanes<false>(tab, run, map, blocks, i, n, fp32, maxn, lanes, st);
   return hipGetLastError();
 }
 
@@ -774,13 +803,14 @@ hipError_t launch_batch_set_cpl(Cpl *ctab, CplIO *iot, int b, const Cpl &C, cons
   return hipGetLastError();
 }
 
-hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, hipStream_t st) {
+// exact: the kind of the grid of step s
+hipError_t launch_drift_bin(const Dev &D, long long s, bool drift, bool force_flag, bool exact, hipStream_t st) {
   const int grid = (D.n + 255) / 256;
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   if (drift)
-    drift_bin<true><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0);
+    drift_bin<true><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0, exact ? 1 : 0);
   else
-    drift_bin<false><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0);
+    drift_bin<false><<<grid, 256, 0, st>>>(D, p2, p3, force_flag ? 1 : 0, exact ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -790,58 +820,58 @@ hipError_t launch_clear_grid(const Dev &D, long long s, hipStream_t st) {
 }
 
 template <typename R, bool ADVANCE, bool CONT, int L, bool ROLL>
-static void launch_fk(const Dev &D, int p2, int p3, const int *src, hipStream_t st, hipEvent_t e0,
+static void launch_fk(const Dev &D, int p2, int p3, const int *src, int gmode, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
   const int grid = (int)(((long long)D.n * L + kForceBlock - 1) / kForceBlock);
   const size_t lds = force_lds_bytes(D.maxn, L);
   if (e0)
     hipExtLaunchKernelGGL(force_kick<R, ADVANCE, CONT, L, ROLL>, dim3(grid), dim3(kForceBlock), lds, st,
-                          e0, e1, 0, D, p2, p3, src);
+                          e0, e1, 0, D, p2, p3, src, gmode);
   else
-    force_kick<R, ADVANCE, CONT, L, ROLL><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src);
+    force_kick<R, ADVANCE, CONT, L, ROLL><<<grid, kForceBlock, lds, st>>>(D, p2, p3, src, gmode);
 }
 
 template <int L, bool ROLL>
-static void launch_fk_lanes(const Dev &D, int p2, int p3, const int *src, bool advance, bool cont,
+static void launch_fk_lanes(const Dev &D, int p2, int p3, const int *src, int gmode, bool advance, bool cont,
                             bool fp32, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (!advance) {
     if (fp32)
-      launch_fk<float, false, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, false, false, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
     else
-      launch_fk<double, false, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, false, false, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
   } else if (fp32) {
     if (cont)
-      launch_fk<float, true, true, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, true, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
     else
-      launch_fk<float, true, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<float, true, false, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
   } else {
     if (cont)
-      launch_fk<double, true, true, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, true, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
     else
-      launch_fk<double, true, false, L, ROLL>(D, p2, p3, src, st, e0, e1);
+      launch_fk<double, true, false, L, ROLL>(D, p2, p3, src, gmode, st, e0, e1);
   }
 }
 
 template <bool ROLL>
-static void launch_fk_roll(const Dev &D, int p2, int p3, const int *src, bool advance, bool cont,
+static void launch_fk_roll(const Dev &D, int p2, int p3, const int *src, int gmode, bool advance, bool cont,
                            bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (lanes == 1)
-    launch_fk_lanes<1, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+    launch_fk_lanes<1, ROLL>(D, p2, p3, src, gmode, advance, cont, fp32, st, e0, e1);
   else if (lanes == 4)
-    launch_fk_lanes<4, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+    launch_fk_lanes<4, ROLL>(D, p2, p3, src, gmode, advance, cont, fp32, st, e0, e1);
   else
-    launch_fk_lanes<2, ROLL>(D, p2, p3, src, advance, cont, fp32, st, e0, e1);
+    launch_fk_lanes<2, ROLL>(D, p2, p3, src, gmode, advance, cont, fp32, st, e0, e1);
 }
 
 // e0/e1: when non-NULL, events recorded at the kernel's own start and end.
-// lanes: 1, 2 or 4.
-hipError_t launch_force_kick(const Dev &D, long long s, const int *src, bool advance, bool cont,
+// lanes: 1, 2 or 4.  gmode: kGrid* bits.
+hipError_t launch_force_kick(const Dev &D, long long s, const int *src, int gmode, bool advance, bool cont,
                              bool fp32, int lanes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int p2 = (int)(s & 1), p3 = (int)(s % 3);
   if (D.pp.mu_r > 0.0 || D.pw.mu_r > 0.0)
-    launch_fk_roll<true>(D, p2, p3, src, advance, cont, fp32, lanes, st, e0, e1);
+    launch_fk_roll<true>(D, p2, p3, src, gmode, advance, cont, fp32, lanes, st, e0, e1);
   else
-    launch_fk_roll<false>(D, p2, p3, src, advance, cont, fp32, lanes, st, e0, e1);
+    launch_fk_roll<false>(D, p2, p3, src, gmode, advance, cont, fp32, lanes, st, e0, e1);
   return hipGetLastError();
 }
 

@@ -83,9 +83,30 @@ struct Dev {
   double *hdt[2];                // 3 x maxn x n tangential overlap of each entry
   unsigned char *wmask;          // bit w: wall w touched at the last evaluation
   double *whdt;                  // 3 x 6 x n tangential overlap against each wall
+  // Re-sort epoch: the particles of cell c were given the sorted indices
+  // start[c] .. start[c] + base[c] - 1 at the last re-sort.  Inside a run of
+  // steps a cell grid may list them implicitly: such a grid counts (and slots)
+  // only the particles away from their home cell, and the broad search takes
+  // the home range of each cell besides its slots.
+  int *home;             // n: cell at the last re-sort (-1: no re-sort yet)
+  int *base;             // ncells: particles sorted into each cell (at most cap)
+  int *start;            // ncells: sorted index of each cell's first particle
   int *occ;              // mesh elements holding particles (coupling step)
   int *err;              // sticky error bits
 };
+
+// Kind of the cell grids around one step (bits of a launch argument): a
+// grid lists every particle in its slots (exact) or only the particles away
+// from their home cell.  The last step of a run bins exactly, so that
+// everything read between runs (coupling, smoothing, re-sort) sees exact grids.
+enum : int {
+  kGridCurExact = 1,   // the grid of step s
+  kGridNextExact = 2,  // the grid of step s + 1 (binned by this launch)
+  kGridPrevExact = 4,  // the grid of step s - 1 (cleared by this launch)
+};
+__host__ __device__ inline int grid_mode(int i, int n) {
+  return (i == n ? kGridCurExact : 0) | (i + 1 == n ? kGridNextExact : 0) | (i == 1 ? kGridPrevExact : 0);
+}
 
 // Batched launches: many independent beds in one launch.  Each block of a
 // batched kernel looks up (bed << kBedShift) | block-of-the-bed in a block
