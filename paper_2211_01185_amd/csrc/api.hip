@@ -573,7 +573,8 @@ __global__ void k_permute(int n, const int *perm, PermSrc s, PermDst d) {
   d.cell[k] = s.cell[o];
   d.home[k] = s.cell[o];
   d.wmask[k] = s.wmask[o];
-  for (int j = 0; j < 3 * kWalls; ++j) d.whdt[(size_t)j * n + k] = s.whdt[(size_t)j * n + o];
+  for (int wall = 0; wall < kWalls; ++wall)
+    for (int c = 0; c < 3; ++c) d.whdt[hist_at(wall, n, k) + c] = s.whdt[hist_at(wall, n, o) + c];
 }
 
 // Kinetic energy of the boundary state: translational sum 1/2 m v^2 and
@@ -762,7 +763,6 @@ __global__ void k_contact_write(Dev D, int lb, const long long *off, long long c
   const int n = D.n;
   const int o = D.oid[k];
   long long w = off[o];
-  const size_t mn = (size_t)D.maxn * n;
   // walls in descending face index (ascending -1-w), then partners by oid
   const unsigned wm = D.wmask[k];
   for (int wall = kWalls - 1; wall >= 0; --wall) {
@@ -770,7 +770,7 @@ __global__ void k_contact_write(Dev D, int lb, const long long *off, long long c
     if (w < cap) {
       pairs[w] = o;
       pairs[cap + w] = -1 - wall;
-      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.whdt[(size_t)(c * kWalls + wall) * n + k];
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.whdt[hist_at(wall, n, k) + c];
     }
     ++w;
   }
@@ -781,7 +781,7 @@ __global__ void k_contact_write(Dev D, int lb, const long long *off, long long c
     if (w < cap) {
       pairs[w] = o;
       pairs[cap + w] = ob;
-      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.hdt[lb][(size_t)c * mn + (size_t)t * n + k];
+      for (int c = 0; c < 3; ++c) dt_out[(size_t)c * cap + w] = D.hdt[lb][hist_at(t, n, k) + c];
     }
     ++w;
   }
@@ -804,7 +804,7 @@ __global__ void k_restore_words(int *err, int lb_word, int cur, int bits) {
 // Checkpoint blob: a 256-byte header, then the state arrays in the context's
 // internal (cell-sorted) order, each at a 256-byte aligned offset.
 constexpr uint64_t kCkptMagic = 0x4b43424d45444643ULL;  // "CFDEMBCK"
-constexpr int kCkptVersion = 2;
+constexpr int kCkptVersion = 3;
 struct CkptHeader {
   uint64_t magic;
   int32_t abi, version;

@@ -371,16 +371,16 @@ struct Entry {
 // b comes from a list entry; an index outside [0, n) (only a slot past the
 // list's length can hold one) reads the particle itself.
 __device__ __forceinline__ Entry load_entry(gptr<const dvec4> P, gptr<const dvec4> VM, gptr<const dvec4> WS,
-                                            gptr<const double> hdt, size_t mn, int n, int a, int b, int t) {
+                                            gptr<const double> hdt, int n, int a, int b, int t) {
   b = (unsigned)b < (unsigned)n ? b : a;
   Entry e;
   e.p = P[b];
   e.v = VM[b];
   e.w = WS[b];
-  const size_t i = (size_t)t * n + a;
+  const size_t i = hist_at(t, n, a);
   e.h[0] = hdt[i];
-  e.h[1] = hdt[mn + i];
-  e.h[2] = hdt[2 * mn + i];
+  e.h[1] = hdt[i + 1];
+  e.h[2] = hdt[i + 2];
   return e;
 }
 
@@ -411,7 +411,6 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
   const unsigned wmask_a = glb(D.wmask)[a];
   const int c_old = gsel(D.cell, r3)[a];
   const int home_a = glb(D.home)[a];
-  const size_t mn = (size_t)D.maxn * n;
   constexpr int kCand8 = 8;     // old list entries per lane and round trip
   int bits = 0;
   int m_new = 0;                // list length after a broad search
@@ -483,8 +482,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       const int from = my_from[t * kGroups];
       if (from) {
         for (int c = 0; c < 3; ++c)
-          gsel(D.hdt, cur)[(size_t)c * mn + (size_t)t * n + a] =
-              gsel(D.hdt, lold)[(size_t)c * mn + (size_t)(from - 1) * n + s];
+          gsel(D.hdt, cur)[hist_at(t, n, a) + c] = gsel(D.hdt, lold)[hist_at(from - 1, n, s) + c];
         carried |= 1ull << t;
       }
     }
@@ -524,7 +522,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     // one round trip per entry: the partner's records, this entry's stored
     // tangential overlap and the next entry's key (its slot clamped to the
     // list capacity; past the list's length its value is not used)
-    const Entry cur_e = load_entry(P, VM, WS, hdt, mn, n, a, (int)(unsigned)(key & 0xffffffffu), t);
+    const Entry cur_e = load_entry(P, VM, WS, hdt, n, a, (int)(unsigned)(key & 0xffffffffu), t);
     key = lst[(size_t)min(t + L, last) * n + a];
     const dvec4 pb = cur_e.p, vb = cur_e.v, wb = cur_e.w;
     const double rb = pb.w;
@@ -555,7 +553,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       F[c] += f[c];
       T[c] += ra * nxft[c];  // R_a n x f_t (n x f_t is the same from both sides)
       if (ROLL) Tr[c] += mr[c];  // the partner's is the exact negation
-      hdt[(size_t)c * mn + (size_t)t * n + a] = dtn[c];
+      hdt[hist_at(t, n, a) + c] = dtn[c];
     }
     mask_new |= 1ull << t;
   }
@@ -581,14 +579,14 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
       vij[1] = va1 + (rw2 * nrm[0] - rw0 * nrm[2]);
       vij[2] = va2 + (rw0 * nrm[1] - rw1 * nrm[0]);
       if ((wold >> wall) & 1u)
-        for (int c = 0; c < 3; ++c) dto[c] = glb(D.whdt)[(size_t)(c * kWalls + wall) * n + a];
+        for (int c = 0; c < 3; ++c) dto[c] = glb(D.whdt)[hist_at(wall, n, a) + c];
       const double wr[3] = {wa0, wa1, wa2};
       contact_law<R, ADVANCE, ROLL>(D.pw, nrm, dn, vij, ra, ma, D.dt, dto, wr, f, nxft, dtn, mr);
       for (int c = 0; c < 3; ++c) {
         F[c] += f[c];
         T[c] += ra * nxft[c];
         if (ROLL) Tr[c] += mr[c];
-        glb(D.whdt)[(size_t)(c * kWalls + wall) * n + a] = dtn[c];
+        glb(D.whdt)[hist_at(wall, n, a) + c] = dtn[c];
       }
       wnew |= 1u << wall;
     }

@@ -80,9 +80,9 @@ struct Dev {
   int *ln[2];                    // entries per particle
   unsigned long long *nbr[2];    // maxn x n: (partner oid << 32) | partner index
   unsigned long long *hmask[2];  // bit t: entry t touched at the last evaluation
-  double *hdt[2];                // 3 x maxn x n tangential overlap of each entry
+  double *hdt[2];                // maxn x n tangential overlaps of the entries (hist_at)
   unsigned char *wmask;          // bit w: wall w touched at the last evaluation
-  double *whdt;                  // 3 x 6 x n tangential overlap against each wall
+  double *whdt;                  // 6 x n tangential overlaps against the walls (hist_at)
   // Re-sort epoch: the particles of cell c were given the sorted indices
   // start[c] .. start[c] + base[c] - 1 at the last re-sort.  Inside a run of
   // steps a cell grid may list them implicitly: such a grid counts (and slots)
@@ -94,6 +94,11 @@ struct Dev {
   int *occ;              // mesh elements holding particles (coupling step)
   int *err;              // sticky error bits
 };
+
+// First of the three components of the tangential overlap of entry (or wall)
+// t of particle a: the components of one contact are adjacent, so that a
+// contact's history is one line, read and written together.
+__host__ __device__ inline size_t hist_at(int t, int n, int a) { return ((size_t)t * n + a) * 3; }
 
 // Kind of the cell grids around one step (bits of a launch argument): a
 // grid lists every particle in its slots (exact) or only the particles away
