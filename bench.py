@@ -74,6 +74,7 @@ METRIC = "DEM+coupling particle-steps/s @100k spheres; batched jobs/s + p99 late
 HBM_PEAK_GBS = 8000.0
 COUPLING_EVERY = 10
 RESORT_EVERY = 100
+FORCE_BLOCK = 128  # threads per block of the contact-force kernels
 # algorithmic bytes of one DEM step (one launch of the contact-force kernel):
 # per particle it must read x, v_half, w_half (72 B), radius and mass (16 B) and
 # the held fluid force (24 B), and write the next step's x, v_half, w_half
@@ -95,7 +96,8 @@ CPL_BYTES_PER_QPT = 40
 WINDOW_WARMUP = 20
 WINDOW_STEPS = 1000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kick_fluidized_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_01185_amd", "csrc", "dem_kernels.hip")
+# the contact-force kernel's source: its file and the device layout it includes
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2211_01185_amd", "csrc", f) for f in ("dem_kernels.hip", "device.h")]
 
 
 def parse():
@@ -129,8 +131,11 @@ def progress(msg):
 
 
 def kernel_source_sha():
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def traffic_entry(lanes, precision="fp32"):
@@ -602,6 +607,12 @@ def batched_ensemble(n_beds, steps, dev):
         "ms_per_step": dt * 1e3 / (chunks * COUPLING_EVERY),
         "dtype": "f32 forces / f64 state", "launch": "shared launches per step, one HIP graph per chunk",
         "contacts_end": int(contacts), "errors": int(errors), "autotune": tune_report,
+        # what a kernel trace of this leg needs to find the ensemble's launches
+        # and to price them: their grid sizes (threads) and the algorithmic
+        # bytes of one DEM step of the ensemble
+        "grid_threads": {"force_kick_batch": sum(-(-w.n * cfg["lanes"] // FORCE_BLOCK) for w in wls) * FORCE_BLOCK,
+                         "drift_bin_batch": sum(-(-w.n // 256) for w in wls) * 256},
+        "algorithmic_bytes_per_step": FORCE_BYTES_PER_PARTICLE * n_total + BYTES_PER_CONTACT * int(contacts),
         "per_bed_fp64_path": {"value": n_total * plain_steps / t_plain, "unit": "particle-steps/s",
                               "steps": plain_steps, "dtype": "f64",
                               "launch": "single-bed entry points, one bed after another"},

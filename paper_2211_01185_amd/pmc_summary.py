@@ -29,7 +29,8 @@ import os
 import re
 
 COPY_KIB = 256 * 1024  # calib.py: 256 MiB read and written per dispatch
-KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "dem_kernels.hip")
+KERNEL_SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+                  for f in ("dem_kernels.hip", "device.h")]
 
 
 def _rows(d):
@@ -89,8 +90,11 @@ def main(argv=None):
     f = _region(args.fetch, "FETCH_SIZE", cfg["lanes"], warmup, steps)
     w = _region(args.write, "WRITE_SIZE", cfg["lanes"], warmup, steps)
     fk, wk = sum(f) / len(f), sum(w) / len(w)
-    with open(KERNEL_SOURCE, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:  # the kernel's file and the device layout it includes
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
     entry = {
         "kernel": f"force_kick<float, true, *, {cfg['lanes']}>",
         "kernel_source_sha256": sha,

@@ -15,7 +15,11 @@ L, false>: no rolling friction) at the main bed's grid size followed by step
 launches of the single-bed kernel; the timed bed runs exactly warm-up + timed
 steps and the window's beds the window's steps (the autotuner's trials run two
 more coupling periods, the settling run thousands of steps, the smoothing run
-fewer).
+fewer).  With --bed batched: the kernels of the batched ensemble's run (from
+the first to the last contact-force launch at the ensemble's grid, which the
+benchmark reports; the tuner's trials run fewer beds, so smaller grids), per
+launch and per ensemble step, and the contact-force kernel's fraction of the
+HBM peak at the ensemble's algorithmic bytes per step.
 """
 from __future__ import annotations
 
@@ -44,12 +48,14 @@ def main(argv=None):
     ap.add_argument("--trace", required=True)
     ap.add_argument("--bench-json", required=True)
     ap.add_argument("--top", type=int, default=12)
-    ap.add_argument("--bed", choices=("main", "spouted"), default="main")
+    ap.add_argument("--bed", choices=("main", "spouted", "batched"), default="main")
     args = ap.parse_args(argv)
     with open(args.bench_json) as fh:
         bench = json.loads([ln for ln in fh if ln.startswith("{")][-1])
     if args.bed == "spouted":
         return spouted(args, bench)
+    if args.bed == "batched":
+        return batched(args, bench)
     lanes = int(bench["config"]["tuned"]["lanes"])
     n = int(bench["config"]["particles"])
     warmup, steps = int(bench["warmup"]), int(bench["steps"])
@@ -145,6 +151,47 @@ def spouted(args, bench):
     print()
     print(f"- bench.py in the same run (under the profiler): {sp['ms_per_step']:.4f} ms per step, "
           f"force kernel {sp['force_kernel']['avg_launch_us']:.2f} us per launch (HIP events, replay)")
+
+
+def batched(args, bench, hbm_peak_gbs=8000.0):
+    bt = bench["batched"]
+    gf = int(bt["grid_threads"]["force_kick_batch"])
+    n, cpe = int(bt["particles"]), 10
+    rows = _one(args.trace, "kernel_trace.csv")
+    key = "Kernel_Name" if "Kernel_Name" in rows[0] else "Name"
+    gkey = "Grid_Size" if "Grid_Size" in rows[0] else "Grid_Size_X"
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    force = [i for i, r in enumerate(rows) if int(r[gkey] or 0) == gf and "force_kick_batch" in r[key]]
+    if not force:
+        raise SystemExit(f"no force_kick_batch launch at grid {gf}")
+    region = rows[force[0]:force[-1] + 1]
+    steps = len(force)  # one contact-force launch per bed group and step (beds without rolling friction)
+    tot = {}
+    for r in region:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        tot.setdefault(r[key], []).append(d)
+    busy = sum(sum(v) for v in tot.values())
+    print(f"Batched ensemble ({bt['beds']} beds, {n} spheres, tuned {bt['autotune']['config']}): kernels from the "
+          f"first to the last contact-force launch at the ensemble's grid ({gf} threads), {steps} DEM steps "
+          f"(warm-up chunks included); {busy / steps:.1f} us of kernel time per ensemble step")
+    print()
+    print("| kernel | calls | mean us | median us | per step us | per particle-step ns |")
+    print("|---|---|---|---|---|---|")
+    for name, v in sorted(tot.items(), key=lambda kv: -sum(kv[1]))[:args.top]:
+        short = name if len(name) <= 72 else name[:69] + "..."
+        x = np.array(v)
+        print(f"| `{short}` | {len(x)} | {x.mean():.1f} | {np.median(x):.1f} | {x.sum() / steps:.1f} | "
+              f"{1e3 * x.sum() / steps / n:.4f} |")
+    fk = np.array([(int(rows[i]["End_Timestamp"]) - int(rows[i]["Start_Timestamp"])) / 1e3 for i in force])
+    alg = float(bt["algorithmic_bytes_per_step"])
+    gbs = alg / (fk.mean() * 1e-6) / 1e9
+    print()
+    print(f"- `force_kick_batch` at the ensemble's grid: {len(fk)} launches, mean {fk.mean():.1f} us, median "
+          f"{np.median(fk):.1f} us; {alg / 1e6:.1f} MB algorithmic per step (184 B per particle, 56 B per "
+          f"contact, {bt['contacts_end']} contacts) gives {gbs:.0f} GB/s, {100 * gbs / hbm_peak_gbs:.1f} % of "
+          f"the {hbm_peak_gbs:.0f} GB/s HBM peak")
+    print(f"- bench.py in the same run (under the profiler): {bt['ms_per_step']:.4f} ms per ensemble step, "
+          f"{bt['value']:.4g} particle-steps/s; coupling every {cpe} steps")
 
 
 if __name__ == "__main__":
