@@ -72,3 +72,74 @@ def test_runs_against_the_oracle():
     ob.step(sum(RUNS[:4]))
     compare_contacts(gb, ob, 1e-8)
     compare_states(gb, ob, 1e-8)
+
+
+def _snapshot(bed):
+    st = gpu_state(bed)
+    i, j, dt = bed.read_contacts()
+    st["ci"], st["cj"], st["cdt"] = i, j, dt
+    return st
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_chunk_lengths_give_the_bits_of_single_steps(graph):
+    """The same for batches: chunks of 1, 2, 3 ... steps (direct launches or
+    graph replay) against one-step chunks, three fast column beds re-sorted
+    every 30 steps."""
+    from paper_2211_01185_amd import cfddem
+
+    wls = []
+    for j, (n, d, e, u) in enumerate([(3000, 2.0e-3, 0.9, 1.0), (1700, 1.3e-3, 0.75, 0.0),
+                                      (5200, 2.6e-3, 0.85, 1.6)]):
+        w = synth.column_bed(synth.rng_for(4, 520 + j), n, d, e, u, name=f"r{j}", precision="fp32")
+        w.v = w.v * 100.0
+        wls.append(w)
+
+    def make():
+        beds = [gpu_bed(w, "fp32", resort_every=RESORT, skin=1e-4) for w in wls]
+        fields = [(torch.as_tensor(w.U, dtype=torch.float64, device="cuda").contiguous(),
+                   torch.as_tensor(w.P, dtype=torch.float64, device="cuda").contiguous()) for w in wls]
+        return beds, cfddem.Batch(beds, fields)
+
+    beds_a, a = make()
+    beds_b, b = make()
+    for n in RUNS:
+        if graph:
+            a.run(1, n, couple=False)
+        else:
+            a.step(n)
+    for _ in range(sum(RUNS)):
+        b.step(1)
+    for x, y in zip(beds_a, beds_b):
+        sa, sb = _snapshot(x), _snapshot(y)
+        assert len(sa["ci"]) > 0
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), k
+        assert x.poll()[0] == 0 and y.poll()[0] == 0
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("resort_every", [0, 50])
+def test_cell_capacity_overflow_is_reported_by_the_end_of_a_run(resort_every):
+    """Cell capacity 1, two spheres in neighbouring cells of a 3 x 3 x 3 cell
+    grid; the second crosses into the first one's cell at the second step
+    without touching it.  Whether the run's inner grids list it as an arrival
+    (with a re-sort at creation) or every grid lists every particle, the
+    sticky capacity error is set by the end of the run."""
+    from paper_2211_01185_amd import cfddem
+
+    d, lo, hi = 3e-3, [0.0, 0.0, 0.0], [0.012, 0.012, 0.012]
+    x = np.array([[1.6e-3, 4.05e-3], [1.6e-3, 3.9e-3], [1.6e-3, 3.9e-3]])
+    v = np.array([[0.0, -5.0], [0.0, 0.0], [0.0, 0.0]])
+    fluid = dict(order=1, n_el=[1, 1, 1], rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    U = np.zeros((3, synth.node_grid(lo, hi, fluid["n_el"], 1).shape[1]))
+    P = np.zeros(U.shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, 0.0], dt=1e-5, **synth._material())
+    wl = synth.Workload("two", x, v, np.zeros((3, 2)), np.full(2, 0.5 * d), np.full(2, 2500.0), dem, fluid,
+                        dict(steps=5, coupling_every=5, precision="fp64"), U, P)
+    gb = gpu_bed(wl, "fp64", cell_capacity=1, resort_every=resort_every, skin=1e-4)
+    assert gb.poll()[0] == 0
+    assert gb.read_cells()[2] == [3, 3, 3]
+    gb.step(5)
+    assert gb.poll()[0] == cfddem.DEM_E_CAPACITY
