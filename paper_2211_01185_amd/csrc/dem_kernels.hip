@@ -321,15 +321,23 @@ __device__ inline int broad_search(const Dev &D, int a, int lane, int p2, int p3
         bq[i] = home ? q + off : slot[at];
         ok[i] = ok[i] && bq[i] != a;
       }
+      // every candidate's loads are issued before any is tested: a test
+      // written next to its load lets the compiler sink each load into the
+      // test's branch, which then waits for it before the next one is issued
       unsigned oq[kCand];
+      dvec4 pbq[kCand];
 #pragma unroll
       for (int i = 0; i < kCand; ++i) {
         const int b = ok[i] ? bq[i] : a;
-        const dvec4 pb = P[b];
+        pbq[i] = P[b];
         oq[i] = (unsigned)glb(D.oid)[b];
-        const double d0 = pb.x - xa0, d1 = pb.y - xa1, d2 = pb.z - xa2;
-        const double cut = rsk + pb.w;
-        ok[i] = ok[i] && d0 * d0 + d1 * d1 + d2 * d2 < cut * cut;
+      }
+      __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < kCand; ++i) {
+        const double d0 = pbq[i].x - xa0, d1 = pbq[i].y - xa1, d2 = pbq[i].z - xa2;
+        const double cut = rsk + pbq[i].w;
+        ok[i] = ok[i] & (d0 * d0 + d1 * d1 + d2 * d2 < cut * cut);
       }
       // insertion by partner original ID, one lane of the group after the
       // other; the list length follows each lane's turn
