@@ -2,8 +2,10 @@
 // & Blais, arXiv 2211.01185), one kernel launch per step:
 //   drift_bin   : opens a run of steps: half kick + drift from the boundary
 //                 state, binning of the new centres into the nested cell grid
-//                 (atomic slot insertion), displacement test that requests a
-//                 new broad search
+//                 (atomic slot insertion; inside a run only for particles
+//                 away from the cell they were sorted into, the others being
+//                 listed by their sorted index range), displacement test that
+//                 requests a new broad search
 //   force_kick  : step s: broad search when requested (cell-list neighbour
 //                 list over the 27-cell stencil: every pair within
 //                 R_i + R_j + skin, the candidates shared out over the lanes
