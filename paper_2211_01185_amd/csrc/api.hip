@@ -34,7 +34,8 @@ hipError_t launch_drift_bin_batch(const Dev *tab, const BedRun *run, const unsig
                                   hipStream_t st);
 hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsigned *map, int blocks,
                                    int i, int n, bool fp32, int maxn, int lanes, bool roll, hipStream_t st);
-hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st);
+hipError_t launch_batch_advance(BedRun *run, int nb, int n, int *cnt, hipStream_t st);
+hipError_t launch_reset_count(int *cnt_words, hipStream_t st);
 hipError_t launch_batch_set_bed(Dev *tab, BedRun *run, int b, const Dev &D, long long s, const int *src,
                                 hipStream_t st);
 hipError_t launch_batch_set_cpl(Cpl *ctab, CplIO *iot, int b, const Cpl &C, const CplIO &io, hipStream_t st);
@@ -1560,6 +1561,9 @@ struct dem_batch {
   unsigned *map_drift = nullptr, *map_force = nullptr, *map_class = nullptr, *list = nullptr;
   long long cap_drift = 0, cap_force = 0, cap_class = 0;
   int *cnt = nullptr;
+  // the counters hold the counts of a coupling step not yet followed by a run
+  // of steps (whose last launch clears them)
+  bool cnt_dirty = false;
   // pinned host staging of the maps, reused once its last upload is done
   unsigned *stage = nullptr;
   hipEvent_t stage_ev = nullptr;
@@ -1731,7 +1735,7 @@ dem_status batch_enqueue_steps(dem_batch *B, int n, hipStream_t st) {
       HIP_TRY(launch_force_kick_batch(B->tab, B->run, B->map_force + B->nb_force_plain, nb_roll, i, n,
                                       B->fp32, B->maxn, B->lanes, true, st));
   }
-  HIP_TRY(launch_batch_advance(B->run, B->n_slots, n, st));
+  HIP_TRY(launch_batch_advance(B->run, B->n_slots, n, B->cnt, st));
   return DEM_OK;
 }
 
@@ -1930,6 +1934,7 @@ dem_status dem_batch_step(dem_batch *B, int32_t n_steps, void *stream) {
   if (r != DEM_OK) return r;
   r = batch_enqueue_steps(B, n_steps, st);
   if (r != DEM_OK) return r;
+  B->cnt_dirty = false;
   batch_mirror_steps(B, n_steps);
   return DEM_OK;
 }
@@ -1943,7 +1948,10 @@ dem_status dem_batch_couple(dem_batch *B, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   r = batch_layout(B, st);
   if (r != DEM_OK) return r;
-  return batch_enqueue_couple(B, st);
+  if (B->cnt_dirty) HIP_TRY(launch_reset_count(B->cnt, st));
+  r = batch_enqueue_couple(B, st);
+  B->cnt_dirty = r == DEM_OK;
+  return r;
 }
 
 dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk, int32_t couple,
@@ -1990,11 +1998,16 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
   // per chunk, the order of dem_batch_couple + dem_batch_step: couple, due
   // re-sorts, steps
   for (int c = 0; c < n_chunks; ++c) {
-    if (couple) HIP_TRY(hipGraphLaunch(B->g_cpl, st));
+    if (couple) {
+      if (B->cnt_dirty) HIP_TRY(launch_reset_count(B->cnt, st));
+      HIP_TRY(hipGraphLaunch(B->g_cpl, st));
+      B->cnt_dirty = true;
+    }
     if (steps_per_chunk > 0) {
       r = batch_resorts(B, st);
       if (r != DEM_OK) return r;
       HIP_TRY(hipGraphLaunch(B->g_step, st));
+      B->cnt_dirty = false;
       batch_mirror_steps(B, steps_per_chunk);
     }
   }

@@ -431,7 +431,7 @@ __device__ inline void particle_force(const Dev &D, const Cpl &C, int k, const i
       f += fS;
       g += fS;
     }
-    D.ffp[c * n + k] = f;
+    glb(D.ffp)[c * n + k] = f;
     sums[1 + c] += beta * up[c];
     sums[4 + c] += fD;
     sums[7 + c] = g;
@@ -453,7 +453,7 @@ __device__ inline void sort_small(int (&v)[N]) {
 }
 
 // Inserts the slot entries [from, m) of a cell into the sorted run ids[w, w+from).
-__device__ inline void insert_rest(int *ids, int w, const int *sl, int from, int m) {
+__device__ inline void insert_rest(int *ids, int w, gptr<const int> sl, int from, int m) {
   for (int s = from; s < m; ++s) {
     const int v = sl[s];
     int k = w + s;
@@ -544,6 +544,11 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   const int gbase = (int)threadIdx.x & (kWave - 1) & ~(GW - 1);  // first lane of the group
   const int ex = e % G.n_el[0], ey = (e / G.n_el[0]) % G.n_el[1], ez = e / (G.n_el[0] * G.n_el[1]);
   const int ee[3] = {ex, ey, ez};
+  // every array through a global-typed pointer: in the batched kernels the
+  // pointers come from device tables, and generic ones would give FLAT
+  // instructions
+  const gptr<const double> Ug = glb(U), Pg = glb(P);
+  const gptr<double> eps_g = glb(eps_q), beta_g = glb(beta_q), fpf_g = glb(fpf_q), esums_g = glb(esums);
   constexpr int p1 = ORD + 1;
   constexpr int nnode = p1 * p1 * p1;
   constexpr int nq = p1 * p1 * p1;  // Gauss points: order + 1 per axis
@@ -562,10 +567,10 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
       const long nv = (long)C.nvx * C.nvy * ((long)ORD * G.n_el[2] + 1);
       const int ia = t % p1, ib = (t / p1) % p1, ic = t / (p1 * p1);
       const long node = (((long)ORD * ez + ic) * C.nvy + (long)ORD * ey + ib) * C.nvx + (long)ORD * ex + ia;
-      un[k][0] = U[node];
-      un[k][1] = U[nv + node];
-      un[k][2] = U[2 * nv + node];
-      if (MODE == 2 && C.smooth) sh.sE[t] = C.eps_nodes[node];  // read after the barrier below
+      un[k][0] = Ug[node];
+      un[k][1] = Ug[nv + node];
+      un[k][2] = Ug[2 * nv + node];
+      if (MODE == 2 && C.smooth) sh.sE[t] = glb(C.eps_nodes)[node];  // read after the barrier below
     }
   }
   constexpr int kPL = NT >= kPressLane + 8 ? kPressLane : 0;
@@ -573,20 +578,20 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
   const int pc = tid - kPL;  // pressure corner of this thread
   if (pc >= 0 && pc < 8) {
     const int ia = pc & 1, ib = (pc >> 1) & 1, ic = pc >> 2;
-    pk = P[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
+    pk = Pg[((long)(ez + ic) * C.npy + (ey + ib)) * C.npx + (ex + ia)];
   }
 
   // ---- 1. particles of this element.  The thread owning cell c of the
   // element (c = tid first) loads its count and its first slot entries at once.
-  const int *cnt = sel(D.cnt, p3);
-  const int *slot = sel(D.slot, p2);
+  const gptr<const int> cnt = gsel(D.cnt, p3);
+  const gptr<const int> slot = gsel(D.slot, p2);
   const int base = e * G.kk;
   const int pre = D.cap < kSlotPre ? D.cap : kSlotPre;
   int m0 = 0;
   int v0[kSlotPre] = {0, 0, 0, 0};
   if (tid < G.kk) {
     m0 = cnt[base + tid];
-    const int *sl = slot + (size_t)(base + tid) * D.cap;
+    const gptr<const int> sl = slot + (size_t)(base + tid) * D.cap;
 #pragma unroll
     for (int s = 0; s < kSlotPre; ++s) v0[s] = s < pre ? sl[s] : 0;
   }
@@ -624,7 +629,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     any_long |= sh.longc[w];
   }
   const bool over = total > elem_capacity<NT>();
-  if (over && tid == 0) atomicOr(D.err, kErrCapacity);
+  if (over && tid == 0) __hip_atomic_fetch_or(glb(D.err), kErrCapacity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (over) total = 0;
   if (total > 0 && any_long && G.kk <= kCplThreads) {
     // one cell per thread: the slot entries are copied by the whole block
@@ -678,7 +683,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
   // ---- 2. void fraction; the state of the thread's first particle is
   // loaded in the same round trip as its radius
-  const dvec4 *X = sel(D.pr, p2);
+  const gptr<const dvec4> X = gsel(D.pr, p2);
   const int k0 = tid < total ? sh.ids[tid] : -1;
   double x0[3] = {0.0, 0.0, 0.0}, u0[3] = {0.0, 0.0, 0.0}, r0 = 0.0;
   if (k0 >= 0) {
@@ -688,11 +693,11 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     x0[2] = p.z;
     r0 = p.w;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u0[c] = D.v[c * n + k0];
+    for (int c = 0; c < 3; ++c) u0[c] = glb(D.v)[c * n + k0];
   }
   double vsum = k0 >= 0 ? 4.0 / 3.0 * kPi * r0 * r0 * r0 : 0.0;
   for (int t = tid + kCplThreads; t < total; t += kCplThreads) {
-    const double r = D.rad[sh.ids[t]];
+    const double r = glb(D.rad)[sh.ids[t]];
     vsum += 4.0 / 3.0 * kPi * r * r * r;
   }
   // lanes of this wavefront holding particles (the others hold zeros)
@@ -718,7 +723,7 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
     const dvec4 p = X[k];
     double xp[3] = {p.x, p.y, p.z}, up[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) up[c] = D.v[c * n + k];
+    for (int c = 0; c < 3; ++c) up[c] = glb(D.v)[c * n + k];
     particle_force<R, ORD, MODE>(D, C, k, ee, xp, up, p.w, eps_c, sh.sU, sh.sP, sh.sE, sums);
   }
   group_sum_n<GW>(sums, active);
@@ -780,18 +785,18 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
           F = -bq * (uq - ubar);
           if (C.model == 1) F -= sums[7 + c] / C.Ve;
         }
-        fpf_q[(long)c * nqtot + (long)e * nq + q] = F;
+        fpf_g[(long)c * nqtot + (long)e * nq + q] = F;
       }
     } else if (t < kFThreads + nq) {
       const long qg = (long)e * nq + (t - kFThreads);
-      eps_q[qg] = eps;
-      beta_q[qg] = bq;
+      eps_g[qg] = eps;
+      beta_g[qg] = bq;
     } else if (esums) {
       const int ne = G.n_elem;
-      esums[0 * ne + e] = (double)total;
-      esums[1 * ne + e] = vsum;
+      esums_g[0 * ne + e] = (double)total;
+      esums_g[1 * ne + e] = vsum;
 #pragma unroll
-      for (int j = 0; j < 10; ++j) esums[(2 + j) * ne + e] = sums[j];
+      for (int j = 0; j < 10; ++j) esums_g[(2 + j) * ne + e] = sums[j];
     }
   }
   cpl_sync<NT>();  // the LDS is reused for the next element
@@ -818,7 +823,7 @@ __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C,
   const int ne = e0 >= G.n_elem ? 0 : (G.n_elem - e0 < kClassElems ? G.n_elem - e0 : kClassElems);
   unsigned occupied = 0;
   if (ne > 0) {  // whole wavefront
-    const int *cnt = sel(D.cnt, p3);
+    const gptr<const int> cnt = gsel(D.cnt, p3);
     for (int c = lane; c - lane < G.kk; c += kWave) {
       int m[kClassElems];
 #pragma unroll
@@ -836,28 +841,28 @@ __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C,
     for (int t = lane; t < ne * nq; t += kWave) {
       if ((occupied >> (t / nq)) & 1u) continue;
       const long qg = q0 + t;
-      eps_q[qg] = 1.0;
-      beta_q[qg] = 0.0;
-      fpf_q[qg] = 0.0;
-      fpf_q[nqtot + qg] = 0.0;
-      fpf_q[2 * nqtot + qg] = 0.0;
+      glb(eps_q)[qg] = 1.0;
+      glb(beta_q)[qg] = 0.0;
+      glb(fpf_q)[qg] = 0.0;
+      glb(fpf_q)[nqtot + qg] = 0.0;
+      glb(fpf_q)[2 * nqtot + qg] = 0.0;
     }
     if (esums && lane < ne && !((occupied >> lane) & 1u))
-      for (int k = 0; k < 12; ++k) esums[(long)k * G.n_elem + e0 + lane] = 0.0;
+      for (int k = 0; k < 12; ++k) glb(esums)[(long)k * G.n_elem + e0 + lane] = 0.0;
   }
   if (lane == 0) s_cnt[wave] = __popc(occupied);
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
     for (int w = 0; w < kWaves; ++w) tot += s_cnt[w];
-    s_cnt[kWaves] = tot > 0 ? atomicAdd(cnt_word, tot) : 0;
+    s_cnt[kWaves] = tot > 0 ? __hip_atomic_fetch_add(glb(cnt_word), tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
   }
   __syncthreads();
   if (occupied) {
     int base = s_cnt[kWaves];
     for (int w = 0; w < wave; ++w) base += s_cnt[w];
     if (lane < ne && ((occupied >> lane) & 1u))
-      list[base + __popc(occupied & ((1u << lane) - 1u))] = tag | (unsigned)(e0 + lane);
+      glb(list)[base + __popc(occupied & ((1u << lane) - 1u))] = tag | (unsigned)(e0 + lane);
   }
 }
 
@@ -988,6 +993,10 @@ __global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple
   // another has (it stages the basis values).
   for (long long i = first; i < nocc; i += (long long)gridDim.x * kG) {
     if (i != first) ent = list[i];
+    // with a whole wavefront per element the entry is the same on every lane:
+    // said so, the bed's tables are read with scalar loads into scalar
+    // registers instead of into vector registers on every lane
+    if (NT >= kWave) ent = __builtin_amdgcn_readfirstlane(ent);
     couple_listed<R, ORD, MODE, NT>(tab, ctab, iot, run, ent, sh[g], sLq);
   }
 }
@@ -1072,6 +1081,12 @@ hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot
                                                                      list + ml.off[M_], mode_elems[M_])),
                     fp32, order, m, nt);
   }
+  return hipGetLastError();
+}
+
+// The occupied-element counters of a batch back to zero before a coupling
+// step (after a run of steps the batch's step-advance launch does it).
+hipError_t launch_reset_count(int *cnt_words, hipStream_t st) {
   reset_count<<<1, 64, 0, st>>>(cnt_words);
   return hipGetLastError();
 }

@@ -450,7 +450,7 @@ __device__ __forceinline__ void force_kick_body(const Dev &D, int blk, int p2, i
     //      (sorted) list by binary search in LDS and notes where each new
     //      entry's history comes from; then every lane stores its own new
     //      entries and copies their history
-    const int s = src ? src[a] : a;
+    const int s = src ? glb(src)[a] : a;
     const int mo = gsel(D.ln, lold)[s];
     const unsigned long long mask_old = gsel(D.hmask, lold)[s];
     const gptr<const unsigned long long> olst = gsel(D.nbr, lold);
@@ -720,9 +720,11 @@ __global__ __launch_bounds__(kForceBlock, 4) void force_kick_batch(const Dev *__
 }
 
 // After a run of n steps: every bed's step index advances, pending
-// permutations have been applied.
-__global__ void batch_advance(BedRun *run, int nb, int n) {
+// permutations have been applied, and the occupied-element counters of the
+// coupling step that opened the run (cnt, 3 words) are cleared for the next.
+__global__ void batch_advance(BedRun *run, int nb, int n, int *cnt) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0 && cnt) cnt[0] = cnt[1] = cnt[2] = 0;
   if (b >= nb) return;
   run[b].s += n;
   run[b].src = nullptr;
@@ -788,8 +790,8 @@ hipError_t launch_force_kick_batch(const Dev *tab, const BedRun *run, const unsi
   return hipGetLastError();
 }
 
-hipError_t launch_batch_advance(BedRun *run, int nb, int n, hipStream_t st) {
-  batch_advance<<<(nb + 255) / 256, 256, 0, st>>>(run, nb, n);
+hipError_t launch_batch_advance(BedRun *run, int nb, int n, int *cnt, hipStream_t st) {
+  batch_advance<<<(nb + 255) / 256, 256, 0, st>>>(run, nb, n, cnt);
   return hipGetLastError();
 }
 

@@ -48,11 +48,11 @@ __device__ __forceinline__ void pcm_elems_body(const Dev &D, double Ve, int p2, 
   unsigned long long sum = 0;
   for (int i = lane; i < G.kk; i += 64) {
     const int c = e * G.kk + i;
-    int m = sel(D.cnt, p3)[c];
+    int m = gsel(D.cnt, p3)[c];
     if (m > D.cap) m = D.cap;
-    const int *sl = sel(D.slot, p2) + (size_t)c * D.cap;
+    const gptr<const int> sl = gsel(D.slot, p2) + (size_t)c * D.cap;
     for (int s = 0; s < m; ++s) {
-      const double r = D.rad[sl[s]];
+      const double r = glb(D.rad)[sl[s]];
       sum += (unsigned long long)llrint(4.0 / 3.0 * kPi * r * r * r * scale);
     }
   }
