@@ -1574,6 +1574,10 @@ struct dem_batch {
   hipGraphExec_t g_cpl = nullptr;
   hipGraphExec_t g_step = nullptr;
   int g_steps = -1;
+  // both in one graph, for the chunks with no re-sort due (a graph launch
+  // costs the device a few microseconds of its own)
+  hipGraphExec_t g_chunk = nullptr;
+  int g_chunk_steps = -1;
   std::vector<std::pair<hipGraphExec_t, hipEvent_t>> stale;
 };
 
@@ -1636,7 +1640,7 @@ void fill_map(unsigned *m, long long &at, int bed, int blocks) {
 
 // Graphs of the old layout are destroyed once their last replay has run.
 void retire_graphs(dem_batch *B, hipStream_t st) {
-  for (hipGraphExec_t *g : {&B->g_cpl, &B->g_step}) {
+  for (hipGraphExec_t *g : {&B->g_cpl, &B->g_step, &B->g_chunk}) {
     if (!*g) continue;
     hipEvent_t e = nullptr;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess && hipEventRecord(e, st) == hipSuccess) {
@@ -1649,6 +1653,7 @@ void retire_graphs(dem_batch *B, hipStream_t st) {
     *g = nullptr;
   }
   B->g_steps = -1;
+  B->g_chunk_steps = -1;
   for (size_t i = 0; i < B->stale.size();) {
     if (hipEventQuery(B->stale[i].second) == hipSuccess) {
       (void)hipGraphExecDestroy(B->stale[i].first);
@@ -1708,6 +1713,13 @@ dem_status batch_layout(dem_batch *B, hipStream_t st) {
   retire_graphs(B, st);
   B->dirty = false;
   return DEM_OK;
+}
+
+// Whether some bed's re-sort is due before its next steps.
+bool batch_resort_due(const dem_batch *B) {
+  for (const dem_ctx *ctx : B->slot)
+    if (ctx && ctx->dp.resort_every > 0 && ctx->since_sort >= ctx->dp.resort_every) return true;
+  return false;
 }
 
 // Re-sorts the beds whose re-sort is due and refreshes their table entries.
@@ -1966,7 +1978,8 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
   // capture what this call needs and is not captured yet
   auto capture = [&](bool cpl, int steps, hipGraphExec_t *exec) -> dem_status {
     HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    const dem_status cr = cpl ? batch_enqueue_couple(B, B->cap) : batch_enqueue_steps(B, steps, B->cap);
+    dem_status cr = cpl ? batch_enqueue_couple(B, B->cap) : DEM_OK;
+    if (cr == DEM_OK && steps > 0) cr = batch_enqueue_steps(B, steps, B->cap);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(B->cap, &g);
     if (cr != DEM_OK || ec != hipSuccess || !g) {
@@ -1995,9 +2008,26 @@ dem_status dem_batch_run(dem_batch *B, int32_t n_chunks, int32_t steps_per_chunk
     if (r != DEM_OK) return r;
     B->g_steps = steps_per_chunk;
   }
+  if (couple && steps_per_chunk > 0 && (!B->g_chunk || B->g_chunk_steps != steps_per_chunk)) {
+    if (B->g_chunk) {
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipGraphExecDestroy(B->g_chunk));
+      B->g_chunk = nullptr;
+    }
+    r = capture(true, steps_per_chunk, &B->g_chunk);
+    if (r != DEM_OK) return r;
+    B->g_chunk_steps = steps_per_chunk;
+  }
   // per chunk, the order of dem_batch_couple + dem_batch_step: couple, due
   // re-sorts, steps
   for (int c = 0; c < n_chunks; ++c) {
+    if (couple && steps_per_chunk > 0 && !batch_resort_due(B)) {
+      if (B->cnt_dirty) HIP_TRY(launch_reset_count(B->cnt, st));
+      HIP_TRY(hipGraphLaunch(B->g_chunk, st));
+      B->cnt_dirty = false;
+      batch_mirror_steps(B, steps_per_chunk);
+      continue;
+    }
     if (couple) {
       if (B->cnt_dirty) HIP_TRY(launch_reset_count(B->cnt, st));
       HIP_TRY(hipGraphLaunch(B->g_cpl, st));
@@ -2025,6 +2055,7 @@ dem_status dem_batch_destroy(dem_batch *B) {
   }
   if (B->g_cpl) (void)hipGraphExecDestroy(B->g_cpl);
   if (B->g_step) (void)hipGraphExecDestroy(B->g_step);
+  if (B->g_chunk) (void)hipGraphExecDestroy(B->g_chunk);
   if (B->cap) (void)hipStreamDestroy(B->cap);
   if (B->stage_ev) {
     (void)hipEventSynchronize(B->stage_ev);
