@@ -888,10 +888,12 @@ dem_status scratch_of_current_device(double **out) {
 
 // Particles per cell of the grid just sorted (at most cap): with start and
 // home, the listing the following runs take as their cells' home ranges.
+namespace {
 __global__ void k_home_base(int ncells, const int *cnt, int cap, int *base) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < ncells) base[c] = min(cnt[c], cap);
 }
+}  // namespace
 
 // No home cells (before the first re-sort, after a restore): every grid
 // lists all of its particles in its slots.
