@@ -183,6 +183,37 @@ def test_graph_replay_equals_launches():
     b.close()
 
 
+def test_coupling_steps_back_to_back():
+    """Coupling steps issued back to back (direct calls, and graph chunks
+    without steps) give the outputs of one, and the steps after them the
+    same bits: the occupied-element counters are cleared before every
+    coupling step that does not follow a run of steps."""
+    wls = _q1_beds()
+    beds_a, fields_a = _make(wls, "fp32", resort=(4, 4, 4))
+    beds_b, fields_b = _make(wls, "fp32", resort=(4, 4, 4))
+    a = cfddem.Batch(beds_a, fields_a)
+    b = cfddem.Batch(beds_b, fields_b)
+    for _ in range(2):
+        a.couple()
+        a.step(5)
+        b.couple()
+        b.couple()
+        b.run(3, 0, couple=True)
+        b.couple()
+        b.step(5)
+    a.couple()
+    b.run(2, 0, couple=True)
+    out_a = [{k: v.cpu().numpy() for k, v in o.items()} for o in a.couple()]
+    out_b = [{k: v.cpu().numpy() for k, v in o.items()} for o in b.couple()]
+    for oa, ob in zip(out_a, out_b):
+        _same(oa, ob)
+    for x, y in zip(beds_a, beds_b):
+        _same(_snapshot(x), _snapshot(y))
+        assert x.poll()[0] == 0 and y.poll()[0] == 0
+    a.close()
+    b.close()
+
+
 def test_batch_of_one_agrees_with_single_bed_path():
     w = _q2_beds()[1]
     (single,), (fld,) = _make([w], "fp64", resort=(3,))
