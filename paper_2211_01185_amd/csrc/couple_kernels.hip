@@ -804,14 +804,18 @@ __device__ __forceinline__ void couple_element(const Dev &D, const Cpl &C, int e
 
 // Classification of kClassElems consecutive elements starting at e0 by one
 // wavefront: empty ones get their outputs, occupied ones are appended to
-// list (entries tag | element) through the counter at cnt_word, with one
-// atomic per block (a device-wide counter is a single address that every
-// XCD contends for: one atomic per wavefront serializes a large mesh).
+// list (cap entries; entries tag | element) through the counter at cnt_word,
+// which is zero before the pass, so that no element is listed twice and the
+// count stays within cap; the stores are bounded by cap all the same.  The
+// counter takes one atomic per block (a device-wide counter is a single
+// address that every XCD contends for: one atomic per wavefront serializes a
+// large mesh).
 // Called by every thread of the block; s_cnt is LDS of kClassBlock / kWave + 1
 // ints.  The order of the list does not matter: each listed element is
 // computed on its own.
 __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C, int e0, int p3,
-                                                     int *cnt_word, unsigned *list, unsigned tag,
+                                                     int *cnt_word, unsigned *list, long long cap,
+                                                     unsigned tag,
                                                      double *__restrict__ eps_q,
                                                      double *__restrict__ beta_q,
                                                      double *__restrict__ fpf_q,
@@ -861,8 +865,8 @@ __device__ __forceinline__ void couple_classify_body(const Dev &D, const Cpl &C,
   if (occupied) {
     int base = s_cnt[kWaves];
     for (int w = 0; w < wave; ++w) base += s_cnt[w];
-    if (lane < ne && ((occupied >> lane) & 1u))
-      glb(list)[base + __popc(occupied & ((1u << lane) - 1u))] = tag | (unsigned)(e0 + lane);
+    const int at = base + __popc(occupied & ((1u << lane) - 1u));
+    if (lane < ne && ((occupied >> lane) & 1u) && at < cap) glb(list)[at] = tag | (unsigned)(e0 + lane);
   }
 }
 
@@ -877,8 +881,8 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify(Dev D, Cpl C, int
   __shared__ int s_cnt[kClassBlock / kWave + 1];
   const int gw = (blockIdx.x * kClassBlock + threadIdx.x) / kWave;
   if (gw == 0 && threadIdx.x == 0) D.err[kOccWord + (parity ^ 1)] = 0;
-  couple_classify_body(D, C, gw * kClassElems, p3, D.err + kOccWord + parity, (unsigned *)D.occ, 0u,
-                       eps_q, beta_q, fpf_q, esums, s_cnt);
+  couple_classify_body(D, C, gw * kClassElems, p3, D.err + kOccWord + parity, (unsigned *)D.occ,
+                       D.grid.n_elem, 0u, eps_q, beta_q, fpf_q, esums, s_cnt);
 }
 
 // Elements a block computes at once (the groups of a wavefront for 16 or 32
@@ -925,7 +929,7 @@ __global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple
   const int last = D.grid.n_elem - 1;
   // the list entry is read in the same round trip as the list length (the
   // list has n_elem entries)
-  const int nocc = D.err[kOccWord + parity];
+  const int nocc = min(D.err[kOccWord + parity], D.grid.n_elem);
   const int e = D.occ[first < last ? first : last];
   __asm__ volatile("" ::: "memory");
   if ((int)blockIdx.x * kG >= nocc) return;  // whole block
@@ -944,7 +948,7 @@ __global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple
 __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
     const Dev *__restrict__ tab, const Cpl *__restrict__ ctab, const CplIO *__restrict__ iot,
     const BedRun *__restrict__ run, const unsigned *__restrict__ map, int *cnt_words, unsigned *list,
-    ModeLists ml) {
+    ModeLists ml, long long list_len) {
   __shared__ int s_cnt[kClassBlock / kWave + 1];
   const unsigned mb = map[blockIdx.x];
   const int b = (int)(mb >> kBedShift), blk = (int)(mb & kBlockMask);
@@ -955,8 +959,9 @@ __global__ __launch_bounds__(kClassBlock) void couple_classify_batch(
   const int gw = blk * (kClassBlock / kWave) + (int)(threadIdx.x / kWave);
   // occupied elements go to the list of the bed's element-kernel variant
   const int m = cpl_mode_of(C.drag, C.shear || C.smooth);
-  couple_classify_body(D, C, gw * kClassElems, p3, cnt_words + m, list + ml.off[m], (unsigned)b << kBedShift,
-                       io.eps_q, io.beta_q, io.fpf_q, io.esums, s_cnt);
+  const long long cap = (m < 2 ? ml.off[m + 1] : list_len) - ml.off[m];
+  couple_classify_body(D, C, gw * kClassElems, p3, cnt_words + m, list + ml.off[m], cap,
+                       (unsigned)b << kBedShift, io.eps_q, io.beta_q, io.fpf_q, io.esums, s_cnt);
 }
 
 template <typename R, int ORD, int MODE, int NT>
@@ -984,7 +989,7 @@ __global__ __launch_bounds__(block_threads<NT>(), occ_waves<MODE>()) void couple
   __shared__ double sLq[3][3];
   const int g = (int)threadIdx.x / NT;
   const long long first = (long long)blockIdx.x * kG + g;
-  const int nocc = *cnt_word;
+  const int nocc = (int)min((long long)*cnt_word, cap);
   unsigned ent = list[first < cap ? first : cap - 1];  // the list region has cap entries
   __asm__ volatile("" ::: "memory");
   // one call site (the element computation is inlined once); the first entry
@@ -1072,8 +1077,8 @@ hipError_t launch_couple_batch(const Dev *tab, const Cpl *ctab, const CplIO *iot
   ml.off[0] = 0;
   ml.off[1] = mode_elems[0];
   ml.off[2] = mode_elems[0] + mode_elems[1];
-  couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(tab, ctab, iot, run, map_class, cnt_words,
-                                                              list, ml);
+  couple_classify_batch<<<blocks_class, kClassBlock, 0, st>>>(
+      tab, ctab, iot, run, map_class, cnt_words, list, ml, mode_elems[0] + mode_elems[1] + mode_elems[2]);
   for (int m = 0; m < 3; ++m) {
     if (mode_elems[m] <= 0) continue;
     CFDDEM_DISPATCH((couple_occupied_batch<RT_, O_, M_, NT_><<<occ_grid<NT_>(mode_elems[m]), block_threads<NT_>(), 0,
