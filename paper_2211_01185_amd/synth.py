@@ -241,6 +241,58 @@ def lattice(n_side=(12, 12, 14), spacing_factor=0.98, seed_index=0, d=3e-3) -> W
                     dict(steps=20, coupling_every=10, precision="fp64"), U, P)
 
 
+def on_faces(seed_index=0) -> Workload:
+    """Spheres of d = 3 mm centred on cell, element and box faces.
+
+    Box 0.0625 x 0.0625 x 0.125 m with 4 x 4 x 8 elements: with the default
+    skin (0.1 d) the contact cells are 2^-8 m wide, so every multiple of
+    2^-8 is a cell face and sits exactly in binary.  Sites every two cells
+    along each axis, from one box face to the other (the outermost centred
+    on the walls, overlapping them by a radius); a third of the sites moved
+    one ulp down on each axis (just below a face); half of the sites with a
+    partner 0.98 d up along a random axis that does not leave the box, so
+    that touching pairs straddle faces or sit on them.  Any two spheres other
+    than a site and its partner are at least 4.8 mm apart."""
+    rng = rng_for(1, 200 + seed_index)
+    d = 3e-3
+    h = 2.0 ** -8
+    lo, hi = [0.0, 0.0, 0.0], [0.0625, 0.0625, 0.125]
+    ns = [int(round((hi[a] - lo[a]) / (2 * h))) + 1 for a in range(3)]
+    k = np.arange(ns[0] * ns[1] * ns[2])
+    idx = np.stack([k % ns[0], (k // ns[0]) % ns[1], k // (ns[0] * ns[1])])
+    sites = idx * (2 * h)
+    down = rng.random(sites.shape[1]) < 1.0 / 3.0
+    for a in range(3):
+        moved = down & (sites[a] > lo[a])
+        sites[a, moved] = np.nextafter(sites[a, moved], -np.inf)
+    pick = rng.random(sites.shape[1]) < 0.5
+    axis = rng.integers(0, 3, size=sites.shape[1])
+    part = []
+    for i in np.flatnonzero(pick):
+        # up along the drawn axis, or the next one off the upper box face (a
+        # site on the upper face of all three axes gets no partner)
+        for t in range(3):
+            a = (axis[i] + t) % 3
+            if idx[a, i] < ns[a] - 1:
+                q = sites[:, i].copy()
+                q[a] += 0.98 * d
+                part.append(q)
+                break
+    x = np.concatenate([sites, np.array(part).T], axis=1)
+    n = x.shape[1]
+    v = rng.normal(0.0, 0.01, size=(3, n))
+    w = rng.normal(0.0, 5.0, size=(3, n))
+    n_el = [4, 4, 8]
+    fluid = dict(order=2, n_el=n_el, rho_f=1.2, mu_f=1.8e-5, model=0, eps_min=0.1)
+    nodes = node_grid(lo, hi, n_el, 2)
+    U = np.zeros((3, nodes.shape[1]))
+    U[2] = 0.5 + 0.05 * rng.standard_normal(nodes.shape[1])
+    P = np.zeros(node_grid(lo, hi, n_el, 1).shape[1])
+    dem = dict(box_lo=lo, box_hi=hi, gravity=[0.0, 0.0, -G], dt=1e-5, **_material())
+    return Workload("on_faces", x, v, w, np.full(n, 0.5 * d), np.full(n, 2500.0), dem, fluid,
+                    dict(steps=3, coupling_every=10, precision="fp64"), U, P)
+
+
 def fluidized(n=100_000, seed_index=0, height=0.4) -> Workload:
     """100,000 spheres, d = 1 mm, rho = 2500, jittered lattice at solid fraction
     0.4; Q2 20x20x80; U = (0,0,1.2) + N(0,0.05) per node; linear pressure."""

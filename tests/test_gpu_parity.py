@@ -43,6 +43,33 @@ def test_binning_is_bit_exact(name):
     assert np.array_equal(cell.cpu().numpy().astype(np.int64), oc)
 
 
+@pytest.mark.parametrize("precision,lanes", [("fp64", 2), ("fp32", 1), ("fp32", 2), ("fp32", 4)])
+def test_spheres_on_cell_element_and_box_faces(precision, lanes):
+    """Centres exactly on cell, element and box faces and one ulp below them:
+    the cells match the oracle's bit for bit, the contact sets (pairs across
+    or on faces, walls touched by spheres centred on them) match, and so do
+    the forces at creation and the states after three steps."""
+    wl = synth.on_faces()
+    gb = gpu_bed(wl, precision, lanes=lanes)
+    elem, cell, k = gb.read_cells()
+    assert k == [4, 4, 4], k  # cells 2^-8 m wide: their faces are exact in binary
+    oe, oc, outside = O.bin_particles(wl.x, wl.dem["box_lo"], wl.dem["box_hi"], wl.fluid["n_el"], k)
+    assert outside == 0
+    assert np.array_equal(elem.cpu().numpy(), oe)
+    assert np.array_equal(cell.cpu().numpy().astype(np.int64), oc)
+    pi, _ = O.find_pairs(wl.x, wl.radius, wl.dem["box_lo"], wl.dem["box_hi"])
+    assert len(pi) > 500
+    ob, _ = oracle_bed(wl)
+    compare_contacts(gb, ob, TOL[precision])
+    compare_states(gb, ob, TOL[precision], keys=("Fc", "Tc"))
+    gb.step(3)
+    ob.step(3)
+    compare_contacts(gb, ob, TOL[precision])
+    compare_states(gb, ob, TOL[precision])
+    err, _ = gb.poll()
+    assert err == 0
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["lattice", "lattice_ragged"])
 def test_priming_forces(name, precision):
@@ -161,6 +188,37 @@ def test_contact_capacity_error():
     from paper_2211_01185_amd import cfddem
     wl = synth.lattice(n_side=(6, 6, 6))
     gb = gpu_bed(wl, max_neighbors=2)
+    err, _ = gb.poll()
+    assert err == cfddem.DEM_E_CAPACITY
+
+
+def test_contact_capacity_at_the_limit():
+    """A neighbour-list capacity equal to the longest list (every candidate
+    within R_a + R_b + skin, counted by brute force) raises no error and
+    gives the oracle's contacts and forces; one entry less raises the
+    capacity error."""
+    from paper_2211_01185_amd import cfddem
+    wl = synth.lattice(n_side=(6, 6, 6))
+    skin = 0.1 * 2.0 * float(wl.radius.min())  # the default skin
+    d = wl.x[:, :, None] - wl.x[:, None, :]
+    dist = np.sqrt((d * d).sum(axis=0))
+    cut = wl.radius[:, None] + wl.radius[None, :] + skin
+    listed = (dist < cut) & ~np.eye(wl.n, dtype=bool)
+    longest = int(listed.sum(axis=1).max())
+    assert 2 <= longest < 64
+    gb = gpu_bed(wl, "fp64", max_neighbors=longest)
+    err, _ = gb.poll()
+    assert err == 0
+    ob, _ = oracle_bed(wl)
+    compare_contacts(gb, ob, TOL["fp64"])
+    gb.step(2)
+    ob.step(2)
+    compare_contacts(gb, ob, TOL["fp64"])
+    compare_states(gb, ob, TOL["fp64"])
+    err, _ = gb.poll()
+    assert err == 0
+    gb.close()
+    gb = gpu_bed(wl, "fp64", max_neighbors=longest - 1)
     err, _ = gb.poll()
     assert err == cfddem.DEM_E_CAPACITY
 
