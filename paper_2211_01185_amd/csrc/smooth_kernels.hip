@@ -123,14 +123,17 @@ __global__ __launch_bounds__(kSB) void smooth_rhs(SmoothOp S, const unsigned lon
 // out[line c, i] = sum_j T[i][j] in[line c, j], optionally scaled by the
 // diagonal: a (n x n) x (n x lines) product on the FP64 matrix cores.  A block
 // of four wavefronts computes kTI outputs along the axis for kTC lines; each
-// wavefront a 16 x 32 part of it as two 16 x 16 tiles of
-// v_mfma_f64_16x16x4f64 (zero padding past n adds exact zeros).  The next
+// wavefront a 16 x 16 part of it as one tile of v_mfma_f64_16x16x4f64 (zero
+// padding past n adds exact zeros).  Tiles of 32 x 32 give the 100k bed's
+// 161 x 41 x 41 lattice 318 to 414 blocks per pass where 32 x 64 gave 162 to
+// 208, fewer than the chip's 256 CUs (the three passes 11.7, 8.2 and 5.6 us
+// against 11.0, 6.9 and 5.1 us; a 96-wide k chunk was slower).  The next
 // kTK-wide chunk of T and of the lines is loaded into registers while the
 // current one is summed, and the result tile is staged through LDS, so that
 // loads and stores follow the order of memory on every axis (along the line
 // for x, across lines otherwise).
 namespace {
-constexpr int kTI = 32, kTC = 64, kTK = 64, kTT = 256;
+constexpr int kTI = 32, kTC = 32, kTK = 64, kTT = 256;
 constexpr int kAL = kTI * kTK / kTT, kBL = kTK * kTC / kTT, kOL = kTI * kTC / kTT;  // per thread
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -195,12 +198,12 @@ __global__ __launch_bounds__(kTT) void fd_transform(SmoothOp S, const double *__
       br[m] = (bb[m] >= 0 && j < n) ? in[bb[m] + (long)j * stride] : 0.0;
     }
   };
-  // this wavefront's part: rows wr .. wr+15, lines wc .. wc+31; the lane's
+  // this wavefront's part: rows wr .. wr+15, lines wc .. wc+15; the lane's
   // operand row / line lr and k offset lk (A: T[row][k], B: line tile[k][line])
   const int lane = t & 63, w = t >> 6;
-  const int wr = 16 * (w & 1), wc = 32 * (w >> 1);
+  const int wr = 16 * (w & 1), wc = 16 * (w >> 1);
   const int lr = lane & 15, lk = lane >> 4;
-  dbl4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+  dbl4 d0 = {0.0, 0.0, 0.0, 0.0};
   load(0);
   for (int j0 = 0; j0 < n; j0 += kTK) {
 #pragma unroll
@@ -219,17 +222,15 @@ __global__ __launch_bounds__(kTT) void fd_transform(SmoothOp S, const double *__
     const int kmax = min(kTK, n - j0);
     for (int kk = 0; kk < kmax; kk += 4) {
       const double av = As[wr + lr][kk + lk];
-      const double b0 = Bs[kk + lk][wc + lr], b1 = Bs[kk + lk][wc + 16 + lr];
+      const double b0 = Bs[kk + lk][wc + lr];
       d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, d0, 0, 0, 0);
-      d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, d1, 0, 0, 0);
     }
     __syncthreads();
   }
-  // result r of a lane: row wr + 4 r + lane / 16, line wc + lane % 16 (+ 16 for d1)
+  // result r of a lane: row wr + 4 r + lane / 16, line wc + lane % 16
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     Os[wr + 4 * r + lk][wc + lr] = d0[r];
-    Os[wr + 4 * r + lk][wc + 16 + lr] = d1[r];
   }
   __syncthreads();
 #pragma unroll

@@ -236,6 +236,10 @@ class Server:
                     if finishing:
                         finish_ready(block=True)  # releases memory a waiting job may need
                         continue
+                    if not pending:
+                        # the last result was read by finish_ready() above,
+                        # after the loop's test: nothing is left
+                        continue
                     # idle until the next arrival
                     wait = (pending[0].arrival - now()) / self.speed
                     if wait > 0:
