@@ -683,16 +683,16 @@ __device__ inline int xcd_block(int i, int nb) {
 }
 
 // Runs of C consecutive blocks dealt to the XCDs in turn (the k-th run of XCD
-// x is run 8k + x), the ragged end of the grid in index order: spatial
-// neighbours stay in one L2 within a run, while the runs spread work of
-// unequal cost (the beds of a batch) over every XCD.  On a 64-bed ensemble
+// x is run 8k + x), the ragged end of the grid in the single bed's XCD order:
+// spatial neighbours stay in one L2 within a run, while the runs spread work
+// of unequal cost (the beds of a batch) over every XCD.  On a 64-bed ensemble
 // (48,234 blocks) runs of 8, 32, 128, 256 and 1,024 blocks measured 0.304,
 // 0.302, 0.302, 0.308 and 0.320 ms per step, the map's own order 0.305 and
 // one contiguous eighth of the map per XCD 0.327.
 constexpr int kBatchXcdRun = 128;
 __device__ inline int xcd_run_block(int i, int nb, int C) {
   const int full = nb / (kXcds * C) * (kXcds * C);
-  if (i >= full) return i;
+  if (i >= full) return full + xcd_block(i - full, nb - full);  // full is a multiple of 8
   const int x = i % kXcds, j = i / kXcds;
   return ((j / C) * kXcds + x) * C + j % C;
 }
