@@ -748,8 +748,9 @@ def served_stream(n_jobs, warmup, dev, config=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(beds shard by bed or by z-slab, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (across GPUs, "
+              "independent beds would be placed whole, and one large bed split into z-slabs that "
+              "exchange ghost particles every step)", file=sys.stderr)
         sys.exit(2)
     import torch
 
