@@ -686,9 +686,11 @@ __device__ inline int xcd_block(int i, int nb) {
 // x is run 8k + x), the ragged end of the grid in the single bed's XCD order:
 // spatial neighbours stay in one L2 within a run, while the runs spread work
 // of unequal cost (the beds of a batch) over every XCD.  On a 64-bed ensemble
-// (48,234 blocks) runs of 8, 32, 128, 256 and 1,024 blocks measured 0.304,
-// 0.302, 0.302, 0.308 and 0.320 ms per step, the map's own order 0.305 and
-// one contiguous eighth of the map per XCD 0.327.
+// in blocks of two wavefronts (48,234 blocks) runs of 8, 32, 128, 256 and
+// 1,024 blocks measured 0.304, 0.302, 0.302, 0.308 and 0.320 ms per step, the
+// map's own order 0.305 and one contiguous eighth of the map per XCD 0.327;
+// in blocks of one wavefront, runs of 128, 256 and 512 blocks 0.294, 0.294
+// and 0.300 ms.
 constexpr int kBatchXcdRun = 128;
 __device__ inline int xcd_run_block(int i, int nb, int C) {
   const int full = nb / (kXcds * C) * (kXcds * C);

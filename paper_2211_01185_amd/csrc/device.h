@@ -8,7 +8,12 @@
 namespace cfddem {
 
 constexpr int kMaxNeighbors = 64;  // bound of dem_params.max_neighbors (one 64-bit mask)
-constexpr int kForceBlock = 128;   // threads per block of the contact-force kernel
+// Threads per block of the contact-force kernel: one wavefront.  Against 128
+// and 256 threads (same registers, four wavefronts per SIMD): fluidized and
+// packed 100k beds about 1 % faster, 500k spouted bed 3 %, 64-bed ensemble
+// 0.302 -> 0.294 ms per step (finer blocks give each XCD's contiguous ranges
+// and the work of unequal beds a finer grain).
+constexpr int kForceBlock = 64;
 constexpr int kForceLanes = 2;     // default lanes sharing one particle in the contact-force kernel
 constexpr int kElemMaxParticles = 1024;  // particles one coupling wave can hold
 constexpr int kWalls = 6;          // partner codes 0..5 are the box faces
