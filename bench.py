@@ -63,6 +63,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -74,7 +75,17 @@ METRIC = "DEM+coupling particle-steps/s @100k spheres; batched jobs/s + p99 late
 HBM_PEAK_GBS = 8000.0
 COUPLING_EVERY = 10
 RESORT_EVERY = 100
-FORCE_BLOCK = 128  # threads per block of the contact-force kernels
+
+
+def _force_block():
+    """Threads per block of the contact-force kernels, as the library's device
+    header defines them (the batched line reports the grid it launches)."""
+    hdr = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2211_01185_amd", "csrc", "device.h")
+    with open(hdr) as f:
+        return int(re.search(r"constexpr int kForceBlock = (\d+);", f.read()).group(1))
+
+
+FORCE_BLOCK = _force_block()
 # algorithmic bytes of one DEM step (one launch of the contact-force kernel):
 # per particle it must read x, v_half, w_half (72 B), radius and mass (16 B) and
 # the held fluid force (24 B), and write the next step's x, v_half, w_half

@@ -32,7 +32,16 @@ import re
 
 import numpy as np
 
-FORCE_BLOCK = 128
+
+
+def _force_block():
+    """Threads per block of the contact-force kernels, from the device header."""
+    hdr = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "device.h")
+    with open(hdr) as f:
+        return int(re.search(r"constexpr int kForceBlock = (\d+);", f.read()).group(1))
+
+
+FORCE_BLOCK = _force_block()
 
 
 def _one(d, suffix):
